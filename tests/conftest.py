@@ -1,0 +1,27 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def pytest_sessionstart(session):
+    # The oracle is plain C; make sure the shared object matches its source.
+    import oracle  # noqa: F401  (test infrastructure)
+
+    oracle._load()
+
+
+@pytest.fixture(scope="session")
+def ref():
+    import oracle
+
+    return oracle
