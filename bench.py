@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of the HELIOS radiative-equilibrium hot path on one MI355X.
+
+A step is one radiative-equilibrium iteration of the whole hot path over the
+batch: opacity mixing (helios_mix_opacity), the flux solve (helios_flux:
+Planck sources, boundary fluxes, sublayer coefficients, 1 + 4 scattering
+passes, Gauss and bin sums) and the FP64 temperature update with the
+interface re-interpolation (helios_radeq), all in the library's HIP kernels,
+with inputs resident in HBM.
+
+Workload: one atmosphere at full spectral size -- 100 layers (201 points)
+over 1e-6..1e3 bar, 3000 bins over 0.3-30 micron, 20 Gauss points, four
+species k-tables on a 20 T x 20 log P grid (float32, 384 MB), seeded
+synthetic inputs (paper_1606_05474_amd.workloads), FP64.  The same loop in
+mixed precision is reported alongside.
+
+Metric: layer*bin*g flux updates per second (one unit = one layer, both
+sublayers, one bin, one g point, through one complete flux call).
+
+Usage:  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+
+
+def sweep_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1606_05474_amd", "csrc", "k_sweep.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def sweep_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
+    """Bytes one flux-sweep launch must move for one atmosphere: opacities at
+    the points, the upward-flux warm start in (the TOA point is never read)
+    and out, the Planck values per (bin, point), w0 and g0 per (bin, layer),
+    the two boundary fluxes and the Gauss weights, and the two Gauss-summed
+    per-bin outputs (float64)."""
+    npt = 2 * n + 1
+    per_bin = (ng * npt * rbytes            # kappa
+               + ng * (npt - 1) * rbytes    # F_up warm start in
+               + ng * npt * rbytes          # F_up out
+               + npt * rbytes               # B
+               + 2 * n * 8                  # w0, g0
+               + 2 * 8                      # F_top, F_int
+               + 2 * npt * 8)               # F_up_bin, F_dn_bin
+    return nb * per_bin + ng * 8
+
+
+def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict):
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+
+    b = H.Batch([atm])
+    ktd = H.KTable(kt)
+    s = H.Solver(b, ktd, prec=prec)
+    s.reset(atm["T0"])
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        s.step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:  # create the events
+        e0.record(stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        H.set_sweep_events(e0, e1)
+        s.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    H.set_sweep_events(None, None)
+    sweep_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps
+    n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
+    units = n * nb * ng
+    wall = t1 - t0
+    rbytes = 4 if prec == H.MIXED else 8
+    alg = sweep_algorithmic_bytes(n, nb, ng, rbytes)
+    return {
+        "value": units * steps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "sweep_ms": sweep_ms,
+        "sweep_bytes": alg,
+        "sweep_gbs": alg / (sweep_ms * 1e-3) / 1e9,
+        "status": int(s.status[0].item()),
+        "updates": int(s.iters[0].item()),
+    }
+
+
+def cpu_baseline(atm: dict, kt: dict, budget_s: float = 10.0):
+    """The FP64 oracle as it stands, timed on the host: whole RE iterations
+    (profile, opacity, flux with 1 + 4 passes, RE step) of the same
+    atmosphere, repeated until about budget_s of wall time has passed."""
+    import numpy as np
+
+    import oracle as ref
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
+    P = ref.grid(atm["P_c"])
+    T_c = np.array(atm["T0"], np.float64)
+    m = np.ones(n)
+    hist = np.zeros(n, np.int32)
+    F_up = np.zeros((nb, ng, 2 * n + 1))
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        T = ref.profile(P, T_c)
+        kap = ref.mix_opacity(kt, T, P, atm["vmr"], atm["bin_index"], ng)
+        res = ref.flux(atm, kap, T, P, F_up, n_scat=4, n_threads=threads, want_dn=False)
+        ref.radeq(atm, P, res["F_bol"], T_c, m, hist)
+        iters += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": n * nb * ng * iters / wall, "unit": "layer*bin*g/s", "cores": threads, "kind": "oracle",
+            "sample": f"{iters} full RE iterations of the same 100-layer x 3000-bin x 20-g atmosphere "
+                      f"({wall:.1f} s wall, OpenMP over columns)"}
+
+
+def traffic_entry(prec_name: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current sweep source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(prec_name)
+    if not e or e.get("source_sha") != sweep_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    args = ap.parse_args(argv)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); the "
+              "per-GPU shard of this path is one independent set of atmospheres, see DESIGN.md",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    H.lib()  # fails loudly if the native library is missing
+    kt = W.table_ktab(2)
+    atm, _ = W.spectral_workload(ktab=kt)
+    fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt)
+    mixed = run_gpu(H.MIXED, args.steps, args.warmup, atm, kt)
+    n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
+    tr = traffic_entry("fp64")
+    line = {
+        "metric": "layer*bin*g flux updates/s",
+        "value": fp64["value"],
+        "unit": "layer*bin*g/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single atmosphere at full spectral size: 100 layers, 3000 bins 0.3-30 um, "
+                               "20 g, four float32 k-tables 20 T x 20 log P, FP64, 1+4 scattering passes",
+                   "n_layer": n, "n_bin": nb, "n_g": ng, "n_scat": 4, "step": "mix_opacity + flux + radeq"},
+        "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep)", "achieved": fp64["sweep_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fp64["sweep_gbs"] / HBM_PEAK_GBS,
+                     "traffic": tr, "algorithmic_bytes_per_launch": fp64["sweep_bytes"],
+                     "avg_launch_ms": fp64["sweep_ms"]},
+        "mixed_precision": {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
+                            "sweep_ms": mixed["sweep_ms"], "sweep_gbs": mixed["sweep_gbs"],
+                            "frac": mixed["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic_entry("mixed")},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(atm, kt, args.cpu_budget)
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

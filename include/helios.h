@@ -1,0 +1,217 @@
+/*
+ * helios.h -- C ABI of the MI355X (gfx950) radiative-equilibrium hot path of
+ * HELIOS (Malik et al. 2017, Sec. 2): the two-stream flux solve that each
+ * temperature iteration runs, and the temperature update it drives.
+ *
+ * Conventions for every call
+ * --------------------------
+ *  * Array arguments are DEVICE pointers unless marked [host].
+ *  * The caller owns all memory, including the flux workspace sized by
+ *    helios_workspace_bytes().  The library keeps no pointer after a call's
+ *    stream-ordered work and allocates no device memory.
+ *  * Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *    is the default stream).  Errors found before anything is enqueued are
+ *    returned synchronously as negative codes; nothing was enqueued then.
+ *  * helios_last_error() returns a thread-local message for the last error.
+ *    No call throws, aborts or prints.
+ *  * Units are cgs: K, dyn cm^-2, cm, erg s^-1 cm^-2 (fluxes per unit
+ *    wavelength: erg s^-1 cm^-3), cm^2 g^-1, cm s^-2.
+ *  * A single atmosphere is a batch of one; all calls take a batch.
+ *
+ * Per-atmosphere data are concatenated in atmosphere order.  With n layers,
+ * npt = 2n+1 points (point 2i = interface i, point 2i+1 = centre of layer i,
+ * bottom to top), nb bins and ng Gauss points, the layouts are
+ *    layer arrays   [n]            offset lay_off[a]
+ *    point arrays   [npt]          offset pt_off[a]
+ *    bin arrays     [nb]           offset bin_off[a]
+ *    bin x layer    [nb][n]        offset lb_off[a]
+ *    bin x point    [nb][npt]      offset pb_off[a]
+ *    cell arrays    [nb][ng][npt]  offset cell_off[a]   (one column per (bin, g))
+ * where each *_off is the exclusive prefix sum of the per-atmosphere sizes,
+ * with n_atm+1 entries.
+ */
+#ifndef HELIOS_H
+#define HELIOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define HELIOS_OK 0
+#define HELIOS_NOT_CONVERGED 1
+#define HELIOS_EINVAL (-1)     /* null pointer, non-positive size, unknown enum */
+#define HELIOS_ESHAPE (-2)     /* inconsistent sizes / offsets / table shape */
+#define HELIOS_EDEVICE (-3)    /* a HIP call failed */
+#define HELIOS_EWORKSPACE (-4) /* workspace smaller than helios_workspace_bytes() */
+#define HELIOS_ENUMERIC (-5)   /* non-finite flux or temperature (per-atmosphere status) */
+
+/* per-atmosphere status words written by helios_radeq */
+#define HELIOS_ATM_RUNNING 0
+#define HELIOS_ATM_CONVERGED 1
+#define HELIOS_ATM_NUMERIC (-5)
+
+#define HELIOS_MAX_SPECIES 8
+#define HELIOS_MAX_NG 32
+#define HELIOS_MAX_LAYERS 400
+
+typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;
+typedef enum { HELIOS_KTAB_TABLE = 0, HELIOS_KTAB_POWERLAW = 1 } helios_ktab_mode;
+typedef enum { HELIOS_NORM_SIGMA_T4 = 0, HELIOS_NORM_SIGMA_TINT4 = 1 } helios_norm;
+
+/* Batch descriptor.  Host mirrors are read for validation and launch shapes;
+ * the device arrays must hold the same values. */
+typedef struct helios_atm {
+    int32_t n_atm;               /* atmospheres in the batch, >= 1 */
+    int32_t n_g;                 /* Gauss points per bin, 1..HELIOS_MAX_NG */
+    const int32_t* n_layer_h;    /* [host][n_atm] layers, 2..HELIOS_MAX_LAYERS */
+    const int32_t* n_bin_h;      /* [host][n_atm] bins, >= 1 */
+    const int32_t* n_layer;      /* [n_atm] */
+    const int32_t* n_bin;        /* [n_atm] */
+    const int64_t* lay_off;      /* [n_atm+1] */
+    const int64_t* pt_off;       /* [n_atm+1] */
+    const int64_t* bin_off;      /* [n_atm+1] */
+    const int64_t* lb_off;       /* [n_atm+1] */
+    const int64_t* pb_off;       /* [n_atm+1] */
+    const int64_t* cell_off;     /* [n_atm+1] */
+    const int32_t* bin_index;    /* [sum nb] k-table bin of each model bin */
+    const double* lambda_c;      /* [sum nb] bin centre wavelength, cm */
+    const double* dlambda;       /* [sum nb] bin width, cm */
+    const double* P_c;           /* [sum n] layer-centre pressure, bottom -> top */
+    double* P_pt;                /* [sum npt] point pressures, written by helios_grid */
+    const double* grav;          /* [n_atm] surface gravity */
+    const double* T_star;        /* [n_atm] stellar blackbody temperature */
+    const double* T_irr;         /* [n_atm] irradiation temperature: TOA flux is (T_irr/T_star)^4 pi B(T_star) */
+    const double* T_int;         /* [n_atm] internal temperature of the BOA flux */
+} helios_atm;
+
+/* Opacity source (Sec. 2.3).  TABLE: k-coefficients on a uniform
+ * T x log10 P grid, interpolated bilinearly and clamped at the table edges.
+ * POWERLAW: k = k0 (P/P_ref)^p_exp (T/T_ref)^t_exp. */
+typedef struct helios_ktab {
+    int32_t mode;                /* helios_ktab_mode */
+    int32_t n_species;           /* 1..HELIOS_MAX_SPECIES */
+    int32_t n_T, n_P;            /* TABLE: nodes per axis, >= 2 */
+    int32_t n_bin_table;         /* bins in the table (bin_index < n_bin_table) */
+    int32_t n_g;                 /* must equal helios_atm.n_g */
+    double T_min, T_step;        /* TABLE: T axis, K */
+    double logP_min, logP_step;  /* TABLE: log10 P axis, P in dyn cm^-2 */
+    const float* k;              /* TABLE: [n_species][n_T][n_P][n_bin_table][n_g] */
+    const double* k0;            /* POWERLAW: [n_species][n_bin_table][n_g] */
+    double p_exp, t_exp, P_ref, T_ref;
+    const double* species_mass;  /* [host][n_species] molecular mass, proton masses */
+    double mmw;                  /* mean molecular mass, proton masses (2.4) */
+} helios_ktab;
+
+/* Options of the temperature update (Sec. 2.2.3-2.2.4). */
+typedef struct helios_re_opts {
+    double tol;       /* convergence threshold on max_i |dF_i| / norm_i */
+    int32_t norm;     /* helios_norm: sigma T_i^4 (paper) or sigma T_int^4 */
+    int32_t window;   /* oscillation-control window, 2..16 (paper: 6) */
+    int32_t osc_any;  /* 0: oscillation = sign alternated over the whole window;
+                         1: any sign change in the window counts */
+    int32_t pad_;
+    double T_floor;   /* lower temperature bound, K */
+    double shrink;    /* multiplier on oscillation (paper: reduce by 33% -> 0.67) */
+    double grow;      /* multiplier when monotonic (paper: +10% -> 1.1) */
+    double fpre_c;    /* f_pre = fpre_c / |dF|^fpre_p (paper: 1e5, 0.9) */
+    double fpre_p;
+} helios_re_opts;
+
+/* Per-layer RE state, owned by the caller, initialised to m = 1, hist = 0.
+ * hist bits 0..15: signs of the most recent dT (bit 0 newest, 1 = warming);
+ * bits 16..31: number of signs recorded (saturates at the window). */
+typedef struct helios_re_state {
+    double* m;        /* [sum n] timestep multipliers */
+    int32_t* hist;    /* [sum n] sign histories */
+    int32_t* iter;    /* [n_atm] temperature updates taken (may be NULL) */
+} helios_re_state;
+
+/* Fills atm->P_pt (Sec. 2.2.1, Fig. 2): centres copied to odd points,
+ * interfaces at the geometric mean of neighbouring centres, the outermost
+ * half a log-step beyond the outermost centres. */
+int helios_grid(const helios_atm* atm, void* stream);
+
+/* Interface temperatures (Sec. 2.2.1): T_pt[odd] = T_c; inner interfaces
+ * linear in ln P between the neighbouring centres; outer interfaces copy the
+ * adjacent centre.  T_c [sum n] -> T_pt [sum npt].  Needs atm->P_pt. */
+int helios_profile(const helios_atm* atm, const double* T_c, double* T_pt, void* stream);
+
+/* Opacity at the points (eq:kappa_gauss, eq:mixing, Sec. 2.3):
+ * kappa[cell] = sum_j X_j m_j/mbar k_j(T_pt, P_pt, bin_index, g).
+ * vmr: [n_species][sum npt] volume mixing ratios.  kappa: cell array, double
+ * (HELIOS_FP64) or float (HELIOS_MIXED). */
+int helios_mix_opacity(const helios_atm* atm, const helios_ktab* kt, const double* T_pt,
+                       const double* vmr, void* kappa, helios_prec prec, void* stream);
+
+/* Sublayer coefficients (eq:trans, eq:cap, eq:isoscat, eq:nonisoscat,
+ * eq:purescat; the branch switches of Sec. 2.1.4 and 2.2.1), for inspection:
+ * for every (bin, g, sublayer s) five doubles {Trans, a, c, S_up, S_dn} with
+ *   F_up(s+1) = a F_up(s) + c F_dn(s+1) + S_up
+ *   F_dn(s)   = a F_dn(s+1) + c F_up(s) + S_dn
+ * out: [sum over atmospheres nb*ng*2n][5] in cell order with 2n sublayers per
+ * column.  The flux sweep computes the same values in registers. */
+int helios_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,
+                        const double* w0, const double* g0, double D, double* out,
+                        helios_prec prec, void* stream);
+
+/* Workspace bytes needed by helios_flux for this batch and precision. */
+size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec);
+
+/* One two-stream flux solve (Sec. 2.1.3, 2.2.2, 2.2.3, 2.3):
+ * Planck sources at the points, TOA/BOA boundary fluxes, sublayer
+ * coefficients, 1 + n_scat scattering passes (down sweep, BOA condition, up
+ * sweep) per (bin, g) column, Gauss sum over g and width-weighted sum over
+ * bins.
+ *   kappa     cell array (double or float by prec) from helios_mix_opacity
+ *   T_pt      [sum npt]
+ *   w0, g0    [bin x layer] single-scattering albedo and asymmetry
+ *   n_scat    additional scattering passes (paper: 4 in the RE loop, 80 post)
+ *   D         diffusivity factor (paper: 2)
+ *   F_up_g    cell array, in: warm start (zeros first), out: upward fluxes
+ *   F_dn_g    cell array, out: downward fluxes (may be NULL)
+ *   F_up_bin, F_dn_bin  [bin x point] double, Gauss-summed fluxes
+ *   F_bol     [sum npt][3] double: bolometric up, down, up - down
+ *   ws        workspace of at least helios_workspace_bytes(atm, prec) bytes
+ * Downward fluxes carry no state between calls: each pass recomputes them
+ * from the TOA condition and the previous upward fluxes. */
+int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g,
+                double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
+                helios_prec prec, void* stream);
+
+/* Temperature update (Sec. 2.2.3 eq:step, Sec. 2.2.4, eq:condition), always
+ * FP64.  For each atmosphere whose status is not CONVERGED: resid = max over
+ * layers of |dF_i| / norm_i with dF_i the net-flux difference across layer i
+ * (interfaces 2i and 2i+2 of F_bol); if resid < tol the status becomes
+ * CONVERGED and nothing moves; otherwise every layer takes
+ * dT_i = -sgn(dF_i) |dF_i|^(1-fpre_p) fpre_c m_i / (sigma T_i^3 ln(P_2i/P_2i+2)),
+ * T is floored, the step multipliers are adapted and T_pt is re-interpolated.
+ * Non-finite input sets the status to NUMERIC (nothing moves).
+ *   status [n_atm] in/out, resid [n_atm] out (may be NULL). */
+int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
+                 const helios_re_state* st, const helios_re_opts* opt, int32_t* status,
+                 double* resid, void* stream);
+
+/* Diagnostics for measurement: when `before` and `after` are non-NULL
+ * hipEvent_t handles (passed as void*), the calling thread's next
+ * helios_flux calls record `before` on their stream just before the flux
+ * sweep kernel is enqueued and `after` just after it, so the sweep's own
+ * duration can be read with hipEventElapsedTime.  NULL, NULL turns it off.
+ * The setting is thread-local; the events are owned by the caller. */
+int helios_set_sweep_events(void* before, void* after);
+
+/* Thread-local description of the last error ("" if none). */
+const char* helios_last_error(void);
+
+/* ABI version of this library. */
+int32_t helios_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELIOS_H */

@@ -1,0 +1,311 @@
+// api.hip -- the C ABI of libhelios: argument validation, workspace layout,
+// launch shapes, and dispatch to the kernels.  See include/helios.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "helios_internal.hpp"
+
+using namespace helios;
+
+namespace {
+
+thread_local char g_err[512] = "";
+thread_local hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(HELIOS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Host view of the batch sizes.
+struct Sizes {
+    int64_t total_n = 0, total_pt = 0, total_bin = 0, total_lb = 0, total_pb = 0, total_cell = 0;
+    int n_max = 0, npt_max = 0, nb_max = 0;
+};
+
+int check_atm(const helios_atm* atm, Sizes& z) {
+    if (!atm) return fail(HELIOS_EINVAL, "atm is NULL");
+    if (atm->n_atm < 1) return fail(HELIOS_EINVAL, "n_atm = %d must be >= 1", atm->n_atm);
+    if (atm->n_g < 1 || atm->n_g > HELIOS_MAX_NG)
+        return fail(HELIOS_EINVAL, "n_g = %d outside 1..%d", atm->n_g, HELIOS_MAX_NG);
+    if (!atm->n_layer_h || !atm->n_bin_h || !atm->n_layer || !atm->n_bin || !atm->lay_off || !atm->pt_off ||
+        !atm->bin_off || !atm->lb_off || !atm->pb_off || !atm->cell_off || !atm->bin_index ||
+        !atm->lambda_c || !atm->dlambda || !atm->P_c || !atm->P_pt || !atm->grav || !atm->T_star ||
+        !atm->T_irr || !atm->T_int)
+        return fail(HELIOS_EINVAL, "a helios_atm array pointer is NULL");
+    for (int a = 0; a < atm->n_atm; ++a) {
+        int n = atm->n_layer_h[a], nb = atm->n_bin_h[a];
+        if (n < 2 || n > HELIOS_MAX_LAYERS)
+            return fail(HELIOS_ESHAPE, "atmosphere %d: n_layer = %d outside 2..%d", a, n, HELIOS_MAX_LAYERS);
+        if (nb < 1) return fail(HELIOS_ESHAPE, "atmosphere %d: n_bin = %d must be >= 1", a, nb);
+        int npt = 2 * n + 1;
+        z.total_n += n;
+        z.total_pt += npt;
+        z.total_bin += nb;
+        z.total_lb += (int64_t)nb * n;
+        z.total_pb += (int64_t)nb * npt;
+        z.total_cell += (int64_t)nb * atm->n_g * npt;
+        z.n_max = std::max(z.n_max, n);
+        z.npt_max = std::max(z.npt_max, npt);
+        z.nb_max = std::max(z.nb_max, nb);
+    }
+    return HELIOS_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t B, F_top, F_int, gw, total;
+};
+
+WsLayout ws_layout(const Sizes& z, bool mixed) {
+    WsLayout w;
+    size_t r = mixed ? sizeof(float) : sizeof(double);
+    w.B = 0;
+    w.F_top = align256(w.B + (size_t)z.total_pb * r);
+    w.F_int = align256(w.F_top + (size_t)z.total_bin * sizeof(double));
+    w.gw = align256(w.F_int + (size_t)z.total_bin * sizeof(double));
+    w.total = align256(w.gw + HELIOS_MAX_NG * sizeof(double));
+    return w;
+}
+
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
+}
+
+// Sweep shape: K sublayers per lane (compiled instantiations) and L lanes per
+// column.  Default: the smallest register footprint that fits the deepest
+// atmosphere with L = 16, else L = 32.
+struct SweepShape {
+    int K, L;
+};
+
+bool k_allowed(int K, bool mixed) {
+    for (int i = 0; i < kNumSweepK; ++i)
+        if (kSweepK[i] == K) return mixed || K <= 13;
+    return false;
+}
+
+int pick_shape(int nsub_max, bool mixed, SweepShape& sh) {
+    int fk = env_int("HELIOS_SWEEP_K", 0), fl = env_int("HELIOS_SWEEP_L", 0);
+    if (fk || fl) {
+        if (!k_allowed(fk, mixed) || (fl != 16 && fl != 32))
+            return fail(HELIOS_EINVAL, "HELIOS_SWEEP_K/L = %d/%d not available", fk, fl);
+        if (fk * fl < nsub_max) return fail(HELIOS_ESHAPE, "K*L = %d < %d sublayers", fk * fl, nsub_max);
+        sh = {fk, fl};
+        return HELIOS_OK;
+    }
+    for (int L : {16, 32}) {
+        for (int i = 0; i < kNumSweepK; ++i) {
+            int K = kSweepK[i];
+            if (!k_allowed(K, mixed)) continue;
+            if (K * L >= nsub_max) {
+                sh = {K, L};
+                return HELIOS_OK;
+            }
+        }
+    }
+    return fail(HELIOS_ESHAPE, "no sweep shape holds %d sublayers", nsub_max);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* helios_last_error(void) { return g_err; }
+
+int helios_set_sweep_events(void* before, void* after) {
+    if ((before == nullptr) != (after == nullptr))
+        return fail(HELIOS_EINVAL, "helios_set_sweep_events: give both events or neither");
+    g_ev_before = (hipEvent_t)before;
+    g_ev_after = (hipEvent_t)after;
+    return HELIOS_OK;
+}
+
+int32_t helios_version(void) { return 1; }
+
+int helios_grid(const helios_atm* atm, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    hipError_t e = launch_grid(atm, z.total_pt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_grid");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_profile(const helios_atm* atm, const double* T_c, double* T_pt, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!T_c || !T_pt) return fail(HELIOS_EINVAL, "helios_profile: T_c or T_pt is NULL");
+    hipError_t e = launch_profile(atm, z.total_pt, T_c, T_pt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_profile");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_mix_opacity(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
+                       void* kappa, helios_prec prec, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!kt || !T_pt || !vmr || !kappa) return fail(HELIOS_EINVAL, "helios_mix_opacity: NULL argument");
+    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    if (kt->mode != HELIOS_KTAB_TABLE && kt->mode != HELIOS_KTAB_POWERLAW)
+        return fail(HELIOS_EINVAL, "unknown k-table mode %d", kt->mode);
+    if (kt->n_species < 1 || kt->n_species > HELIOS_MAX_SPECIES)
+        return fail(HELIOS_EINVAL, "n_species = %d outside 1..%d", kt->n_species, HELIOS_MAX_SPECIES);
+    if (kt->n_g != atm->n_g) return fail(HELIOS_ESHAPE, "table n_g %d != batch n_g %d", kt->n_g, atm->n_g);
+    if (kt->n_bin_table < 1) return fail(HELIOS_ESHAPE, "n_bin_table = %d", kt->n_bin_table);
+    if (!kt->species_mass || !(kt->mmw > 0.0)) return fail(HELIOS_EINVAL, "species masses / mmw missing");
+    if (kt->mode == HELIOS_KTAB_TABLE) {
+        if (!kt->k) return fail(HELIOS_EINVAL, "TABLE mode without k");
+        if (kt->n_T < 2 || kt->n_P < 2) return fail(HELIOS_ESHAPE, "table needs >= 2 nodes per axis");
+        if (!(kt->T_step > 0.0) || !(kt->logP_step > 0.0)) return fail(HELIOS_EINVAL, "non-positive table step");
+    } else {
+        if (!kt->k0) return fail(HELIOS_EINVAL, "POWERLAW mode without k0");
+        if (!(kt->P_ref > 0.0) || !(kt->T_ref > 0.0)) return fail(HELIOS_EINVAL, "non-positive P_ref/T_ref");
+    }
+    hipError_t e = launch_mix(atm, kt, T_pt, vmr, kappa, prec == HELIOS_MIXED, z.total_pt, atm->n_layer_h,
+                              atm->n_bin_h, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_mix_opacity");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_transmission(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                        const double* g0, double D, double* out, helios_prec prec, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!kappa || !T_pt || !w0 || !g0 || !out) return fail(HELIOS_EINVAL, "helios_transmission: NULL argument");
+    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
+    int64_t total_sub = z.total_cell - (int64_t)atm->n_g * z.total_bin;
+    hipError_t e = launch_transmission(atm, kappa, T_pt, w0, g0, D, out, total_sub, prec == HELIOS_MIXED,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_transmission");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec) {
+    Sizes z;
+    if (check_atm(atm, z)) return 0;
+    return ws_layout(z, prec == HELIOS_MIXED).total;
+}
+
+int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
+                double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!kappa || !T_pt || !w0 || !g0 || !F_up_g || !F_up_bin || !F_dn_bin || !F_bol || !ws)
+        return fail(HELIOS_EINVAL, "helios_flux: NULL argument");
+    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    if (n_scat < 0 || n_scat > 100000) return fail(HELIOS_EINVAL, "n_scat = %d", n_scat);
+    if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
+    const bool mixed = prec == HELIOS_MIXED;
+    WsLayout w = ws_layout(z, mixed);
+    if (ws_bytes < w.total)
+        return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, w.total);
+    SweepShape sh;
+    rc = pick_shape(2 * z.n_max, mixed, sh);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    void* B = wsb + w.B;
+    double* F_top = (double*)(wsb + w.F_top);
+    double* F_int = (double*)(wsb + w.F_int);
+    double* gw = (double*)(wsb + w.gw);
+
+    hipError_t e = launch_planck(atm, z.total_pb, T_pt, B, F_top, F_int, gw, mixed, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_flux (sources)");
+
+    SweepArgs A;
+    A.n_layer = atm->n_layer;
+    A.pt_off = atm->pt_off;
+    A.bin_off = atm->bin_off;
+    A.lb_off = atm->lb_off;
+    A.pb_off = atm->pb_off;
+    A.cell_off = atm->cell_off;
+    A.P_pt = atm->P_pt;
+    A.grav = atm->grav;
+    A.kappa = kappa;
+    A.B = B;
+    A.F_top = F_top;
+    A.F_int = F_int;
+    A.w0 = w0;
+    A.g0 = g0;
+    A.F_up_g = F_up_g;
+    A.F_dn_g = F_dn_g;
+    A.F_up_bin = F_up_bin;
+    A.F_dn_bin = F_dn_bin;
+    A.gb_begin = 0;
+    A.gb_end = z.total_bin;
+    A.n_atm = atm->n_atm;
+    A.n_g = atm->n_g;
+    A.L = sh.L;
+    A.log2L = 0;
+    while ((1 << A.log2L) < sh.L) ++A.log2L;
+    A.n_scat = n_scat;
+    A.npt_max = z.npt_max;
+    A.D = D;
+    A.gw = gw;
+    int block = ((atm->n_g * sh.L + 63) / 64) * 64;
+    int64_t grid64 = z.total_bin;
+    int cap = env_int("HELIOS_SWEEP_GRID", 0);
+    if (cap > 0 && grid64 > cap) grid64 = cap;
+    if (g_ev_before && g_ev_after) {
+        e = hipEventRecord(g_ev_before, s);
+        if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
+    }
+    e = launch_sweep(A, sh.K, mixed, block, (int)grid64, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_flux (sweep)");
+    if (g_ev_before && g_ev_after) {
+        e = hipEventRecord(g_ev_after, s);
+        if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
+    }
+    e = launch_bolometric(atm, F_up_bin, F_dn_bin, F_bol, z.npt_max, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_flux (bolometric)");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
+                 const helios_re_state* st, const helios_re_opts* opt, int32_t* status, double* resid,
+                 void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!F_bol || !T_c || !T_pt || !st || !st->m || !st->hist || !opt || !status)
+        return fail(HELIOS_EINVAL, "helios_radeq: NULL argument");
+    if (opt->window < 2 || opt->window > 16) return fail(HELIOS_EINVAL, "window = %d outside 2..16", opt->window);
+    if (opt->norm != HELIOS_NORM_SIGMA_T4 && opt->norm != HELIOS_NORM_SIGMA_TINT4)
+        return fail(HELIOS_EINVAL, "unknown norm %d", opt->norm);
+    if (!(opt->tol >= 0.0) || !(opt->shrink > 0.0) || !(opt->grow > 0.0) || !(opt->fpre_c > 0.0))
+        return fail(HELIOS_EINVAL, "helios_radeq: bad options");
+    hipError_t e = launch_radeq(atm, F_bol, T_c, T_pt, st, *opt, status, resid, z.n_max, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_radeq");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// helios_internal.hpp -- types, constants and device helpers shared by the
+// HIP translation units of libhelios (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/helios.h"
+
+namespace helios {
+
+// CODATA 2018 exact constants, cgs.
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kH = 6.62607015e-27;   // erg s
+constexpr double kC = 2.99792458e10;    // cm s^-1
+constexpr double kKB = 1.380649e-16;    // erg K^-1
+// sigma = 2 pi^5 k^4 / (15 h^3 c^2)
+__host__ __device__ inline double sigma_sb() {
+    const double k2 = kKB * kKB;
+    const double pi2 = kPi * kPi;
+    return 2.0 * pi2 * pi2 * kPi * k2 * k2 / (15.0 * kH * kH * kH * kC * kC);
+}
+
+// Index of the atmosphere owning global element idx: the largest a with
+// off[a] <= idx (off has n_atm+1 non-decreasing entries).
+__device__ inline int find_atm(const int64_t* __restrict__ off, int n_atm, int64_t idx) {
+    int lo = 0, hi = n_atm;  // invariant: off[lo] <= idx < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= idx) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Planck function per unit wavelength and steradian at the bin centre.
+__device__ inline double planck_d(double lambda, double T) {
+    if (!(T > 0.0)) return 0.0;
+    const double c1 = 2.0 * kH * kC * kC;
+    const double x = kH * kC / (lambda * kKB * T);
+    const double l2 = lambda * lambda;
+    return c1 / (l2 * l2 * lambda) / expm1(x);
+}
+
+// Compensated pair (value + error) for float sums.
+struct fpair {
+    float s, c;
+};
+__device__ inline fpair two_sum_add(fpair a, fpair b) {
+    float s = a.s + b.s;
+    float bb = s - a.s;
+    float err = (a.s - (s - bb)) + (b.s - bb);
+    return {s, a.c + b.c + err};
+}
+
+// ----------------------------------------------------------- launch args
+struct SweepArgs {
+    const int32_t* n_layer;
+    const int64_t* pt_off;
+    const int64_t* bin_off;
+    const int64_t* lb_off;
+    const int64_t* pb_off;
+    const int64_t* cell_off;
+    const double* P_pt;
+    const double* grav;
+    const void* kappa;    // cell array, R
+    const void* B;        // [bin x point], R (workspace)
+    const double* F_top;  // [sum nb] (workspace)
+    const double* F_int;  // [sum nb] (workspace)
+    const double* w0;
+    const double* g0;
+    void* F_up_g;         // cell array, R, in/out
+    void* F_dn_g;         // cell array, R, out, may be null
+    double* F_up_bin;
+    double* F_dn_bin;
+    int64_t gb_begin, gb_end;  // global bin range covered by the launch
+    int32_t n_atm, n_g;
+    int32_t L, log2L;
+    int32_t n_scat, npt_max;
+    double D;
+    const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
+};
+
+// Host-side launchers (defined in the .hip files).
+hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s);
+hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double* T_c, double* T_pt,
+                          hipStream_t s);
+hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, void* B,
+                         double* F_top, double* F_int, double* gw, bool mixed, hipStream_t s);
+hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
+                      void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
+                      const int32_t* n_bin_h, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs& a, int K, bool mixed, int block, int grid, hipStream_t s);
+hipError_t launch_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,
+                               const double* w0, const double* g0, double D, double* out,
+                               int64_t total_sub, bool mixed, hipStream_t s);
+hipError_t launch_bolometric(const helios_atm* atm, const double* F_up_bin, const double* F_dn_bin,
+                             double* F_bol, int npt_max, hipStream_t s);
+hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
+                        const helios_re_state* st, const helios_re_opts& o, int32_t* status,
+                        double* resid, int n_max, hipStream_t s);
+
+// Sweep instantiations available (sublayers per lane).
+constexpr int kSweepK[] = {4, 7, 13, 25};
+constexpr int kNumSweepK = 4;
+
+}  // namespace helios

@@ -1,0 +1,333 @@
+// k_small.hip -- the light kernels of the hot path: point grid and interface
+// temperatures (Sec. 2.2.1), Planck sources and boundary fluxes (Sec. 2.2.2),
+// the width-weighted bin sum to bolometric fluxes (Sec. 2.2.3) and the FP64
+// temperature update (Sec. 2.2.3-2.2.4).
+#include "helios_internal.hpp"
+
+namespace helios {
+
+// ------------------------------------------------------------------ grid
+// One thread per point.  Centres are copied to odd points; interface i sits
+// at the geometric mean of centres i-1 and i; the outer interfaces are half a
+// log-step beyond the outermost centres.
+__global__ void grid_kernel(helios_atm atm, int64_t total_pt) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total_pt) return;
+    int a = find_atm(atm.pt_off, atm.n_atm, idx);
+    int p = (int)(idx - atm.pt_off[a]);
+    int n = atm.n_layer[a];
+    const double* Pc = atm.P_c + atm.lay_off[a];
+    int i = p >> 1;
+    double P;
+    if (p & 1) P = Pc[i];
+    else if (i == 0) P = Pc[0] * sqrt(Pc[0] / Pc[1]);
+    else if (i == n) P = Pc[n - 1] * sqrt(Pc[n - 1] / Pc[n - 2]);
+    else P = sqrt(Pc[i - 1] * Pc[i]);
+    atm.P_pt[idx] = P;
+}
+
+hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s) {
+    int block = 256;
+    int64_t grid = (total_pt + block - 1) / block;
+    hipLaunchKernelGGL(grid_kernel, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pt);
+    return hipGetLastError();
+}
+
+// Interface temperature of point p of one atmosphere from its centres.
+__device__ inline double interface_T(const double* __restrict__ P, const double* __restrict__ Tc, int n,
+                                     int p) {
+    int i = p >> 1;
+    if (p & 1) return Tc[i];
+    if (i == 0) return Tc[0];
+    if (i == n) return Tc[n - 1];
+    double x0 = log(P[p - 1]), x1 = log(P[p + 1]), x = log(P[p]);
+    double f = (x - x0) / (x1 - x0);
+    return Tc[i - 1] + f * (Tc[i] - Tc[i - 1]);
+}
+
+__global__ void profile_kernel(helios_atm atm, int64_t total_pt, const double* __restrict__ T_c,
+                               double* __restrict__ T_pt) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total_pt) return;
+    int a = find_atm(atm.pt_off, atm.n_atm, idx);
+    int p = (int)(idx - atm.pt_off[a]);
+    T_pt[idx] = interface_T(atm.P_pt + atm.pt_off[a], T_c + atm.lay_off[a], atm.n_layer[a], p);
+}
+
+hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double* T_c, double* T_pt,
+                          hipStream_t s) {
+    int block = 256;
+    int64_t grid = (total_pt + block - 1) / block;
+    hipLaunchKernelGGL(profile_kernel, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pt, T_c, T_pt);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- sources
+// B[bin][pt] at the bin centres, one thread per (bin, point) element.
+template <typename R>
+__global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __restrict__ T_pt,
+                              R* __restrict__ B) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total_pb) return;
+    int a = find_atm(atm.pb_off, atm.n_atm, idx);
+    int npt = 2 * atm.n_layer[a] + 1;
+    int64_t rel = idx - atm.pb_off[a];
+    int l = (int)(rel / npt);
+    int p = (int)(rel - (int64_t)l * npt);
+    double lam = atm.lambda_c[atm.bin_off[a] + l];
+    B[idx] = (R)planck_d(lam, T_pt[atm.pt_off[a] + p]);
+}
+
+// Boundary fluxes, one workgroup per atmosphere (Sec. 2.2.2): TOA
+// (T_irr/T_star)^4 pi B(T_star); BOA pi B(T_int) scaled so that its
+// width-weighted sum over the model's bins is sigma T_int^4.  The scale's sum
+// is a fixed-order tree in LDS.
+// Gauss-Legendre weight w_g/2 of node g (ascending nodes (1+y_g)/2 on [0,1],
+// Sec. 2.3), from Newton's method on the Legendre three-term recurrence.
+__device__ double gauss_weight(int n, int g) {
+    const int i = n - 1 - g;  // roots are generated in descending order
+    double y = cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double a = 1.0, b = y;
+        for (int k = 2; k <= n; ++k) {
+            double c = ((2 * k - 1) * y * b - (k - 1) * a) / k;
+            a = b;
+            b = c;
+        }
+        if (n == 1) a = 1.0;
+        dp = n * (y * b - a) / (y * y - 1.0);
+        double step = b / dp;
+        y -= step;
+        if (fabs(step) < 1e-16) {
+            a = 1.0;
+            b = y;
+            for (int k = 2; k <= n; ++k) {
+                double c = ((2 * k - 1) * y * b - (k - 1) * a) / k;
+                a = b;
+                b = c;
+            }
+            if (n == 1) a = 1.0;
+            dp = n * (y * b - a) / (y * y - 1.0);
+            break;
+        }
+    }
+    return 1.0 / ((1.0 - y * y) * dp * dp);
+}
+
+__global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* __restrict__ F_top,
+                                                       double* __restrict__ F_int, double* __restrict__ gw) {
+    __shared__ double red[256];
+    int a = blockIdx.x;
+    if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gauss_weight(atm.n_g, threadIdx.x);
+    int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
+    int64_t b0 = atm.bin_off[a];
+    double Ts = atm.T_star[a], Ti = atm.T_int[a];
+    double r = (Ts > 0.0) ? atm.T_irr[a] / Ts : 0.0;
+    double dil = r * r * r * r;
+    double part = 0.0;
+    for (int l = threadIdx.x; l < nb; l += blockDim.x) {
+        double lam = atm.lambda_c[b0 + l];
+        F_top[b0 + l] = dil * kPi * planck_d(lam, Ts);
+        double fi = kPi * planck_d(lam, Ti);
+        F_int[b0 + l] = fi;
+        part += fi * atm.dlambda[b0 + l];
+    }
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    double sum = red[0];
+    double t2 = Ti * Ti;
+    double scale = (sum > 0.0) ? sigma_sb() * t2 * t2 / sum : 0.0;
+    for (int l = threadIdx.x; l < nb; l += blockDim.x) F_int[b0 + l] *= scale;
+}
+
+hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, void* B,
+                         double* F_top, double* F_int, double* gw, bool mixed, hipStream_t s) {
+    int block = 256;
+    int64_t grid = (total_pb + block - 1) / block;
+    if (mixed)
+        hipLaunchKernelGGL(planck_kernel<float>, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb,
+                           T_pt, (float*)B);
+    else
+        hipLaunchKernelGGL(planck_kernel<double>, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb,
+                           T_pt, (double*)B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_top, F_int, gw);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ bolometric sums
+// F_bol[pt] = (sum_l dlambda_l F_up_bin[l][pt], same for down, difference).
+// Workgroup = (atmosphere, tile of 64 points); its 1024 threads are 64 points
+// x 16 bin chunks; each thread runs a Neumaier-compensated sum over its chunk
+// in bin order and the 16 chunk sums are combined in chunk order.
+struct nacc {
+    double s, c;
+};
+__device__ inline void nadd(nacc& a, double v) {
+    double t = a.s + v;
+    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
+    else a.c += (v - t) + a.s;
+    a.s = t;
+}
+
+__global__ void __launch_bounds__(1024) bolometric_kernel(helios_atm atm, const double* __restrict__ up,
+                                                          const double* __restrict__ dn,
+                                                          double* __restrict__ F_bol, int tiles_per_atm) {
+    __shared__ double red[2][16][64][2];
+    int a = blockIdx.x / tiles_per_atm;
+    int tile = blockIdx.x - a * tiles_per_atm;
+    int pl = threadIdx.x & 63, chunk = threadIdx.x >> 6;
+    int npt = 2 * atm.n_layer[a] + 1;
+    int p = tile * 64 + pl;
+    int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
+    if (tile * 64 >= npt) return;  // whole workgroup idle (uniform)
+    int per = (nb + 15) / 16;
+    int l0 = chunk * per, l1 = min(nb, l0 + per);
+    nacc au = {0.0, 0.0}, ad = {0.0, 0.0};
+    if (p < npt) {
+        const double* dl = atm.dlambda + atm.bin_off[a];
+        const double* U = up + atm.pb_off[a];
+        const double* Dn = dn + atm.pb_off[a];
+        for (int l = l0; l < l1; ++l) {
+            double w = dl[l];
+            nadd(au, w * U[(int64_t)l * npt + p]);
+            nadd(ad, w * Dn[(int64_t)l * npt + p]);
+        }
+    }
+    red[0][chunk][pl][0] = au.s;
+    red[0][chunk][pl][1] = au.c;
+    red[1][chunk][pl][0] = ad.s;
+    red[1][chunk][pl][1] = ad.c;
+    __syncthreads();
+    if (chunk == 0 && p < npt) {
+        nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
+        for (int k = 0; k < 16; ++k) {
+            nadd(tu, red[0][k][pl][0]);
+            nadd(td, red[1][k][pl][0]);
+        }
+        double cu = 0.0, cd = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            cu += red[0][k][pl][1];
+            cd += red[1][k][pl][1];
+        }
+        double fu = tu.s + (tu.c + cu), fd = td.s + (td.c + cd);
+        double* o = F_bol + 3 * (atm.pt_off[a] + p);
+        o[0] = fu;
+        o[1] = fd;
+        o[2] = fu - fd;
+    }
+}
+
+hipError_t launch_bolometric(const helios_atm* atm, const double* F_up_bin, const double* F_dn_bin,
+                             double* F_bol, int npt_max, hipStream_t s) {
+    int tiles = (npt_max + 63) / 64;
+    hipLaunchKernelGGL(bolometric_kernel, dim3(atm->n_atm * tiles), dim3(1024), 0, s, *atm, F_up_bin,
+                       F_dn_bin, F_bol, tiles);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- RE update
+// One workgroup per atmosphere; threads over layers.  Always FP64.
+__global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double* __restrict__ F_bol,
+                                                    double* __restrict__ T_c, double* __restrict__ T_pt,
+                                                    double* __restrict__ m, int32_t* __restrict__ hist,
+                                                    int32_t* __restrict__ iter, helios_re_opts o,
+                                                    int32_t* __restrict__ status, double* __restrict__ resid) {
+    __shared__ double red[256];
+    __shared__ int bad[256];
+    const int a = blockIdx.x;
+    const int n = atm.n_layer[a];
+    const int npt = 2 * n + 1;
+    if (status[a] == HELIOS_ATM_CONVERGED) return;  // frozen (uniform per workgroup)
+    const double* F = F_bol + 3 * atm.pt_off[a];
+    const double* P = atm.P_pt + atm.pt_off[a];
+    double* Tc = T_c + atm.lay_off[a];
+    double* ma = m + atm.lay_off[a];
+    int32_t* ha = hist + atm.lay_off[a];
+    const double sig = sigma_sb();
+    const double ti2 = atm.T_int[a] * atm.T_int[a];
+    // convergence measure (eq:condition), on the fluxes handed in
+    double worst = 0.0;
+    int nonfinite = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double dF = F[3 * (2 * i + 2) + 2] - F[3 * (2 * i) + 2];
+        double T = Tc[i];
+        if (!isfinite(dF) || !isfinite(T)) nonfinite = 1;
+        double t2 = T * T;
+        double norm = (o.norm == HELIOS_NORM_SIGMA_TINT4) ? sig * ti2 * ti2 : sig * t2 * t2;
+        double r = fabs(dF) / norm;
+        worst = fmax(worst, r);
+    }
+    red[threadIdx.x] = worst;
+    bad[threadIdx.x] = nonfinite;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+            bad[threadIdx.x] |= bad[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    worst = red[0];
+    nonfinite = bad[0];
+    if (threadIdx.x == 0 && resid) resid[a] = nonfinite ? __longlong_as_double(0x7ff8000000000000LL) : worst;
+    if (nonfinite) {
+        if (threadIdx.x == 0) status[a] = HELIOS_ATM_NUMERIC;
+        return;
+    }
+    if (worst < o.tol) {
+        if (threadIdx.x == 0) status[a] = HELIOS_ATM_CONVERGED;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        status[a] = HELIOS_ATM_RUNNING;
+        if (iter) iter[a] += 1;
+    }
+    const uint32_t mask = (1u << o.window) - 1u;
+    // the alternating patterns ...0101 and ...1010 within the window
+    uint32_t alt = 0;
+    for (int k = 0; k < o.window; k += 2) alt |= 1u << k;
+    const uint32_t alt1 = alt & mask, alt2 = (~alt) & mask;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double dF = F[3 * (2 * i + 2) + 2] - F[3 * (2 * i) + 2];
+        double T = Tc[i];
+        double dT = 0.0;
+        if (dF != 0.0) {
+            double lnR = log(P[2 * i] / P[2 * i + 2]);
+            double mag = pow(fabs(dF), 1.0 - o.fpre_p) * o.fpre_c * ma[i] / (sig * T * T * T * lnR);
+            dT = (dF > 0.0) ? -mag : mag;
+        }
+        uint32_t h = (uint32_t)ha[i];
+        uint32_t bits = h & 0xFFFFu, cnt = h >> 16;
+        uint32_t sg = (dT > 0.0) ? 1u : (dT < 0.0) ? 0u : (cnt > 0 ? (bits & 1u) : 1u);
+        bits = ((bits << 1) | sg) & mask;
+        if (cnt < (uint32_t)o.window) cnt += 1;
+        if (cnt >= (uint32_t)o.window) {
+            if (bits == 0u || bits == mask) ma[i] *= o.grow;
+            else if (o.osc_any || bits == alt1 || bits == alt2) ma[i] *= o.shrink;
+        }
+        ha[i] = (int32_t)((cnt << 16) | bits);
+        double Tn = T + dT;
+        Tc[i] = (Tn > o.T_floor) ? Tn : o.T_floor;
+    }
+    __syncthreads();
+    // re-interpolate the point temperatures of this atmosphere
+    double* Tp = T_pt + atm.pt_off[a];
+    for (int p = threadIdx.x; p < npt; p += blockDim.x) Tp[p] = interface_T(P, Tc, n, p);
+}
+
+hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
+                        const helios_re_state* st, const helios_re_opts& o, int32_t* status,
+                        double* resid, int /*n_max*/, hipStream_t s) {
+    hipLaunchKernelGGL(radeq_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_bol, T_c, T_pt, st->m,
+                       st->hist, st->iter, o, status, resid);
+    return hipGetLastError();
+}
+
+}  // namespace helios

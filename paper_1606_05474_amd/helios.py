@@ -1,0 +1,361 @@
+"""Python binding of libhelios (include/helios.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  torch provides device memory and streams.  The library must be
+built (``python -m paper_1606_05474_amd.build``); importing this module on a
+machine without it raises.
+
+Names follow the C ABI: ``grid``, ``profile``, ``mix_opacity``,
+``transmission``, ``workspace_bytes``, ``flux``, ``radeq`` wrap
+``helios_grid`` ... ``helios_radeq``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelios.so")
+
+HELIOS_OK = 0
+HELIOS_NOT_CONVERGED = 1
+FP64, MIXED = 0, 1
+KTAB_TABLE, KTAB_POWERLAW = 0, 1
+NORM_SIGMA_T4, NORM_SIGMA_TINT4 = 0, 1
+ATM_RUNNING, ATM_CONVERGED, ATM_NUMERIC = 0, 1, -5
+MAX_SPECIES = 8
+
+_P = ctypes.c_void_p
+
+
+class HeliosAtm(ctypes.Structure):
+    _fields_ = [("n_atm", ctypes.c_int32), ("n_g", ctypes.c_int32),
+                ("n_layer_h", _P), ("n_bin_h", _P), ("n_layer", _P), ("n_bin", _P),
+                ("lay_off", _P), ("pt_off", _P), ("bin_off", _P), ("lb_off", _P), ("pb_off", _P),
+                ("cell_off", _P), ("bin_index", _P), ("lambda_c", _P), ("dlambda", _P), ("P_c", _P),
+                ("P_pt", _P), ("grav", _P), ("T_star", _P), ("T_irr", _P), ("T_int", _P)]
+
+
+class HeliosKtab(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n_species", ctypes.c_int32), ("n_T", ctypes.c_int32),
+                ("n_P", ctypes.c_int32), ("n_bin_table", ctypes.c_int32), ("n_g", ctypes.c_int32),
+                ("T_min", ctypes.c_double), ("T_step", ctypes.c_double), ("logP_min", ctypes.c_double),
+                ("logP_step", ctypes.c_double), ("k", _P), ("k0", _P), ("p_exp", ctypes.c_double),
+                ("t_exp", ctypes.c_double), ("P_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+                ("species_mass", _P), ("mmw", ctypes.c_double)]
+
+
+class HeliosReOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("norm", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("osc_any", ctypes.c_int32), ("pad_", ctypes.c_int32), ("T_floor", ctypes.c_double),
+                ("shrink", ctypes.c_double), ("grow", ctypes.c_double), ("fpre_c", ctypes.c_double),
+                ("fpre_p", ctypes.c_double)]
+
+
+class HeliosReState(ctypes.Structure):
+    _fields_ = [("m", _P), ("hist", _P), ("iter", _P)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libhelios.so not found at {LIB_PATH}; build it with "
+                               "`python -m paper_1606_05474_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        A = ctypes.POINTER(HeliosAtm)
+        i32, dbl, sz = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        L.helios_grid.argtypes = [A, _P]
+        L.helios_profile.argtypes = [A, _P, _P, _P]
+        L.helios_mix_opacity.argtypes = [A, ctypes.POINTER(HeliosKtab), _P, _P, _P, ctypes.c_int, _P]
+        L.helios_transmission.argtypes = [A, _P, _P, _P, _P, dbl, _P, ctypes.c_int, _P]
+        L.helios_workspace_bytes.argtypes = [A, ctypes.c_int]
+        L.helios_workspace_bytes.restype = sz
+        L.helios_flux.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
+        L.helios_radeq.argtypes = [A, _P, _P, _P, ctypes.POINTER(HeliosReState), ctypes.POINTER(HeliosReOpts),
+                                   _P, _P, _P]
+        L.helios_set_sweep_events.argtypes = [_P, _P]
+        L.helios_set_sweep_events.restype = ctypes.c_int
+        L.helios_last_error.restype = ctypes.c_char_p
+        L.helios_version.restype = i32
+        for f in ("helios_grid", "helios_profile", "helios_mix_opacity", "helios_transmission",
+                  "helios_flux", "helios_radeq"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class HeliosError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"helios error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise HeliosError(rc, lib().helios_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------ batch layout
+class Batch:
+    """A batch of atmospheres resident on the device, with its descriptor.
+
+    ``atms`` is a list of dicts with keys n, ng, P_c, grav, T_star, T_irr,
+    T_int, lambda_c, dlambda, bin_index, w0 [nb][n], g0 [nb][n], vmr
+    [nsp][2n+1] (the workload generator's format).  Arrays are concatenated
+    in the order of the list.
+    """
+
+    def __init__(self, atms: list, device="cuda"):
+        if not atms:
+            raise ValueError("empty batch")
+        dev = torch.device(device)
+        self.atms = atms
+        self.n_atm = len(atms)
+        self.ng = int(atms[0]["ng"])
+        if any(int(a["ng"]) != self.ng for a in atms):
+            raise ValueError("all atmospheres of a batch share n_g")
+        n = np.array([int(a["n"]) for a in atms], np.int64)
+        nb = np.array([len(a["lambda_c"]) for a in atms], np.int64)
+        npt = 2 * n + 1
+        self.n, self.nb, self.npt = n, nb, npt
+
+        def off(x):
+            return np.concatenate([[0], np.cumsum(x)]).astype(np.int64)
+
+        self.lay_off, self.pt_off, self.bin_off = off(n), off(npt), off(nb)
+        self.lb_off, self.pb_off, self.cell_off = off(nb * n), off(nb * npt), off(nb * self.ng * npt)
+        self.total_n, self.total_pt = int(self.lay_off[-1]), int(self.pt_off[-1])
+        self.total_bin, self.total_cell = int(self.bin_off[-1]), int(self.cell_off[-1])
+        self.total_lb, self.total_pb = int(self.lb_off[-1]), int(self.pb_off[-1])
+        self.nsp = int(np.asarray(atms[0]["vmr"]).shape[0])
+
+        f64 = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)  # noqa: E731
+        i32 = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.int32), device=dev)    # noqa: E731
+        i64 = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.int64), device=dev)    # noqa: E731
+        cat = lambda key: np.concatenate([np.ravel(np.asarray(a[key], np.float64)) for a in atms])  # noqa: E731
+        self.h_n_layer = np.ascontiguousarray(n, np.int32)
+        self.h_n_bin = np.ascontiguousarray(nb, np.int32)
+        self.d = {
+            "n_layer": i32(n), "n_bin": i32(nb), "lay_off": i64(self.lay_off), "pt_off": i64(self.pt_off),
+            "bin_off": i64(self.bin_off), "lb_off": i64(self.lb_off), "pb_off": i64(self.pb_off),
+            "cell_off": i64(self.cell_off),
+            "bin_index": i32(np.concatenate([np.asarray(a["bin_index"], np.int32) for a in atms])),
+            "lambda_c": f64(cat("lambda_c")), "dlambda": f64(cat("dlambda")), "P_c": f64(cat("P_c")),
+            "P_pt": torch.zeros(self.total_pt, dtype=torch.float64, device=dev),
+            "grav": f64([a["grav"] for a in atms]), "T_star": f64([a["T_star"] for a in atms]),
+            "T_irr": f64([a["T_irr"] for a in atms]), "T_int": f64([a["T_int"] for a in atms]),
+        }
+        self.w0 = f64(cat("w0"))
+        self.g0 = f64(cat("g0"))
+        vmr = np.concatenate([np.asarray(a["vmr"], np.float64) for a in atms], axis=1)
+        self.vmr = f64(vmr)  # [nsp][total_pt]
+        self.desc = HeliosAtm(
+            self.n_atm, self.ng, self.h_n_layer.ctypes.data, self.h_n_bin.ctypes.data,
+            *[_ptr(self.d[k]) for k in ("n_layer", "n_bin", "lay_off", "pt_off", "bin_off", "lb_off",
+                                         "pb_off", "cell_off", "bin_index", "lambda_c", "dlambda", "P_c",
+                                         "P_pt", "grav", "T_star", "T_irr", "T_int")])
+        self.device = dev
+
+    @property
+    def P_pt(self):
+        return self.d["P_pt"]
+
+    # ---- helpers to cut concatenated arrays back into atmospheres
+    def split_pt(self, x):
+        return [x[self.pt_off[a]:self.pt_off[a + 1]] for a in range(self.n_atm)]
+
+    def split_layer(self, x):
+        return [x[self.lay_off[a]:self.lay_off[a + 1]] for a in range(self.n_atm)]
+
+    def split_cell(self, x):
+        return [x[self.cell_off[a]:self.cell_off[a + 1]].reshape(int(self.nb[a]), self.ng, int(self.npt[a]))
+                for a in range(self.n_atm)]
+
+    def split_pb(self, x):
+        return [x[self.pb_off[a]:self.pb_off[a + 1]].reshape(int(self.nb[a]), int(self.npt[a]))
+                for a in range(self.n_atm)]
+
+    def cat_layer(self, per_atm):
+        return torch.as_tensor(np.concatenate([np.asarray(v, np.float64) for v in per_atm]),
+                               device=self.device)
+
+
+class KTable:
+    """An opacity source resident on the device (helios_ktab)."""
+
+    def __init__(self, kt: dict, device="cuda"):
+        dev = torch.device(device)
+        self.mass = np.ascontiguousarray(kt["mass"], np.float64)
+        self.nsp = self.mass.size
+        if kt["mode"] == "table":
+            k = np.ascontiguousarray(kt["k"], np.float32)
+            self.k = torch.as_tensor(k, device=dev)
+            _, nT, nP, nbt, ng = k.shape
+            self.desc = HeliosKtab(KTAB_TABLE, self.nsp, nT, nP, nbt, ng, kt["T_min"], kt["T_step"],
+                                   kt["logP_min"], kt["logP_step"], self.k.data_ptr(), None, 0.0, 0.0,
+                                   1.0, 1.0, self.mass.ctypes.data, kt["mmw"])
+        else:
+            k0 = np.ascontiguousarray(kt["k0"], np.float64)
+            self.k0 = torch.as_tensor(k0, device=dev)
+            _, nbt, ng = k0.shape
+            self.desc = HeliosKtab(KTAB_POWERLAW, self.nsp, 0, 0, nbt, ng, 0.0, 0.0, 0.0, 0.0, None,
+                                   self.k0.data_ptr(), kt["p_exp"], kt["t_exp"], kt["P_ref"], kt["T_ref"],
+                                   self.mass.ctypes.data, kt["mmw"])
+
+
+def rdtype(prec: int):
+    return torch.float32 if prec == MIXED else torch.float64
+
+
+# --------------------------------------------------------------- the calls
+def grid(b: Batch, stream=None):
+    _check(lib().helios_grid(ctypes.byref(b.desc), _stream(stream)))
+    return b.P_pt
+
+
+def profile(b: Batch, T_c, T_pt, stream=None):
+    _check(lib().helios_profile(ctypes.byref(b.desc), _ptr(T_c), _ptr(T_pt), _stream(stream)))
+    return T_pt
+
+
+def mix_opacity(b: Batch, kt: KTable, T_pt, kappa, prec=FP64, vmr=None, stream=None):
+    v = b.vmr if vmr is None else vmr
+    _check(lib().helios_mix_opacity(ctypes.byref(b.desc), ctypes.byref(kt.desc), _ptr(T_pt), _ptr(v),
+                                    _ptr(kappa), prec, _stream(stream)))
+    return kappa
+
+
+def transmission(b: Batch, kappa, T_pt, out, D=2.0, prec=FP64, stream=None):
+    _check(lib().helios_transmission(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
+                                     float(D), _ptr(out), prec, _stream(stream)))
+    return out
+
+
+def set_sweep_events(before=None, after=None):
+    """Record torch.cuda.Event pairs around the flux sweep kernel of this
+    thread's next helios_flux calls (None, None turns it off)."""
+    hb = None if before is None else before.cuda_event
+    ha = None if after is None else after.cuda_event
+    _check(lib().helios_set_sweep_events(hb, ha))
+
+
+def workspace_bytes(b: Batch, prec=FP64) -> int:
+    return int(lib().helios_workspace_bytes(ctypes.byref(b.desc), prec))
+
+
+def flux(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, n_scat=4, D=2.0, F_dn_g=None,
+         prec=FP64, stream=None):
+    _check(lib().helios_flux(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
+                             int(n_scat), float(D), _ptr(F_up_g), _ptr(F_dn_g), _ptr(F_up_bin),
+                             _ptr(F_dn_bin), _ptr(F_bol), _ptr(ws), ws.numel() * ws.element_size(),
+                             prec, _stream(stream)))
+
+
+@dataclass
+class REOptions:
+    tol: float = 1e-3
+    norm: int = NORM_SIGMA_TINT4
+    window: int = 6
+    osc_any: int = 0
+    T_floor: float = 10.0
+    shrink: float = 0.67
+    grow: float = 1.1
+    fpre_c: float = 1e5
+    fpre_p: float = 0.9
+
+    def c(self) -> HeliosReOpts:
+        return HeliosReOpts(self.tol, self.norm, self.window, self.osc_any, 0, self.T_floor, self.shrink,
+                            self.grow, self.fpre_c, self.fpre_p)
+
+
+def radeq(b: Batch, F_bol, T_c, T_pt, m, hist, status, resid=None, opts: REOptions | None = None,
+          iters=None, stream=None):
+    st = HeliosReState(_ptr(m), _ptr(hist), _ptr(iters))
+    o = (opts or REOptions()).c()
+    _check(lib().helios_radeq(ctypes.byref(b.desc), _ptr(F_bol), _ptr(T_c), _ptr(T_pt), ctypes.byref(st),
+                              ctypes.byref(o), _ptr(status), _ptr(resid), _stream(stream)))
+
+
+# ------------------------------------------------------------ RE buffers
+class Solver:
+    """Device buffers of one batch's radiative-equilibrium iteration, and the
+    iteration itself: profile -> opacity -> flux -> RE step per iteration,
+    all enqueued on one stream; the host reads the per-atmosphere status
+    every ``check_every`` iterations."""
+
+    def __init__(self, b: Batch, kt: KTable, prec=FP64, n_scat=4, D=2.0, opts: REOptions | None = None):
+        dev = b.device
+        rd = rdtype(prec)
+        self.b, self.kt, self.prec, self.n_scat, self.D = b, kt, prec, n_scat, D
+        self.opts = opts or REOptions()
+        self.T_c = torch.zeros(b.total_n, dtype=torch.float64, device=dev)
+        self.T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device=dev)
+        self.kappa = torch.zeros(b.total_cell, dtype=rd, device=dev)
+        self.F_up_g = torch.zeros(b.total_cell, dtype=rd, device=dev)
+        self.F_up_bin = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
+        self.F_dn_bin = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
+        self.F_bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device=dev)
+        self.ws = torch.zeros(workspace_bytes(b, prec), dtype=torch.uint8, device=dev)
+        self.m = torch.ones(b.total_n, dtype=torch.float64, device=dev)
+        self.hist = torch.zeros(b.total_n, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(b.n_atm, dtype=torch.int32, device=dev)
+        self.resid = torch.zeros(b.n_atm, dtype=torch.float64, device=dev)
+        self.iters = torch.zeros(b.n_atm, dtype=torch.int32, device=dev)
+        grid(b)
+
+    def reset(self, T_init):
+        self.T_c.copy_(torch.as_tensor(T_init, dtype=torch.float64, device=self.b.device))
+        self.F_up_g.zero_()
+        self.m.fill_(1.0)
+        self.hist.zero_()
+        self.status.zero_()
+        self.iters.zero_()
+        profile(self.b, self.T_c, self.T_pt)
+
+    def step(self, stream=None):
+        """One RE iteration for every atmosphere of the batch (enqueue only)."""
+        b = self.b
+        mix_opacity(b, self.kt, self.T_pt, self.kappa, self.prec, stream=stream)
+        flux(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol, self.ws,
+             n_scat=self.n_scat, D=self.D, prec=self.prec, stream=stream)
+        radeq(b, self.F_bol, self.T_c, self.T_pt, self.m, self.hist, self.status, self.resid, self.opts,
+              iters=self.iters, stream=stream)
+
+    def solve(self, T_init, max_iter=200, check_every=10):
+        """Iterate until every atmosphere converged or max_iter temperature
+        updates were taken.  Returns (converged flags, updates taken) per
+        atmosphere as numpy arrays; the counts come from the device, so
+        checking only every ``check_every`` steps loses nothing (converged
+        atmospheres are frozen)."""
+        self.reset(T_init)
+        done = 0
+        while done <= max_iter:
+            k = min(check_every, max_iter + 1 - done)
+            for _ in range(k):
+                self.step()
+            done += k
+            st = self.status.cpu().numpy()
+            if np.all(st != ATM_RUNNING):
+                break
+        st = self.status.cpu().numpy()
+        return st == ATM_CONVERGED, self.iters.cpu().numpy()

@@ -1,0 +1,37 @@
+"""Shared helpers of the GPU tests: run the oracle on the same inputs and
+compare.  Oracle inputs never come from the GPU path."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as ref
+
+
+def oracle_state(atm: dict, kt: dict, T_c):
+    P = ref.grid(atm["P_c"])
+    T = ref.profile(P, np.asarray(T_c, np.float64))
+    kap = ref.mix_opacity(kt, T, P, atm["vmr"], atm["bin_index"], atm["ng"])
+    return P, T, kap
+
+
+def smooth_profile(atm: dict, T_bot=1700.0, T_top=900.0, wiggle=60.0):
+    """A non-isothermal test temperature profile (monotone plus a bump)."""
+    n = atm["n"]
+    x = np.linspace(0.0, 1.0, n)
+    return T_bot + (T_top - T_bot) * x + wiggle * np.sin(7.0 * x)
+
+
+def net_flux_error(F_bol_gpu, F_bol_ref):
+    """Per-point |net_gpu - net_ref| / (up_ref + down_ref)."""
+    F_bol_gpu = np.asarray(F_bol_gpu).reshape(-1, 3)
+    F_bol_ref = np.asarray(F_bol_ref).reshape(-1, 3)
+    gross = F_bol_ref[:, 0] + F_bol_ref[:, 1]
+    return np.abs(F_bol_gpu[:, 2] - F_bol_ref[:, 2]) / gross
+
+
+def col_rel_error(x, y, axis=-1):
+    """|x - y| relative to the largest |y| along `axis` (per column)."""
+    x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+    scale = np.max(np.abs(y), axis=axis, keepdims=True)
+    scale = np.where(scale > 0, scale, 1.0)
+    return np.abs(x - y) / scale

@@ -1,0 +1,399 @@
+"""GPU (HIP, gfx950) path versus the FP64 CPU oracle, element by element, on
+the same seeded inputs.  Tolerances:
+  * FP64: net flux per point within 1e-10 of the oracle's gross flux
+    (|net_gpu - net_ref| / (up_ref + down_ref)), per-g and per-bin fluxes
+    within 1e-11 of their column's largest value, temperatures of a single
+    update within 1e-9 K;
+  * MIXED (FP32 sweeps, compensated sums, FP64 update): net flux within 1e-4
+    of the gross flux.
+All calls go through the C ABI (libhelios.so) via the ctypes binding.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as ref
+from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile
+from paper_1606_05474_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+H = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global H
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1606_05474_amd import helios
+
+    H = helios
+    H.lib()
+    yield
+
+
+def _t(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _np(x):
+    return x.detach().cpu().numpy()
+
+
+def test_native_library_is_the_in_tree_build():
+    import paper_1606_05474_amd
+
+    pkg = os.path.dirname(os.path.abspath(paper_1606_05474_amd.__file__))
+    assert os.path.dirname(H.LIB_PATH) == pkg
+    with open("/proc/self/maps") as f:
+        maps = f.read()
+    assert H.LIB_PATH in maps
+
+
+# ------------------------------------------------------------- grid / profile
+def test_grid_and_profile_match_oracle():
+    atms = [W.plain_workload(n=n, nb=3)[0] for n in (2, 7, 50)]
+    b = H.Batch(atms)
+    H.grid(b)
+    torch.cuda.synchronize()
+    T_c = [smooth_profile(a) for a in atms]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_c), T_pt)
+    P_all, T_all = _np(b.P_pt), _np(T_pt)
+    for a, atm in enumerate(atms):
+        P = ref.grid(atm["P_c"])
+        np.testing.assert_allclose(b.split_pt(P_all)[a], P, rtol=4e-16, atol=0)
+        np.testing.assert_allclose(b.split_pt(T_all)[a], ref.profile(P, T_c[a]), rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------ opacity
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mix_opacity_powerlaw(prec):
+    atm, kt = W.plain_workload()
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap_ref = oracle_state(atm, kt, T_c)
+    T_pt = _t(T)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(kt), T_pt, kap, prec)
+    got = _np(kap).astype(np.float64).reshape(kap_ref.shape)
+    np.testing.assert_allclose(got, kap_ref, rtol=1e-13 if prec == 0 else 2e-6, atol=0)
+
+
+@pytest.fixture(scope="module")
+def small_table():
+    return W.table_ktab(2, nbt=300)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mix_opacity_table_with_clamping(prec, small_table):
+    kt = small_table
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(7)
+    atm = W.spectral_atmosphere(rng, 40, lc, dl, 77)
+    b = H.Batch([atm])
+    H.grid(b)
+    # span the table and beyond it on both axes (T 50..3400 K; P beyond 1e3 bar at the bottom)
+    T_c = np.linspace(3400.0, 50.0, atm["n"])
+    P, T, kap_ref = oracle_state(atm, kt, T_c)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(kt), _t(T), kap, prec)
+    got = _np(kap).astype(np.float64).reshape(kap_ref.shape)
+    np.testing.assert_allclose(got, kap_ref, rtol=1e-13 if prec == 0 else 3e-6, atol=0)
+
+
+# ------------------------------------------------------- sublayer coefficients
+def test_transmission_coefficients_match_oracle(small_table):
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(8)
+    atm = W.spectral_atmosphere(rng, 30, lc, dl, 12, ng=20)
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap_ref = oracle_state(atm, small_table, T_c)
+    out = torch.zeros(b.total_cell - b.ng * b.total_bin, 5, dtype=torch.float64, device="cuda")
+    H.transmission(b, _t(kap_ref), _t(T), out)
+    got = _np(out).reshape(12, 20, 60, 5)
+    n = atm["n"]
+    worst = 0.0
+    branches = set()
+    for l in range(12):
+        B = np.array([ref.planck(atm["lambda_c"][l], t) for t in T])
+        for g in range(0, 20, 3):
+            for s in range(2 * n):
+                dtau = 0.5 * (kap_ref[l, g, s] + kap_ref[l, g, s + 1]) * (P[s] - P[s + 1]) / atm["grav"]
+                w0, g0 = atm["w0"][l, s // 2], atm["g0"][l, s // 2]
+                branches.add(ref.branch(dtau, w0))
+                Bu, Bd = B[s + 1], B[s]
+                a_ref = ref.sub_up(dtau, w0, g0, 2.0, 0, 0, 1.0, 0.0)
+                c_ref = ref.sub_up(dtau, w0, g0, 2.0, 0, 0, 0.0, 1.0)
+                su_ref = ref.sub_up(dtau, w0, g0, 2.0, Bu, Bd, 0.0, 0.0)
+                sd_ref = ref.sub_down(dtau, w0, g0, 2.0, Bu, Bd, 0.0, 0.0)
+                T_ref = ref.sub_trans(dtau, w0, g0)
+                v = got[l, g, s]
+                scale_s = max(abs(su_ref), abs(sd_ref), np.pi * max(Bu, Bd)) + 1e-300
+                errs = [abs(v[0] - T_ref), abs(v[1] - a_ref), abs(v[2] - c_ref),
+                        abs(v[3] - su_ref) / scale_s, abs(v[4] - sd_ref) / scale_s]
+                worst = max(worst, max(errs))
+    assert branches >= {1, 2}, branches
+    assert worst < 1e-11, worst
+
+
+# ------------------------------------------------------------------- flux
+def _gpu_flux(b, kap, T, prec, n_scat=4, F_up0=None, want_dn=True):
+    rd = H.rdtype(prec)
+    F_up = torch.zeros(b.total_cell, dtype=rd, device="cuda") if F_up0 is None else F_up0
+    F_dn = torch.zeros(b.total_cell, dtype=rd, device="cuda") if want_dn else None
+    ub = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    db = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(H.workspace_bytes(b, prec), dtype=torch.uint8, device="cuda")
+    H.flux(b, kap.to(rd), T, F_up, ub, db, bol, ws, n_scat=n_scat, F_dn_g=F_dn, prec=prec)
+    torch.cuda.synchronize()
+    return F_up, F_dn, ub, db, bol
+
+
+def _check_flux_fp64(b, a, res_ref, F_up_ref, F_up, F_dn, ub, db, bol, tol=1e-10):
+    err_net = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], res_ref["F_bol"])
+    assert err_net.max() < tol, err_net.max()
+    gu = b.split_cell(_np(F_up))[a]
+    assert col_rel_error(gu, F_up_ref).max() < 1e-11
+    if F_dn is not None:
+        gd = b.split_cell(_np(F_dn))[a]
+        assert col_rel_error(gd, res_ref["F_dn"]).max() < 1e-11
+    assert col_rel_error(b.split_pb(_np(ub))[a], res_ref["F_up_bin"]).max() < 1e-11
+    assert col_rel_error(b.split_pb(_np(db))[a], res_ref["F_dn_bin"]).max() < 1e-11
+    bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
+    np.testing.assert_allclose(bol_a[:, :2], res_ref["F_bol"][:, :2], rtol=1e-12)
+
+
+def test_flux_fp64_plain_two_calls_warm_start():
+    atm, kt = W.plain_workload()
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap = oracle_state(atm, kt, T_c)
+    up_ref = np.zeros(kap.shape)
+    r1 = ref.flux(atm, kap, T, P, up_ref)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0)
+    _check_flux_fp64(b, 0, r1, up_ref, F_up, F_dn, ub, db, bol)
+    # second call warm-started from the first call's upward fluxes, new temperatures
+    T2 = T * 1.01
+    r2 = ref.flux(atm, kap, T2, P, up_ref)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T2), 0, F_up0=F_up)
+    _check_flux_fp64(b, 0, r2, up_ref, F_up, F_dn, ub, db, bol)
+
+
+@pytest.mark.parametrize("n,nb,n_scat", [(100, 40, 4), (37, 9, 0), (61, 5, 11), (200, 6, 4)])
+def test_flux_fp64_table_scattering(n, nb, n_scat, small_table):
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(n)
+    atm = W.spectral_atmosphere(rng, n, lc, dl, nb)
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap = oracle_state(atm, small_table, T_c)
+    up_ref = np.zeros(kap.shape)
+    r = ref.flux(atm, kap, T, P, up_ref, n_scat=n_scat)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0, n_scat=n_scat)
+    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+
+
+def test_flux_without_downward_output_is_identical():
+    atm, kt = W.plain_workload()
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
+    a = _gpu_flux(b, _t(kap), _t(T), 0, want_dn=True)
+    c = _gpu_flux(b, _t(kap), _t(T), 0, want_dn=False)
+    assert torch.equal(a[0], c[0]) and torch.equal(a[4], c[4])
+
+
+def test_flux_mixed_precision_within_tolerance(small_table):
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(3)
+    atm = W.spectral_atmosphere(rng, 100, lc, dl, 60)
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
+    up_ref = np.zeros(kap.shape)
+    r = ref.flux(atm, kap, T, P, up_ref)
+    # the mixed path computes its own float32 opacities from the same table
+    kap_m = torch.zeros(b.total_cell, dtype=torch.float32, device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), _t(T), kap_m, 1)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, kap_m, _t(T), 1)
+    err = net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"])
+    assert err.max() < 1e-4, err.max()
+    assert col_rel_error(b.split_pb(_np(ub))[0], r["F_up_bin"]).max() < 1e-4
+
+
+# ----------------------------------------------------------------- RE step
+def test_radeq_matches_oracle_single_update():
+    atms = [W.plain_workload(n=n, nb=8)[0] for n in (50, 23)]
+    b = H.Batch(atms)
+    H.grid(b)
+    rng = np.random.default_rng(5)
+    F_bols, T_cs, ms, hs = [], [], [], []
+    for atm in atms:
+        n = atm["n"]
+        P = ref.grid(atm["P_c"])
+        net = 9e4 + np.cumsum(rng.normal(0, 3e4, 2 * n + 1))
+        F = np.zeros((2 * n + 1, 3))
+        F[:, 0] = 5e8 + net
+        F[:, 1] = 5e8
+        F[:, 2] = F[:, 0] - F[:, 1]
+        F_bols.append(F)
+        T_cs.append(smooth_profile(atm))
+        ms.append(rng.uniform(0.1, 2.0, n))
+        # random histories with full and partial windows
+        hs.append(((rng.integers(0, 7, n) << 16) | rng.integers(0, 64, n)).astype(np.int32))
+    F_d = _t(np.concatenate([f.ravel() for f in F_bols]))
+    T_d = b.cat_layer(T_cs)
+    m_d = b.cat_layer(ms)
+    h_d = _t(np.concatenate(hs), torch.int32)
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    status = torch.zeros(b.n_atm, dtype=torch.int32, device="cuda")
+    resid = torch.zeros(b.n_atm, dtype=torch.float64, device="cuda")
+    iters = torch.zeros(b.n_atm, dtype=torch.int32, device="cuda")
+    H.radeq(b, F_d, T_d, T_pt, m_d, h_d, status, resid, iters=iters)
+    torch.cuda.synchronize()
+    for a, atm in enumerate(atms):
+        T_ref, m_ref, h_ref = T_cs[a].copy(), ms[a].copy(), hs[a].copy()
+        code, r = ref.radeq(atm, ref.grid(atm["P_c"]), F_bols[a], T_ref, m_ref, h_ref)
+        assert code == 0
+        np.testing.assert_allclose(b.split_layer(_np(T_d))[a], T_ref, rtol=0, atol=1e-9)
+        np.testing.assert_allclose(b.split_layer(_np(m_d))[a], m_ref, rtol=1e-15)
+        np.testing.assert_array_equal(b.split_layer(_np(h_d))[a], h_ref)
+        assert _np(resid)[a] == pytest.approx(r, rel=1e-13)
+        P = ref.grid(atm["P_c"])
+        np.testing.assert_allclose(b.split_pt(_np(T_pt))[a], ref.profile(P, T_ref), rtol=1e-14)
+    assert np.all(_np(status) == H.ATM_RUNNING) and np.all(_np(iters) == 1)
+
+
+def test_radeq_converged_and_numeric_status():
+    atm = W.plain_workload(n=10, nb=4)[0]
+    b = H.Batch([atm, atm, atm])
+    H.grid(b)
+    npt = 21
+    F = np.zeros((3, npt, 3))
+    F[:, :, 0] = 1e8
+    F[:, :, 1] = 1e8 - 9.07e4
+    F[:, :, 2] = F[:, :, 0] - F[:, :, 1]
+    F[1, 5, 2] += 5e3  # not converged
+    F[2, 7, 2] = np.nan
+    T = b.cat_layer([np.full(10, 800.0)] * 3)
+    T0 = _np(T).copy()
+    m = torch.ones(30, dtype=torch.float64, device="cuda")
+    h = torch.zeros(30, dtype=torch.int32, device="cuda")
+    st = torch.zeros(3, dtype=torch.int32, device="cuda")
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.radeq(b, _t(F.ravel()), T, T_pt, m, h, st)
+    torch.cuda.synchronize()
+    assert list(_np(st)) == [H.ATM_CONVERGED, H.ATM_RUNNING, H.ATM_NUMERIC]
+    Tn = _np(T)
+    assert np.all(Tn[:10] == T0[:10]) and np.all(Tn[20:] == T0[20:]) and np.any(Tn[10:20] != T0[10:20])
+    # a converged atmosphere stays frozen even if its fluxes change
+    F[0, 3, 2] += 1e6
+    H.radeq(b, _t(F.ravel()), T, T_pt, m, h, st)
+    torch.cuda.synchronize()
+    assert np.all(_np(T)[:10] == T0[:10]) and _np(st)[0] == H.ATM_CONVERGED
+
+
+# ---------------------------------------------------------- end to end
+def test_plain_re_solve_matches_oracle():
+    """The plain FP64 workload: same number of temperature updates to reach
+    |dF|/sigma T_int^4 < 1e-3 and the same converged profile."""
+    atm, kt = W.plain_workload()
+    sol = ref.solve(atm, kt, max_iter=200)
+    assert sol["converged"]
+    b = H.Batch([atm])
+    s = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    conv, iters = s.solve(atm["T0"], max_iter=200)
+    assert conv[0]
+    T_gpu = _np(s.T_c)
+    dT = np.abs(T_gpu - sol["T_c"])
+    assert dT.max() < 0.1, dT.max()
+    assert abs(int(iters[0]) - sol["iterations"]) <= 10, (iters[0], sol["iterations"])
+
+
+# ---------------------------------------------------------- ragged batches
+def test_ragged_batch_equals_oracle_per_atmosphere(small_table):
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(21)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb, T_irr=ti, T_int=tint, grav=gr)
+            for n, nb, ti, tint, gr in [(50, 30, 1200.0, 150.0, 900.0), (120, 7, 2500.0, 500.0, 3000.0),
+                                        (9, 60, 900.0, 0.0, 500.0), (200, 3, 1800.0, 300.0, 2000.0)]]
+    b = H.Batch(atms)
+    H.grid(b)
+    T_cs = [smooth_profile(a, 1500 + 100 * i, 700 + 50 * i) for i, a in enumerate(atms)]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, 0)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, 0)
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
+        np.testing.assert_allclose(b.split_cell(_np(kap))[a], kap_ref, rtol=1e-13)
+        up_ref = np.zeros(kap_ref.shape)
+        r = ref.flux(atm, kap_ref, T, P, up_ref)
+        _check_flux_fp64(b, a, r, up_ref, F_up, F_dn, ub, db, bol)
+
+
+# ------------------------------------------------------------- edge cases
+def test_edge_minimal_atmosphere_one_bin_one_g():
+    rng = np.random.default_rng(2)
+    lc, dl = W.bins(1)
+    atm = {"n": 2, "ng": 1, "P_c": W.pressure_centres(2), "grav": 1000.0, "T_star": 5000.0,
+           "T_irr": 1500.0, "T_int": 0.0, "lambda_c": lc, "dlambda": dl,
+           "bin_index": np.zeros(1, np.int32), "w0": rng.uniform(0, 0.5, (1, 2)),
+           "g0": rng.uniform(-0.5, 0.5, (1, 2)), "vmr": np.ones((1, 5)), "T0": np.full(2, 1000.0)}
+    kt = {"mode": "powerlaw", "k0": np.array([[[0.05]]]), "p_exp": 0.5, "t_exp": 1.0, "P_ref": 1e6,
+          "T_ref": 1000.0, "mass": np.array([2.4]), "mmw": 2.4}
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, kt, [1300.0, 800.0])
+    up_ref = np.zeros(kap.shape)
+    r = ref.flux(atm, kap, T, P, up_ref)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0)
+    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+
+
+def test_edge_pure_scattering_and_isothermal_layers():
+    """w0 = 1 everywhere (pure-scattering branch) and optically thin layers
+    (isothermal branch) in one column set."""
+    lc, dl = W.bins(4)
+    n = 12
+    w0 = np.ones((4, n))
+    w0[1] = 0.3
+    atm = {"n": n, "ng": 3, "P_c": W.pressure_centres(n), "grav": 1000.0, "T_star": 5000.0,
+           "T_irr": 1500.0, "T_int": 300.0, "lambda_c": lc, "dlambda": dl,
+           "bin_index": np.arange(4, dtype=np.int32), "w0": w0, "g0": np.full((4, n), 0.2),
+           "vmr": np.ones((1, 2 * n + 1)), "T0": np.full(n, 1000.0)}
+    kt = {"mode": "powerlaw", "k0": np.array([[[1e-9, 1e-7, 1e-6]] * 4]), "p_exp": 0.5, "t_exp": 1.0,
+          "P_ref": 1e6, "T_ref": 1000.0, "mass": np.array([2.4]), "mmw": 2.4}
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
+    up_ref = np.zeros(kap.shape)
+    r = ref.flux(atm, kap, T, P, up_ref, n_scat=6)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0, n_scat=6)
+    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+
+
+def test_errors_are_reported_and_nothing_runs():
+    atm, kt = W.plain_workload()
+    b = H.Batch([atm])
+    H.grid(b)
+    z = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+    small_ws = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    pb = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HeliosError) as e:
+        H.flux(b, z, b.P_pt, z, pb, pb, bol, small_ws)
+    assert e.value.code == -4
+    with pytest.raises(H.HeliosError) as e:
+        H.flux(b, z, b.P_pt, z, pb, pb, bol, small_ws, n_scat=-1)
+    assert e.value.code == -1
