@@ -282,8 +282,8 @@ def test_radeq_converged_and_numeric_status():
     F[:, :, 0] = 1e8
     F[:, :, 1] = 1e8 - 9.07e4
     F[:, :, 2] = F[:, :, 0] - F[:, :, 1]
-    F[1, 5, 2] += 5e3  # not converged
-    F[2, 7, 2] = np.nan
+    F[1, 6, 2] += 5e3  # an interface: not converged
+    F[2, 8, 2] = np.nan
     T = b.cat_layer([np.full(10, 800.0)] * 3)
     T0 = _np(T).copy()
     m = torch.ones(30, dtype=torch.float64, device="cuda")
