@@ -149,6 +149,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--prec", choices=["both", "fp64", "mixed"], default="both",
+                    help="precisions to run (profiling runs pick one)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -165,11 +169,23 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        # a copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * x.numel() * 4, "launches": 5}))
+        return 0
     H.lib()  # fails loudly if the native library is missing
     kt = W.table_ktab(2)
     atm, _ = W.spectral_workload(ktab=kt)
-    fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt)
-    mixed = run_gpu(H.MIXED, args.steps, args.warmup, atm, kt)
+    fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt) if args.prec in ("both", "fp64") else None
+    mixed = run_gpu(H.MIXED, args.steps, args.warmup, atm, kt) if args.prec in ("both", "mixed") else None
+    if fp64 is None or mixed is None:
+        print(json.dumps({"fp64": fp64, "mixed": mixed}))
+        return 0
     n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
     tr = traffic_entry("fp64")
     line = {

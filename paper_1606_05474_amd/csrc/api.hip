@@ -69,17 +69,27 @@ int check_atm(const helios_atm* atm, Sizes& z) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t B, F_top, F_int, gw, total;
+    size_t B, F_top, F_int, gw, part_up, part_dn, chunk, total;
 };
 
-WsLayout ws_layout(const Sizes& z, bool mixed) {
+// Waves per bin for L lanes per column: each wave holds 64/L columns.
+int waves_per_bin(int n_g, int L) { return (n_g + (64 / L) - 1) / (64 / L); }
+
+// The workspace is sized for the largest waves-per-bin any sweep shape uses
+// (L = 32), so the shape can be chosen per call.
+WsLayout ws_layout(const Sizes& z, int n_g, bool mixed) {
     WsLayout w;
     size_t r = mixed ? sizeof(float) : sizeof(double);
+    const size_t wpb = (size_t)waves_per_bin(n_g, 32);
+    const size_t n_chunk = (size_t)((z.nb_max + kBolChunk - 1) / kBolChunk);
     w.B = 0;
     w.F_top = align256(w.B + (size_t)z.total_pb * r);
     w.F_int = align256(w.F_top + (size_t)z.total_bin * sizeof(double));
     w.gw = align256(w.F_int + (size_t)z.total_bin * sizeof(double));
-    w.total = align256(w.gw + HELIOS_MAX_NG * sizeof(double));
+    w.part_up = align256(w.gw + HELIOS_MAX_NG * sizeof(double));
+    w.part_dn = align256(w.part_up + (size_t)z.total_pb * wpb * 8);
+    w.chunk = align256(w.part_dn + (size_t)z.total_pb * wpb * 8);
+    w.total = align256(w.chunk + (size_t)z.total_pt * n_chunk * 4 * sizeof(double));
     return w;
 }
 
@@ -97,7 +107,7 @@ struct SweepShape {
 
 bool k_allowed(int K, bool mixed) {
     for (int i = 0; i < kNumSweepK; ++i)
-        if (kSweepK[i] == K) return mixed || K <= 13;
+        if (kSweepK[i] == K) return mixed || K <= 14;
     return false;
 }
 
@@ -208,7 +218,7 @@ int helios_transmission(const helios_atm* atm, const void* kappa, const double* 
 size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec) {
     Sizes z;
     if (check_atm(atm, z)) return 0;
-    return ws_layout(z, prec == HELIOS_MIXED).total;
+    return ws_layout(z, atm->n_g, prec == HELIOS_MIXED).total;
 }
 
 int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
@@ -223,7 +233,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     if (n_scat < 0 || n_scat > 100000) return fail(HELIOS_EINVAL, "n_scat = %d", n_scat);
     if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
     const bool mixed = prec == HELIOS_MIXED;
-    WsLayout w = ws_layout(z, mixed);
+    WsLayout w = ws_layout(z, atm->n_g, mixed);
     if (ws_bytes < w.total)
         return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, w.total);
     SweepShape sh;
@@ -256,34 +266,41 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     A.g0 = g0;
     A.F_up_g = F_up_g;
     A.F_dn_g = F_dn_g;
-    A.F_up_bin = F_up_bin;
-    A.F_dn_bin = F_dn_bin;
-    A.gb_begin = 0;
-    A.gb_end = z.total_bin;
+    A.part_up = wsb + w.part_up;
+    A.part_dn = wsb + w.part_dn;
+    A.gw = gw;
     A.n_atm = atm->n_atm;
     A.n_g = atm->n_g;
-    A.L = sh.L;
-    A.log2L = 0;
-    while ((1 << A.log2L) < sh.L) ++A.log2L;
+    A.wpb = waves_per_bin(atm->n_g, sh.L);
     A.n_scat = n_scat;
-    A.npt_max = z.npt_max;
     A.D = D;
-    A.gw = gw;
-    int block = ((atm->n_g * sh.L + 63) / 64) * 64;
-    int64_t grid64 = z.total_bin;
+    A.w_begin = 0;
+    A.w_end = z.total_bin * A.wpb;
+    int64_t grid64 = A.w_end;
     int cap = env_int("HELIOS_SWEEP_GRID", 0);
     if (cap > 0 && grid64 > cap) grid64 = cap;
     if (g_ev_before && g_ev_after) {
         e = hipEventRecord(g_ev_before, s);
         if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
     }
-    e = launch_sweep(A, sh.K, mixed, block, (int)grid64, s);
+    e = launch_sweep(A, sh.K, sh.L, mixed, (int)grid64, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (sweep)");
     if (g_ev_before && g_ev_after) {
         e = hipEventRecord(g_ev_after, s);
         if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
     }
-    e = launch_bolometric(atm, F_up_bin, F_dn_bin, F_bol, z.npt_max, s);
+    BolArgs Bo;
+    Bo.atm = *atm;
+    Bo.part_up = A.part_up;
+    Bo.part_dn = A.part_dn;
+    Bo.F_up_bin = F_up_bin;
+    Bo.F_dn_bin = F_dn_bin;
+    Bo.chunk = (double*)(wsb + w.chunk);
+    Bo.F_bol = F_bol;
+    Bo.wpb = A.wpb;
+    Bo.n_chunk = (z.nb_max + kBolChunk - 1) / kBolChunk;
+    Bo.mixed = mixed ? 1 : 0;
+    e = launch_bolometric(Bo, z.npt_max, z.nb_max, z.total_pt, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (bolometric)");
     g_err[0] = 0;
     return HELIOS_OK;

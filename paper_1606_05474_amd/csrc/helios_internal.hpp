@@ -70,14 +70,25 @@ struct SweepArgs {
     const double* g0;
     void* F_up_g;         // cell array, R, in/out
     void* F_dn_g;         // cell array, R, out, may be null
+    void* part_up;        // [bin x wave-of-bin x point] Gauss partial sums (workspace)
+    void* part_dn;
+    const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
+    int64_t w_begin, w_end;  // global wave range covered by the launch
+    int32_t n_atm, n_g;
+    int32_t wpb;          // waves per bin
+    int32_t n_scat;
+    double D;
+};
+
+struct BolArgs {
+    helios_atm atm;
+    const void* part_up;  // partial sums from the sweep (double, or compensated float pairs)
+    const void* part_dn;
     double* F_up_bin;
     double* F_dn_bin;
-    int64_t gb_begin, gb_end;  // global bin range covered by the launch
-    int32_t n_atm, n_g;
-    int32_t L, log2L;
-    int32_t n_scat, npt_max;
-    double D;
-    const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
+    double* chunk;        // [sum npt][n_chunk][4] Neumaier pairs of bin-chunk sums (workspace)
+    double* F_bol;
+    int32_t wpb, n_chunk, mixed;
 };
 
 // Host-side launchers (defined in the .hip files).
@@ -89,18 +100,18 @@ hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* 
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);
-hipError_t launch_sweep(const SweepArgs& a, int K, bool mixed, int block, int grid, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs& a, int K, int L, bool mixed, int grid, hipStream_t s);
 hipError_t launch_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,
                                const double* w0, const double* g0, double D, double* out,
                                int64_t total_sub, bool mixed, hipStream_t s);
-hipError_t launch_bolometric(const helios_atm* atm, const double* F_up_bin, const double* F_dn_bin,
-                             double* F_bol, int npt_max, hipStream_t s);
+hipError_t launch_bolometric(const BolArgs& a, int npt_max, int nb_max, int64_t total_pt, hipStream_t s);
 hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
                         const helios_re_state* st, const helios_re_opts& o, int32_t* status,
                         double* resid, int n_max, hipStream_t s);
 
 // Sweep instantiations available (sublayers per lane).
-constexpr int kSweepK[] = {4, 7, 13, 25};
+constexpr int kSweepK[] = {4, 8, 14, 26};
+constexpr int kBolChunk = 64;  // bins per bolometric chunk
 constexpr int kNumSweepK = 4;
 
 }  // namespace helios

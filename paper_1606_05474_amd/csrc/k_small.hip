@@ -88,7 +88,7 @@ __device__ double gauss_weight(int n, int g) {
     const int i = n - 1 - g;  // roots are generated in descending order
     double y = cos(kPi * (i + 0.75) / (n + 0.5));
     double dp = 1.0;
-    for (int it = 0; it < 60; ++it) {
+    for (int it = 0; it < 12; ++it) {
         double a = 1.0, b = y;
         for (int k = 2; k <= n; ++k) {
             double c = ((2 * k - 1) * y * b - (k - 1) * a) / k;
@@ -99,7 +99,7 @@ __device__ double gauss_weight(int n, int g) {
         dp = n * (y * b - a) / (y * y - 1.0);
         double step = b / dp;
         y -= step;
-        if (fabs(step) < 1e-16) {
+        if (fabs(step) < 4e-16 || it == 11) {
             a = 1.0;
             b = y;
             for (int k = 2; k <= n; ++k) {
@@ -162,10 +162,12 @@ hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* 
 }
 
 // ------------------------------------------------------ bolometric sums
-// F_bol[pt] = (sum_l dlambda_l F_up_bin[l][pt], same for down, difference).
-// Workgroup = (atmosphere, tile of 64 points); its 1024 threads are 64 points
-// x 16 bin chunks; each thread runs a Neumaier-compensated sum over its chunk
-// in bin order and the 16 chunk sums are combined in chunk order.
+// Stage 1: workgroup = (atmosphere, 64-point tile, chunk of kBolChunk bins);
+// 256 threads = 64 points x 4 sub-chunks of kBolChunk/4 bins.  Each thread
+// combines the sweep's per-wave Gauss partials of a bin (fixed order) into
+// F_up_bin / F_dn_bin, writes them, and accumulates dlambda * F in a
+// Neumaier sum; the 4 sub-chunk sums are combined in order and stored per
+// (point, chunk).  Stage 2: one thread per point sums its chunks in order.
 struct nacc {
     double s, c;
 };
@@ -176,59 +178,96 @@ __device__ inline void nadd(nacc& a, double v) {
     a.s = t;
 }
 
-__global__ void __launch_bounds__(1024) bolometric_kernel(helios_atm atm, const double* __restrict__ up,
-                                                          const double* __restrict__ dn,
-                                                          double* __restrict__ F_bol, int tiles_per_atm) {
-    __shared__ double red[2][16][64][2];
-    int a = blockIdx.x / tiles_per_atm;
-    int tile = blockIdx.x - a * tiles_per_atm;
-    int pl = threadIdx.x & 63, chunk = threadIdx.x >> 6;
-    int npt = 2 * atm.n_layer[a] + 1;
-    int p = tile * 64 + pl;
-    int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
-    if (tile * 64 >= npt) return;  // whole workgroup idle (uniform)
-    int per = (nb + 15) / 16;
-    int l0 = chunk * per, l1 = min(nb, l0 + per);
+__device__ inline double combine_partials(const void* part, int64_t base, int wpb, int npt, bool mixed) {
+    if (!mixed) {
+        const double* p = static_cast<const double*>(part) + base;
+        double s = 0.0;
+        for (int j = 0; j < wpb; ++j) s += p[(int64_t)j * npt];
+        return s;
+    }
+    const fpair* p = static_cast<const fpair*>(part) + base;
+    fpair acc = {0.0f, 0.0f};
+    for (int j = 0; j < wpb; ++j) acc = two_sum_add(acc, p[(int64_t)j * npt]);
+    return (double)acc.s + (double)acc.c;
+}
+
+__global__ void __launch_bounds__(256) bin_sum_kernel(const BolArgs A) {
+    __shared__ double red[4][64][4];
+    const int a = blockIdx.x;
+    const int tile = blockIdx.y, ch = blockIdx.z;
+    const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int npt = 2 * A.atm.n_layer[a] + 1;
+    const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
+    if (tile * 64 >= npt || ch * kBolChunk >= nb) return;  // uniform per workgroup
+    const int p = tile * 64 + pl;
+    const int per = kBolChunk / 4;
+    const int l0 = ch * kBolChunk + q * per, l1 = min(nb, l0 + per);
     nacc au = {0.0, 0.0}, ad = {0.0, 0.0};
     if (p < npt) {
-        const double* dl = atm.dlambda + atm.bin_off[a];
-        const double* U = up + atm.pb_off[a];
-        const double* Dn = dn + atm.pb_off[a];
+        const double* dl = A.atm.dlambda + A.atm.bin_off[a];
+        const int64_t pb = A.atm.pb_off[a];
         for (int l = l0; l < l1; ++l) {
-            double w = dl[l];
-            nadd(au, w * U[(int64_t)l * npt + p]);
-            nadd(ad, w * Dn[(int64_t)l * npt + p]);
+            const int64_t base = pb * A.wpb + ((int64_t)l * A.wpb) * npt + p;
+            const double fu = combine_partials(A.part_up, base, A.wpb, npt, A.mixed);
+            const double fd = combine_partials(A.part_dn, base, A.wpb, npt, A.mixed);
+            A.F_up_bin[pb + (int64_t)l * npt + p] = fu;
+            A.F_dn_bin[pb + (int64_t)l * npt + p] = fd;
+            nadd(au, dl[l] * fu);
+            nadd(ad, dl[l] * fd);
         }
     }
-    red[0][chunk][pl][0] = au.s;
-    red[0][chunk][pl][1] = au.c;
-    red[1][chunk][pl][0] = ad.s;
-    red[1][chunk][pl][1] = ad.c;
+    red[q][pl][0] = au.s;
+    red[q][pl][1] = au.c;
+    red[q][pl][2] = ad.s;
+    red[q][pl][3] = ad.c;
     __syncthreads();
-    if (chunk == 0 && p < npt) {
+    if (q == 0 && p < npt) {
         nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
-        for (int k = 0; k < 16; ++k) {
-            nadd(tu, red[0][k][pl][0]);
-            nadd(td, red[1][k][pl][0]);
-        }
         double cu = 0.0, cd = 0.0;
-        for (int k = 0; k < 16; ++k) {
-            cu += red[0][k][pl][1];
-            cd += red[1][k][pl][1];
+        for (int k = 0; k < 4; ++k) {
+            nadd(tu, red[k][pl][0]);
+            nadd(td, red[k][pl][2]);
+            cu += red[k][pl][1];
+            cd += red[k][pl][3];
         }
-        double fu = tu.s + (tu.c + cu), fd = td.s + (td.c + cd);
-        double* o = F_bol + 3 * (atm.pt_off[a] + p);
-        o[0] = fu;
-        o[1] = fd;
-        o[2] = fu - fd;
+        double* o = A.chunk + ((A.atm.pt_off[a] + p) * A.n_chunk + ch) * 4;
+        o[0] = tu.s;
+        o[1] = tu.c + cu;
+        o[2] = td.s;
+        o[3] = td.c + cd;
     }
 }
 
-hipError_t launch_bolometric(const helios_atm* atm, const double* F_up_bin, const double* F_dn_bin,
-                             double* F_bol, int npt_max, hipStream_t s) {
-    int tiles = (npt_max + 63) / 64;
-    hipLaunchKernelGGL(bolometric_kernel, dim3(atm->n_atm * tiles), dim3(1024), 0, s, *atm, F_up_bin,
-                       F_dn_bin, F_bol, tiles);
+__global__ void bol_final_kernel(const BolArgs A, int64_t total_pt) {
+    const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= total_pt) return;
+    const int a = find_atm(A.atm.pt_off, A.atm.n_atm, gp);
+    const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
+    const int nch = (nb + kBolChunk - 1) / kBolChunk;
+    const double* c = A.chunk + gp * A.n_chunk * 4;
+    nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
+    double cu = 0.0, cd = 0.0;
+    for (int k = 0; k < nch; ++k) {
+        nadd(tu, c[4 * k + 0]);
+        cu += c[4 * k + 1];
+        nadd(td, c[4 * k + 2]);
+        cd += c[4 * k + 3];
+    }
+    const double fu = tu.s + (tu.c + cu), fd = td.s + (td.c + cd);
+    double* o = A.F_bol + 3 * gp;
+    o[0] = fu;
+    o[1] = fd;
+    o[2] = fu - fd;
+}
+
+hipError_t launch_bolometric(const BolArgs& a, int npt_max, int nb_max, int64_t total_pt, hipStream_t s) {
+    dim3 grid(a.atm.n_atm, (npt_max + 63) / 64, (nb_max + kBolChunk - 1) / kBolChunk);
+    hipLaunchKernelGGL(bin_sum_kernel, grid, dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int block = 256;
+    hipLaunchKernelGGL(bol_final_kernel, dim3((unsigned)((total_pt + block - 1) / block)), dim3(block), 0, s, a,
+                       total_pt);
     return hipGetLastError();
 }
 

@@ -45,8 +45,9 @@ template <typename R>
 struct Prec;
 template <>
 struct Prec<double> {
+    // T = exp(-x) and om = 1 - T from one transcendental: om is accurate for
+    // thin layers, T accurate in absolute terms
     __device__ static inline void t_om(double x, double& T, double& om) {
-        // one transcendental: om accurate for small x, T accurate in absolute terms
         double em = expm1(-x);
         om = -em;
         T = 1.0 + em;
@@ -60,145 +61,170 @@ struct Prec<float> {
         T = __expf(-x);
         om = -expm1f(-x);
     }
-    __device__ static inline float rcp(float v) { return __frcp_rn(v); }
-    __device__ static inline float sqrt_(float v) { return sqrtf(v); }
+    __device__ static inline float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+    __device__ static inline float sqrt_(float v) { return __builtin_sqrtf(v); }
 };
 
-// Coefficients {T, a, c, S_up, S_dn} of one sublayer.
+// Per-layer quantities shared by a layer's two sublayers and all g.
+template <typename R>
+struct LayerQ {
+    R r, zp, zm, kx, f, purescat_gd;  // purescat_gd = D (1 - g0)/2 (used when w0 ~ 1)
+    bool purescat;
+};
+
+template <typename R>
+__device__ inline LayerQ<R> layer_q(R w0, R g0, R D) {
+    LayerQ<R> q;
+    const R one = (R)1;
+    q.purescat = (one - w0) < (R)1e-6;
+    const R omg = one - w0 * g0;
+    const R iomg = Prec<R>::rcp(omg);
+    q.r = Prec<R>::sqrt_((one - w0) * iomg);
+    q.zp = (R)0.5 * (one + q.r);
+    q.zm = (R)0.5 * (one - q.r);
+    q.kx = D * Prec<R>::sqrt_(omg * (one - w0));
+    q.f = iomg / D;  // eps / (1 - w0 g0)
+    q.purescat_gd = D * (one - g0) * (R)0.5;
+    return q;
+}
+
+// Coefficients {T, a, c, S_up, S_dn} of one sublayer from its layer's
+// quantities, optical depth and end Planck values.  den = zp^2 - zm^2 T^2
+// factors as (zp - zm T)(zp + zm T), so one reciprocal serves all three
+// denominators.
+template <typename R>
+__device__ inline void sub_coeffs_q(const LayerQ<R>& q, R dtau, R D, R Bu, R Bd, R& Tr, R& a, R& c, R& su,
+                                    R& sd) {
+    const R one = (R)1;
+    const R two_pi_eps = (R)(2.0 * kPi) / D;
+    R T, om;
+    Prec<R>::t_om(q.kx * dtau, T, om);
+    const R u = q.zp - q.zm * T, v = q.zp + q.zm * T;
+    const R iden = Prec<R>::rcp(u * v);
+    R a_ = q.r * T * iden;
+    R c_ = q.zp * q.zm * om * (one + T) * iden;
+    R s_iso = two_pi_eps * (R)0.5 * (Bu + Bd) * q.r * om * u * iden;
+    const R gterm = q.f * (Bd - Bu) * Prec<R>::rcp(dtau) * om * v * iden;
+    const R e2 = q.zp + q.zm * T * T;
+    R su_ = two_pi_eps * (q.r * (Bu * e2 - Bd * T) * iden + gterm);
+    R sd_ = two_pi_eps * (q.r * (Bd * e2 - Bu * T) * iden - gterm);
+    const bool iso = dtau < (R)1e-4;
+    su_ = iso ? s_iso : su_;
+    sd_ = iso ? s_iso : sd_;
+    // eq:purescat
+    const R gd = q.purescat_gd * dtau;
+    const R qq = gd * Prec<R>::rcp(one + gd);
+    Tr = q.purescat ? one : T;
+    a = q.purescat ? one - qq : a_;
+    c = q.purescat ? qq : c_;
+    su = q.purescat ? (R)0 : su_;
+    sd = q.purescat ? (R)0 : sd_;
+}
+
+// Coefficients of one sublayer from (dtau, w0, g0): the inspection kernel's
+// entry to the same arithmetic.
 template <typename R>
 __device__ inline void sub_coeffs(R dtau, R w0, R g0, R D, R Bu, R Bd, R& Tr, R& a, R& c, R& su, R& sd) {
-    const R one = (R)1;
-    const R eps = one / D;
-    const R two_pi_eps = (R)(2.0 * kPi) * eps;
-    if (one - w0 < (R)1e-6) {
-        const R gd = D * (one - g0) * (R)0.5 * dtau;
-        const R q = gd / (one + gd);
-        Tr = one;
-        a = one - q;
-        c = q;
-        su = (R)0;
-        sd = (R)0;
-        return;
-    }
-    const R omg = one - w0 * g0;
-    const R r = Prec<R>::sqrt_((one - w0) / omg);
-    const R zp = (R)0.5 * (one + r), zm = (R)0.5 * (one - r);
-    const R x = D * Prec<R>::sqrt_(omg * (one - w0)) * dtau;
-    R T, om;
-    Prec<R>::t_om(x, T, om);
-    const R den = zp * zp - zm * zm * T * T;
-    const R iden = one / den;
-    Tr = T;
-    a = r * T * iden;
-    c = zp * zm * om * (one + T) * iden;
-    if (dtau < (R)1e-4) {
-        const R s = two_pi_eps * (R)0.5 * (Bu + Bd) * r * om / (zp + zm * T);
-        su = s;
-        sd = s;
-    } else {
-        const R f = eps / omg;
-        const R gterm = f * (Bd - Bu) / dtau * om / (zp - zm * T);
-        const R e2 = zp + zm * T * T;
-        su = two_pi_eps * (r * (Bu * e2 - Bd * T) * iden + gterm);
-        sd = two_pi_eps * (r * (Bd * e2 - Bu * T) * iden - gterm);
-    }
+    LayerQ<R> q = layer_q<R>(w0, g0, D);
+    sub_coeffs_q<R>(q, dtau, D, Bu, Bd, Tr, a, c, su, sd);
 }
 
-template <typename R>
-__device__ inline R shfl_down_w(R v, int d, int width) {
-    return __shfl_down(v, (unsigned)d, width);
-}
-template <typename R>
-__device__ inline R shfl_up_w(R v, int d, int width) {
-    return __shfl_up(v, (unsigned)d, width);
-}
-
-// Partial g-sums of one point: sum over the wave's columns by xor shuffles,
-// then the first column of each wave writes its partial to LDS.
+// Partial g-sums of one point over the wave's columns (xor shuffles over
+// the column index); the first column's lanes hold the result.
 template <typename R>
 struct GSum;
 template <>
 struct GSum<double> {
     using slot = double;
-    __device__ static inline void wave_reduce_store(double v, int L, bool writer, slot* dst) {
+    template <int L>
+    __device__ static inline slot wave_reduce(double v) {
+#pragma unroll
         for (int d = L; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-        if (writer) *dst = v;
-    }
-    __device__ static inline double combine(const slot* src, int stride, int nw) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += src[w * stride];
-        return s;
+        return v;
     }
 };
 template <>
 struct GSum<float> {
     using slot = fpair;
-    __device__ static inline void wave_reduce_store(float v, int L, bool writer, slot* dst) {
+    template <int L>
+    __device__ static inline slot wave_reduce(float v) {
         fpair p = {v, 0.0f};
+#pragma unroll
         for (int d = L; d < 64; d <<= 1) {
             fpair o = {__shfl_xor(p.s, d, 64), __shfl_xor(p.c, d, 64)};
             p = two_sum_add(p, o);
         }
-        if (writer) *dst = p;
-    }
-    __device__ static inline double combine(const slot* src, int stride, int nw) {
-        fpair acc = {0.0f, 0.0f};
-        for (int w = 0; w < nw; ++w) acc = two_sum_add(acc, src[w * stride]);
-        return (double)acc.s + (double)acc.c;
+        return p;
     }
 };
 
-template <int K, typename R, int MAXT>
-__global__ void __launch_bounds__(MAXT) sweep_kernel(const SweepArgs A) {
+// One workgroup = one wave = C = 64/L columns (consecutive g of one bin) of
+// L lanes.  Wave j of bin l covers g in [j*C, j*C + C).  No LDS, no barrier:
+// the wave's Gauss partial sums go to the workspace and the bolometric
+// kernel combines the partials of a bin in fixed order.
+template <int K, int L, typename R, int OCC>
+__global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using GS = GSum<R>;
     using slot = typename GS::slot;
-    extern __shared__ unsigned char smem_raw[];
-    slot* part = reinterpret_cast<slot*>(smem_raw);  // [nwaves][npt_max]
-
-    const int t = threadIdx.x;
-    const int L = A.L;
-    const int seg = t & (L - 1);
-    const int col = t >> A.log2L;
-    const int wave = t >> 6;
-    const int nwaves = blockDim.x >> 6;
-    const bool writer = (t & 63) < L;  // first column of its wave
+    constexpr int C = 64 / L;
+    static_assert(K % 2 == 0, "segments hold whole layers");
+    const int lane = threadIdx.x;
+    const int seg = lane & (L - 1);
+    const int cw = lane / L;
     const R* __restrict__ kap_all = static_cast<const R*>(A.kappa);
     const R* __restrict__ B_all = static_cast<const R*>(A.B);
     R* __restrict__ Fu_all = static_cast<R*>(A.F_up_g);
     R* __restrict__ Fd_all = static_cast<R*>(A.F_dn_g);
+    slot* __restrict__ part_up = static_cast<slot*>(A.part_up);
+    slot* __restrict__ part_dn = static_cast<slot*>(A.part_dn);
 
-    for (int64_t gb = A.gb_begin + blockIdx.x; gb < A.gb_end; gb += gridDim.x) {
+    for (int64_t gwave = A.w_begin + blockIdx.x; gwave < A.w_end; gwave += gridDim.x) {
+        const int64_t gb = gwave / A.wpb;
+        const int j = (int)(gwave - gb * A.wpb);
         const int at = find_atm(A.bin_off, A.n_atm, gb);
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
         const int nsub = 2 * n, npt = nsub + 1;
         const int nact = (nsub + K - 1) / K;
-        const bool colok = col < A.n_g;
+        const int g = j * C + cw;
+        const bool colok = g < A.n_g;
         const int lo = seg * K;
-        // points owned by this segment (its sublayers' lower ends), whatever the column
-        const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;
-        const bool top_seg = (seg == nact - 1);  // also owns the TOA point
+        const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // points owned (any column)
+        const bool top_seg = (seg == nact - 1);                 // also owns the TOA point
         const int cnt = colok ? scnt : 0;
-        const int64_t cell = A.cell_off[at] + ((int64_t)l * A.n_g + (colok ? col : 0)) * npt;
+        const int64_t cell = A.cell_off[at] + ((int64_t)l * A.n_g + (colok ? g : 0)) * npt;
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
+        const int64_t poff = (A.pb_off[at] * A.wpb) + ((int64_t)l * A.wpb + j) * npt;
         const double* __restrict__ P = A.P_pt + A.pt_off[at];
         const double grav = A.grav[at];
         const R D = (R)A.D;
         const R Ftop = (R)A.F_top[A.bin_off[at] + l];
         const R Fint = (R)A.F_int[A.bin_off[at] + l];
-        const R wg = colok ? (R)A.gw[col] : (R)0;
+        const R wg = colok ? (R)A.gw[g] : (R)0;
 
-        // ---- load and build the sublayer coefficients (once per call)
+        // per-lane base pointers: every access below is base + small constant
+        const R* __restrict__ kcol = kap_all + cell + lo;
+        const R* __restrict__ Bcol = B_all + pb + lo;
+        const double* __restrict__ Pcol = P + lo;
+        R* __restrict__ fucol = Fu_all + cell + lo;
+        R* __restrict__ fdcol = Fd_all ? Fd_all + cell + lo : nullptr;
+        slot* __restrict__ pucol = part_up + poff + lo;
+        slot* __restrict__ pdcol = part_dn + poff + lo;
+        const double* __restrict__ w0l = A.w0 + lb + (lo >> 1);
+        const double* __restrict__ g0l = A.g0 + lb + (lo >> 1);
+
+        // ---- sublayer coefficients and warm start (once per call)
         R ca[K], cc[K], su[K], sd[K], fu[K], bu[K];
         {
             R kp = (R)0, Bp = (R)0;
             double Pp = 1.0;
             if (cnt > 0) {
-                kp = kap_all[cell + lo];
-                Bp = B_all[pb + lo];
-                Pp = P[lo];
+                kp = kcol[0];
+                Bp = Bcol[0];
+                Pp = Pcol[0];
             }
+            LayerQ<R> q;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 ca[k] = (R)1;
@@ -208,16 +234,14 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(const SweepArgs A) {
                 fu[k] = (R)0;
                 bu[k] = (R)0;
                 if (k < cnt) {
-                    const int s = lo + k;
-                    const R kn = kap_all[cell + s + 1];
-                    const R Bn = B_all[pb + s + 1];
-                    const double Pn = P[s + 1];
+                    if ((k & 1) == 0) q = layer_q<R>((R)w0l[k >> 1], (R)g0l[k >> 1], D);
+                    const R kn = kcol[k + 1];
+                    const R Bn = Bcol[k + 1];
+                    const double Pn = Pcol[k + 1];
                     const R dtau = (R)0.5 * (kp + kn) * (R)((Pp - Pn) / grav);
-                    const R w0 = (R)A.w0[lb + (s >> 1)];
-                    const R g0 = (R)A.g0[lb + (s >> 1)];
                     R Tr;
-                    sub_coeffs<R>(dtau, w0, g0, D, Bn, Bp, Tr, ca[k], cc[k], su[k], sd[k]);
-                    fu[k] = Fu_all[cell + s];
+                    sub_coeffs_q<R>(q, dtau, D, Bn, Bp, Tr, ca[k], cc[k], su[k], sd[k]);
+                    fu[k] = fucol[k];
                     kp = kn;
                     Bp = Bn;
                     Pp = Pn;
@@ -226,50 +250,42 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(const SweepArgs A) {
         }
 
         R ftoa = (R)0;
-        const int base = (t & 63) & ~(L - 1);  // lane of seg 0 in this column
+        const int base = lane & ~(L - 1);  // seg 0 of this column
         for (int pass = 0; pass <= A.n_scat; ++pass) {
             const bool last = (pass == A.n_scat);
             // ---------------- downward sweep: compose my segment (top -> bottom)
             R MA = (R)1, MB = (R)0;
 #pragma unroll
             for (int k = K - 1; k >= 0; --k) {
-                const R b = cc[k] * fu[k] + sd[k];
-                MB = ca[k] * MB + b;
+                MB = ca[k] * MB + (cc[k] * fu[k] + sd[k]);
                 MA = ca[k] * MA;
             }
+#pragma unroll
             for (int d = 1; d < L; d <<= 1) {  // suffix scan towards the BOA
-                const R A2 = shfl_down_w(MA, d, L), B2 = shfl_down_w(MB, d, L);
+                const R A2 = __shfl_down(MA, (unsigned)d, L), B2 = __shfl_down(MB, (unsigned)d, L);
                 if (seg + d < L) {
                     MB = MA * B2 + MB;
                     MA = MA * A2;
                 }
             }
             const R xbot = MA * Ftop + MB;
-            R xtop = shfl_down_w(xbot, 1, L);
+            R xtop = __shfl_down(xbot, 1u, L);
             if (seg == L - 1) xtop = Ftop;
-            // replay: downward fluxes, and the up-sweep inputs b_up
             R x = xtop;
             if (last) {
-                // F_dn at the TOA point is the boundary value; the top segment owns it
-                GS::wave_reduce_store((top_seg && colok) ? wg * Ftop : (R)0, L, writer && top_seg,
-                                      &part[wave * A.npt_max + nsub]);
-                if (top_seg && colok && Fd_all) Fd_all[cell + nsub] = Ftop;
+                const slot v = GS::template wave_reduce<L>((top_seg && colok) ? wg * Ftop : (R)0);
+                if (cw == 0 && top_seg) pdcol[nsub - lo] = v;
+                if (top_seg && colok && fdcol) fdcol[nsub - lo] = Ftop;
             }
 #pragma unroll
             for (int k = K - 1; k >= 0; --k) {
                 bu[k] = cc[k] * x + su[k];
                 x = ca[k] * x + (cc[k] * fu[k] + sd[k]);
                 if (last) {
-                    GS::wave_reduce_store((k < cnt) ? wg * x : (R)0, L, writer && k < scnt,
-                                          &part[wave * A.npt_max + min(lo + k, nsub)]);
-                    if (k < cnt && Fd_all) Fd_all[cell + lo + k] = x;
+                    const slot v = GS::template wave_reduce<L>((k < cnt) ? wg * x : (R)0);
+                    if (cw == 0 && k < scnt) pdcol[k] = v;
+                    if (k < cnt && fdcol) fdcol[k] = x;
                 }
-            }
-            if (last) {
-                __syncthreads();
-                double* outb = A.F_dn_bin + pb;
-                for (int p = t; p < npt; p += blockDim.x) outb[p] = GS::combine(part + p, A.npt_max, nwaves);
-                __syncthreads();
             }
             // ---------------- BOA: F_up(0) = F_dn(0) + F_int
             const R y0 = __shfl(x, base, 64) + Fint;
@@ -281,15 +297,16 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(const SweepArgs A) {
                 MB = ca[k] * MB + bu[k];
                 MA = ca[k] * MA;
             }
+#pragma unroll
             for (int d = 1; d < L; d <<= 1) {  // prefix scan towards the TOA
-                const R A2 = shfl_up_w(MA, d, L), B2 = shfl_up_w(MB, d, L);
+                const R A2 = __shfl_up(MA, (unsigned)d, L), B2 = __shfl_up(MB, (unsigned)d, L);
                 if (seg >= d) {
                     MB = MA * B2 + MB;
                     MA = MA * A2;
                 }
             }
             const R ytop = MA * y0 + MB;
-            R ybot = shfl_up_w(ytop, 1, L);
+            R ybot = __shfl_up(ytop, 1u, L);
             if (seg == 0) ybot = y0;
             R y = ybot;
 #pragma unroll
@@ -300,49 +317,45 @@ __global__ void __launch_bounds__(MAXT) sweep_kernel(const SweepArgs A) {
             ftoa = y;
         }
 
-        // ---- outputs: upward fluxes (warm start for the next call) and their g-sum
+        // ---- outputs: upward fluxes (warm start of the next call) and their partial g-sums
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            GS::wave_reduce_store((k < cnt) ? wg * fu[k] : (R)0, L, writer && k < scnt,
-                                  &part[wave * A.npt_max + min(lo + k, nsub)]);
-            if (k < cnt) Fu_all[cell + lo + k] = fu[k];
+            const slot v = GS::template wave_reduce<L>((k < cnt) ? wg * fu[k] : (R)0);
+            if (cw == 0 && k < scnt) pucol[k] = v;
+            if (k < cnt) fucol[k] = fu[k];
         }
-        GS::wave_reduce_store((top_seg && colok) ? wg * ftoa : (R)0, L, writer && top_seg,
-                              &part[wave * A.npt_max + nsub]);
-        if (top_seg && colok) Fu_all[cell + nsub] = ftoa;
-        __syncthreads();
-        double* outb = A.F_up_bin + pb;
-        for (int p = t; p < npt; p += blockDim.x) outb[p] = GS::combine(part + p, A.npt_max, nwaves);
-        __syncthreads();
+        {
+            const slot v = GS::template wave_reduce<L>((top_seg && colok) ? wg * ftoa : (R)0);
+            if (cw == 0 && top_seg) pucol[nsub - lo] = v;
+            if (top_seg && colok) fucol[nsub - lo] = ftoa;
+        }
     }
 }
 
-template <int K, int MAXT>
-static hipError_t launch_k(const SweepArgs& a, bool mixed, int block, int grid, hipStream_t s) {
-    const int nwaves = block / 64;
-    if (mixed) {
-        size_t sh = (size_t)nwaves * a.npt_max * sizeof(fpair);
-        hipLaunchKernelGGL((sweep_kernel<K, float, MAXT>), dim3(grid), dim3(block), sh, s, a);
-    } else {
-        size_t sh = (size_t)nwaves * a.npt_max * sizeof(double);
-        hipLaunchKernelGGL((sweep_kernel<K, double, MAXT>), dim3(grid), dim3(block), sh, s, a);
-    }
+template <int K, int L, int OCC>
+static hipError_t launch_k(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL((sweep_kernel<K, L, float, OCC>), dim3(grid), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<K, L, double, OCC>), dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
 template <int K>
-static hipError_t launch_kb(const SweepArgs& a, bool mixed, int block, int grid, hipStream_t s) {
-    if (block <= 320) return launch_k<K, 320>(a, mixed, block, grid, s);
-    if (block <= 640) return launch_k<K, 640>(a, mixed, block, grid, s);
+static hipError_t launch_kl(const SweepArgs& a, int L, bool mixed, int grid, hipStream_t s) {
+    // occupancy hint: two waves per SIMD for the widest segments, more for narrower ones
+    constexpr int OCC = (K >= 14) ? 2 : (K >= 8 ? 3 : 4);
+    if (L == 16) return launch_k<K, 16, OCC>(a, mixed, grid, s);
+    if (L == 32) return launch_k<K, 32, OCC>(a, mixed, grid, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int K, bool mixed, int block, int grid, hipStream_t s) {
+hipError_t launch_sweep(const SweepArgs& a, int K, int L, bool mixed, int grid, hipStream_t s) {
     switch (K) {
-        case 4: return launch_kb<4>(a, mixed, block, grid, s);
-        case 7: return launch_kb<7>(a, mixed, block, grid, s);
-        case 13: return launch_kb<13>(a, mixed, block, grid, s);
-        case 25: return launch_kb<25>(a, mixed, block, grid, s);
+        case 4: return launch_kl<4>(a, L, mixed, grid, s);
+        case 8: return launch_kl<8>(a, L, mixed, grid, s);
+        case 14: return launch_kl<14>(a, L, mixed, grid, s);
+        case 26: return launch_kl<26>(a, L, mixed, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
