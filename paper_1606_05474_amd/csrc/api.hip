@@ -93,6 +93,43 @@ WsLayout ws_layout(const Sizes& z, int n_g, bool mixed) {
     return w;
 }
 
+// Gauss-Legendre rule on [0,1] (Sec. 2.3): weights w_g/2 at the nodes
+// (1 + y_g)/2, y_g the roots of P_n, by Newton's method on the Legendre
+// three-term recurrence; nodes ascending.  Computed once per n on the host.
+void legendre(int n, double y, double& pn, double& dpn) {
+    double a = 1.0, b = y;  // P_0, P_1
+    for (int k = 2; k <= n; ++k) {
+        double c = ((2.0 * k - 1.0) * y * b - (k - 1.0) * a) / k;
+        a = b;
+        b = c;
+    }
+    if (n == 1) a = 1.0;
+    pn = b;
+    dpn = n * (y * b - a) / (y * y - 1.0);
+}
+
+const GaussTable& gauss_table(int n) {
+    static GaussTable tab[HELIOS_MAX_NG + 1];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int m = 1; m <= HELIOS_MAX_NG; ++m) {
+            memset(tab[m].w, 0, sizeof(tab[m].w));
+            for (int i = 0; i < m; ++i) {
+                double y = cos(kPi * (i + 0.75) / (m + 0.5)), pn = 0.0, dpn = 1.0;
+                for (int it = 0; it < 100; ++it) {
+                    legendre(m, y, pn, dpn);
+                    double step = pn / dpn;
+                    y -= step;
+                    if (fabs(step) < 1e-16) break;
+                }
+                legendre(m, y, pn, dpn);
+                tab[m].w[m - 1 - i] = 1.0 / ((1.0 - y * y) * dpn * dpn);
+            }
+        }
+    });
+    return tab[n];
+}
+
 int env_int(const char* name, int dflt) {
     const char* v = getenv(name);
     return (v && *v) ? atoi(v) : dflt;
@@ -246,7 +283,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     double* F_int = (double*)(wsb + w.F_int);
     double* gw = (double*)(wsb + w.gw);
 
-    hipError_t e = launch_planck(atm, z.total_pb, T_pt, B, F_top, F_int, gw, mixed, s);
+    hipError_t e = launch_planck(atm, z.total_pb, T_pt, B, F_top, F_int, gw, gauss_table(atm->n_g), mixed, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (sources)");
 
     SweepArgs A;

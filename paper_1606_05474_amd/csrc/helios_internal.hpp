@@ -80,6 +80,10 @@ struct SweepArgs {
     double D;
 };
 
+struct GaussTable {
+    double w[HELIOS_MAX_NG];  // weights on [0,1] (sum 1), ascending nodes
+};
+
 struct BolArgs {
     helios_atm atm;
     const void* part_up;  // partial sums from the sweep (double, or compensated float pairs)
@@ -96,7 +100,8 @@ hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s);
 hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double* T_c, double* T_pt,
                           hipStream_t s);
 hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, void* B,
-                         double* F_top, double* F_int, double* gw, bool mixed, hipStream_t s);
+                         double* F_top, double* F_int, double* gw, const GaussTable& gt, bool mixed,
+                         hipStream_t s);
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);
@@ -111,7 +116,7 @@ hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c,
 
 // Sweep instantiations available (sublayers per lane).
 constexpr int kSweepK[] = {4, 8, 14, 26};
-constexpr int kBolChunk = 64;  // bins per bolometric chunk
+constexpr int kBolChunk = 32;  // bins per bolometric chunk
 constexpr int kNumSweepK = 4;
 
 }  // namespace helios

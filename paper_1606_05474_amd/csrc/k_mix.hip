@@ -16,8 +16,8 @@
 
 namespace helios {
 
-constexpr int kMixPts = 16;
-constexpr int kMixCols = 256;
+constexpr int kMixPts = 32;
+constexpr int kMixCols = 128;
 
 struct MixArgs {
     helios_atm atm;
@@ -33,27 +33,33 @@ struct MixArgs {
     double mratio[HELIOS_MAX_SPECIES];  // m_j / mbar
 };
 
+// A workgroup owns kMixPts consecutive points of the concatenated point axis
+// (possibly straddling atmospheres) and kMixCols consecutive (bin, g)
+// columns.  Per point the table cell, corner weights and mass mixing ratios
+// are computed once (LDS).  Consecutive points usually fall in the same
+// (T, log P) cell; a thread keeps the cell's corner values of its column in
+// registers and reloads them only when the cell changes (a workgroup-uniform
+// decision).
 template <typename R>
 __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
-    __shared__ int s_atm[kMixPts], s_p[kMixPts], s_npt[kMixPts], s_ncol[kMixPts];
-    __shared__ int s_iT[kMixPts], s_iP[kMixPts];
-    __shared__ R s_w[kMixPts][4];                       // bilinear corner weights or power-law scale
-    __shared__ R s_x[kMixPts][HELIOS_MAX_SPECIES];      // mass mixing ratios
+    __shared__ int s_atm[kMixPts], s_p[kMixPts], s_npt[kMixPts], s_ncol[kMixPts], s_cell[kMixPts];
+    __shared__ R s_w[kMixPts][4];                   // bilinear corner weights or power-law scale
+    __shared__ R s_x[kMixPts][HELIOS_MAX_SPECIES];  // mass mixing ratios
     __shared__ R tile[kMixPts][kMixCols + 1];
 
     const int t = threadIdx.x;
     const int64_t p0 = (int64_t)blockIdx.x * kMixPts;
     const int c0 = blockIdx.y * kMixCols;
     if (t < kMixPts) {
-        int64_t gp = p0 + t;
+        const int64_t gp = p0 + t;
         if (gp < A.total_pt) {
-            int a = find_atm(A.atm.pt_off, A.atm.n_atm, gp);
-            int n = A.atm.n_layer[a];
+            const int a = find_atm(A.atm.pt_off, A.atm.n_atm, gp);
+            const int n = A.atm.n_layer[a];
             s_atm[t] = a;
             s_p[t] = (int)(gp - A.atm.pt_off[a]);
             s_npt[t] = 2 * n + 1;
             s_ncol[t] = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]) * A.ng;
-            double T = A.T_pt[gp], P = A.atm.P_pt[gp];
+            const double T = A.T_pt[gp], P = A.atm.P_pt[gp];
             for (int j = 0; j < A.n_species; ++j)
                 s_x[t][j] = (R)(A.vmr[(int64_t)j * A.total_pt + gp] * A.mratio[j]);
             if (A.mode == HELIOS_KTAB_TABLE) {
@@ -61,53 +67,73 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
                 double y = (log10(P) - A.logP_min) / A.logP_step;
                 x = fmin(fmax(x, 0.0), (double)(A.nT - 1));
                 y = fmin(fmax(y, 0.0), (double)(A.nP - 1));
-                int iT = min((int)floor(x), A.nT - 2);
-                int iP = min((int)floor(y), A.nP - 2);
-                double fT = x - iT, fP = y - iP;
-                s_iT[t] = iT;
-                s_iP[t] = iP;
+                const int iT = min((int)floor(x), A.nT - 2);
+                const int iP = min((int)floor(y), A.nP - 2);
+                const double fT = x - iT, fP = y - iP;
+                s_cell[t] = (a * A.nT + iT) * A.nP + iP;
                 s_w[t][0] = (R)((1.0 - fT) * (1.0 - fP));
                 s_w[t][1] = (R)((1.0 - fT) * fP);
                 s_w[t][2] = (R)(fT * (1.0 - fP));
                 s_w[t][3] = (R)(fT * fP);
             } else {
-                s_iT[t] = 0;
-                s_iP[t] = 0;
+                s_cell[t] = a;
                 s_w[t][0] = (R)(pow(P / A.P_ref, A.p_exp) * pow(T / A.T_ref, A.t_exp));
             }
         } else {
             s_atm[t] = -1;
             s_ncol[t] = 0;
+            s_cell[t] = -1;
         }
     }
     __syncthreads();
 
     const int c = c0 + t;
     const size_t row = (size_t)A.nbt * A.ng;  // one (species, T, P) corner row
-#pragma unroll 4
+    R kc[HELIOS_MAX_SPECIES][4];
+#pragma unroll
+    for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
+        kc[sp][0] = kc[sp][1] = kc[sp][2] = kc[sp][3] = (R)0;
+    int cur = -2;
     for (int j = 0; j < kMixPts; ++j) {
         R acc = (R)0;
-        if (s_atm[j] >= 0 && c < s_ncol[j]) {
-            const int a = s_atm[j];
-            const int l = c / A.ng, g = c - l * A.ng;
-            // a bad caller index must not read outside the table
-            const int bt = min(max(A.atm.bin_index[A.atm.bin_off[a] + l], 0), A.nbt - 1);
-            const size_t off = (size_t)bt * A.ng + g;
+        const int a = s_atm[j];
+        if (a >= 0 && s_cell[j] != cur) {  // uniform: load the new cell's corners
+            cur = s_cell[j];
+            if (c < s_ncol[j]) {
+                const int l = c / A.ng, g = c - l * A.ng;
+                // a bad caller index must not read outside the table
+                const int bt = min(max(A.atm.bin_index[A.atm.bin_off[a] + l], 0), A.nbt - 1);
+                const size_t off = (size_t)bt * A.ng + g;
+                if (A.mode == HELIOS_KTAB_TABLE) {
+                    const int cell = cur - a * A.nT * A.nP;  // iT * nP + iP
+#pragma unroll
+                    for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp) {
+                        if (sp < A.n_species) {
+                            const float* kb = A.k + ((size_t)sp * A.nT * A.nP + cell) * row + off;
+                            kc[sp][0] = (R)kb[0];
+                            kc[sp][1] = (R)kb[row];
+                            kc[sp][2] = (R)kb[(size_t)A.nP * row];
+                            kc[sp][3] = (R)kb[(size_t)(A.nP + 1) * row];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
+                        if (sp < A.n_species) kc[sp][0] = (R)A.k0[(size_t)sp * row + off];
+                }
+            }
+        }
+        if (a >= 0 && c < s_ncol[j]) {
             if (A.mode == HELIOS_KTAB_TABLE) {
                 const R w00 = s_w[j][0], w01 = s_w[j][1], w10 = s_w[j][2], w11 = s_w[j][3];
-                const size_t cT0 = (size_t)s_iT[j] * A.nP + s_iP[j];
-                for (int sp = 0; sp < A.n_species; ++sp) {
-                    const float* kb = A.k + ((size_t)sp * A.nT * A.nP + cT0) * row + off;
-                    R k00 = (R)kb[0];
-                    R k01 = (R)kb[row];
-                    R k10 = (R)kb[(size_t)A.nP * row];
-                    R k11 = (R)kb[(size_t)(A.nP + 1) * row];
-                    R kj = w00 * k00 + w01 * k01 + w10 * k10 + w11 * k11;
-                    acc += s_x[j][sp] * kj;
-                }
+#pragma unroll
+                for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
+                    if (sp < A.n_species)
+                        acc += s_x[j][sp] * (w00 * kc[sp][0] + w01 * kc[sp][1] + w10 * kc[sp][2] + w11 * kc[sp][3]);
             } else {
-                for (int sp = 0; sp < A.n_species; ++sp)
-                    acc += s_x[j][sp] * (R)A.k0[(size_t)sp * row + off];
+#pragma unroll
+                for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
+                    if (sp < A.n_species) acc += s_x[j][sp] * kc[sp][0];
                 acc *= s_w[j][0];
             }
         }

@@ -82,44 +82,12 @@ __global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __
 // (T_irr/T_star)^4 pi B(T_star); BOA pi B(T_int) scaled so that its
 // width-weighted sum over the model's bins is sigma T_int^4.  The scale's sum
 // is a fixed-order tree in LDS.
-// Gauss-Legendre weight w_g/2 of node g (ascending nodes (1+y_g)/2 on [0,1],
-// Sec. 2.3), from Newton's method on the Legendre three-term recurrence.
-__device__ double gauss_weight(int n, int g) {
-    const int i = n - 1 - g;  // roots are generated in descending order
-    double y = cos(kPi * (i + 0.75) / (n + 0.5));
-    double dp = 1.0;
-    for (int it = 0; it < 12; ++it) {
-        double a = 1.0, b = y;
-        for (int k = 2; k <= n; ++k) {
-            double c = ((2 * k - 1) * y * b - (k - 1) * a) / k;
-            a = b;
-            b = c;
-        }
-        if (n == 1) a = 1.0;
-        dp = n * (y * b - a) / (y * y - 1.0);
-        double step = b / dp;
-        y -= step;
-        if (fabs(step) < 4e-16 || it == 11) {
-            a = 1.0;
-            b = y;
-            for (int k = 2; k <= n; ++k) {
-                double c = ((2 * k - 1) * y * b - (k - 1) * a) / k;
-                a = b;
-                b = c;
-            }
-            if (n == 1) a = 1.0;
-            dp = n * (y * b - a) / (y * y - 1.0);
-            break;
-        }
-    }
-    return 1.0 / ((1.0 - y * y) * dp * dp);
-}
-
 __global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* __restrict__ F_top,
-                                                       double* __restrict__ F_int, double* __restrict__ gw) {
+                                                       double* __restrict__ F_int, double* __restrict__ gw,
+                                                       GaussTable gt) {
     __shared__ double red[256];
     int a = blockIdx.x;
-    if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gauss_weight(atm.n_g, threadIdx.x);
+    if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gt.w[threadIdx.x];
     int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
     int64_t b0 = atm.bin_off[a];
     double Ts = atm.T_star[a], Ti = atm.T_int[a];
@@ -146,7 +114,8 @@ __global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* _
 }
 
 hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, void* B,
-                         double* F_top, double* F_int, double* gw, bool mixed, hipStream_t s) {
+                         double* F_top, double* F_int, double* gw, const GaussTable& gt, bool mixed,
+                         hipStream_t s) {
     int block = 256;
     int64_t grid = (total_pb + block - 1) / block;
     if (mixed)
@@ -157,7 +126,7 @@ hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* 
                            T_pt, (double*)B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_top, F_int, gw);
+    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_top, F_int, gw, gt);
     return hipGetLastError();
 }
 
@@ -191,8 +160,9 @@ __device__ inline double combine_partials(const void* part, int64_t base, int wp
     return (double)acc.s + (double)acc.c;
 }
 
-__global__ void __launch_bounds__(256) bin_sum_kernel(const BolArgs A) {
-    __shared__ double red[4][64][4];
+// Stage 1 workgroup: 64 points x 16 groups of kBolChunk/16 consecutive bins.
+__global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
+    __shared__ double red[16][64][4];
     const int a = blockIdx.x;
     const int tile = blockIdx.y, ch = blockIdx.z;
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -200,20 +170,24 @@ __global__ void __launch_bounds__(256) bin_sum_kernel(const BolArgs A) {
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
     if (tile * 64 >= npt || ch * kBolChunk >= nb) return;  // uniform per workgroup
     const int p = tile * 64 + pl;
-    const int per = kBolChunk / 4;
-    const int l0 = ch * kBolChunk + q * per, l1 = min(nb, l0 + per);
+    constexpr int per = kBolChunk / 16;
+    const int l0 = ch * kBolChunk + q * per;
     nacc au = {0.0, 0.0}, ad = {0.0, 0.0};
     if (p < npt) {
         const double* dl = A.atm.dlambda + A.atm.bin_off[a];
         const int64_t pb = A.atm.pb_off[a];
-        for (int l = l0; l < l1; ++l) {
-            const int64_t base = pb * A.wpb + ((int64_t)l * A.wpb) * npt + p;
-            const double fu = combine_partials(A.part_up, base, A.wpb, npt, A.mixed);
-            const double fd = combine_partials(A.part_dn, base, A.wpb, npt, A.mixed);
-            A.F_up_bin[pb + (int64_t)l * npt + p] = fu;
-            A.F_dn_bin[pb + (int64_t)l * npt + p] = fd;
-            nadd(au, dl[l] * fu);
-            nadd(ad, dl[l] * fd);
+#pragma unroll
+        for (int i = 0; i < per; ++i) {
+            const int l = l0 + i;
+            if (l < nb) {
+                const int64_t base = pb * A.wpb + ((int64_t)l * A.wpb) * npt + p;
+                const double fu = combine_partials(A.part_up, base, A.wpb, npt, A.mixed);
+                const double fd = combine_partials(A.part_dn, base, A.wpb, npt, A.mixed);
+                A.F_up_bin[pb + (int64_t)l * npt + p] = fu;
+                A.F_dn_bin[pb + (int64_t)l * npt + p] = fd;
+                nadd(au, dl[l] * fu);
+                nadd(ad, dl[l] * fd);
+            }
         }
     }
     red[q][pl][0] = au.s;
@@ -224,7 +198,7 @@ __global__ void __launch_bounds__(256) bin_sum_kernel(const BolArgs A) {
     if (q == 0 && p < npt) {
         nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
         double cu = 0.0, cd = 0.0;
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 16; ++k) {
             nadd(tu, red[k][pl][0]);
             nadd(td, red[k][pl][2]);
             cu += red[k][pl][1];
@@ -238,36 +212,56 @@ __global__ void __launch_bounds__(256) bin_sum_kernel(const BolArgs A) {
     }
 }
 
-__global__ void bol_final_kernel(const BolArgs A, int64_t total_pt) {
-    const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gp >= total_pt) return;
-    const int a = find_atm(A.atm.pt_off, A.atm.n_atm, gp);
+// Stage 2 workgroup: 64 points x 16 groups; group q sums chunks q, q+16, ...
+// in order, then the 16 group sums are combined in order.
+__global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
+    __shared__ double red[16][64][4];
+    const int a = blockIdx.x, tile = blockIdx.y;
+    const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int npt = 2 * A.atm.n_layer[a] + 1;
+    if (tile * 64 >= npt) return;
+    const int p = tile * 64 + pl;
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
     const int nch = (nb + kBolChunk - 1) / kBolChunk;
-    const double* c = A.chunk + gp * A.n_chunk * 4;
     nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
     double cu = 0.0, cd = 0.0;
-    for (int k = 0; k < nch; ++k) {
-        nadd(tu, c[4 * k + 0]);
-        cu += c[4 * k + 1];
-        nadd(td, c[4 * k + 2]);
-        cd += c[4 * k + 3];
+    if (p < npt) {
+        const double* c = A.chunk + (A.atm.pt_off[a] + p) * A.n_chunk * 4;
+        for (int k = q; k < nch; k += 16) {
+            nadd(tu, c[4 * k + 0]);
+            cu += c[4 * k + 1];
+            nadd(td, c[4 * k + 2]);
+            cd += c[4 * k + 3];
+        }
     }
-    const double fu = tu.s + (tu.c + cu), fd = td.s + (td.c + cd);
-    double* o = A.F_bol + 3 * gp;
-    o[0] = fu;
-    o[1] = fd;
-    o[2] = fu - fd;
+    red[q][pl][0] = tu.s;
+    red[q][pl][1] = tu.c + cu;
+    red[q][pl][2] = td.s;
+    red[q][pl][3] = td.c + cd;
+    __syncthreads();
+    if (q == 0 && p < npt) {
+        nacc su = {0.0, 0.0}, sd = {0.0, 0.0};
+        double eu = 0.0, ed = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            nadd(su, red[k][pl][0]);
+            eu += red[k][pl][1];
+            nadd(sd, red[k][pl][2]);
+            ed += red[k][pl][3];
+        }
+        const double fu = su.s + (su.c + eu), fd = sd.s + (sd.c + ed);
+        double* o = A.F_bol + 3 * (A.atm.pt_off[a] + p);
+        o[0] = fu;
+        o[1] = fd;
+        o[2] = fu - fd;
+    }
 }
 
-hipError_t launch_bolometric(const BolArgs& a, int npt_max, int nb_max, int64_t total_pt, hipStream_t s) {
+hipError_t launch_bolometric(const BolArgs& a, int npt_max, int nb_max, int64_t /*total_pt*/, hipStream_t s) {
     dim3 grid(a.atm.n_atm, (npt_max + 63) / 64, (nb_max + kBolChunk - 1) / kBolChunk);
-    hipLaunchKernelGGL(bin_sum_kernel, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(bin_sum_kernel, grid, dim3(1024), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int block = 256;
-    hipLaunchKernelGGL(bol_final_kernel, dim3((unsigned)((total_pt + block - 1) / block)), dim3(block), 0, s, a,
-                       total_pt);
+    hipLaunchKernelGGL(bol_final_kernel, dim3(a.atm.n_atm, (npt_max + 63) / 64), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

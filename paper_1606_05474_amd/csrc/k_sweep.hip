@@ -129,6 +129,79 @@ __device__ inline void sub_coeffs(R dtau, R w0, R g0, R D, R Bu, R Bd, R& Tr, R&
     sub_coeffs_q<R>(q, dtau, D, Bu, Bd, Tr, a, c, su, sd);
 }
 
+// Shifts within a column's group of L lanes.  For L = 16 the group is one
+// DPP row, so row_shl/row_shr moves (out-of-row sources read 0) replace LDS
+// permutes; wider groups use shuffles (out-of-group sources read the own
+// value, which the callers never use).
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// value of lane seg + D of the group (TOA direction)
+template <int L, int D, typename R>
+__device__ inline R grp_down(R v) {
+    if constexpr (L == 16) return dpp_mov<0x100 + D>(v);
+    else return __shfl_down(v, (unsigned)D, L);
+}
+// value of lane seg - D of the group (BOA direction)
+template <int L, int D, typename R>
+__device__ inline R grp_up(R v) {
+    if constexpr (L == 16) return dpp_mov<0x110 + D>(v);
+    else return __shfl_up(v, (unsigned)D, L);
+}
+
+// One scan step of affine maps whose multipliers are pass-invariant:
+// MB <- mult * MB(partner) + MB.
+template <int L, int T, typename R>
+__device__ inline R scan_down_step(R MB, R mult) {
+    return mult * grp_down<L, (1 << T)>(MB) + MB;
+}
+template <int L, int T, typename R>
+__device__ inline R scan_up_step(R MB, R mult) {
+    return mult * grp_up<L, (1 << T)>(MB) + MB;
+}
+
+// Full scan step pairs (multiplier and offset) for when the multipliers are
+// not kept between passes.
+template <int L, int D, typename R>
+__device__ inline void down_pair(R& MA, R& MB, int seg) {
+    const R a2 = grp_down<L, D>(MA), b2 = grp_down<L, D>(MB);
+    const bool ok = seg + D < L;
+    MB = ok ? MA * b2 + MB : MB;
+    MA = ok ? MA * a2 : MA;
+}
+template <int L, int D, typename R>
+__device__ inline void up_pair(R& MA, R& MB, int seg) {
+    const R a2 = grp_up<L, D>(MA), b2 = grp_up<L, D>(MB);
+    const bool ok = seg >= D;
+    MB = ok ? MA * b2 + MB : MB;
+    MA = ok ? MA * a2 : MA;
+}
+template <int L, typename R>
+__device__ inline void scan_down_full(R& MA, R& MB, int seg) {
+    down_pair<L, 1>(MA, MB, seg);
+    down_pair<L, 2>(MA, MB, seg);
+    down_pair<L, 4>(MA, MB, seg);
+    down_pair<L, 8>(MA, MB, seg);
+    if constexpr (L > 16) down_pair<L, 16>(MA, MB, seg);
+}
+template <int L, typename R>
+__device__ inline void scan_up_full(R& MA, R& MB, int seg) {
+    up_pair<L, 1>(MA, MB, seg);
+    up_pair<L, 2>(MA, MB, seg);
+    up_pair<L, 4>(MA, MB, seg);
+    up_pair<L, 8>(MA, MB, seg);
+    if constexpr (L > 16) up_pair<L, 16>(MA, MB, seg);
+}
+
 // Partial g-sums of one point over the wave's columns (xor shuffles over
 // the column index); the first column's lanes hold the result.
 template <typename R>
@@ -249,29 +322,60 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             }
         }
 
+        // ---- pass-invariant parts of the column scans.  A segment's map is
+        // x -> P x + b with P the product of its a_s (the same for both sweeps
+        // and every pass).  The boundary values are folded into the end
+        // segments (top: F_dn = F_top; bottom: F_up = F_dn + F_int), so every
+        // scanned map ends up constant and only its offset b is scanned, with
+        // the multipliers precomputed here.
+        constexpr int LOG2L = (L == 16) ? 4 : 5;
+        // keep the multipliers in registers unless that would spill (wide FP64 segments)
+        constexpr bool PRECOMP = (sizeof(R) == 4) || (K <= 8);
+        R pseg = (R)1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) pseg *= ca[k];
+        R mdn[PRECOMP ? LOG2L : 1], mup[PRECOMP ? LOG2L : 1];
+        if constexpr (PRECOMP) {
+            R ma = (seg == L - 1) ? (R)0 : pseg;
+            R mb = (seg == 0) ? (R)0 : pseg;
+#pragma unroll
+            for (int t = 0; t < LOG2L; ++t) {
+                const int d = 1 << t;
+                R a2, b2;
+                if (t == 0) { a2 = grp_down<L, 1>(ma); b2 = grp_up<L, 1>(mb); }
+                else if (t == 1) { a2 = grp_down<L, 2>(ma); b2 = grp_up<L, 2>(mb); }
+                else if (t == 2) { a2 = grp_down<L, 4>(ma); b2 = grp_up<L, 4>(mb); }
+                else if (t == 3) { a2 = grp_down<L, 8>(ma); b2 = grp_up<L, 8>(mb); }
+                else { a2 = grp_down<L, 16>(ma); b2 = grp_up<L, 16>(mb); }
+                const bool okd = seg + d < L, oku = seg >= d;
+                mdn[t] = okd ? ma : (R)0;
+                mup[t] = oku ? mb : (R)0;
+                ma = okd ? ma * a2 : ma;
+                mb = oku ? mb * b2 : mb;
+            }
+        }
+        const R ftop_fold = pseg * Ftop;
+
         R ftoa = (R)0;
-        const int base = lane & ~(L - 1);  // seg 0 of this column
         for (int pass = 0; pass <= A.n_scat; ++pass) {
             const bool last = (pass == A.n_scat);
             // ---------------- downward sweep: compose my segment (top -> bottom)
-            R MA = (R)1, MB = (R)0;
+            R MB = (R)0;
 #pragma unroll
-            for (int k = K - 1; k >= 0; --k) {
-                MB = ca[k] * MB + (cc[k] * fu[k] + sd[k]);
-                MA = ca[k] * MA;
+            for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + (cc[k] * fu[k] + sd[k]);
+            if (seg == L - 1) MB = ftop_fold + MB;
+            if constexpr (PRECOMP) {  // suffix scan towards the BOA
+                MB = scan_down_step<L, 0>(MB, mdn[0]);
+                MB = scan_down_step<L, 1>(MB, mdn[1]);
+                MB = scan_down_step<L, 2>(MB, mdn[2]);
+                MB = scan_down_step<L, 3>(MB, mdn[3]);
+                if constexpr (LOG2L > 4) MB = scan_down_step<L, 4>(MB, mdn[LOG2L - 1]);
+            } else {
+                R MA = (seg == L - 1) ? (R)0 : pseg;
+                scan_down_full<L>(MA, MB, seg);
             }
-#pragma unroll
-            for (int d = 1; d < L; d <<= 1) {  // suffix scan towards the BOA
-                const R A2 = __shfl_down(MA, (unsigned)d, L), B2 = __shfl_down(MB, (unsigned)d, L);
-                if (seg + d < L) {
-                    MB = MA * B2 + MB;
-                    MA = MA * A2;
-                }
-            }
-            const R xbot = MA * Ftop + MB;
-            R xtop = __shfl_down(xbot, 1u, L);
-            if (seg == L - 1) xtop = Ftop;
-            R x = xtop;
+            R x = grp_down<L, 1>(MB);  // F_dn at my segment's top point
+            if (seg == L - 1) x = Ftop;
             if (last) {
                 const slot v = GS::template wave_reduce<L>((top_seg && colok) ? wg * Ftop : (R)0);
                 if (cw == 0 && top_seg) pdcol[nsub - lo] = v;
@@ -287,28 +391,25 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     if (k < cnt && fdcol) fdcol[k] = x;
                 }
             }
-            // ---------------- BOA: F_up(0) = F_dn(0) + F_int
-            const R y0 = __shfl(x, base, 64) + Fint;
-            // ---------------- upward sweep: compose (bottom -> top)
-            MA = (R)1;
+            // ---------------- upward sweep: compose (bottom -> top); the BOA
+            // condition F_up(0) = F_dn(0) + F_int lives in segment 0
+            const R y0 = x + Fint;  // meaningful in segment 0 only
             MB = (R)0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                MB = ca[k] * MB + bu[k];
-                MA = ca[k] * MA;
+            for (int k = 0; k < K; ++k) MB = ca[k] * MB + bu[k];
+            if (seg == 0) MB = pseg * y0 + MB;
+            if constexpr (PRECOMP) {  // prefix scan towards the TOA
+                MB = scan_up_step<L, 0>(MB, mup[0]);
+                MB = scan_up_step<L, 1>(MB, mup[1]);
+                MB = scan_up_step<L, 2>(MB, mup[2]);
+                MB = scan_up_step<L, 3>(MB, mup[3]);
+                if constexpr (LOG2L > 4) MB = scan_up_step<L, 4>(MB, mup[LOG2L - 1]);
+            } else {
+                R MA = (seg == 0) ? (R)0 : pseg;
+                scan_up_full<L>(MA, MB, seg);
             }
-#pragma unroll
-            for (int d = 1; d < L; d <<= 1) {  // prefix scan towards the TOA
-                const R A2 = __shfl_up(MA, (unsigned)d, L), B2 = __shfl_up(MB, (unsigned)d, L);
-                if (seg >= d) {
-                    MB = MA * B2 + MB;
-                    MA = MA * A2;
-                }
-            }
-            const R ytop = MA * y0 + MB;
-            R ybot = __shfl_up(ytop, 1u, L);
-            if (seg == 0) ybot = y0;
-            R y = ybot;
+            R y = grp_up<L, 1>(MB);  // F_up at my segment's bottom point
+            if (seg == 0) y = y0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 fu[k] = y;

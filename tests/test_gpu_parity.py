@@ -397,3 +397,29 @@ def test_errors_are_reported_and_nothing_runs():
     with pytest.raises(H.HeliosError) as e:
         H.flux(b, z, b.P_pt, z, pb, pb, bol, small_ws, n_scat=-1)
     assert e.value.code == -1
+
+
+SHAPES = [(K, L, prec) for K in (4, 8, 14, 26) for L in (16, 32) for prec in (0, 1)
+          if K * L >= 100 and not (prec == 0 and K > 14)]
+
+
+@pytest.mark.parametrize("K,L,prec", SHAPES)
+def test_flux_every_sweep_shape(K, L, prec, small_table, monkeypatch):
+    """Every compiled (sublayers per lane, lanes per column) instantiation of
+    the sweep gives the oracle's fluxes (FP64 1e-10, mixed 1e-4)."""
+    monkeypatch.setenv("HELIOS_SWEEP_K", str(K))
+    monkeypatch.setenv("HELIOS_SWEEP_L", str(L))
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(K * 100 + L)
+    atm = W.spectral_atmosphere(rng, 50, lc, dl, 7)
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
+    up_ref = np.zeros(kap.shape)
+    r = ref.flux(atm, kap, T, P, up_ref, n_scat=3)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), prec, n_scat=3)
+    if prec == 0:
+        _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+    else:
+        assert net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"]).max() < 1e-4
+        assert col_rel_error(b.split_cell(_np(F_up))[0], up_ref).max() < 1e-4
