@@ -310,6 +310,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     A.n_g = atm->n_g;
     A.wpb = waves_per_bin(atm->n_g, sh.L);
     A.n_scat = n_scat;
+    A.npt_max = z.npt_max;
     A.D = D;
     A.w_begin = 0;
     A.w_end = z.total_bin * A.wpb;

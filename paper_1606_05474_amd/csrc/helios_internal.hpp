@@ -77,6 +77,7 @@ struct SweepArgs {
     int32_t n_atm, n_g;
     int32_t wpb;          // waves per bin
     int32_t n_scat;
+    int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
     double D;
 };
 

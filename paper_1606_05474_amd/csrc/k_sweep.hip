@@ -52,28 +52,44 @@ struct Prec<double> {
         om = -em;
         T = 1.0 + em;
     }
-    __device__ static inline double rcp(double v) { return 1.0 / v; }
+    // reciprocal: hardware estimate refined by two Newton steps (the
+    // arguments here are well scaled: no denormals, no overflow)
+    __device__ static inline double rcp(double v) {
+        double r = __builtin_amdgcn_rcp(v);
+        double e = fma(-v, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-v, r, 1.0);
+        return fma(r, e, r);
+    }
     __device__ static inline double sqrt_(double v) { return sqrt(v); }
 };
 template <>
 struct Prec<float> {
+    // om = 1 - exp(-x): degree-6 Taylor polynomial below x = 0.25 (truncation
+    // below one float ulp), 1 - exp(-x) above (no cancellation there)
     __device__ static inline void t_om(float x, float& T, float& om) {
         T = __expf(-x);
-        om = -expm1f(-x);
+        float p = x * (-1.0f / 720.0f) + (1.0f / 120.0f);
+        p = x * p - (1.0f / 24.0f);
+        p = x * p + (1.0f / 6.0f);
+        p = x * p - 0.5f;
+        p = x * p + 1.0f;
+        om = (x < 0.25f) ? x * p : 1.0f - T;
     }
     __device__ static inline float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
-    __device__ static inline float sqrt_(float v) { return __builtin_sqrtf(v); }
+    // hardware square root (about 1 ulp), enough for the mixed path
+    __device__ static inline float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
 };
 
 // Per-layer quantities shared by a layer's two sublayers and all g.
 template <typename R>
 struct LayerQ {
-    R r, zp, zm, kx, f, purescat_gd;  // purescat_gd = D (1 - g0)/2 (used when w0 ~ 1)
+    R r, zp, zm, zpzm, kx, f, tpr, purescat_gd;  // tpr = 2 pi eps r; purescat_gd = D (1 - g0)/2
     bool purescat;
 };
 
 template <typename R>
-__device__ inline LayerQ<R> layer_q(R w0, R g0, R D) {
+__device__ inline LayerQ<R> layer_q(R w0, R g0, R D, R inv_D, R two_pi_eps) {
     LayerQ<R> q;
     const R one = (R)1;
     q.purescat = (one - w0) < (R)1e-6;
@@ -82,8 +98,10 @@ __device__ inline LayerQ<R> layer_q(R w0, R g0, R D) {
     q.r = Prec<R>::sqrt_((one - w0) * iomg);
     q.zp = (R)0.5 * (one + q.r);
     q.zm = (R)0.5 * (one - q.r);
-    q.kx = D * Prec<R>::sqrt_(omg * (one - w0));
-    q.f = iomg / D;  // eps / (1 - w0 g0)
+    q.zpzm = q.zp * q.zm;
+    q.kx = D * q.r * omg;  // D sqrt((1 - w0 g0)(1 - w0))
+    q.f = iomg * inv_D;  // eps / (1 - w0 g0)
+    q.tpr = two_pi_eps * q.r;
     q.purescat_gd = D * (one - g0) * (R)0.5;
     return q;
 }
@@ -91,42 +109,47 @@ __device__ inline LayerQ<R> layer_q(R w0, R g0, R D) {
 // Coefficients {T, a, c, S_up, S_dn} of one sublayer from its layer's
 // quantities, optical depth and end Planck values.  den = zp^2 - zm^2 T^2
 // factors as (zp - zm T)(zp + zm T), so one reciprocal serves all three
-// denominators.
+// denominators.  The pure-scattering override is evaluated only when some
+// lane of the wave needs it (a wave-uniform branch).
 template <typename R>
-__device__ inline void sub_coeffs_q(const LayerQ<R>& q, R dtau, R D, R Bu, R Bd, R& Tr, R& a, R& c, R& su,
-                                    R& sd) {
+__device__ inline void sub_coeffs_q(const LayerQ<R>& q, R dtau, R two_pi_eps, R Bu, R Bd, R& Tr, R& a, R& c,
+                                    R& su, R& sd) {
     const R one = (R)1;
-    const R two_pi_eps = (R)(2.0 * kPi) / D;
     R T, om;
     Prec<R>::t_om(q.kx * dtau, T, om);
     const R u = q.zp - q.zm * T, v = q.zp + q.zm * T;
     const R iden = Prec<R>::rcp(u * v);
-    R a_ = q.r * T * iden;
-    R c_ = q.zp * q.zm * om * (one + T) * iden;
-    R s_iso = two_pi_eps * (R)0.5 * (Bu + Bd) * q.r * om * u * iden;
-    const R gterm = q.f * (Bd - Bu) * Prec<R>::rcp(dtau) * om * v * iden;
+    const R omi = om * iden;
+    a = q.r * T * iden;
+    c = q.zpzm * (one + T) * omi;
+    const R s_iso = (R)0.5 * q.tpr * (Bu + Bd) * u * omi;
+    const R gterm = q.f * (Bd - Bu) * Prec<R>::rcp(dtau) * v * omi;
     const R e2 = q.zp + q.zm * T * T;
-    R su_ = two_pi_eps * (q.r * (Bu * e2 - Bd * T) * iden + gterm);
-    R sd_ = two_pi_eps * (q.r * (Bd * e2 - Bu * T) * iden - gterm);
+    const R tu = q.tpr * iden;
+    R su_ = tu * (Bu * e2 - Bd * T) + two_pi_eps * gterm;
+    R sd_ = tu * (Bd * e2 - Bu * T) - two_pi_eps * gterm;
     const bool iso = dtau < (R)1e-4;
-    su_ = iso ? s_iso : su_;
-    sd_ = iso ? s_iso : sd_;
-    // eq:purescat
-    const R gd = q.purescat_gd * dtau;
-    const R qq = gd * Prec<R>::rcp(one + gd);
-    Tr = q.purescat ? one : T;
-    a = q.purescat ? one - qq : a_;
-    c = q.purescat ? qq : c_;
-    su = q.purescat ? (R)0 : su_;
-    sd = q.purescat ? (R)0 : sd_;
+    su = iso ? s_iso : su_;
+    sd = iso ? s_iso : sd_;
+    Tr = T;
+    if (__any(q.purescat)) {  // eq:purescat
+        const R gd = q.purescat_gd * dtau;
+        const R qq = gd * Prec<R>::rcp(one + gd);
+        Tr = q.purescat ? one : Tr;
+        a = q.purescat ? one - qq : a;
+        c = q.purescat ? qq : c;
+        su = q.purescat ? (R)0 : su;
+        sd = q.purescat ? (R)0 : sd;
+    }
 }
 
 // Coefficients of one sublayer from (dtau, w0, g0): the inspection kernel's
 // entry to the same arithmetic.
 template <typename R>
 __device__ inline void sub_coeffs(R dtau, R w0, R g0, R D, R Bu, R Bd, R& Tr, R& a, R& c, R& su, R& sd) {
-    LayerQ<R> q = layer_q<R>(w0, g0, D);
-    sub_coeffs_q<R>(q, dtau, D, Bu, Bd, Tr, a, c, su, sd);
+    const R inv_D = (R)1 / D, tpe = (R)(2.0 * kPi) * inv_D;
+    LayerQ<R> q = layer_q<R>(w0, g0, D, inv_D, tpe);
+    sub_coeffs_q<R>(q, dtau, tpe, Bu, Bd, Tr, a, c, su, sd);
 }
 
 // Shifts within a column's group of L lanes.  For L = 16 the group is one
@@ -202,45 +225,51 @@ __device__ inline void scan_up_full(R& MA, R& MB, int seg) {
     if constexpr (L > 16) up_pair<L, 16>(MA, MB, seg);
 }
 
-// Partial g-sums of one point over the wave's columns (xor shuffles over
-// the column index); the first column's lanes hold the result.
+// Gauss partial sum of one point over the wave's ncols columns staged in
+// LDS (column stride npt), in column order; compensated pairs in FP32.
 template <typename R>
 struct GSum;
 template <>
 struct GSum<double> {
     using slot = double;
-    template <int L>
-    __device__ static inline slot wave_reduce(double v) {
-#pragma unroll
-        for (int d = L; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-        return v;
+    __device__ static inline slot col_sum(const double* col, int npt, int ncols, const double* w) {
+        double acc = 0.0;
+        for (int c = 0; c < ncols; ++c) acc += w[c] * col[c * npt];
+        return acc;
     }
 };
 template <>
 struct GSum<float> {
     using slot = fpair;
-    template <int L>
-    __device__ static inline slot wave_reduce(float v) {
-        fpair p = {v, 0.0f};
-#pragma unroll
-        for (int d = L; d < 64; d <<= 1) {
-            fpair o = {__shfl_xor(p.s, d, 64), __shfl_xor(p.c, d, 64)};
-            p = two_sum_add(p, o);
-        }
-        return p;
+    __device__ static inline slot col_sum(const float* col, int npt, int ncols, const float* w) {
+        fpair acc = {0.0f, 0.0f};
+        for (int c = 0; c < ncols; ++c) acc = two_sum_add(acc, fpair{w[c] * col[c * npt], 0.0f});
+        return acc;
     }
 };
 
 // One workgroup = one wave = C = 64/L columns (consecutive g of one bin) of
-// L lanes.  Wave j of bin l covers g in [j*C, j*C + C).  No LDS, no barrier:
-// the wave's Gauss partial sums go to the workspace and the bolometric
-// kernel combines the partials of a bin in fixed order.
+// L lanes.  Wave j of bin l covers g in [j*C, j*C + C); its C columns are
+// contiguous in the [bin][g][point] arrays, so the wave stages them (and
+// the bin's Planck values, sublayer column masses, w0 and g0) in LDS with
+// coalesced loads, and writes its outputs back through LDS the same way.
+// No barrier spans more than the wave; the Gauss partial sums go to the
+// workspace and the bolometric kernel combines a bin's partials in fixed order.
 template <int K, int L, typename R, int OCC>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using GS = GSum<R>;
     using slot = typename GS::slot;
     constexpr int C = 64 / L;
     static_assert(K % 2 == 0, "segments hold whole layers");
+    extern __shared__ unsigned char smem_raw[];
+    const int npt_max = A.npt_max;
+    R* s_kap = reinterpret_cast<R*>(smem_raw);  // [C][npt]   opacities, later partials / F_dn
+    R* s_fu = s_kap + C * npt_max;              // [C][npt]   warm start, later F_up
+    R* s_B = s_fu + C * npt_max;                // [npt]
+    R* s_dm = s_B + npt_max;                    // [npt - 1]  sublayer column masses
+    R* s_w0 = s_dm + npt_max;                   // [n]
+    R* s_g0 = s_w0 + npt_max / 2;               // [n]
+
     const int lane = threadIdx.x;
     const int seg = lane & (L - 1);
     const int cw = lane / L;
@@ -260,42 +289,56 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const int nsub = 2 * n, npt = nsub + 1;
         const int nact = (nsub + K - 1) / K;
         const int g = j * C + cw;
-        const bool colok = g < A.n_g;
+        const int ncols = min(C, A.n_g - j * C);  // columns of this wave
+        const bool colok = cw < ncols;
         const int lo = seg * K;
         const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // points owned (any column)
         const bool top_seg = (seg == nact - 1);                 // also owns the TOA point
         const int cnt = colok ? scnt : 0;
-        const int64_t cell = A.cell_off[at] + ((int64_t)l * A.n_g + (colok ? g : 0)) * npt;
+        const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * npt;  // first column
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
         const int64_t poff = (A.pb_off[at] * A.wpb) + ((int64_t)l * A.wpb + j) * npt;
         const double* __restrict__ P = A.P_pt + A.pt_off[at];
-        const double grav = A.grav[at];
+        const double igrav = 1.0 / A.grav[at];
         const R D = (R)A.D;
+        const R inv_D = (R)(1.0 / A.D);
+        const R tpe = (R)(2.0 * kPi / A.D);
         const R Ftop = (R)A.F_top[A.bin_off[at] + l];
         const R Fint = (R)A.F_int[A.bin_off[at] + l];
-        const R wg = colok ? (R)A.gw[g] : (R)0;
+        R wcol[C];  // Gauss weights of the wave's columns
+#pragma unroll
+        for (int c = 0; c < C; ++c) wcol[c] = (c < ncols) ? (R)A.gw[j * C + c] : (R)0;
 
-        // per-lane base pointers: every access below is base + small constant
-        const R* __restrict__ kcol = kap_all + cell + lo;
-        const R* __restrict__ Bcol = B_all + pb + lo;
-        const double* __restrict__ Pcol = P + lo;
-        R* __restrict__ fucol = Fu_all + cell + lo;
-        R* __restrict__ fdcol = Fd_all ? Fd_all + cell + lo : nullptr;
-        slot* __restrict__ pucol = part_up + poff + lo;
-        slot* __restrict__ pdcol = part_dn + poff + lo;
-        const double* __restrict__ w0l = A.w0 + lb + (lo >> 1);
-        const double* __restrict__ g0l = A.g0 + lb + (lo >> 1);
+        // ---- stage the wave's inputs in LDS (coalesced)
+        {
+            const int nc = ncols * npt;
+            const R* kb = kap_all + cell0;
+            const R* fb = Fu_all + cell0;
+            for (int i = lane; i < nc; i += 64) {
+                s_kap[i] = kb[i];
+                s_fu[i] = fb[i];
+            }
+            for (int i = lane; i < npt; i += 64) s_B[i] = B_all[pb + i];
+            for (int i = lane; i < nsub; i += 64) s_dm[i] = (R)((P[i] - P[i + 1]) * igrav);
+            for (int i = lane; i < n; i += 64) {
+                s_w0[i] = (R)A.w0[lb + i];
+                s_g0[i] = (R)A.g0[lb + i];
+            }
+        }
+        __syncthreads();
 
         // ---- sublayer coefficients and warm start (once per call)
         R ca[K], cc[K], su[K], sd[K], fu[K], bu[K];
         {
+            const R* kc = s_kap + cw * npt + lo;
+            const R* fc = s_fu + cw * npt + lo;
+            const R* Bc = s_B + lo;
+            const R* dmc = s_dm + lo;
             R kp = (R)0, Bp = (R)0;
-            double Pp = 1.0;
             if (cnt > 0) {
-                kp = kcol[0];
-                Bp = Bcol[0];
-                Pp = Pcol[0];
+                kp = kc[0];
+                Bp = Bc[0];
             }
             LayerQ<R> q;
 #pragma unroll
@@ -307,17 +350,15 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 fu[k] = (R)0;
                 bu[k] = (R)0;
                 if (k < cnt) {
-                    if ((k & 1) == 0) q = layer_q<R>((R)w0l[k >> 1], (R)g0l[k >> 1], D);
-                    const R kn = kcol[k + 1];
-                    const R Bn = Bcol[k + 1];
-                    const double Pn = Pcol[k + 1];
-                    const R dtau = (R)0.5 * (kp + kn) * (R)((Pp - Pn) / grav);
+                    if ((k & 1) == 0) q = layer_q<R>(s_w0[(lo + k) >> 1], s_g0[(lo + k) >> 1], D, inv_D, tpe);
+                    const R kn = kc[k + 1];
+                    const R Bn = Bc[k + 1];
+                    const R dtau = (R)0.5 * (kp + kn) * dmc[k];
                     R Tr;
-                    sub_coeffs_q<R>(q, dtau, D, Bn, Bp, Tr, ca[k], cc[k], su[k], sd[k]);
-                    fu[k] = fucol[k];
+                    sub_coeffs_q<R>(q, dtau, tpe, Bn, Bp, Tr, ca[k], cc[k], su[k], sd[k]);
+                    fu[k] = fc[k];
                     kp = kn;
                     Bp = Bn;
-                    Pp = Pn;
                 }
             }
         }
@@ -326,8 +367,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // x -> P x + b with P the product of its a_s (the same for both sweeps
         // and every pass).  The boundary values are folded into the end
         // segments (top: F_dn = F_top; bottom: F_up = F_dn + F_int), so every
-        // scanned map ends up constant and only its offset b is scanned, with
-        // the multipliers precomputed here.
+        // scanned map ends up constant and only its offset b is scanned.
         constexpr int LOG2L = (L == 16) ? 4 : 5;
         // keep the multipliers in registers unless that would spill (wide FP64 segments)
         constexpr bool PRECOMP = (sizeof(R) == 4) || (K <= 8);
@@ -376,20 +416,28 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             }
             R x = grp_down<L, 1>(MB);  // F_dn at my segment's top point
             if (seg == L - 1) x = Ftop;
-            if (last) {
-                const slot v = GS::template wave_reduce<L>((top_seg && colok) ? wg * Ftop : (R)0);
-                if (cw == 0 && top_seg) pdcol[nsub - lo] = v;
-                if (top_seg && colok && fdcol) fdcol[nsub - lo] = Ftop;
-            }
 #pragma unroll
             for (int k = K - 1; k >= 0; --k) {
                 bu[k] = cc[k] * x + su[k];
                 x = ca[k] * x + (cc[k] * fu[k] + sd[k]);
-                if (last) {
-                    const slot v = GS::template wave_reduce<L>((k < cnt) ? wg * x : (R)0);
-                    if (cw == 0 && k < scnt) pdcol[k] = v;
-                    if (k < cnt && fdcol) fdcol[k] = x;
+                if (last) sd[k] = x;  // sd[k] is dead from here on in the last pass
+            }
+            if (last) {
+                // downward fluxes of the final pass: staged in LDS, then the Gauss
+                // partials (column sums) and, optionally, the per-g values are
+                // stored coalesced
+                R* s_out = s_fu;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k < cnt) s_out[cw * npt + lo + k] = sd[k];
+                if (top_seg && colok) s_out[cw * npt + nsub] = Ftop;
+                __syncthreads();
+                for (int i = lane; i < npt; i += 64) part_dn[poff + i] = GS::col_sum(s_out + i, npt, ncols, wcol);
+                if (Fd_all) {
+                    R* db = Fd_all + cell0;
+                    for (int i = lane; i < ncols * npt; i += 64) db[i] = s_out[i];
                 }
+                __syncthreads();
             }
             // ---------------- upward sweep: compose (bottom -> top); the BOA
             // condition F_up(0) = F_dn(0) + F_int lives in segment 0
@@ -418,36 +466,51 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             ftoa = y;
         }
 
-        // ---- outputs: upward fluxes (warm start of the next call) and their partial g-sums
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const slot v = GS::template wave_reduce<L>((k < cnt) ? wg * fu[k] : (R)0);
-            if (cw == 0 && k < scnt) pucol[k] = v;
-            if (k < cnt) fucol[k] = fu[k];
-        }
+        // ---- outputs: upward fluxes (warm start of the next call) and their
+        // Gauss partials, staged in LDS and stored coalesced
         {
-            const slot v = GS::template wave_reduce<L>((top_seg && colok) ? wg * ftoa : (R)0);
-            if (cw == 0 && top_seg) pucol[nsub - lo] = v;
-            if (top_seg && colok) fucol[nsub - lo] = ftoa;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k < cnt) s_fu[cw * npt + lo + k] = fu[k];
+            if (top_seg && colok) s_fu[cw * npt + nsub] = ftoa;
+            __syncthreads();
+            for (int i = lane; i < npt; i += 64) part_up[poff + i] = GS::col_sum(s_fu + i, npt, ncols, wcol);
+            R* ub = Fu_all + cell0;
+            for (int i = lane; i < ncols * npt; i += 64) ub[i] = s_fu[i];
+            __syncthreads();
         }
     }
 }
 
-template <int K, int L, int OCC>
-static hipError_t launch_k(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
+// LDS bytes of one sweep workgroup.
+template <int L>
+static size_t sweep_lds(const SweepArgs& a, size_t rbytes) {
+    constexpr int C = 64 / L;
+    return (size_t)(2 * C * a.npt_max + 2 * a.npt_max + a.npt_max) * rbytes + 64;
+}
+
+// Occupancy hint (waves per SIMD) so the register arrays fit without spills.
+template <int K, bool F64>
+constexpr int sweep_occ() {
+    if (F64) return K <= 4 ? 3 : 2;
+    return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
+}
+
+template <int K, int L>
+static hipError_t launch_kp(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL((sweep_kernel<K, L, float, OCC>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, false>()>), dim3(grid), dim3(64),
+                           sweep_lds<L>(a, 4), s, a);
     else
-        hipLaunchKernelGGL((sweep_kernel<K, L, double, OCC>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, true>()>), dim3(grid), dim3(64),
+                           sweep_lds<L>(a, 8), s, a);
     return hipGetLastError();
 }
 
 template <int K>
 static hipError_t launch_kl(const SweepArgs& a, int L, bool mixed, int grid, hipStream_t s) {
-    // occupancy hint: two waves per SIMD for the widest segments, more for narrower ones
-    constexpr int OCC = (K >= 14) ? 2 : (K >= 8 ? 3 : 4);
-    if (L == 16) return launch_k<K, 16, OCC>(a, mixed, grid, s);
-    if (L == 32) return launch_k<K, 32, OCC>(a, mixed, grid, s);
+    if (L == 16) return launch_kp<K, 16>(a, mixed, grid, s);
+    if (L == 32) return launch_kp<K, 32>(a, mixed, grid, s);
     return hipErrorInvalidValue;
 }
 
