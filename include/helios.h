@@ -26,9 +26,12 @@
  *    bin arrays     [nb]           offset bin_off[a]
  *    bin x layer    [nb][n]        offset lb_off[a]
  *    bin x point    [nb][npt]      offset pb_off[a]
- *    cell arrays    [nb][ng][npt]  offset cell_off[a]   (one column per (bin, g))
+ *    cell arrays    [nb][ng][cs]   offset cell_off[a]   (one column per (bin, g))
  * where each *_off is the exclusive prefix sum of the per-atmosphere sizes,
- * with n_atm+1 entries.
+ * with n_atm+1 entries, and cs = npt rounded up to a multiple of
+ * HELIOS_CELL_ALIGN: a column's points start on a 128-byte boundary.  The
+ * cs - npt padding entries of a column are ignored on input and unspecified
+ * on output.
  */
 #ifndef HELIOS_H
 #define HELIOS_H
@@ -57,6 +60,7 @@ extern "C" {
 #define HELIOS_MAX_SPECIES 8
 #define HELIOS_MAX_NG 32
 #define HELIOS_MAX_LAYERS 400
+#define HELIOS_CELL_ALIGN 32
 
 typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;
 typedef enum { HELIOS_KTAB_TABLE = 0, HELIOS_KTAB_POWERLAW = 1 } helios_ktab_mode;
@@ -152,8 +156,9 @@ int helios_mix_opacity(const helios_atm* atm, const helios_ktab* kt, const doubl
  * for every (bin, g, sublayer s) five doubles {Trans, a, c, S_up, S_dn} with
  *   F_up(s+1) = a F_up(s) + c F_dn(s+1) + S_up
  *   F_dn(s)   = a F_dn(s+1) + c F_up(s) + S_dn
- * out: [sum over atmospheres nb*ng*2n][5] in cell order with 2n sublayers per
- * column.  The flux sweep computes the same values in registers. */
+ * out: [sum over atmospheres nb*ng*2n][5] in (atmosphere, bin, g, sublayer)
+ * order (offset 2*ng*lb_off[a]).  The flux sweep computes the same values in
+ * registers. */
 int helios_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,
                         const double* w0, const double* g0, double D, double* out,
                         helios_prec prec, void* stream);

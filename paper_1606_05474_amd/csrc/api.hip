@@ -58,7 +58,7 @@ int check_atm(const helios_atm* atm, Sizes& z) {
         z.total_bin += nb;
         z.total_lb += (int64_t)nb * n;
         z.total_pb += (int64_t)nb * npt;
-        z.total_cell += (int64_t)nb * atm->n_g * npt;
+        z.total_cell += (int64_t)nb * atm->n_g * col_stride(n);
         z.n_max = std::max(z.n_max, n);
         z.npt_max = std::max(z.npt_max, npt);
         z.nb_max = std::max(z.nb_max, nb);
@@ -244,7 +244,7 @@ int helios_transmission(const helios_atm* atm, const void* kappa, const double* 
     if (!kappa || !T_pt || !w0 || !g0 || !out) return fail(HELIOS_EINVAL, "helios_transmission: NULL argument");
     if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
     if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
-    int64_t total_sub = z.total_cell - (int64_t)atm->n_g * z.total_bin;
+    int64_t total_sub = 2 * (int64_t)atm->n_g * z.total_lb;
     hipError_t e = launch_transmission(atm, kappa, T_pt, w0, g0, D, out, total_sub, prec == HELIOS_MIXED,
                                        (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "helios_transmission");

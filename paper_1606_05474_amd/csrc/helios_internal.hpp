@@ -21,6 +21,11 @@ __host__ __device__ inline double sigma_sb() {
     return 2.0 * pi2 * pi2 * kPi * k2 * k2 / (15.0 * kH * kH * kH * kC * kC);
 }
 
+// Column stride of the cell arrays: 2n+1 points rounded up to HELIOS_CELL_ALIGN.
+__host__ __device__ inline int col_stride(int n) {
+    return ((2 * n + 1) + HELIOS_CELL_ALIGN - 1) & ~(HELIOS_CELL_ALIGN - 1);
+}
+
 // Index of the atmosphere owning global element idx: the largest a with
 // off[a] <= idx (off has n_atm+1 non-decreasing entries).
 __device__ inline int find_atm(const int64_t* __restrict__ off, int n_atm, int64_t idx) {

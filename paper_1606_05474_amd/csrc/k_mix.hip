@@ -3,21 +3,23 @@
 // with k_j bilinear in (T, log10 P) on a uniform table grid, coordinates
 // clamped to the table, or a power law in P and T.
 //
-// Work decomposition: a workgroup owns 16 consecutive points of the
-// concatenated point axis (possibly straddling two atmospheres) and 256
-// consecutive (bin, g) columns.  Per point, the interpolation weights and
-// mass mixing ratios are computed once and kept in LDS.  For a fixed point,
-// the 256 threads read consecutive (bin, g) entries of each table corner row
-// (coalesced, contiguous when bin_index is), and neighbouring points of one
-// workgroup reuse the same corner rows through the caches.  Results go
-// through an LDS tile so that each column's 16 points are written as one
-// contiguous run in the [bin][g][pt] output.
+// Work decomposition: a workgroup owns one aligned chunk of kMixPts points of
+// one atmosphere and kMixCols consecutive (bin, g) columns; each thread is
+// one column.  Per point the table cell, corner weights and mass mixing
+// ratios are computed once (LDS).  Consecutive points usually fall in the
+// same (T, log P) cell: a thread keeps the cell's corner values of its column
+// in registers and reloads them only when the cell changes (a
+// workgroup-uniform decision).  For a fixed point the threads read
+// consecutive (bin, g) entries of each corner row (coalesced).  A thread's
+// kMixPts results are one or two whole aligned 128-byte lines of its column
+// (the column stride is padded to a multiple of kMixPts) and are written
+// with vector stores.
 #include "helios_internal.hpp"
 
 namespace helios {
 
-constexpr int kMixPts = 32;
-constexpr int kMixCols = 128;
+constexpr int kMixPts = HELIOS_CELL_ALIGN;
+constexpr int kMixCols = 256;
 
 struct MixArgs {
     helios_atm atm;
@@ -28,132 +30,125 @@ struct MixArgs {
     void* kappa;
     int64_t total_pt;
     int32_t mode, n_species, nT, nP, nbt, ng;
+    int32_t max_chunks;  // chunks of kMixPts points per atmosphere (largest)
     double T_min, T_step, logP_min, logP_step;
     double p_exp, t_exp, P_ref, T_ref;
     double mratio[HELIOS_MAX_SPECIES];  // m_j / mbar
 };
 
-// A workgroup owns kMixPts consecutive points of the concatenated point axis
-// (possibly straddling atmospheres) and kMixCols consecutive (bin, g)
-// columns.  Per point the table cell, corner weights and mass mixing ratios
-// are computed once (LDS).  Consecutive points usually fall in the same
-// (T, log P) cell; a thread keeps the cell's corner values of its column in
-// registers and reloads them only when the cell changes (a workgroup-uniform
-// decision).
 template <typename R>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float4;
+    static constexpr int per = 4;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+    static constexpr int per = 2;
+};
+
+template <typename R, int NSP>
 __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
-    __shared__ int s_atm[kMixPts], s_p[kMixPts], s_npt[kMixPts], s_ncol[kMixPts], s_cell[kMixPts];
-    __shared__ R s_w[kMixPts][4];                   // bilinear corner weights or power-law scale
-    __shared__ R s_x[kMixPts][HELIOS_MAX_SPECIES];  // mass mixing ratios
-    __shared__ R tile[kMixPts][kMixCols + 1];
+    __shared__ int s_cell[kMixPts];
+    __shared__ R s_w[kMixPts][4];    // bilinear corner weights or power-law scale
+    __shared__ R s_x[kMixPts][NSP];  // mass mixing ratios
 
     const int t = threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * kMixPts;
-    const int c0 = blockIdx.y * kMixCols;
-    if (t < kMixPts) {
-        const int64_t gp = p0 + t;
-        if (gp < A.total_pt) {
-            const int a = find_atm(A.atm.pt_off, A.atm.n_atm, gp);
-            const int n = A.atm.n_layer[a];
-            s_atm[t] = a;
-            s_p[t] = (int)(gp - A.atm.pt_off[a]);
-            s_npt[t] = 2 * n + 1;
-            s_ncol[t] = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]) * A.ng;
-            const double T = A.T_pt[gp], P = A.atm.P_pt[gp];
-            for (int j = 0; j < A.n_species; ++j)
-                s_x[t][j] = (R)(A.vmr[(int64_t)j * A.total_pt + gp] * A.mratio[j]);
-            if (A.mode == HELIOS_KTAB_TABLE) {
-                double x = (T - A.T_min) / A.T_step;
-                double y = (log10(P) - A.logP_min) / A.logP_step;
-                x = fmin(fmax(x, 0.0), (double)(A.nT - 1));
-                y = fmin(fmax(y, 0.0), (double)(A.nP - 1));
-                const int iT = min((int)floor(x), A.nT - 2);
-                const int iP = min((int)floor(y), A.nP - 2);
-                const double fT = x - iT, fP = y - iP;
-                s_cell[t] = (a * A.nT + iT) * A.nP + iP;
-                s_w[t][0] = (R)((1.0 - fT) * (1.0 - fP));
-                s_w[t][1] = (R)((1.0 - fT) * fP);
-                s_w[t][2] = (R)(fT * (1.0 - fP));
-                s_w[t][3] = (R)(fT * fP);
-            } else {
-                s_cell[t] = a;
-                s_w[t][0] = (R)(pow(P / A.P_ref, A.p_exp) * pow(T / A.T_ref, A.t_exp));
-            }
+    const int a = blockIdx.x / A.max_chunks;
+    const int ch = blockIdx.x - a * A.max_chunks;
+    const int n = A.atm.n_layer[a];
+    const int npt = 2 * n + 1;
+    const int p0 = ch * kMixPts;
+    if (p0 >= npt) return;  // uniform: past this atmosphere's points
+    const int ncol = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]) * A.ng;
+    const int c = blockIdx.y * kMixCols + t;
+    if ((int)blockIdx.y * kMixCols >= ncol) return;  // uniform: past this atmosphere's columns
+    const int npts = min(kMixPts, npt - p0);        // valid points of the chunk
+    if (t < npts) {
+        const int64_t gp = A.atm.pt_off[a] + p0 + t;
+        const double T = A.T_pt[gp], P = A.atm.P_pt[gp];
+        for (int j = 0; j < NSP; ++j)
+            s_x[t][j] = (j < A.n_species) ? (R)(A.vmr[(int64_t)j * A.total_pt + gp] * A.mratio[j]) : (R)0;
+        if (A.mode == HELIOS_KTAB_TABLE) {
+            double x = (T - A.T_min) / A.T_step;
+            double y = (log10(P) - A.logP_min) / A.logP_step;
+            x = fmin(fmax(x, 0.0), (double)(A.nT - 1));
+            y = fmin(fmax(y, 0.0), (double)(A.nP - 1));
+            const int iT = min((int)floor(x), A.nT - 2);
+            const int iP = min((int)floor(y), A.nP - 2);
+            const double fT = x - iT, fP = y - iP;
+            s_cell[t] = iT * A.nP + iP;
+            s_w[t][0] = (R)((1.0 - fT) * (1.0 - fP));
+            s_w[t][1] = (R)((1.0 - fT) * fP);
+            s_w[t][2] = (R)(fT * (1.0 - fP));
+            s_w[t][3] = (R)(fT * fP);
         } else {
-            s_atm[t] = -1;
-            s_ncol[t] = 0;
-            s_cell[t] = -1;
+            s_cell[t] = 0;
+            s_w[t][0] = (R)(pow(P / A.P_ref, A.p_exp) * pow(T / A.T_ref, A.t_exp));
         }
     }
     __syncthreads();
+    if (c >= ncol) return;
 
-    const int c = c0 + t;
+    const int l = c / A.ng, g = c - l * A.ng;
+    // a bad caller index must not read outside the table
+    const int bt = min(max(A.atm.bin_index[A.atm.bin_off[a] + l], 0), A.nbt - 1);
     const size_t row = (size_t)A.nbt * A.ng;  // one (species, T, P) corner row
-    R kc[HELIOS_MAX_SPECIES][4];
+    const size_t off = (size_t)bt * A.ng + g;
+    R kc[NSP][4];
+    R vals[kMixPts];
+    int cur = -1;
 #pragma unroll
-    for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
-        kc[sp][0] = kc[sp][1] = kc[sp][2] = kc[sp][3] = (R)0;
-    int cur = -2;
     for (int j = 0; j < kMixPts; ++j) {
         R acc = (R)0;
-        const int a = s_atm[j];
-        if (a >= 0 && s_cell[j] != cur) {  // uniform: load the new cell's corners
-            cur = s_cell[j];
-            if (c < s_ncol[j]) {
-                const int l = c / A.ng, g = c - l * A.ng;
-                // a bad caller index must not read outside the table
-                const int bt = min(max(A.atm.bin_index[A.atm.bin_off[a] + l], 0), A.nbt - 1);
-                const size_t off = (size_t)bt * A.ng + g;
-                if (A.mode == HELIOS_KTAB_TABLE) {
-                    const int cell = cur - a * A.nT * A.nP;  // iT * nP + iP
-#pragma unroll
-                    for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp) {
-                        if (sp < A.n_species) {
-                            const float* kb = A.k + ((size_t)sp * A.nT * A.nP + cell) * row + off;
-                            kc[sp][0] = (R)kb[0];
-                            kc[sp][1] = (R)kb[row];
-                            kc[sp][2] = (R)kb[(size_t)A.nP * row];
-                            kc[sp][3] = (R)kb[(size_t)(A.nP + 1) * row];
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
-                        if (sp < A.n_species) kc[sp][0] = (R)A.k0[(size_t)sp * row + off];
-                }
-            }
-        }
-        if (a >= 0 && c < s_ncol[j]) {
+        if (j < npts) {
             if (A.mode == HELIOS_KTAB_TABLE) {
+                if (s_cell[j] != cur) {  // uniform: load the new cell's corners
+                    cur = s_cell[j];
+#pragma unroll
+                    for (int sp = 0; sp < NSP; ++sp) {
+                        const float* kb = A.k + ((size_t)sp * A.nT * A.nP + cur) * row + off;
+                        const bool ok = sp < A.n_species;
+                        kc[sp][0] = ok ? (R)kb[0] : (R)0;
+                        kc[sp][1] = ok ? (R)kb[row] : (R)0;
+                        kc[sp][2] = ok ? (R)kb[(size_t)A.nP * row] : (R)0;
+                        kc[sp][3] = ok ? (R)kb[(size_t)(A.nP + 1) * row] : (R)0;
+                    }
+                }
                 const R w00 = s_w[j][0], w01 = s_w[j][1], w10 = s_w[j][2], w11 = s_w[j][3];
 #pragma unroll
-                for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
-                    if (sp < A.n_species)
-                        acc += s_x[j][sp] * (w00 * kc[sp][0] + w01 * kc[sp][1] + w10 * kc[sp][2] + w11 * kc[sp][3]);
+                for (int sp = 0; sp < NSP; ++sp)
+                    acc += s_x[j][sp] * (w00 * kc[sp][0] + w01 * kc[sp][1] + w10 * kc[sp][2] + w11 * kc[sp][3]);
             } else {
+                if (cur < 0) {
+                    cur = 0;
 #pragma unroll
-                for (int sp = 0; sp < HELIOS_MAX_SPECIES; ++sp)
-                    if (sp < A.n_species) acc += s_x[j][sp] * kc[sp][0];
+                    for (int sp = 0; sp < NSP; ++sp)
+                        kc[sp][0] = (sp < A.n_species) ? (R)A.k0[(size_t)sp * row + off] : (R)0;
+                }
+#pragma unroll
+                for (int sp = 0; sp < NSP; ++sp) acc += s_x[j][sp] * kc[sp][0];
                 acc *= s_w[j][0];
             }
         }
-        tile[j][t] = acc;
+        vals[j] = acc;
     }
-    __syncthreads();
-
-    R* out = (R*)A.kappa;
-    for (int e = t; e < kMixPts * kMixCols; e += kMixCols) {
-        const int cl = e / kMixPts, j = e - cl * kMixPts;
-        const int cc = c0 + cl;
-        if (s_atm[j] >= 0 && cc < s_ncol[j]) {
-            const int a = s_atm[j];
-            out[A.atm.cell_off[a] + (int64_t)cc * s_npt[j] + s_p[j]] = tile[j][cl];
-        }
+    using V = typename Vec2<R>::type;
+    constexpr int per = Vec2<R>::per;
+    V* dst = reinterpret_cast<V*>(static_cast<R*>(A.kappa) + A.atm.cell_off[a] + (int64_t)c * col_stride(n) + p0);
+#pragma unroll
+    for (int v = 0; v < kMixPts / per; ++v) {
+        V w;
+        if constexpr (per == 4) w = V{vals[4 * v], vals[4 * v + 1], vals[4 * v + 2], vals[4 * v + 3]};
+        else w = V{vals[2 * v], vals[2 * v + 1]};
+        dst[v] = w;
     }
 }
 
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
-                      void* kappa, bool mixed, int64_t total_pt, const int32_t* /*n_layer_h*/,
+                      void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s) {
     MixArgs A;
     A.atm = *atm;
@@ -179,13 +174,21 @@ hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double
     A.T_ref = kt->T_ref;
     for (int j = 0; j < HELIOS_MAX_SPECIES; ++j)
         A.mratio[j] = (j < kt->n_species) ? kt->species_mass[j] / kt->mmw : 0.0;
-    int max_cols = 0;
-    for (int a = 0; a < atm->n_atm; ++a) max_cols = max(max_cols, n_bin_h[a] * kt->n_g);
-    dim3 grid((unsigned)((total_pt + kMixPts - 1) / kMixPts), (unsigned)((max_cols + kMixCols - 1) / kMixCols));
-    if (mixed)
-        hipLaunchKernelGGL(mix_kernel<float>, grid, dim3(kMixCols), 0, s, A);
-    else
-        hipLaunchKernelGGL(mix_kernel<double>, grid, dim3(kMixCols), 0, s, A);
+    int max_cols = 0, max_chunks = 1;
+    for (int a = 0; a < atm->n_atm; ++a) {
+        max_cols = max(max_cols, n_bin_h[a] * kt->n_g);
+        max_chunks = max(max_chunks, col_stride(n_layer_h[a]) / kMixPts);
+    }
+    A.max_chunks = max_chunks;
+    dim3 grid((unsigned)(atm->n_atm * max_chunks), (unsigned)((max_cols + kMixCols - 1) / kMixCols));
+    const bool few = kt->n_species <= 4;
+    if (mixed) {
+        if (few) hipLaunchKernelGGL((mix_kernel<float, 4>), grid, dim3(kMixCols), 0, s, A);
+        else hipLaunchKernelGGL((mix_kernel<float, HELIOS_MAX_SPECIES>), grid, dim3(kMixCols), 0, s, A);
+    } else {
+        if (few) hipLaunchKernelGGL((mix_kernel<double, 4>), grid, dim3(kMixCols), 0, s, A);
+        else hipLaunchKernelGGL((mix_kernel<double, HELIOS_MAX_SPECIES>), grid, dim3(kMixCols), 0, s, A);
+    }
     return hipGetLastError();
 }
 

@@ -295,7 +295,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // points owned (any column)
         const bool top_seg = (seg == nact - 1);                 // also owns the TOA point
         const int cnt = colok ? scnt : 0;
-        const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * npt;  // first column
+        const int cs = col_stride(n);
+        const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * cs;  // first column
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
         const int64_t poff = (A.pb_off[at] * A.wpb) + ((int64_t)l * A.wpb + j) * npt;
@@ -312,12 +313,13 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 
         // ---- stage the wave's inputs in LDS (coalesced)
         {
-            const int nc = ncols * npt;
-            const R* kb = kap_all + cell0;
-            const R* fb = Fu_all + cell0;
-            for (int i = lane; i < nc; i += 64) {
-                s_kap[i] = kb[i];
-                s_fu[i] = fb[i];
+            for (int cc = 0; cc < ncols; ++cc) {
+                const R* kb = kap_all + cell0 + (int64_t)cc * cs;
+                const R* fb = Fu_all + cell0 + (int64_t)cc * cs;
+                for (int i = lane; i < npt; i += 64) {
+                    s_kap[cc * npt + i] = kb[i];
+                    s_fu[cc * npt + i] = fb[i];
+                }
             }
             for (int i = lane; i < npt; i += 64) s_B[i] = B_all[pb + i];
             for (int i = lane; i < nsub; i += 64) s_dm[i] = (R)((P[i] - P[i + 1]) * igrav);
@@ -434,8 +436,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 __syncthreads();
                 for (int i = lane; i < npt; i += 64) part_dn[poff + i] = GS::col_sum(s_out + i, npt, ncols, wcol);
                 if (Fd_all) {
-                    R* db = Fd_all + cell0;
-                    for (int i = lane; i < ncols * npt; i += 64) db[i] = s_out[i];
+                    for (int cc = 0; cc < ncols; ++cc) {
+                        R* db = Fd_all + cell0 + (int64_t)cc * cs;
+                        for (int i = lane; i < npt; i += 64) db[i] = s_out[cc * npt + i];
+                    }
                 }
                 __syncthreads();
             }
@@ -475,8 +479,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             if (top_seg && colok) s_fu[cw * npt + nsub] = ftoa;
             __syncthreads();
             for (int i = lane; i < npt; i += 64) part_up[poff + i] = GS::col_sum(s_fu + i, npt, ncols, wcol);
-            R* ub = Fu_all + cell0;
-            for (int i = lane; i < ncols * npt; i += 64) ub[i] = s_fu[i];
+            for (int cc = 0; cc < ncols; ++cc) {
+                R* ub = Fu_all + cell0 + (int64_t)cc * cs;
+                for (int i = lane; i < npt; i += 64) ub[i] = s_fu[cc * npt + i];
+            }
             __syncthreads();
         }
     }
@@ -533,19 +539,19 @@ __global__ void transmission_kernel(helios_atm atm, const R* __restrict__ kap, c
                                     double* __restrict__ out, int64_t total_sub) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total_sub) return;
-    // sub offsets: cell_off[a] - n_g * bin_off[a] counts nb*ng*2n per atmosphere
+    // sublayer-cell offsets: nb*ng*2n per atmosphere = 2 ng lb_off
     int lo = 0, hi = atm.n_atm;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (atm.cell_off[mid] - (int64_t)atm.n_g * atm.bin_off[mid] <= idx) lo = mid; else hi = mid;
+        if (2 * (int64_t)atm.n_g * atm.lb_off[mid] <= idx) lo = mid; else hi = mid;
     }
     const int a = lo;
-    const int64_t rel = idx - (atm.cell_off[a] - (int64_t)atm.n_g * atm.bin_off[a]);
-    const int n = atm.n_layer[a], nsub = 2 * n, npt = nsub + 1;
+    const int64_t rel = idx - 2 * (int64_t)atm.n_g * atm.lb_off[a];
+    const int n = atm.n_layer[a], nsub = 2 * n;
     const int64_t colx = rel / nsub;
     const int s = (int)(rel - colx * nsub);
     const int l = (int)(colx / atm.n_g);
-    const int64_t cell = atm.cell_off[a] + colx * npt;
+    const int64_t cell = atm.cell_off[a] + colx * col_stride(n);
     const double* P = atm.P_pt + atm.pt_off[a];
     const double lam = atm.lambda_c[atm.bin_off[a] + l];
     const R Bd = (R)planck_d(lam, T_pt[atm.pt_off[a] + s]);

@@ -28,6 +28,7 @@ KTAB_TABLE, KTAB_POWERLAW = 0, 1
 NORM_SIGMA_T4, NORM_SIGMA_TINT4 = 0, 1
 ATM_RUNNING, ATM_CONVERGED, ATM_NUMERIC = 0, 1, -5
 MAX_SPECIES = 8
+CELL_ALIGN = 32  # column stride of the cell arrays: 2n+1 rounded up to this
 
 _P = ctypes.c_void_p
 
@@ -137,13 +138,14 @@ class Batch:
         n = np.array([int(a["n"]) for a in atms], np.int64)
         nb = np.array([len(a["lambda_c"]) for a in atms], np.int64)
         npt = 2 * n + 1
-        self.n, self.nb, self.npt = n, nb, npt
+        cs = (npt + CELL_ALIGN - 1) // CELL_ALIGN * CELL_ALIGN
+        self.n, self.nb, self.npt, self.cs = n, nb, npt, cs
 
         def off(x):
             return np.concatenate([[0], np.cumsum(x)]).astype(np.int64)
 
         self.lay_off, self.pt_off, self.bin_off = off(n), off(npt), off(nb)
-        self.lb_off, self.pb_off, self.cell_off = off(nb * n), off(nb * npt), off(nb * self.ng * npt)
+        self.lb_off, self.pb_off, self.cell_off = off(nb * n), off(nb * npt), off(nb * self.ng * cs)
         self.total_n, self.total_pt = int(self.lay_off[-1]), int(self.pt_off[-1])
         self.total_bin, self.total_cell = int(self.bin_off[-1]), int(self.cell_off[-1])
         self.total_lb, self.total_pb = int(self.lb_off[-1]), int(self.pb_off[-1])
@@ -188,8 +190,17 @@ class Batch:
         return [x[self.lay_off[a]:self.lay_off[a + 1]] for a in range(self.n_atm)]
 
     def split_cell(self, x):
-        return [x[self.cell_off[a]:self.cell_off[a + 1]].reshape(int(self.nb[a]), self.ng, int(self.npt[a]))
-                for a in range(self.n_atm)]
+        """Per-atmosphere [bin][g][point] views of a cell array (padding dropped)."""
+        return [x[self.cell_off[a]:self.cell_off[a + 1]].reshape(int(self.nb[a]), self.ng, int(self.cs[a]))
+                [:, :, :int(self.npt[a])] for a in range(self.n_atm)]
+
+    def pack_cell(self, per_atm, dtype=torch.float64):
+        """A device cell array from per-atmosphere [bin][g][point] arrays."""
+        out = np.zeros(self.total_cell, np.float64)
+        for a, arr in enumerate(per_atm):
+            v = out[self.cell_off[a]:self.cell_off[a + 1]].reshape(int(self.nb[a]), self.ng, int(self.cs[a]))
+            v[:, :, :int(self.npt[a])] = np.asarray(arr, np.float64)
+        return torch.as_tensor(out, device=self.device).to(dtype)
 
     def split_pb(self, x):
         return [x[self.pb_off[a]:self.pb_off[a + 1]].reshape(int(self.nb[a]), int(self.npt[a]))

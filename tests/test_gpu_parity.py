@@ -79,7 +79,7 @@ def test_mix_opacity_powerlaw(prec):
     T_pt = _t(T)
     kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
     H.mix_opacity(b, H.KTable(kt), T_pt, kap, prec)
-    got = _np(kap).astype(np.float64).reshape(kap_ref.shape)
+    got = b.split_cell(_np(kap).astype(np.float64))[0]
     np.testing.assert_allclose(got, kap_ref, rtol=1e-13 if prec == 0 else 2e-6, atol=0)
 
 
@@ -101,7 +101,7 @@ def test_mix_opacity_table_with_clamping(prec, small_table):
     P, T, kap_ref = oracle_state(atm, kt, T_c)
     kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
     H.mix_opacity(b, H.KTable(kt), _t(T), kap, prec)
-    got = _np(kap).astype(np.float64).reshape(kap_ref.shape)
+    got = b.split_cell(_np(kap).astype(np.float64))[0]
     np.testing.assert_allclose(got, kap_ref, rtol=1e-13 if prec == 0 else 3e-6, atol=0)
 
 
@@ -114,8 +114,8 @@ def test_transmission_coefficients_match_oracle(small_table):
     H.grid(b)
     T_c = smooth_profile(atm)
     P, T, kap_ref = oracle_state(atm, small_table, T_c)
-    out = torch.zeros(b.total_cell - b.ng * b.total_bin, 5, dtype=torch.float64, device="cuda")
-    H.transmission(b, _t(kap_ref), _t(T), out)
+    out = torch.zeros(2 * b.ng * b.total_lb, 5, dtype=torch.float64, device="cuda")
+    H.transmission(b, b.pack_cell([kap_ref]), _t(T), out)
     got = _np(out).reshape(12, 20, 60, 5)
     n = atm["n"]
     worst = 0.0
@@ -178,12 +178,12 @@ def test_flux_fp64_plain_two_calls_warm_start():
     P, T, kap = oracle_state(atm, kt, T_c)
     up_ref = np.zeros(kap.shape)
     r1 = ref.flux(atm, kap, T, P, up_ref)
-    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0)
     _check_flux_fp64(b, 0, r1, up_ref, F_up, F_dn, ub, db, bol)
     # second call warm-started from the first call's upward fluxes, new temperatures
     T2 = T * 1.01
     r2 = ref.flux(atm, kap, T2, P, up_ref)
-    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T2), 0, F_up0=F_up)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T2), 0, F_up0=F_up)
     _check_flux_fp64(b, 0, r2, up_ref, F_up, F_dn, ub, db, bol)
 
 
@@ -198,7 +198,7 @@ def test_flux_fp64_table_scattering(n, nb, n_scat, small_table):
     P, T, kap = oracle_state(atm, small_table, T_c)
     up_ref = np.zeros(kap.shape)
     r = ref.flux(atm, kap, T, P, up_ref, n_scat=n_scat)
-    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0, n_scat=n_scat)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0, n_scat=n_scat)
     _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
@@ -207,8 +207,8 @@ def test_flux_without_downward_output_is_identical():
     b = H.Batch([atm])
     H.grid(b)
     P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
-    a = _gpu_flux(b, _t(kap), _t(T), 0, want_dn=True)
-    c = _gpu_flux(b, _t(kap), _t(T), 0, want_dn=False)
+    a = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0, want_dn=True)
+    c = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0, want_dn=False)
     assert torch.equal(a[0], c[0]) and torch.equal(a[4], c[4])
 
 
@@ -357,7 +357,7 @@ def test_edge_minimal_atmosphere_one_bin_one_g():
     P, T, kap = oracle_state(atm, kt, [1300.0, 800.0])
     up_ref = np.zeros(kap.shape)
     r = ref.flux(atm, kap, T, P, up_ref)
-    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0)
     _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
@@ -379,7 +379,7 @@ def test_edge_pure_scattering_and_isothermal_layers():
     P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
     up_ref = np.zeros(kap.shape)
     r = ref.flux(atm, kap, T, P, up_ref, n_scat=6)
-    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), 0, n_scat=6)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0, n_scat=6)
     _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
@@ -417,7 +417,7 @@ def test_flux_every_sweep_shape(K, L, prec, small_table, monkeypatch):
     P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
     up_ref = np.zeros(kap.shape)
     r = ref.flux(atm, kap, T, P, up_ref, n_scat=3)
-    F_up, F_dn, ub, db, bol = _gpu_flux(b, _t(kap), _t(T), prec, n_scat=3)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), prec, n_scat=3)
     if prec == 0:
         _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
     else:
