@@ -90,6 +90,11 @@ typedef struct helios_atm {
     const double* T_star;        /* [n_atm] stellar blackbody temperature */
     const double* T_irr;         /* [n_atm] irradiation temperature: TOA flux is (T_irr/T_star)^4 pi B(T_star) */
     const double* T_int;         /* [n_atm] internal temperature of the BOA flux */
+    const int32_t* status;       /* [n_atm] optional (NULL: all active): atmospheres whose
+                                    status is not HELIOS_ATM_RUNNING are skipped by
+                                    helios_mix_opacity and helios_flux, their outputs left
+                                    unchanged (a batch's active set shrinks on the device,
+                                    without a new descriptor) */
 } helios_atm;
 
 /* Opacity source (Sec. 2.3).  TABLE: k-coefficients on a uniform
@@ -201,10 +206,35 @@ int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double
                  const helios_re_state* st, const helios_re_opts* opt, int32_t* status,
                  double* resid, void* stream);
 
+/* Autotuner of the flux sweep (a batching aid; the paper runs one
+ * atmosphere at a time).  helios_flux groups atmospheres into size classes by
+ * layer count (n <= 32, 64, 112, 208, 400) and sweeps each class with one
+ * launch of its own shape (sublayers per lane x lanes per column).  For each
+ * class present in the batch, every compiled shape that holds the class's
+ * deepest atmosphere is timed here on up to 1024 bins of that atmosphere
+ * (same arguments as helios_flux, status ignored), and the fastest is used
+ * by later helios_flux calls of this process with the same precision and
+ * n_g.  Synchronous: returns after the timing.  F_up_g is restored to its
+ * input values; the workspace must be at least helios_workspace_bytes(atm,
+ * prec) bytes.  Atmospheres of a class that are adjacent in the batch share
+ * one contiguous launch range; ordering a batch by layer count keeps every
+ * class's range free of other classes' bins. */
+int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                    const double* g0, int32_t n_scat, double D, void* F_up_g, void* ws, size_t ws_bytes,
+                    helios_prec prec, void* stream);
+
+/* The sweep shapes helios_flux would use for this batch: for each of the 5
+ * size classes (out holds 3 x max_classes int32, max_classes >= 5) the
+ * class's upper layer-count bound, then K (sublayers per lane) and L (lanes
+ * per column), both 0 for a class with no member.  Returns the number of
+ * classes (> 0) or an error code. */
+int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, int32_t max_classes);
+
 /* Diagnostics for measurement: when `before` and `after` are non-NULL
  * hipEvent_t handles (passed as void*), the calling thread's next
  * helios_flux calls record `before` on their stream just before the flux
- * sweep kernel is enqueued and `after` just after it, so the sweep's own
+ * sweep launches (one per size class present) are enqueued and `after` just
+ * after them, so the sweep's own
  * duration can be read with hipEventElapsedTime.  NULL, NULL turns it off.
  * The setting is thread-local; the events are owned by the caller. */
 int helios_set_sweep_events(void* before, void* after);

@@ -7,7 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "helios_internal.hpp"
@@ -31,10 +33,29 @@ int hip_fail(hipError_t e, const char* where) {
     return fail(HELIOS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 
+// Size classes of the batched sweep, by layer count: atmospheres of one
+// class share a sweep launch and its shape, so a short atmosphere does not
+// run with the lane count of the deepest one.
+constexpr int kNumClasses = 5;
+constexpr int kClassNHi[kNumClasses] = {32, 64, 112, 208, HELIOS_MAX_LAYERS};
+static_assert(kNumClasses <= kMaxClasses, "class table");
+
+int class_of(int n) {
+    for (int k = 0; k < kNumClasses; ++k)
+        if (n <= kClassNHi[k]) return k;
+    return kNumClasses - 1;
+}
+int class_nlo(int k) { return k == 0 ? 0 : kClassNHi[k - 1] + 1; }
+
 // Host view of the batch sizes.
 struct Sizes {
     int64_t total_n = 0, total_pt = 0, total_bin = 0, total_lb = 0, total_pb = 0, total_cell = 0;
     int n_max = 0, npt_max = 0, nb_max = 0;
+    // per class: deepest member, bin range [bin_lo, bin_hi) spanning its members,
+    // and the member with the most bins among the deepest (autotuner sample)
+    int cls_nmax[kNumClasses] = {};
+    int64_t cls_bin_lo[kNumClasses] = {}, cls_bin_hi[kNumClasses] = {};
+    int cls_rep[kNumClasses] = {};
 };
 
 int check_atm(const helios_atm* atm, Sizes& z) {
@@ -63,6 +84,19 @@ int check_atm(const helios_atm* atm, Sizes& z) {
         z.npt_max = std::max(z.npt_max, npt);
         z.nb_max = std::max(z.nb_max, nb);
     }
+    int64_t b0 = 0;
+    for (int a = 0; a < atm->n_atm; ++a) {
+        int n = atm->n_layer_h[a], nb = atm->n_bin_h[a], k = class_of(n);
+        if (z.cls_nmax[k] == 0) {
+            z.cls_bin_lo[k] = b0;
+            z.cls_rep[k] = a;
+        }
+        int r = z.cls_rep[k];
+        if (n > z.cls_nmax[k] || (n == atm->n_layer_h[r] && nb > atm->n_bin_h[r])) z.cls_rep[k] = a;
+        z.cls_nmax[k] = std::max(z.cls_nmax[k], n);
+        b0 += nb;
+        z.cls_bin_hi[k] = b0;
+    }
     return HELIOS_OK;
 }
 
@@ -76,7 +110,8 @@ struct WsLayout {
 int waves_per_bin(int n_g, int L) { return (n_g + (64 / L) - 1) / (64 / L); }
 
 // The workspace is sized for the largest waves-per-bin any sweep shape uses
-// (L = 32), so the shape can be chosen per call.
+// (L = 32), which is also the stride of the partial-sum layout, so the shape
+// can be chosen per call and per size class.
 WsLayout ws_layout(const Sizes& z, int n_g, bool mixed) {
     WsLayout w;
     size_t r = mixed ? sizeof(float) : sizeof(double);
@@ -148,15 +183,11 @@ bool k_allowed(int K, bool mixed) {
     return false;
 }
 
-int pick_shape(int nsub_max, bool mixed, SweepShape& sh) {
-    int fk = env_int("HELIOS_SWEEP_K", 0), fl = env_int("HELIOS_SWEEP_L", 0);
-    if (fk || fl) {
-        if (!k_allowed(fk, mixed) || (fl != 16 && fl != 32))
-            return fail(HELIOS_EINVAL, "HELIOS_SWEEP_K/L = %d/%d not available", fk, fl);
-        if (fk * fl < nsub_max) return fail(HELIOS_ESHAPE, "K*L = %d < %d sublayers", fk * fl, nsub_max);
-        sh = {fk, fl};
-        return HELIOS_OK;
-    }
+// Shapes chosen by helios_autotune, per (precision, n_g, size class).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, SweepShape> g_tuned;
+
+int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
     for (int L : {16, 32}) {
         for (int i = 0; i < kNumSweepK; ++i) {
             int K = kSweepK[i];
@@ -168,6 +199,112 @@ int pick_shape(int nsub_max, bool mixed, SweepShape& sh) {
         }
     }
     return fail(HELIOS_ESHAPE, "no sweep shape holds %d sublayers", nsub_max);
+}
+
+// Shape of class k (deepest member nsub_max sublayers): an environment
+// override (HELIOS_SWEEP_K / HELIOS_SWEEP_L, for measurement), else the
+// autotuned one, else the default.
+int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh) {
+    int fk = env_int("HELIOS_SWEEP_K", 0), fl = env_int("HELIOS_SWEEP_L", 0);
+    if (fk || fl) {
+        if (!k_allowed(fk, mixed) || (fl != 16 && fl != 32))
+            return fail(HELIOS_EINVAL, "HELIOS_SWEEP_K/L = %d/%d not available", fk, fl);
+        if (fk * fl < nsub_max) return fail(HELIOS_ESHAPE, "K*L = %d < %d sublayers", fk * fl, nsub_max);
+        sh = {fk, fl};
+        return HELIOS_OK;
+    }
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find({mixed ? 1 : 0, n_g, k});
+        if (it != g_tuned.end() && it->second.K * it->second.L >= nsub_max) {
+            sh = it->second;
+            return HELIOS_OK;
+        }
+    }
+    return default_shape(nsub_max, mixed, sh);
+}
+
+// Everything one flux call needs after validation.
+struct FluxPlan {
+    Sizes z;
+    WsLayout w;
+    bool mixed;
+    SweepShape sh[kNumClasses];
+};
+
+int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0, const double* g0,
+              int32_t n_scat, double D, const void* F_up_g, const void* ws, size_t ws_bytes, helios_prec prec,
+              FluxPlan& p) {
+    int rc = check_atm(atm, p.z);
+    if (rc) return rc;
+    if (!kappa || !T_pt || !w0 || !g0 || !F_up_g || !ws) return fail(HELIOS_EINVAL, "flux: NULL argument");
+    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    if (n_scat < 0 || n_scat > 100000) return fail(HELIOS_EINVAL, "n_scat = %d", n_scat);
+    if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
+    p.mixed = prec == HELIOS_MIXED;
+    p.w = ws_layout(p.z, atm->n_g, p.mixed);
+    if (ws_bytes < p.w.total)
+        return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, p.w.total);
+    for (int k = 0; k < kNumClasses; ++k) {
+        p.sh[k] = {0, 0};
+        if (p.z.cls_nmax[k] == 0) continue;
+        rc = pick_shape(k, 2 * p.z.cls_nmax[k], atm->n_g, p.mixed, p.sh[k]);
+        if (rc) return rc;
+    }
+    return HELIOS_OK;
+}
+
+SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa, const double* w0,
+                     const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, char* wsb) {
+    SweepArgs A;
+    A.n_layer = atm->n_layer;
+    A.pt_off = atm->pt_off;
+    A.bin_off = atm->bin_off;
+    A.lb_off = atm->lb_off;
+    A.pb_off = atm->pb_off;
+    A.cell_off = atm->cell_off;
+    A.P_pt = atm->P_pt;
+    A.grav = atm->grav;
+    A.kappa = kappa;
+    A.B = wsb + p.w.B;
+    A.F_top = (double*)(wsb + p.w.F_top);
+    A.F_int = (double*)(wsb + p.w.F_int);
+    A.w0 = w0;
+    A.g0 = g0;
+    A.F_up_g = F_up_g;
+    A.F_dn_g = F_dn_g;
+    A.part_up = wsb + p.w.part_up;
+    A.part_dn = wsb + p.w.part_dn;
+    A.gw = (double*)(wsb + p.w.gw);
+    A.status = atm->status;
+    A.n_atm = atm->n_atm;
+    A.n_g = atm->n_g;
+    A.wpb_stride = waves_per_bin(atm->n_g, 32);
+    A.n_scat = n_scat;
+    A.npt_max = p.z.npt_max;
+    A.D = D;
+    return A;
+}
+
+// One sweep launch for class k over bins [b_lo, b_hi).
+hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, int64_t b_hi, bool mixed,
+                       hipStream_t s) {
+    A.wpb = waves_per_bin(A.n_g, sh.L);
+    A.n_lo = class_nlo(k);
+    A.n_hi = kClassNHi[k];
+    A.w_begin = b_lo * A.wpb;
+    A.w_end = b_hi * A.wpb;
+    int64_t grid64 = A.w_end - A.w_begin;
+    int cap = env_int("HELIOS_SWEEP_GRID", 0);
+    if (cap > 0 && grid64 > cap) grid64 = cap;
+    if (grid64 > 0x7fffffff) grid64 = 0x7fffffff;  // the kernel strides over the rest
+    return launch_sweep(A, sh.K, sh.L, mixed, (int)grid64, s);
+}
+
+hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double* T_pt, char* wsb,
+                          hipStream_t s) {
+    return launch_planck(atm, p.z.total_pb, T_pt, wsb + p.w.B, (double*)(wsb + p.w.F_top),
+                         (double*)(wsb + p.w.F_int), (double*)(wsb + p.w.gw), gauss_table(atm->n_g), p.mixed, s);
 }
 
 }  // namespace
@@ -261,68 +398,25 @@ size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec) {
 int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                 const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
                 double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream) {
-    Sizes z;
-    int rc = check_atm(atm, z);
+    FluxPlan p;
+    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p);
     if (rc) return rc;
-    if (!kappa || !T_pt || !w0 || !g0 || !F_up_g || !F_up_bin || !F_dn_bin || !F_bol || !ws)
-        return fail(HELIOS_EINVAL, "helios_flux: NULL argument");
-    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
-    if (n_scat < 0 || n_scat > 100000) return fail(HELIOS_EINVAL, "n_scat = %d", n_scat);
-    if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
-    const bool mixed = prec == HELIOS_MIXED;
-    WsLayout w = ws_layout(z, atm->n_g, mixed);
-    if (ws_bytes < w.total)
-        return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, w.total);
-    SweepShape sh;
-    rc = pick_shape(2 * z.n_max, mixed, sh);
-    if (rc) return rc;
+    if (!F_up_bin || !F_dn_bin || !F_bol) return fail(HELIOS_EINVAL, "helios_flux: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)ws;
-    void* B = wsb + w.B;
-    double* F_top = (double*)(wsb + w.F_top);
-    double* F_int = (double*)(wsb + w.F_int);
-    double* gw = (double*)(wsb + w.gw);
-
-    hipError_t e = launch_planck(atm, z.total_pb, T_pt, B, F_top, F_int, gw, gauss_table(atm->n_g), mixed, s);
+    hipError_t e = launch_sources(atm, p, T_pt, wsb, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (sources)");
 
-    SweepArgs A;
-    A.n_layer = atm->n_layer;
-    A.pt_off = atm->pt_off;
-    A.bin_off = atm->bin_off;
-    A.lb_off = atm->lb_off;
-    A.pb_off = atm->pb_off;
-    A.cell_off = atm->cell_off;
-    A.P_pt = atm->P_pt;
-    A.grav = atm->grav;
-    A.kappa = kappa;
-    A.B = B;
-    A.F_top = F_top;
-    A.F_int = F_int;
-    A.w0 = w0;
-    A.g0 = g0;
-    A.F_up_g = F_up_g;
-    A.F_dn_g = F_dn_g;
-    A.part_up = wsb + w.part_up;
-    A.part_dn = wsb + w.part_dn;
-    A.gw = gw;
-    A.n_atm = atm->n_atm;
-    A.n_g = atm->n_g;
-    A.wpb = waves_per_bin(atm->n_g, sh.L);
-    A.n_scat = n_scat;
-    A.npt_max = z.npt_max;
-    A.D = D;
-    A.w_begin = 0;
-    A.w_end = z.total_bin * A.wpb;
-    int64_t grid64 = A.w_end;
-    int cap = env_int("HELIOS_SWEEP_GRID", 0);
-    if (cap > 0 && grid64 > cap) grid64 = cap;
+    SweepArgs A = sweep_args(atm, p, kappa, w0, g0, n_scat, D, F_up_g, F_dn_g, wsb);
     if (g_ev_before && g_ev_after) {
         e = hipEventRecord(g_ev_before, s);
         if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
     }
-    e = launch_sweep(A, sh.K, sh.L, mixed, (int)grid64, s);
-    if (e != hipSuccess) return hip_fail(e, "helios_flux (sweep)");
+    for (int k = 0; k < kNumClasses; ++k) {
+        if (p.z.cls_nmax[k] == 0) continue;
+        e = sweep_class(A, p.sh[k], k, p.z.cls_bin_lo[k], p.z.cls_bin_hi[k], p.mixed, s);
+        if (e != hipSuccess) return hip_fail(e, "helios_flux (sweep)");
+    }
     if (g_ev_before && g_ev_after) {
         e = hipEventRecord(g_ev_after, s);
         if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
@@ -333,15 +427,113 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     Bo.part_dn = A.part_dn;
     Bo.F_up_bin = F_up_bin;
     Bo.F_dn_bin = F_dn_bin;
-    Bo.chunk = (double*)(wsb + w.chunk);
+    Bo.chunk = (double*)(wsb + p.w.chunk);
     Bo.F_bol = F_bol;
-    Bo.wpb = A.wpb;
-    Bo.n_chunk = (z.nb_max + kBolChunk - 1) / kBolChunk;
-    Bo.mixed = mixed ? 1 : 0;
-    e = launch_bolometric(Bo, z.npt_max, z.nb_max, z.total_pt, s);
+    Bo.wpb_stride = A.wpb_stride;
+    Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
+    Bo.mixed = p.mixed ? 1 : 0;
+    Bo.n_cls = kNumClasses;
+    for (int k = 0; k < kNumClasses; ++k) {
+        Bo.cls_nhi[k] = kClassNHi[k];
+        Bo.cls_wpb[k] = p.sh[k].L ? waves_per_bin(atm->n_g, p.sh[k].L) : 1;
+    }
+    e = launch_bolometric(Bo, p.z.npt_max, p.z.nb_max, p.z.total_pt, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (bolometric)");
     g_err[0] = 0;
     return HELIOS_OK;
+}
+
+int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                    const double* g0, int32_t n_scat, double D, void* F_up_g, void* ws, size_t ws_bytes,
+                    helios_prec prec, void* stream) {
+    FluxPlan p;
+    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    const size_t r = p.mixed ? sizeof(float) : sizeof(double);
+    hipError_t e = launch_sources(atm, p, T_pt, wsb, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_autotune (sources)");
+    SweepArgs A = sweep_args(atm, p, kappa, w0, g0, n_scat, D, F_up_g, nullptr, wsb);
+    A.status = nullptr;  // time the work even where the batch marks a member converged
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<char> saved;
+    auto cleanup = [&](int code) {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        return code;
+    };
+    if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess)
+        return cleanup(hip_fail(e, "helios_autotune (events)"));
+    for (int k = 0; k < kNumClasses; ++k) {
+        if (p.z.cls_nmax[k] == 0) continue;
+        // sample: up to 1024 bins of the class's deepest atmosphere
+        const int a = p.z.cls_rep[k];
+        int64_t b_lo = 0, c_lo = 0;
+        for (int i = 0; i < a; ++i) {
+            b_lo += atm->n_bin_h[i];
+            c_lo += (int64_t)atm->n_bin_h[i] * atm->n_g * col_stride(atm->n_layer_h[i]);
+        }
+        const int64_t nbs = std::min<int64_t>(atm->n_bin_h[a], 1024);
+        const size_t cells = (size_t)nbs * atm->n_g * col_stride(atm->n_layer_h[a]);
+        char* fu = (char*)F_up_g + c_lo * r;
+        saved.resize(cells * r);
+        if ((e = hipMemcpyAsync(saved.data(), fu, cells * r, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return cleanup(hip_fail(e, "helios_autotune (save)"));
+        const int nsub = 2 * p.z.cls_nmax[k];
+        SweepShape best = p.sh[k];
+        float best_ms = 1e30f;
+        for (int L : {16, 32}) {
+            for (int i = 0; i < kNumSweepK; ++i) {
+                SweepShape c = {kSweepK[i], L};
+                if (!k_allowed(c.K, p.mixed) || c.K * c.L < nsub) continue;
+                if ((e = sweep_class(A, c, k, b_lo, b_lo + nbs, p.mixed, s)) != hipSuccess)  // warm-up
+                    return cleanup(hip_fail(e, "helios_autotune (sweep)"));
+                float ms_min = 1e30f;
+                for (int rep = 0; rep < 3; ++rep) {
+                    float ms = 0.f;
+                    if ((e = hipEventRecord(ev0, s)) != hipSuccess ||
+                        (e = sweep_class(A, c, k, b_lo, b_lo + nbs, p.mixed, s)) != hipSuccess ||
+                        (e = hipEventRecord(ev1, s)) != hipSuccess || (e = hipEventSynchronize(ev1)) != hipSuccess ||
+                        (e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess)
+                        return cleanup(hip_fail(e, "helios_autotune (timing)"));
+                    ms_min = std::min(ms_min, ms);
+                }
+                if (ms_min < best_ms) {
+                    best_ms = ms_min;
+                    best = c;
+                }
+            }
+        }
+        if ((e = hipMemcpyAsync(fu, saved.data(), cells * r, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return cleanup(hip_fail(e, "helios_autotune (restore)"));
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[{p.mixed ? 1 : 0, atm->n_g, k}] = best;
+    }
+    g_err[0] = 0;
+    return cleanup(HELIOS_OK);
+}
+
+int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, int32_t max_classes) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!out || max_classes < kNumClasses) return fail(HELIOS_EINVAL, "out needs %d classes", kNumClasses);
+    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    for (int k = 0; k < kNumClasses; ++k) {
+        SweepShape sh = {0, 0};
+        if (z.cls_nmax[k]) {
+            rc = pick_shape(k, 2 * z.cls_nmax[k], atm->n_g, prec == HELIOS_MIXED, sh);
+            if (rc) return rc;
+        }
+        out[3 * k] = kClassNHi[k];
+        out[3 * k + 1] = sh.K;
+        out[3 * k + 2] = sh.L;
+    }
+    g_err[0] = 0;
+    return kNumClasses;
 }
 
 int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,

@@ -26,6 +26,12 @@ __host__ __device__ inline int col_stride(int n) {
     return ((2 * n + 1) + HELIOS_CELL_ALIGN - 1) & ~(HELIOS_CELL_ALIGN - 1);
 }
 
+// True when the batch marks atmosphere a as no longer running (converged or
+// failed): opacity mixing and the flux solve skip it.
+__device__ inline bool frozen(const int32_t* status, int a) {
+    return status != nullptr && status[a] != HELIOS_ATM_RUNNING;
+}
+
 // Index of the atmosphere owning global element idx: the largest a with
 // off[a] <= idx (off has n_atm+1 non-decreasing entries).
 __device__ inline int find_atm(const int64_t* __restrict__ off, int n_atm, int64_t idx) {
@@ -78,13 +84,18 @@ struct SweepArgs {
     void* part_up;        // [bin x wave-of-bin x point] Gauss partial sums (workspace)
     void* part_dn;
     const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
+    const int32_t* status;   // optional: converged atmospheres are skipped
     int64_t w_begin, w_end;  // global wave range covered by the launch
     int32_t n_atm, n_g;
-    int32_t wpb;          // waves per bin
+    int32_t wpb;          // waves per bin of this launch's shape
+    int32_t wpb_stride;   // waves-per-bin stride of the partial-sum layout (largest shape)
+    int32_t n_lo, n_hi;   // this launch serves atmospheres with n_lo <= n <= n_hi
     int32_t n_scat;
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
     double D;
 };
+
+constexpr int kMaxClasses = 8;
 
 struct GaussTable {
     double w[HELIOS_MAX_NG];  // weights on [0,1] (sum 1), ascending nodes
@@ -98,8 +109,18 @@ struct BolArgs {
     double* F_dn_bin;
     double* chunk;        // [sum npt][n_chunk][4] Neumaier pairs of bin-chunk sums (workspace)
     double* F_bol;
-    int32_t wpb, n_chunk, mixed;
+    int32_t wpb_stride, n_chunk, mixed;
+    int32_t n_cls;                   // size classes: atmosphere with n <= cls_nhi[k] (first k)
+    int32_t cls_nhi[kMaxClasses];    // uses cls_wpb[k] waves per bin
+    int32_t cls_wpb[kMaxClasses];
 };
+
+// Waves per bin of an atmosphere with n layers under the class table.
+__device__ inline int class_wpb(const BolArgs& A, int n) {
+    for (int k = 0; k < A.n_cls; ++k)
+        if (n <= A.cls_nhi[k]) return A.cls_wpb[k];
+    return A.cls_wpb[A.n_cls - 1];
+}
 
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s);

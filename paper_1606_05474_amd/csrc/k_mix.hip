@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
     const int n = A.atm.n_layer[a];
     const int npt = 2 * n + 1;
     const int p0 = ch * kMixPts;
-    if (p0 >= npt) return;  // uniform: past this atmosphere's points
+    if (p0 >= npt || frozen(A.atm.status, a)) return;  // uniform: past the points, or converged
     const int ncol = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]) * A.ng;
     const int c = blockIdx.y * kMixCols + t;
     if ((int)blockIdx.y * kMixCols >= ncol) return;  // uniform: past this atmosphere's columns

@@ -70,6 +70,7 @@ __global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total_pb) return;
     int a = find_atm(atm.pb_off, atm.n_atm, idx);
+    if (frozen(atm.status, a)) return;
     int npt = 2 * atm.n_layer[a] + 1;
     int64_t rel = idx - atm.pb_off[a];
     int l = (int)(rel / npt);
@@ -88,6 +89,7 @@ __global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* _
     __shared__ double red[256];
     int a = blockIdx.x;
     if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gt.w[threadIdx.x];
+    if (frozen(atm.status, a)) return;  // uniform per workgroup
     int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
     int64_t b0 = atm.bin_off[a];
     double Ts = atm.T_star[a], Ti = atm.T_int[a];
@@ -166,9 +168,11 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     const int a = blockIdx.x;
     const int tile = blockIdx.y, ch = blockIdx.z;
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int npt = 2 * A.atm.n_layer[a] + 1;
+    const int n = A.atm.n_layer[a];
+    const int npt = 2 * n + 1;
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
-    if (tile * 64 >= npt || ch * kBolChunk >= nb) return;  // uniform per workgroup
+    if (tile * 64 >= npt || ch * kBolChunk >= nb || frozen(A.atm.status, a)) return;  // uniform
+    const int wpb = class_wpb(A, n);
     const int p = tile * 64 + pl;
     constexpr int per = kBolChunk / 16;
     const int l0 = ch * kBolChunk + q * per;
@@ -180,9 +184,9 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
         for (int i = 0; i < per; ++i) {
             const int l = l0 + i;
             if (l < nb) {
-                const int64_t base = pb * A.wpb + ((int64_t)l * A.wpb) * npt + p;
-                const double fu = combine_partials(A.part_up, base, A.wpb, npt, A.mixed);
-                const double fd = combine_partials(A.part_dn, base, A.wpb, npt, A.mixed);
+                const int64_t base = pb * A.wpb_stride + ((int64_t)l * A.wpb_stride) * npt + p;
+                const double fu = combine_partials(A.part_up, base, wpb, npt, A.mixed);
+                const double fd = combine_partials(A.part_dn, base, wpb, npt, A.mixed);
                 A.F_up_bin[pb + (int64_t)l * npt + p] = fu;
                 A.F_dn_bin[pb + (int64_t)l * npt + p] = fd;
                 nadd(au, dl[l] * fu);
@@ -219,7 +223,7 @@ __global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
     const int a = blockIdx.x, tile = blockIdx.y;
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int npt = 2 * A.atm.n_layer[a] + 1;
-    if (tile * 64 >= npt) return;
+    if (tile * 64 >= npt || frozen(A.atm.status, a)) return;
     const int p = tile * 64 + pl;
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
     const int nch = (nb + kBolChunk - 1) / kBolChunk;

@@ -286,6 +286,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const int at = find_atm(A.bin_off, A.n_atm, gb);
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
+        if (n < A.n_lo || n > A.n_hi || frozen(A.status, at)) continue;  // uniform per wave
         const int nsub = 2 * n, npt = nsub + 1;
         const int nact = (nsub + K - 1) / K;
         const int g = j * C + cw;
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * cs;  // first column
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
-        const int64_t poff = (A.pb_off[at] * A.wpb) + ((int64_t)l * A.wpb + j) * npt;
+        const int64_t poff = (A.pb_off[at] * A.wpb_stride) + ((int64_t)l * A.wpb_stride + j) * npt;
         const double* __restrict__ P = A.P_pt + A.pt_off[at];
         const double igrav = 1.0 / A.grav[at];
         const R D = (R)A.D;

@@ -11,6 +11,7 @@ Names follow the C ABI: ``grid``, ``profile``, ``mix_opacity``,
 """
 from __future__ import annotations
 
+import copy
 import ctypes
 import os
 from dataclasses import dataclass
@@ -38,7 +39,7 @@ class HeliosAtm(ctypes.Structure):
                 ("n_layer_h", _P), ("n_bin_h", _P), ("n_layer", _P), ("n_bin", _P),
                 ("lay_off", _P), ("pt_off", _P), ("bin_off", _P), ("lb_off", _P), ("pb_off", _P),
                 ("cell_off", _P), ("bin_index", _P), ("lambda_c", _P), ("dlambda", _P), ("P_c", _P),
-                ("P_pt", _P), ("grav", _P), ("T_star", _P), ("T_irr", _P), ("T_int", _P)]
+                ("P_pt", _P), ("grav", _P), ("T_star", _P), ("T_irr", _P), ("T_int", _P), ("status", _P)]
 
 
 class HeliosKtab(ctypes.Structure):
@@ -83,12 +84,14 @@ def lib():
         L.helios_flux.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
         L.helios_radeq.argtypes = [A, _P, _P, _P, ctypes.POINTER(HeliosReState), ctypes.POINTER(HeliosReOpts),
                                    _P, _P, _P]
+        L.helios_autotune.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, sz, ctypes.c_int, _P]
+        L.helios_sweep_shapes.argtypes = [A, ctypes.c_int, _P, i32]
         L.helios_set_sweep_events.argtypes = [_P, _P]
         L.helios_set_sweep_events.restype = ctypes.c_int
         L.helios_last_error.restype = ctypes.c_char_p
         L.helios_version.restype = i32
         for f in ("helios_grid", "helios_profile", "helios_mix_opacity", "helios_transmission",
-                  "helios_flux", "helios_radeq"):
+                  "helios_flux", "helios_radeq", "helios_autotune", "helios_sweep_shapes"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -175,8 +178,18 @@ class Batch:
             self.n_atm, self.ng, self.h_n_layer.ctypes.data, self.h_n_bin.ctypes.data,
             *[_ptr(self.d[k]) for k in ("n_layer", "n_bin", "lay_off", "pt_off", "bin_off", "lb_off",
                                          "pb_off", "cell_off", "bin_index", "lambda_c", "dlambda", "P_c",
-                                         "P_pt", "grav", "T_star", "T_irr", "T_int")])
+                                         "P_pt", "grav", "T_star", "T_irr", "T_int")], None)
         self.device = dev
+
+    def with_status(self, status):
+        """A view of this batch whose descriptor carries a device status
+        array: atmospheres that are not ATM_RUNNING are skipped by
+        mix_opacity and flux.  Shares every buffer with this batch."""
+        v = copy.copy(self)
+        v.desc = HeliosAtm.from_buffer_copy(self.desc)
+        v.desc.status = _ptr(status)
+        v._status = status  # keep the array alive with the view
+        return v
 
     @property
     def P_pt(self):
@@ -270,6 +283,22 @@ def set_sweep_events(before=None, after=None):
     _check(lib().helios_set_sweep_events(hb, ha))
 
 
+def autotune(b: Batch, kappa, T_pt, F_up_g, ws, n_scat=4, D=2.0, prec=FP64, stream=None):
+    """Time the compiled sweep shapes per size class of the batch and keep
+    the fastest for later flux calls (synchronous; F_up_g is restored)."""
+    _check(lib().helios_autotune(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
+                                 int(n_scat), float(D), _ptr(F_up_g), _ptr(ws), ws.numel() * ws.element_size(),
+                                 prec, _stream(stream)))
+
+
+def sweep_shapes(b: Batch, prec=FP64):
+    """{class upper layer bound: (K, L)} for the classes present in the batch."""
+    out = np.zeros(3 * 8, np.int32)
+    k = _check(lib().helios_sweep_shapes(ctypes.byref(b.desc), prec, out.ctypes.data, 8))
+    o = out[:3 * k].reshape(k, 3)
+    return {int(r[0]): (int(r[1]), int(r[2])) for r in o if r[1] > 0}
+
+
 def workspace_bytes(b: Batch, prec=FP64) -> int:
     return int(lib().helios_workspace_bytes(ctypes.byref(b.desc), prec))
 
@@ -310,14 +339,21 @@ def radeq(b: Batch, F_bol, T_c, T_pt, m, hist, status, resid=None, opts: REOptio
 # ------------------------------------------------------------ RE buffers
 class Solver:
     """Device buffers of one batch's radiative-equilibrium iteration, and the
-    iteration itself: profile -> opacity -> flux -> RE step per iteration,
-    all enqueued on one stream; the host reads the per-atmosphere status
-    every ``check_every`` iterations."""
+    iteration itself: opacity -> flux -> RE step per iteration, all enqueued
+    on one stream; the host reads the per-atmosphere status every
+    ``check_every`` iterations.
+
+    The batch descriptor the solver passes carries its status array, so an
+    atmosphere that converged (or failed) is skipped by every later kernel
+    while the rest of the batch iterates on.  ``graph=True`` in ``solve``
+    captures ``check_every`` iterations into one HIP graph (torch.cuda.CUDAGraph)
+    and replays it, so a block of iterations costs one launch from the host.
+    """
 
     def __init__(self, b: Batch, kt: KTable, prec=FP64, n_scat=4, D=2.0, opts: REOptions | None = None):
         dev = b.device
         rd = rdtype(prec)
-        self.b, self.kt, self.prec, self.n_scat, self.D = b, kt, prec, n_scat, D
+        self.kt, self.prec, self.n_scat, self.D = kt, prec, n_scat, D
         self.opts = opts or REOptions()
         self.T_c = torch.zeros(b.total_n, dtype=torch.float64, device=dev)
         self.T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device=dev)
@@ -332,6 +368,8 @@ class Solver:
         self.status = torch.zeros(b.n_atm, dtype=torch.int32, device=dev)
         self.resid = torch.zeros(b.n_atm, dtype=torch.float64, device=dev)
         self.iters = torch.zeros(b.n_atm, dtype=torch.int32, device=dev)
+        self.b = b.with_status(self.status)
+        self._graph = None
         grid(b)
 
     def reset(self, T_init):
@@ -344,7 +382,7 @@ class Solver:
         profile(self.b, self.T_c, self.T_pt)
 
     def step(self, stream=None):
-        """One RE iteration for every atmosphere of the batch (enqueue only)."""
+        """One RE iteration for every running atmosphere of the batch (enqueue only)."""
         b = self.b
         mix_opacity(b, self.kt, self.T_pt, self.kappa, self.prec, stream=stream)
         flux(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol, self.ws,
@@ -352,19 +390,57 @@ class Solver:
         radeq(b, self.F_bol, self.T_c, self.T_pt, self.m, self.hist, self.status, self.resid, self.opts,
               iters=self.iters, stream=stream)
 
-    def solve(self, T_init, max_iter=200, check_every=10):
+    def autotune(self):
+        """Pick the sweep shape per size class on the current state (the
+        opacities are mixed first); the solver's buffers are left as they were
+        apart from kappa."""
+        mix_opacity(self.b, self.kt, self.T_pt, self.kappa, self.prec)
+        autotune(self.b, self.kappa, self.T_pt, self.F_up_g, self.ws, n_scat=self.n_scat, D=self.D,
+                 prec=self.prec)
+
+    def capture(self, n_steps):
+        """Capture n_steps iterations into a HIP graph (replayed by
+        ``replay``).  The captured kernels read the solver's buffers in place,
+        so a later ``reset`` needs no new capture."""
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for _ in range(n_steps):
+                    self.step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self._graph = (g, n_steps)
+        return g
+
+    def replay(self):
+        self._graph[0].replay()
+
+    def solve(self, T_init, max_iter=200, check_every=10, graph=False):
         """Iterate until every atmosphere converged or max_iter temperature
         updates were taken.  Returns (converged flags, updates taken) per
         atmosphere as numpy arrays; the counts come from the device, so
         checking only every ``check_every`` steps loses nothing (converged
-        atmospheres are frozen)."""
+        atmospheres are frozen).  With graph=True the blocks of check_every
+        iterations are replayed from one captured graph (the last block may
+        run a few iterations past max_iter + 1 calls; frozen atmospheres make
+        that harmless apart from the time)."""
         self.reset(T_init)
+        if graph and (self._graph is None or self._graph[1] != check_every):
+            # capturing enqueues nothing that runs; the state is untouched
+            self.capture(check_every)
         done = 0
         while done <= max_iter:
-            k = min(check_every, max_iter + 1 - done)
-            for _ in range(k):
-                self.step()
-            done += k
+            if graph:
+                self.replay()
+                done += check_every
+            else:
+                k = min(check_every, max_iter + 1 - done)
+                for _ in range(k):
+                    self.step()
+                done += k
             st = self.status.cpu().numpy()
             if np.all(st != ATM_RUNNING):
                 break

@@ -54,7 +54,7 @@ int main(void) {
   printf("helios_ktab %zu\\n", sizeof(helios_ktab));
   printf("helios_re_opts %zu\\n", sizeof(helios_re_opts));
   printf("helios_re_state %zu\\n", sizeof(helios_re_state));
-  P(helios_atm, T_int) P(helios_atm, P_pt) P(helios_ktab, k) P(helios_ktab, mmw) P(helios_ktab, species_mass)
+  P(helios_atm, T_int) P(helios_atm, status) P(helios_atm, P_pt) P(helios_ktab, k) P(helios_ktab, mmw) P(helios_ktab, species_mass)
   P(helios_re_opts, T_floor) P(helios_re_opts, fpre_p) P(helios_re_state, iter)
   return 0;
 }
@@ -67,6 +67,7 @@ int main(void) {
     assert int(got["helios_re_opts"]) == ctypes.sizeof(H.HeliosReOpts)
     assert int(got["helios_re_state"]) == ctypes.sizeof(H.HeliosReState)
     assert int(got["helios_atm.T_int"]) == H.HeliosAtm.T_int.offset
+    assert int(got["helios_atm.status"]) == H.HeliosAtm.status.offset
     assert int(got["helios_atm.P_pt"]) == H.HeliosAtm.P_pt.offset
     assert int(got["helios_ktab.k"]) == H.HeliosKtab.k.offset
     assert int(got["helios_ktab.mmw"]) == H.HeliosKtab.mmw.offset

@@ -423,3 +423,128 @@ def test_flux_every_sweep_shape(K, L, prec, small_table, monkeypatch):
     else:
         assert net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"]).max() < 1e-4
         assert col_rel_error(b.split_cell(_np(F_up))[0], up_ref).max() < 1e-4
+
+
+# ------------------------------------------------------- batching features
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ragged_batch_spanning_every_size_class(prec, small_table):
+    """One atmosphere per size class (and the class edges), interleaved so
+    that each class launch skips other classes' bins; FP64 stops at the
+    deepest atmosphere its compiled shapes hold (224 layers)."""
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(31 + prec)
+    ns = [65, 2, 209 if prec else 150, 32, 113, 33, 64] + ([400] if prec else [224])
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, 3 + (i % 3)) for i, n in enumerate(ns)]
+    b = H.Batch(atms)
+    H.grid(b)
+    shapes = H.sweep_shapes(b, prec)
+    assert len(shapes) == 5
+    for hi, (K, L) in shapes.items():
+        assert K * L >= 2 * max(n for n in ns if n <= hi)
+    T_cs = [smooth_profile(a) for a in atms]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, prec)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, prec)
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
+        up_ref = np.zeros(kap_ref.shape)
+        r = ref.flux(atm, kap_ref, T, P, up_ref)
+        if prec == 0:
+            _check_flux_fp64(b, a, r, up_ref, F_up, F_dn, ub, db, bol)
+        else:
+            err = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], r["F_bol"])
+            assert err.max() < 1e-4, (a, err.max())
+
+
+def test_status_skips_atmospheres_that_are_not_running(small_table):
+    """Atmospheres marked converged or failed in the descriptor's status are
+    left untouched by mix_opacity and flux; the others match the oracle."""
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(41)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb) for n, nb in [(40, 9), (70, 5), (25, 12)]]
+    b0 = H.Batch(atms)
+    H.grid(b0)
+    status = _t([H.ATM_RUNNING, H.ATM_CONVERGED, H.ATM_NUMERIC], torch.int32)
+    b = b0.with_status(status)
+    T_cs = [smooth_profile(a) for a in atms]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    sentinel = 12345.0
+    kap = torch.full((b.total_cell,), sentinel, dtype=torch.float64, device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, 0)
+    F_up = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+    F_dn = torch.full((b.total_cell,), sentinel, dtype=torch.float64, device="cuda")
+    ub = torch.full((b.total_pb,), sentinel, dtype=torch.float64, device="cuda")
+    db = torch.full((b.total_pb,), sentinel, dtype=torch.float64, device="cuda")
+    bol = torch.full((b.total_pt * 3,), sentinel, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(H.workspace_bytes(b, 0), dtype=torch.uint8, device="cuda")
+    H.flux(b, kap, T_pt, F_up, ub, db, bol, ws, F_dn_g=F_dn, prec=0)
+    torch.cuda.synchronize()
+    for a in (1, 2):
+        assert np.all(b.split_cell(_np(kap))[a] == sentinel)
+        assert np.all(b.split_cell(_np(F_up))[a] == 0.0)
+        assert np.all(b.split_cell(_np(F_dn))[a] == sentinel)
+        assert np.all(b.split_pb(_np(ub))[a] == sentinel) and np.all(b.split_pb(_np(db))[a] == sentinel)
+        assert np.all(b.split_pt(_np(bol).reshape(-1, 3))[a] == sentinel)
+    P, T, kap_ref = oracle_state(atms[0], small_table, T_cs[0])
+    np.testing.assert_allclose(b.split_cell(_np(kap))[0], kap_ref, rtol=1e-13)
+    up_ref = np.zeros(kap_ref.shape)
+    r = ref.flux(atms[0], kap_ref, T, P, up_ref)
+    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_restores_warm_start_and_keeps_parity(prec, small_table):
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(51)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb) for n, nb in [(30, 40), (100, 30), (60, 20)]]
+    b = H.Batch(atms)
+    H.grid(b)
+    T_cs = [smooth_profile(a) for a in atms]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, prec)
+    F_up0 = torch.rand(b.total_cell, dtype=torch.float64, device="cuda", generator=torch.Generator(
+        device="cuda").manual_seed(5)).to(H.rdtype(prec)) * 1e5
+    F_up = F_up0.clone()
+    ws = torch.zeros(H.workspace_bytes(b, prec), dtype=torch.uint8, device="cuda")
+    H.autotune(b, kap, T_pt, F_up, ws, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(F_up, F_up0)
+    shapes = H.sweep_shapes(b, prec)
+    assert set(shapes) == {32, 64, 112}
+    for hi, (K, L) in shapes.items():
+        assert K * L >= 2 * max(a["n"] for a in atms if a["n"] <= hi)
+        assert L in (16, 32) and (prec == 1 or K <= 14)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, prec)
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
+        up_ref = np.zeros(kap_ref.shape)
+        r = ref.flux(atm, kap_ref, T, P, up_ref)
+        err = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], r["F_bol"])
+        assert err.max() < (1e-10 if prec == 0 else 1e-4), (a, err.max())
+
+
+def test_graph_replayed_solve_equals_eager_solve():
+    """Blocks of RE iterations captured into one HIP graph and replayed
+    (host status reads between replays) reach bit-for-bit the eager loop's
+    temperatures, update counts and fluxes; the kernels' sums run in a fixed
+    order, so the two loops are the same arithmetic."""
+    atms = [W.plain_workload(n=n, nb=16)[0] for n in (30, 50, 12)]
+    kt = W.plain_workload(n=30, nb=16)[1]
+    T0 = np.concatenate([a["T0"] for a in atms])
+    b = H.Batch(atms)
+    eager = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    ce, ie = eager.solve(T0, max_iter=300, check_every=7)
+    graphed = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    cg, ig = graphed.solve(T0, max_iter=300, check_every=7, graph=True)
+    assert ce.all() and cg.all()
+    assert np.array_equal(ie, ig)
+    assert torch.equal(eager.T_c, graphed.T_c)
+    assert torch.equal(eager.F_bol, graphed.F_bol)
+    # a second solve replays the same graph from a fresh state
+    cg2, ig2 = graphed.solve(T0, max_iter=300, check_every=7, graph=True)
+    assert np.array_equal(ig2, ie) and torch.equal(graphed.T_c, eager.T_c)
