@@ -119,6 +119,9 @@ def run_batch(prec: int, steps: int, warmup: int, atms: list, kt: dict, max_iter
         s.step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()  # torch creates the underlying events on their first record
+    e1.record()
+    torch.cuda.synchronize()
     sweep_ms = 0.0
     t0 = time.perf_counter()
     for _ in range(steps):

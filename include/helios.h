@@ -230,6 +230,73 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
  * classes (> 0) or an error code. */
 int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, int32_t max_classes);
 
+/* ------------------------------------------------------------------
+ * Learned warm start (an addition to the method: the paper starts every
+ * atmosphere from a fixed profile).  A multilayer perceptron maps six
+ * atmosphere parameters -- irradiation temperature [K], internal temperature
+ * [K], log10 gravity [m s^-2], metallicity [M/H], C/O, log10 opacity scale --
+ * to temperatures at n_out fixed pressures:
+ *   n_in -> n_hidden (n_hidden_layers times, GELU z Phi(z) after each) -> n_out
+ * (linear).  Weights, inputs, hidden activations and back-propagated errors
+ * are BF16 on the matrix cores with FP32 accumulation; biases, master
+ * parameters, Adam moments, pre-activations and outputs are FP32.
+ * Inputs are normalised as (x - in_shift) * in_scale; the network's outputs
+ * y are normalised temperatures, T = out_shift + out_scale * y.
+ * Flat parameter layout (param_count entries): for each layer in order,
+ * W [out][in] row-major, then b [out].
+ * Limits: 1 <= n_in <= 64, 1 <= n_hidden <= 1024, 1 <= n_hidden_layers <= 8,
+ * 1 <= n_out <= 1024, 1 <= batch <= 2^22. */
+typedef struct {
+    int32_t n_in, n_hidden, n_hidden_layers, n_out;
+    float* params;               /* [param_count] FP32 master parameters */
+    uint16_t* params_bf16;       /* [param_count] BF16 copy read by the products (bit pattern) */
+    float* adam_m;               /* [param_count] first moments (training only, else NULL) */
+    float* adam_v;               /* [param_count] second moments (training only, else NULL) */
+    const float* in_shift;       /* [n_in] */
+    const float* in_scale;       /* [n_in] */
+    const float* out_shift;      /* [n_out] */
+    const float* out_scale;      /* [n_out] */
+} helios_mlp;
+
+/* Number of parameters (0 if the dimensions are invalid). */
+size_t helios_mlp_param_count(const helios_mlp* net);
+
+/* Workspace bytes for a batch of `batch` rows (0 if invalid); also the
+ * workspace of helios_warm_start with batch = n_atm. */
+size_t helios_mlp_workspace_bytes(const helios_mlp* net, int32_t batch);
+
+/* params_bf16 <- bf16(params), after the master parameters were written. */
+int helios_mlp_sync(const helios_mlp* net, void* stream);
+
+/* Inference: T [batch][n_out] (FP32, kelvin) from x [batch][n_in] (FP32). */
+int helios_mlp_forward(const helios_mlp* net, const float* x, int32_t batch, float* T, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Loss and gradient: loss (one float on the device) = mean over batch and
+ * outputs of (y - (T_target - out_shift)/out_scale)^2, and grad
+ * [param_count] (FP32, flat layout) its gradient by back-propagation.  The
+ * output error 2 (y - t)/(batch n_out) and the back-propagated errors are
+ * rounded to BF16 before each product; bias gradients sum those BF16 values. */
+int helios_mlp_backward(const helios_mlp* net, const float* x, const float* T_target, int32_t batch,
+                        float* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba 2015, with bias correction; step counts from 1)
+ * on params, adam_m, adam_v from grad; refreshes params_bf16. */
+int helios_mlp_adam(const helios_mlp* net, const float* grad, int32_t step, float lr, float beta1,
+                    float beta2, float eps, void* stream);
+
+/* Initial profiles for a batch: the network's temperatures for each
+ * atmosphere's parameters x [n_atm][n_in], given at log10 pressures
+ * logP_net [n_out] (device, dyn cm^-2, strictly monotone), interpolated
+ * linearly in log10 P onto the atmosphere's layer centres atm->P_c (end
+ * values held outside).  An atmosphere whose network profile has a value
+ * that is not finite or outside [T_lo, T_hi] gets T_iso in every layer and
+ * fallback[a] = 1 (else 0).  T_c [sum n] out; workspace of at least
+ * helios_mlp_workspace_bytes(net, n_atm) bytes. */
+int helios_warm_start(const helios_atm* atm, const helios_mlp* net, const float* x, const double* logP_net,
+                      double T_iso, double T_lo, double T_hi, double* T_c, int32_t* fallback, void* ws,
+                      size_t ws_bytes, void* stream);
+
 /* Diagnostics for measurement: when `before` and `after` are non-NULL
  * hipEvent_t handles (passed as void*), the calling thread's next
  * helios_flux calls record `before` on their stream just before the flux

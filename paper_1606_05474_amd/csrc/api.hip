@@ -307,6 +307,108 @@ hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double
                          (double*)(wsb + p.w.F_int), (double*)(wsb + p.w.gw), gauss_table(atm->n_g), p.mixed, s);
 }
 
+// ------------------------------------------------------ warm-start network
+struct NetLayout {
+    int nl;                        // affine layers (hidden + output)
+    int in[9], out[9];
+    size_t offW[9], offb[9], count;
+};
+
+bool net_layout(const helios_mlp* net, NetLayout& L) {
+    if (!net || net->n_in < 1 || net->n_in > 64 || net->n_hidden < 1 || net->n_hidden > 1024 ||
+        net->n_hidden_layers < 1 || net->n_hidden_layers > 8 || net->n_out < 1 || net->n_out > kMaxNetOut)
+        return false;
+    L.nl = net->n_hidden_layers + 1;
+    size_t off = 0;
+    for (int l = 0; l < L.nl; ++l) {
+        L.in[l] = l == 0 ? net->n_in : net->n_hidden;
+        L.out[l] = l == L.nl - 1 ? net->n_out : net->n_hidden;
+        L.offW[l] = off;
+        off += (size_t)L.in[l] * L.out[l];
+        L.offb[l] = off;
+        off += (size_t)L.out[l];
+    }
+    L.count = off;
+    return true;
+}
+
+struct NetWs {
+    size_t X0, Z, A, Y, dY, D0, D1, partial, T, total;  // Z, A: n_hidden_layers consecutive [B][H] blocks
+};
+constexpr int kLossBlocks = 512;
+
+NetWs net_ws(const helios_mlp* net, int64_t B) {
+    NetWs w;
+    const size_t H = (size_t)net->n_hidden, nh = (size_t)net->n_hidden_layers, no = (size_t)net->n_out;
+    w.X0 = 0;
+    w.Z = align256(w.X0 + (size_t)B * net->n_in * 2);
+    w.A = align256(w.Z + nh * B * H * 4);
+    w.Y = align256(w.A + nh * B * H * 2);
+    w.dY = align256(w.Y + (size_t)B * no * 4);
+    w.D0 = align256(w.dY + (size_t)B * no * 2);
+    w.D1 = align256(w.D0 + (size_t)B * H * 2);
+    w.partial = align256(w.D1 + (size_t)B * H * 2);
+    w.T = align256(w.partial + kLossBlocks * sizeof(double));
+    w.total = align256(w.T + (size_t)B * no * 4);
+    return w;
+}
+
+int check_net(const helios_mlp* net, NetLayout& L, bool training) {
+    if (!net_layout(net, L)) return fail(HELIOS_EINVAL, "helios_mlp: dimensions outside the limits");
+    if (!net->params || !net->params_bf16 || !net->in_shift || !net->in_scale || !net->out_shift || !net->out_scale)
+        return fail(HELIOS_EINVAL, "helios_mlp: NULL array");
+    if (training && (!net->adam_m || !net->adam_v)) return fail(HELIOS_EINVAL, "helios_mlp: no Adam moments");
+    return HELIOS_OK;
+}
+
+GemmArgs gemm(const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbn, int64_t sbk, int M, int N,
+              int K) {
+    GemmArgs g = {};
+    g.A = A;
+    g.sam = sam;
+    g.sak = sak;
+    g.B = B;
+    g.sbn = sbn;
+    g.sbk = sbk;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    return g;
+}
+
+// Forward pass of B rows: X0, then Z_l / A_l per hidden layer, then the
+// output layer into out (normalised y, or T when scaled).
+hipError_t net_forward(const helios_mlp* net, const NetLayout& L, const NetWs& w, char* wsb, const float* x, int B,
+                       float* out, bool scaled, hipStream_t s) {
+    const int H = net->n_hidden;
+    uint16_t* X0 = (uint16_t*)(wsb + w.X0);
+    hipError_t e = launch_mlp_input(x, (int64_t)B * net->n_in, net->n_in, net->in_shift, net->in_scale, X0, s);
+    if (e != hipSuccess) return e;
+    const uint16_t* h = X0;
+    for (int l = 0; l < L.nl; ++l) {
+        GemmArgs g = gemm(h, L.in[l], 1, net->params_bf16 + L.offW[l], L.in[l], 1, B, L.out[l], L.in[l]);
+        g.bias = net->params + L.offb[l];
+        if (l < L.nl - 1) {
+            g.out_f = (float*)(wsb + w.Z) + (size_t)l * B * H;
+            g.ld_f = H;
+            g.out_b = (uint16_t*)(wsb + w.A) + (size_t)l * B * H;
+            g.ld_b = H;
+            e = launch_gemm(g, kEpiGelu, s);
+            h = g.out_b;
+        } else {
+            g.out_f = out;
+            g.ld_f = net->n_out;
+            if (scaled) {
+                g.oshift = net->out_shift;
+                g.oscale = net->out_scale;
+            }
+            e = launch_gemm(g, kEpiLinear, s);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -534,6 +636,131 @@ int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, i
     }
     g_err[0] = 0;
     return kNumClasses;
+}
+
+size_t helios_mlp_param_count(const helios_mlp* net) {
+    NetLayout L;
+    return net_layout(net, L) ? L.count : 0;
+}
+
+size_t helios_mlp_workspace_bytes(const helios_mlp* net, int32_t batch) {
+    NetLayout L;
+    if (!net_layout(net, L) || batch < 1 || batch > (1 << 22)) return 0;
+    return net_ws(net, batch).total;
+}
+
+int helios_mlp_sync(const helios_mlp* net, void* stream) {
+    NetLayout L;
+    int rc = check_net(net, L, false);
+    if (rc) return rc;
+    hipError_t e = launch_mlp_sync(net->params, net->params_bf16, (int64_t)L.count, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_mlp_sync");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_mlp_forward(const helios_mlp* net, const float* x, int32_t batch, float* T, void* ws, size_t ws_bytes,
+                       void* stream) {
+    NetLayout L;
+    int rc = check_net(net, L, false);
+    if (rc) return rc;
+    if (!x || !T || !ws) return fail(HELIOS_EINVAL, "helios_mlp_forward: NULL argument");
+    if (batch < 1 || batch > (1 << 22)) return fail(HELIOS_EINVAL, "batch = %d outside 1..2^22", batch);
+    NetWs w = net_ws(net, batch);
+    if (ws_bytes < w.total) return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, w.total);
+    hipError_t e = net_forward(net, L, w, (char*)ws, x, batch, T, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_mlp_forward");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_mlp_backward(const helios_mlp* net, const float* x, const float* T_target, int32_t batch, float* loss,
+                        float* grad, void* ws, size_t ws_bytes, void* stream) {
+    NetLayout L;
+    int rc = check_net(net, L, false);
+    if (rc) return rc;
+    if (!x || !T_target || !loss || !grad || !ws) return fail(HELIOS_EINVAL, "helios_mlp_backward: NULL argument");
+    if (batch < 1 || batch > (1 << 22)) return fail(HELIOS_EINVAL, "batch = %d outside 1..2^22", batch);
+    NetWs w = net_ws(net, batch);
+    if (ws_bytes < w.total) return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, w.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    const int B = batch, H = net->n_hidden, no = net->n_out;
+    float* Y = (float*)(wsb + w.Y);
+    hipError_t e = net_forward(net, L, w, wsb, x, B, Y, false, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_mlp_backward (forward)");
+    uint16_t* dY = (uint16_t*)(wsb + w.dY);
+    e = launch_mlp_loss(Y, T_target, (int64_t)B * no, no, net->out_shift, net->out_scale, dY,
+                        (double*)(wsb + w.partial), kLossBlocks, loss, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_mlp_backward (loss)");
+    uint16_t* Dbuf[2] = {(uint16_t*)(wsb + w.D0), (uint16_t*)(wsb + w.D1)};
+    const uint16_t* E = dY;  // error at the output of layer l, [B][out_l]
+    int cur = 0;
+    for (int l = L.nl - 1; l >= 0; --l) {
+        const int in = L.in[l], out = L.out[l];
+        const uint16_t* h = l == 0 ? (const uint16_t*)(wsb + w.X0) : (const uint16_t*)(wsb + w.A) + (size_t)(l - 1) * B * H;
+        // weight gradient: dW[o][i] = sum_b E[b][o] h[b][i]
+        GemmArgs g = gemm(E, 1, out, h, 1, in, out, in, B);
+        g.out_f = grad + L.offW[l];
+        g.ld_f = in;
+        if ((e = launch_gemm(g, kEpiStore, s)) != hipSuccess) return hip_fail(e, "helios_mlp_backward (dW)");
+        if ((e = launch_mlp_bias_grad(E, B, out, grad + L.offb[l], s)) != hipSuccess)
+            return hip_fail(e, "helios_mlp_backward (db)");
+        if (l == 0) break;
+        // error at the output of layer l-1: (E W_l) * gelu'(Z_{l-1}), rounded to BF16
+        GemmArgs d = gemm(E, out, 1, net->params_bf16 + L.offW[l], 1, in, B, in, out);
+        d.zin = (const float*)(wsb + w.Z) + (size_t)(l - 1) * B * H;
+        d.ld_z = H;
+        d.out_b = Dbuf[cur];
+        d.ld_b = H;
+        if ((e = launch_gemm(d, kEpiDGelu, s)) != hipSuccess) return hip_fail(e, "helios_mlp_backward (dX)");
+        E = Dbuf[cur];
+        cur ^= 1;
+    }
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_mlp_adam(const helios_mlp* net, const float* grad, int32_t step, float lr, float beta1, float beta2,
+                    float eps, void* stream) {
+    NetLayout L;
+    int rc = check_net(net, L, true);
+    if (rc) return rc;
+    if (!grad) return fail(HELIOS_EINVAL, "helios_mlp_adam: grad is NULL");
+    if (step < 1) return fail(HELIOS_EINVAL, "step = %d must be >= 1", step);
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(HELIOS_EINVAL, "helios_mlp_adam: bad hyper-parameters");
+    const double bc1 = 1.0 - pow((double)beta1, step), bc2 = 1.0 - pow((double)beta2, step);
+    hipError_t e = launch_mlp_adam(net->params, net->params_bf16, net->adam_m, net->adam_v, grad, (int64_t)L.count,
+                                   lr, beta1, beta2, eps, (float)bc1, (float)bc2, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_mlp_adam");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
+int helios_warm_start(const helios_atm* atm, const helios_mlp* net, const float* x, const double* logP_net,
+                      double T_iso, double T_lo, double T_hi, double* T_c, int32_t* fallback, void* ws,
+                      size_t ws_bytes, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    NetLayout L;
+    if ((rc = check_net(net, L, false))) return rc;
+    if (!x || !logP_net || !T_c || !fallback || !ws) return fail(HELIOS_EINVAL, "helios_warm_start: NULL argument");
+    if (net->n_out < 2) return fail(HELIOS_EINVAL, "helios_warm_start: the network needs >= 2 outputs");
+    if (!(T_lo <= T_hi) || !(T_iso > 0.0)) return fail(HELIOS_EINVAL, "helios_warm_start: bad temperature bounds");
+    if (atm->n_atm > (1 << 22)) return fail(HELIOS_EINVAL, "n_atm = %d above 2^22", atm->n_atm);
+    NetWs w = net_ws(net, atm->n_atm);
+    if (ws_bytes < w.total) return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, w.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    float* T_net = (float*)(wsb + w.T);
+    hipError_t e = net_forward(net, L, w, wsb, x, atm->n_atm, T_net, true, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_warm_start (network)");
+    e = launch_warm_start(atm, T_net, net->n_out, logP_net, T_iso, T_lo, T_hi, T_c, fallback, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_warm_start (profiles)");
+    g_err[0] = 0;
+    return HELIOS_OK;
 }
 
 int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,

@@ -123,6 +123,41 @@ __device__ inline int class_wpb(const BolArgs& A, int n) {
 }
 
 // Host-side launchers (defined in the .hip files).
+// ------------------------------------------------------ warm-start network
+// C = A B^T: A(m, k) = A[m sam + k sak], B(n, k) = B[n sbn + k sbk], BF16.
+struct GemmArgs {
+    const uint16_t* A;
+    int64_t sam, sak;
+    const uint16_t* B;
+    int64_t sbn, sbk;
+    int M, N, K;
+    const float* bias;     // [N] (kEpiGelu, kEpiLinear)
+    float* out_f;          // FP32 output (pre-activation, output, or weight gradient)
+    int64_t ld_f;
+    uint16_t* out_b;       // BF16 output (activation or back-propagated error)
+    int64_t ld_b;
+    const float* zin;      // pre-activation read by kEpiDGelu
+    int64_t ld_z;
+    const float* oshift;   // optional output scaling (kEpiLinear): y -> oshift + oscale y
+    const float* oscale;
+};
+enum { kEpiGelu = 0, kEpiLinear = 1, kEpiDGelu = 2, kEpiStore = 3 };
+constexpr int kMaxNetOut = 1024;  // largest network output (warm start stages it in LDS)
+
+hipError_t launch_gemm(const GemmArgs& g, int epi, hipStream_t s);
+hipError_t launch_mlp_input(const float* x, int64_t count, int n_in, const float* shift, const float* scale,
+                            uint16_t* X0, hipStream_t s);
+hipError_t launch_mlp_loss(const float* Y, const float* T, int64_t count, int n_out, const float* shift,
+                           const float* scale, uint16_t* dY, double* partial, int nblk, float* loss,
+                           hipStream_t s);
+hipError_t launch_mlp_bias_grad(const uint16_t* D, int64_t rows, int N, float* gb, hipStream_t s);
+hipError_t launch_mlp_adam(float* p, uint16_t* pb, float* m, float* v, const float* grad, int64_t count, float lr,
+                           float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t launch_mlp_sync(const float* p, uint16_t* pb, int64_t count, hipStream_t s);
+hipError_t launch_warm_start(const helios_atm* atm, const float* T_net, int n_out, const double* logP_net,
+                             double T_iso, double T_lo, double T_hi, double* T_c, int32_t* fallback,
+                             hipStream_t s);
+
 hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s);
 hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double* T_c, double* T_pt,
                           hipStream_t s);

@@ -62,6 +62,12 @@ class HeliosReState(ctypes.Structure):
     _fields_ = [("m", _P), ("hist", _P), ("iter", _P)]
 
 
+class HeliosMlp(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_hidden_layers", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("params", _P), ("params_bf16", _P), ("adam_m", _P), ("adam_v", _P),
+                ("in_shift", _P), ("in_scale", _P), ("out_shift", _P), ("out_scale", _P)]
+
+
 _lib = None
 
 
@@ -86,12 +92,23 @@ def lib():
                                    _P, _P, _P]
         L.helios_autotune.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, sz, ctypes.c_int, _P]
         L.helios_sweep_shapes.argtypes = [A, ctypes.c_int, _P, i32]
+        N = ctypes.POINTER(HeliosMlp)
+        L.helios_mlp_param_count.argtypes = [N]
+        L.helios_mlp_param_count.restype = sz
+        L.helios_mlp_workspace_bytes.argtypes = [N, i32]
+        L.helios_mlp_workspace_bytes.restype = sz
+        L.helios_mlp_sync.argtypes = [N, _P]
+        L.helios_mlp_forward.argtypes = [N, _P, i32, _P, _P, sz, _P]
+        L.helios_mlp_backward.argtypes = [N, _P, _P, i32, _P, _P, _P, sz, _P]
+        L.helios_mlp_adam.argtypes = [N, _P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]
+        L.helios_warm_start.argtypes = [A, N, _P, _P, dbl, dbl, dbl, _P, _P, _P, sz, _P]
         L.helios_set_sweep_events.argtypes = [_P, _P]
         L.helios_set_sweep_events.restype = ctypes.c_int
         L.helios_last_error.restype = ctypes.c_char_p
         L.helios_version.restype = i32
         for f in ("helios_grid", "helios_profile", "helios_mix_opacity", "helios_transmission",
-                  "helios_flux", "helios_radeq", "helios_autotune", "helios_sweep_shapes"):
+                  "helios_flux", "helios_radeq", "helios_autotune", "helios_sweep_shapes", "helios_mlp_sync",
+                  "helios_mlp_forward", "helios_mlp_backward", "helios_mlp_adam", "helios_warm_start"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -334,6 +351,156 @@ def radeq(b: Batch, F_bol, T_c, T_pt, m, hist, status, resid=None, opts: REOptio
     o = (opts or REOptions()).c()
     _check(lib().helios_radeq(ctypes.byref(b.desc), _ptr(F_bol), _ptr(T_c), _ptr(T_pt), ctypes.byref(st),
                               ctypes.byref(o), _ptr(status), _ptr(resid), _stream(stream)))
+
+
+# ------------------------------------------------------- warm-start network
+class MLP:
+    """The warm-start network's device state (helios_mlp): FP32 master
+    parameters, their BF16 copy, Adam moments and the normalisation of inputs
+    and outputs.  dims = (n_in, n_hidden, ..., n_hidden, n_out)."""
+
+    def __init__(self, dims=(6, 256, 256, 256, 100), device="cuda", training=True):
+        dims = tuple(int(d) for d in dims)
+        if len(dims) < 3 or len(set(dims[1:-1])) != 1:
+            raise ValueError("dims must be (n_in, H, ..., H, n_out)")
+        dev = torch.device(device)
+        self.dims, self.device = dims, dev
+        self.count = sum(dims[i + 1] * dims[i] + dims[i + 1] for i in range(len(dims) - 1))
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.params = torch.zeros(self.count, **f32)
+        self.params_bf16 = torch.zeros(self.count, dtype=torch.int16, device=dev)
+        self.adam_m = torch.zeros(self.count, **f32) if training else None
+        self.adam_v = torch.zeros(self.count, **f32) if training else None
+        self.in_shift = torch.zeros(dims[0], **f32)
+        self.in_scale = torch.ones(dims[0], **f32)
+        self.out_shift = torch.zeros(dims[-1], **f32)
+        self.out_scale = torch.ones(dims[-1], **f32)
+        self.desc = HeliosMlp(dims[0], dims[1], len(dims) - 2, dims[-1], _ptr(self.params), _ptr(self.params_bf16),
+                              _ptr(self.adam_m), _ptr(self.adam_v), _ptr(self.in_shift), _ptr(self.in_scale),
+                              _ptr(self.out_shift), _ptr(self.out_scale))
+        n = int(lib().helios_mlp_param_count(ctypes.byref(self.desc)))
+        if n != self.count:
+            raise HeliosError(-1, f"parameter count {n} != {self.count}")
+        self._ws = {}
+        self.grad = torch.zeros(self.count, **f32)
+        self.loss = torch.zeros(1, **f32)
+        self.step_count = 0
+
+    def layers(self, flat=None):
+        """[(W, b)] views of a flat parameter vector (default: the master parameters)."""
+        flat = self.params if flat is None else flat
+        out, off = [], 0
+        for i in range(len(self.dims) - 1):
+            o, n = self.dims[i + 1], self.dims[i]
+            out.append((flat[off:off + o * n].view(o, n), flat[off + o * n:off + o * n + o]))
+            off += o * n + o
+        return out
+
+    def init(self, seed=0):
+        """He-normal hidden weights, scaled-down output layer, zero biases."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for i in range(len(self.dims) - 1):
+            o, n = self.dims[i + 1], self.dims[i]
+            sd = np.sqrt(2.0 / n) if i < len(self.dims) - 2 else np.sqrt(1.0 / n) * 0.1
+            parts += [rng.normal(0.0, sd, o * n), np.zeros(o)]
+        self.set_params(np.concatenate(parts))
+        self.adam_m is not None and self.adam_m.zero_()
+        self.adam_v is not None and self.adam_v.zero_()
+        self.step_count = 0
+
+    def set_params(self, flat):
+        self.params.copy_(torch.as_tensor(np.asarray(flat, np.float32), device=self.device))
+        _check(lib().helios_mlp_sync(ctypes.byref(self.desc), _stream(None)))
+
+    def set_norm(self, in_shift, in_scale, out_shift, out_scale):
+        for t, v in ((self.in_shift, in_shift), (self.in_scale, in_scale), (self.out_shift, out_shift),
+                     (self.out_scale, out_scale)):
+            t.copy_(torch.as_tensor(np.asarray(v, np.float32), device=self.device))
+
+    def norm(self):
+        return {k: getattr(self, k).cpu().numpy().astype(np.float64)
+                for k in ("in_shift", "in_scale", "out_shift", "out_scale")}
+
+    def workspace(self, batch):
+        ws = self._ws.get(batch)
+        if ws is None:
+            nbytes = int(lib().helios_mlp_workspace_bytes(ctypes.byref(self.desc), int(batch)))
+            if nbytes == 0:
+                raise HeliosError(-1, f"bad batch {batch}")
+            ws = self._ws[batch] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return ws
+
+    def _rows(self, x, width, name):
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        if x.dim() != 2 or x.shape[1] != width:
+            raise ValueError(f"{name} must be [batch][{width}], got {tuple(x.shape)}")
+        return x
+
+    def forward(self, x, out=None, stream=None):
+        x = self._rows(x, self.dims[0], "x")
+        B = x.shape[0]
+        out = torch.empty(B, self.dims[-1], dtype=torch.float32, device=self.device) if out is None else out
+        if out.dtype != torch.float32 or out.numel() != B * self.dims[-1] or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 [batch][n_out] tensor")
+        ws = self.workspace(B)
+        _check(lib().helios_mlp_forward(ctypes.byref(self.desc), _ptr(x), B, _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream(stream)))
+        return out
+
+    def backward(self, x, T, stream=None):
+        """Loss (device scalar) and gradient (flat, device) on a batch."""
+        x = self._rows(x, self.dims[0], "x")
+        T = self._rows(T, self.dims[-1], "T")
+        B = x.shape[0]
+        if T.shape[0] != B:
+            raise ValueError("x and T need the same number of rows")
+        ws = self.workspace(B)
+        _check(lib().helios_mlp_backward(ctypes.byref(self.desc), _ptr(x), _ptr(T), B, _ptr(self.loss),
+                                         _ptr(self.grad), _ptr(ws), ws.numel(), _stream(stream)))
+        return self.loss, self.grad
+
+    def adam(self, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step_count += 1
+        g = self.grad if grad is None else grad
+        if g.dtype != torch.float32 or g.numel() != self.count or not g.is_contiguous():
+            raise ValueError("grad must be a contiguous float32 vector of param_count entries")
+        _check(lib().helios_mlp_adam(ctypes.byref(self.desc), _ptr(g), self.step_count, lr, beta1, beta2, eps,
+                                     _stream(stream)))
+
+    def train_step(self, x, T, lr=1e-3, stream=None):
+        loss, _ = self.backward(x, T, stream=stream)
+        self.adam(lr=lr, stream=stream)
+        return loss
+
+    def save(self, path):
+        np.savez(path, dims=np.array(self.dims), params=self.params.cpu().numpy(),
+                 **{k: v.astype(np.float32) for k, v in self.norm().items()})
+
+    @classmethod
+    def load(cls, path, device="cuda", training=False):
+        d = np.load(path)  # plain arrays only, no pickled objects
+        net = cls(tuple(int(v) for v in d["dims"]), device=device, training=training)
+        net.set_norm(d["in_shift"], d["in_scale"], d["out_shift"], d["out_scale"])
+        net.set_params(d["params"])
+        return net
+
+
+def warm_start(b: Batch, net: MLP, x, logP_net, T_c, fallback, T_iso=1000.0, T_lo=10.0, T_hi=1.0e4, stream=None):
+    """Initial layer temperatures of every atmosphere of the batch from the
+    network (helios_warm_start); fallback[a] = 1 where the isothermal start
+    was taken instead."""
+    x = net._rows(x, net.dims[0], "x")
+    lp = torch.as_tensor(logP_net, dtype=torch.float64, device=b.device).contiguous()
+    if x.shape[0] != b.n_atm or lp.numel() != net.dims[-1]:
+        raise ValueError("x needs one row per atmosphere and logP_net one value per network output")
+    if T_c.numel() != b.total_n or fallback.numel() != b.n_atm or fallback.dtype != torch.int32:
+        raise ValueError("T_c needs one value per layer, fallback one int32 per atmosphere")
+    ws = net.workspace(b.n_atm)
+    _check(lib().helios_warm_start(ctypes.byref(b.desc), ctypes.byref(net.desc), _ptr(x), _ptr(lp), float(T_iso),
+                                   float(T_lo), float(T_hi), _ptr(T_c), _ptr(fallback), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return T_c, fallback
 
 
 # ------------------------------------------------------------ RE buffers

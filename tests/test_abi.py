@@ -54,6 +54,8 @@ int main(void) {
   printf("helios_ktab %zu\\n", sizeof(helios_ktab));
   printf("helios_re_opts %zu\\n", sizeof(helios_re_opts));
   printf("helios_re_state %zu\\n", sizeof(helios_re_state));
+  printf("helios_mlp %zu\\n", sizeof(helios_mlp));
+  P(helios_mlp, params) P(helios_mlp, out_scale)
   P(helios_atm, T_int) P(helios_atm, status) P(helios_atm, P_pt) P(helios_ktab, k) P(helios_ktab, mmw) P(helios_ktab, species_mass)
   P(helios_re_opts, T_floor) P(helios_re_opts, fpre_p) P(helios_re_state, iter)
   return 0;
@@ -66,6 +68,9 @@ int main(void) {
     assert int(got["helios_ktab"]) == ctypes.sizeof(H.HeliosKtab)
     assert int(got["helios_re_opts"]) == ctypes.sizeof(H.HeliosReOpts)
     assert int(got["helios_re_state"]) == ctypes.sizeof(H.HeliosReState)
+    assert int(got["helios_mlp"]) == ctypes.sizeof(H.HeliosMlp)
+    assert int(got["helios_mlp.params"]) == H.HeliosMlp.params.offset
+    assert int(got["helios_mlp.out_scale"]) == H.HeliosMlp.out_scale.offset
     assert int(got["helios_atm.T_int"]) == H.HeliosAtm.T_int.offset
     assert int(got["helios_atm.status"]) == H.HeliosAtm.status.offset
     assert int(got["helios_atm.P_pt"]) == H.HeliosAtm.P_pt.offset
