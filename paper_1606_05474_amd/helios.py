@@ -537,15 +537,47 @@ class Solver:
         self.iters = torch.zeros(b.n_atm, dtype=torch.int32, device=dev)
         self.b = b.with_status(self.status)
         self._graph = None
+        self._warm = None
+        self._T_iso = 1000.0
         grid(b)
 
-    def reset(self, T_init):
-        self.T_c.copy_(torch.as_tensor(T_init, dtype=torch.float64, device=self.b.device))
+    def _reset_state(self):
         self.F_up_g.zero_()
         self.m.fill_(1.0)
         self.hist.zero_()
         self.status.zero_()
         self.iters.zero_()
+        profile(self.b, self.T_c, self.T_pt)
+
+    def reset(self, T_init):
+        """Start every atmosphere from the given layer temperatures."""
+        self.T_c.copy_(torch.as_tensor(T_init, dtype=torch.float64, device=self.b.device))
+        self._warm = None
+        self._reset_state()
+
+    def warm_reset(self, net: MLP, x, logP_net, T_iso=1000.0, T_lo=10.0, T_hi=1.0e4):
+        """Start from the network's profiles (helios_warm_start); atmospheres
+        whose network profile is unusable start isothermal at T_iso.
+        Returns the per-atmosphere fallback flags (numpy)."""
+        fb = torch.zeros(self.b.n_atm, dtype=torch.int32, device=self.b.device)
+        warm_start(self.b, net, x, logP_net, self.T_c, fb, T_iso=T_iso, T_lo=T_lo, T_hi=T_hi)
+        self._reset_state()
+        fb = fb.cpu().numpy()
+        self._warm = fb == 0
+        self._T_iso = float(T_iso)
+        return fb
+
+    def restart(self, which, T_iso=1000.0):
+        """Restart the listed atmospheres from the isothermal profile (their
+        update counters keep counting); the others are untouched."""
+        b = self.b
+        for a in which:
+            a = int(a)
+            self.T_c[int(b.lay_off[a]):int(b.lay_off[a + 1])] = T_iso
+            self.m[int(b.lay_off[a]):int(b.lay_off[a + 1])] = 1.0
+            self.hist[int(b.lay_off[a]):int(b.lay_off[a + 1])] = 0
+            self.F_up_g[int(b.cell_off[a]):int(b.cell_off[a + 1])] = 0
+            self.status[a] = ATM_RUNNING
         profile(self.b, self.T_c, self.T_pt)
 
     def step(self, stream=None):
@@ -585,19 +617,16 @@ class Solver:
     def replay(self):
         self._graph[0].replay()
 
-    def solve(self, T_init, max_iter=200, check_every=10, graph=False):
-        """Iterate until every atmosphere converged or max_iter temperature
-        updates were taken.  Returns (converged flags, updates taken) per
-        atmosphere as numpy arrays; the counts come from the device, so
-        checking only every ``check_every`` steps loses nothing (converged
-        atmospheres are frozen).  With graph=True the blocks of check_every
-        iterations are replayed from one captured graph (the last block may
-        run a few iterations past max_iter + 1 calls; frozen atmospheres make
-        that harmless apart from the time)."""
-        self.reset(T_init)
+    def run(self, max_iter=200, check_every=10, graph=False, restart_after=None):
+        """Iterate from the current state until every atmosphere converged or
+        about max_iter steps were taken (see solve).  With restart_after, a
+        warm-started atmosphere still running after that many updates is
+        restarted once from the isothermal profile.  Returns (converged
+        flags, updates taken, restarted flags) as numpy arrays."""
         if graph and (self._graph is None or self._graph[1] != check_every):
             # capturing enqueues nothing that runs; the state is untouched
             self.capture(check_every)
+        restarted = np.zeros(self.b.n_atm, bool)
         done = 0
         while done <= max_iter:
             if graph:
@@ -609,7 +638,27 @@ class Solver:
                     self.step()
                 done += k
             st = self.status.cpu().numpy()
+            if restart_after is not None and self._warm is not None:
+                it = self.iters.cpu().numpy()
+                late = np.where(self._warm & ~restarted & (st != ATM_CONVERGED) & (it >= restart_after))[0]
+                if late.size:
+                    self.restart(late, self._T_iso)
+                    restarted[late] = True
+                    st = self.status.cpu().numpy()
             if np.all(st != ATM_RUNNING):
                 break
         st = self.status.cpu().numpy()
-        return st == ATM_CONVERGED, self.iters.cpu().numpy()
+        return st == ATM_CONVERGED, self.iters.cpu().numpy(), restarted
+
+    def solve(self, T_init, max_iter=200, check_every=10, graph=False):
+        """Iterate until every atmosphere converged or max_iter temperature
+        updates were taken.  Returns (converged flags, updates taken) per
+        atmosphere as numpy arrays; the counts come from the device, so
+        checking only every ``check_every`` steps loses nothing (converged
+        atmospheres are frozen).  With graph=True the blocks of check_every
+        iterations are replayed from one captured graph (the last block may
+        run a few iterations past max_iter + 1 calls; frozen atmospheres make
+        that harmless apart from the time)."""
+        self.reset(T_init)
+        conv, iters, _ = self.run(max_iter, check_every, graph)
+        return conv, iters

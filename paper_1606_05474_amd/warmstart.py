@@ -1,0 +1,205 @@
+"""The learned warm start: training data from the solver, training of the
+network on the device, and its evaluation against the isothermal start.
+
+    python -m paper_1606_05474_amd.warmstart generate --seed 4 --count 20000 --out data.npz
+    python -m paper_1606_05474_amd.warmstart train --data data.npz --test test.npz --out mlp.npz
+    python -m paper_1606_05474_amd.warmstart evaluate --weights mlp.npz --seed 40 --count 256
+
+* generate: atmospheres described by six parameters (workloads.learned_workload:
+  100 layers, 1000 strided bins, 20 g) are solved to radiative equilibrium
+  from the isothermal 1000 K start by the batched solver, in chunks; the
+  converged layer temperatures are the targets.
+* train: the network (6 -> 256 x 3 -> 100, GELU) is fitted by the library's
+  BF16 forward/backward kernels and its Adam step, mean squared error in
+  normalised units; normalisation constants come from the training set.
+* evaluate: the same atmospheres solved from the isothermal start and from
+  the network's start (helios_warm_start, isothermal fallback, restart after
+  a cap); reports updates to converge and wall time for both.
+
+Everything that computes runs in libhelios; this module only moves arrays.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import helios as H
+from . import workloads as W
+
+DIMS = (6, 256, 256, 256, 100)
+
+
+def generate(seed: int, count: int, start: int = 0, chunk: int = 1024, prec: int = H.MIXED, max_iter: int = 400,
+             n: int = 100, nb: int = 1000, log=print):
+    """Converged profiles of atmospheres start..start+count-1 of a parameter
+    set.  Returns dict(params [N][6] f32, T [N][n] f64, converged [N], updates
+    [N], logP [n] log10 dyn cm^-2 of the layer centres, seconds)."""
+    kt = W.table_ktab(2, nbt=3000)
+    ktd = H.KTable(kt)
+    P, T, conv, its = [], [], [], []
+    t0 = time.perf_counter()
+    logP = None
+    for c0 in range(start, start + count, chunk):
+        c = min(chunk, start + count - c0)
+        atms, _ = W.learned_workload(seed, c, c0, n=n, nb=nb, ktab=kt)
+        b = H.Batch(atms)
+        s = H.Solver(b, ktd, prec=prec)
+        T0 = np.concatenate([a["T0"] for a in atms])
+        cv, it = s.solve(T0, max_iter=max_iter, check_every=10, graph=True)
+        P.append(np.stack([a["params"] for a in atms]))
+        T.append(s.T_c.cpu().numpy().reshape(c, n))
+        conv.append(cv)
+        its.append(it)
+        logP = np.log10(atms[0]["P_c"])
+        log(f"chunk {c0}..{c0 + c - 1}: {int(cv.sum())}/{c} converged, median updates {np.median(it):.0f}, "
+            f"{time.perf_counter() - t0:.0f} s")
+        del s, b
+        torch.cuda.empty_cache()
+    return {"params": np.concatenate(P), "T": np.concatenate(T), "converged": np.concatenate(conv),
+            "updates": np.concatenate(its), "logP": logP, "seconds": time.perf_counter() - t0}
+
+
+def train(data: dict, test: dict | None = None, epochs: int = 400, batch: int = 512, lr: float = 1e-3,
+          seed: int = 0, log=print):
+    """Fit the network to the converged profiles of `data` on the device.
+    Returns (net, history)."""
+    ok = data["converged"].astype(bool)
+    x = data["params"][ok].astype(np.float32)
+    T = data["T"][ok].astype(np.float32)
+    net = H.MLP(DIMS)
+    net.init(seed)
+    net.set_norm(x.mean(0), 1.0 / (x.std(0) + 1e-6), T.mean(0), T.std(0) + 1e-3)
+    net.logP = np.asarray(data["logP"], np.float64)
+    xd = torch.as_tensor(x, device="cuda")
+    Td = torch.as_tensor(T, device="cuda")
+    N = x.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    hist = []
+    t0 = time.perf_counter()
+    steps_per_epoch = max(1, N // batch)
+    total = epochs * steps_per_epoch
+    k = 0
+    for ep in range(epochs):
+        perm = torch.randperm(N, device="cuda", generator=g)
+        for j in range(steps_per_epoch):
+            idx = perm[j * batch:(j + 1) * batch]
+            # cosine decay of the step size over the run
+            rate = lr * 0.5 * (1.0 + np.cos(np.pi * k / total))
+            net.train_step(xd[idx].contiguous(), Td[idx].contiguous(), lr=float(max(rate, lr * 0.01)))
+            k += 1
+        if ep % 50 == 0 or ep == epochs - 1:
+            rec = {"epoch": ep, "train_rms_K": rms_error(net, x, T)}
+            if test is not None:
+                tok = test["converged"].astype(bool)
+                rec["test_rms_K"] = rms_error(net, test["params"][tok], test["T"][tok])
+            rec["seconds"] = time.perf_counter() - t0
+            hist.append(rec)
+            log(json.dumps(rec))
+    return net, hist
+
+
+def rms_error(net: H.MLP, x, T) -> float:
+    """Root-mean-square temperature error of the network's profiles (K)."""
+    pred = net.forward(np.asarray(x, np.float32)).cpu().numpy().astype(np.float64)
+    return float(np.sqrt(np.mean((pred - np.asarray(T, np.float64)) ** 2)))
+
+
+def save(net: H.MLP, path: str, meta: dict | None = None):
+    np.savez(path, dims=np.array(net.dims), params=net.params.cpu().numpy(), logP=net.logP,
+             meta=np.frombuffer(json.dumps(meta or {}).encode(), np.uint8),
+             **{k: v.astype(np.float32) for k, v in net.norm().items()})
+
+
+def load(path: str) -> H.MLP:
+    d = np.load(path)  # plain arrays only
+    net = H.MLP(tuple(int(v) for v in d["dims"]), training=False)
+    net.set_norm(d["in_shift"], d["in_scale"], d["out_shift"], d["out_scale"])
+    net.set_params(d["params"])
+    net.logP = d["logP"].astype(np.float64)
+    return net
+
+
+def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec: int = H.FP64, max_iter: int = 400,
+             restart_after: int = 150, n: int = 100, nb: int = 1000, log=print):
+    """Updates to converge and wall time from the isothermal start and from
+    the network's start, same atmospheres, same tolerance."""
+    kt = W.table_ktab(2, nbt=3000)
+    atms, _ = W.learned_workload(seed, count, start, n=n, nb=nb, ktab=kt)
+    b = H.Batch(atms)
+    s = H.Solver(b, H.KTable(kt), prec=prec)
+    x = np.stack([a["params"] for a in atms])
+    T0 = np.concatenate([a["T0"] for a in atms])
+    out = {}
+    for mode in ("isothermal", "network"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "isothermal":
+            s.reset(T0)
+            conv, it, rs = s.run(max_iter, 10, graph=True)
+            fb = np.zeros(count, np.int32)
+        else:
+            fb = s.warm_reset(net, x, net.logP)
+            conv, it, rs = s.run(max_iter, 10, graph=True, restart_after=restart_after)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[mode] = {"converged": int(conv.sum()), "count": count, "median_updates": float(np.median(it)),
+                     "mean_updates": float(np.mean(it)), "median_updates_converged":
+                         float(np.median(it[conv])) if conv.any() else None,
+                     "fallbacks": int(fb.sum()), "restarts": int(rs.sum()), "seconds": wall,
+                     "converged_per_s": float(conv.sum()) / wall}
+        log(mode, json.dumps(out[mode]))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("generate")
+    g.add_argument("--seed", type=int, default=4)
+    g.add_argument("--count", type=int, default=20000)
+    g.add_argument("--start", type=int, default=0)
+    g.add_argument("--chunk", type=int, default=1024)
+    g.add_argument("--prec", choices=["fp64", "mixed"], default="mixed")
+    g.add_argument("--max-iter", type=int, default=400)
+    g.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--data", required=True, nargs="+")
+    t.add_argument("--test")
+    t.add_argument("--epochs", type=int, default=400)
+    t.add_argument("--batch", type=int, default=512)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--out", required=True)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--seed", type=int, default=40)
+    e.add_argument("--count", type=int, default=256)
+    e.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
+    e.add_argument("--restart-after", type=int, default=150)
+    e.add_argument("--max-iter", type=int, default=400)
+    a = ap.parse_args(argv)
+    H.lib()
+    log = lambda *v: print(*v, flush=True)  # noqa: E731
+    if a.cmd == "generate":
+        d = generate(a.seed, a.count, a.start, a.chunk, H.MIXED if a.prec == "mixed" else H.FP64, a.max_iter, log=log)
+        np.savez(a.out, **d)
+    elif a.cmd == "train":
+        parts = [dict(np.load(p)) for p in a.data]
+        data = {k: np.concatenate([p[k] for p in parts]) for k in ("params", "T", "converged", "updates")}
+        data["logP"] = parts[0]["logP"]
+        test = dict(np.load(a.test)) if a.test else None
+        net, hist = train(data, test, a.epochs, a.batch, a.lr, log=log)
+        save(net, a.out, {"history": hist, "n_train": int(data["converged"].sum())})
+    else:
+        net = load(a.weights)
+        evaluate(net, a.seed, a.count, prec=H.MIXED if a.prec == "mixed" else H.FP64, max_iter=a.max_iter,
+                 restart_after=a.restart_after, log=log)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -18,6 +18,11 @@ Gauss points, 0.3-30 micron bins log-spaced, blackbody star):
   batch     uneven atmospheres (n in 50..200, bins 400..3000 as strided
             subsets of the 3000-bin tables), per-atmosphere irradiation,
             internal temperature and gravity
+  learned   atmospheres described by six parameters (irradiation and
+            internal temperature, gravity, metallicity, C/O, opacity scale)
+            with a smooth stand-in chemistry, for the warm-start network
+            (100 layers x 1000 bins) and the production sweep (200 layers x
+            3000 bins)
 """
 from __future__ import annotations
 
@@ -184,4 +189,75 @@ def batch_workload(seed: int = 3, n_atm: int = 512, n_range=(50, 200), nb_range=
         T_int = float(rng.uniform(100.0, 600.0))
         grav = float(10.0 ** rng.uniform(0.7, 1.7)) * 100.0
         atms.append(spectral_atmosphere(rng, n, lc_full, dl_full, nb, ng, T_irr, T_int, grav))
+    return atms, ktab
+
+
+# ------------------------------------------------------ learned warm start
+PARAM_NAMES = ("T_irr", "T_int", "log10_g", "metallicity", "C_to_O", "log10_opacity_scale")
+SOLAR_C, SOLAR_O = 2.5e-4, 5.0e-4  # number ratios to H2 (stand-in solar values)
+
+
+def draw_params(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Six parameters per atmosphere [count][6], float32, drawn per index i
+    from default_rng([seed, 1, i]) in this order: T_irr ~ U(800, 2800) K,
+    T_int ~ U(100, 600) K, log10 g[m s^-2] ~ U(0.7, 1.7), [M/H] ~ U(-1, 2),
+    C/O ~ U(0.3, 1.5), log10 opacity scale ~ U(-1, 1)."""
+    out = np.empty((count, 6), np.float64)
+    for k in range(count):
+        rng = np.random.default_rng([seed, 1, start + k])
+        out[k] = [rng.uniform(800.0, 2800.0), rng.uniform(100.0, 600.0), rng.uniform(0.7, 1.7),
+                  rng.uniform(-1.0, 2.0), rng.uniform(0.3, 1.5), rng.uniform(-1.0, 1.0)]
+    return out.astype(np.float32)
+
+
+def standin_vmr(lp_bar: np.ndarray, metallicity: float, c_to_o: float) -> np.ndarray:
+    """Volume mixing ratios of CO, CO2, H2O, CH4 at log10 P (bar) for a
+    metallicity and C/O: oxygen n_O = 5e-4 10^[M/H], carbon n_C = C/O n_O;
+    the carbon sits in CH4 at depth and in CO (90 %) and CO2 (10 %) aloft,
+    switching smoothly around 1 bar (logistic in log P, width 0.75 dex);
+    water takes the oxygen left over.  Each ratio is clipped to
+    [1e-8, 1e-3].  A smooth stand-in for an equilibrium-chemistry table,
+    input construction only."""
+    n_O = SOLAR_O * 10.0 ** metallicity
+    n_C = c_to_o * n_O
+    f_deep = 1.0 / (1.0 + np.exp(-lp_bar / 0.75))
+    ch4 = n_C * f_deep
+    co = 0.9 * n_C * (1.0 - f_deep)
+    co2 = 0.1 * n_C * (1.0 - f_deep)
+    h2o = np.maximum(n_O - co - 2.0 * co2, 0.0)
+    return np.clip(np.stack([co, co2, h2o, ch4]), 1e-8, 1e-3)
+
+
+def param_atmosphere(params, index_seed, n: int, lambda_c_full: np.ndarray, dlambda_full: np.ndarray, nb: int,
+                     ng: int = N_G) -> dict:
+    """The atmosphere of one parameter row: stand-in chemistry times the
+    opacity scale, w0 ~ U(0, 0.9) and g0 ~ U(0, 0.5) per (bin, layer) from
+    default_rng(index_seed), T_star = 5000 K, isothermal 1000 K start."""
+    T_irr, T_int, lg, mh, co, lsc = (float(v) for v in params)
+    rng = np.random.default_rng(index_seed)
+    if nb == lambda_c_full.size:
+        idx, lc, dl = np.arange(nb, dtype=np.int32), lambda_c_full.copy(), dlambda_full.copy()
+    else:
+        idx, lc, dl = subset_bins(lambda_c_full, nb)
+    vmr = standin_vmr(point_log10p_bar(n), mh, co) * 10.0 ** lsc
+    return {
+        "n": n, "ng": ng, "P_c": pressure_centres(n), "grav": 10.0 ** lg * 100.0,
+        "T_star": 5000.0, "T_irr": T_irr, "T_int": T_int, "mmw": MMW,
+        "lambda_c": lc, "dlambda": dl, "bin_index": idx,
+        "w0": rng.uniform(0.0, 0.9, size=(nb, n)), "g0": rng.uniform(0.0, 0.5, size=(nb, n)),
+        "vmr": vmr, "T0": np.full(n, 1000.0), "params": np.asarray(params, np.float32),
+    }
+
+
+def learned_workload(seed: int, count: int, start: int = 0, n: int = 100, nb: int = 1000, ng: int = N_G,
+                     ktab: dict | None = None):
+    """Atmospheres start..start+count-1 of a parameter set: seed 4 is the
+    training set and 40 the held-out set of the warm-start network (100
+    layers, 1000 strided bins); seed 5 with n = 200, nb = 3000 is the
+    production sweep.  Returns (atms, ktab)."""
+    if ktab is None:
+        ktab = table_ktab(2, nbt=3000, ng=ng)
+    lc_full, dl_full = bins(ktab["k"].shape[3])
+    P = draw_params(seed, count, start)
+    atms = [param_atmosphere(P[k], [seed, 2, start + k], n, lc_full, dl_full, nb, ng) for k in range(count)]
     return atms, ktab
