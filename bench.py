@@ -41,14 +41,14 @@ def sweep_source_hash() -> str:
 def sweep_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
     """Bytes one flux-sweep launch must move for one atmosphere: opacities at
     the points, the upward-flux warm start in (the TOA point is never read)
-    and out, the Planck values per (bin, point), w0 and g0 per (bin, layer),
-    the two boundary fluxes and the Gauss weights, and the two Gauss-summed
-    per-bin outputs (float64)."""
+    and out, the Planck values per (bin, point) (float64 in both precisions),
+    w0 and g0 per (bin, layer), the two boundary fluxes and the Gauss
+    weights, and the two Gauss-summed per-bin outputs (float64)."""
     npt = 2 * n + 1
     per_bin = (ng * npt * rbytes            # kappa
                + ng * (npt - 1) * rbytes    # F_up warm start in
                + ng * npt * rbytes          # F_up out
-               + npt * rbytes               # B
+               + npt * 8                    # B
                + 2 * n * 8                  # w0, g0
                + 2 * 8                      # F_top, F_int
                + 2 * npt * 8)               # F_up_bin, F_dn_bin
@@ -63,6 +63,9 @@ def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict):
     b = H.Batch([atm])
     ktd = H.KTable(kt)
     s = H.Solver(b, ktd, prec=prec)
+    s.reset(atm["T0"])
+    s.autotune()  # the library's sweep-shape autotuner (kept for the process)
+    shape = H.sweep_shapes(s.b, prec)
     s.reset(atm["T0"])
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -92,6 +95,7 @@ def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict):
         "sweep_ms": sweep_ms,
         "sweep_bytes": alg,
         "sweep_gbs": alg / (sweep_ms * 1e-3) / 1e9,
+        "shape": {str(k): list(v) for k, v in shape.items()},
         "status": int(s.status[0].item()),
         "updates": int(s.iters[0].item()),
     }
@@ -200,6 +204,56 @@ def batch_main(args):
     return 0
 
 
+def production_main(args):
+    """Converged atmospheres per second: the production form (batched chunks,
+    network warm start with isothermal fallback, mixed precision) against the
+    plain form (FP64, one atmosphere at a time, isothermal start) on the same
+    parameter set (seed 5: 200 layers x 3000 bins x 20 g), same tolerance."""
+    import numpy as np
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import warmstart as WS
+
+    H.lib()
+    if not os.path.exists(args.weights):
+        print(f"no trained warm-start network at {args.weights}", file=sys.stderr)
+        return 2
+    net = WS.load(args.weights)
+    log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
+    prod = WS.production(net, seed=5, count=args.n_atm, chunk=args.chunk, max_iter=args.max_iter,
+                         keep_T=args.plain_count, log=log)
+    base = WS.plain(seed=5, count=args.plain_count, max_iter=args.max_iter, keep_T=args.plain_count, log=log)
+    both = [k for k in range(args.plain_count) if base["conv_flags"][k] and prod["conv_flags"][k]]
+    dT = [float(np.abs(prod["T"][k] - base["T"][k]).max()) for k in both]
+    units = 200 * 3000 * 20
+    line = {
+        "metric": "converged atmospheres/s",
+        "value": prod["converged_per_s"],
+        "unit": "atmospheres/s",
+        "n_gpus": 1, "steps": int(prod["updates"].max()), "warmup": 0,
+        "ms_per_step": prod["seconds"] / max(1, int(prod["updates"].sum())) * args.chunk * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n_atm} parameter-described atmospheres (seed 5), 200 layers x 3000 bins x "
+                               f"20 g, chunks of {args.chunk}, mixed precision, network warm start with isothermal "
+                               "fallback and restart after 150 updates, tolerance 1e-3 sigma T_int^4",
+                   "n_atm": args.n_atm, "chunk": args.chunk},
+        "production": {"converged": prod["converged"], "count": prod["count"], "seconds": prod["seconds"],
+                       "median_updates": float(np.median(prod["updates"])), "fallbacks": prod["fallbacks"],
+                       "restarts": prod["restarts"],
+                       "layer_bin_g_per_s": float(prod["updates"].sum()) * units / prod["seconds"]},
+        "plain_fp64_one_at_a_time": {"converged": base["converged"], "count": base["count"],
+                                     "seconds": base["seconds"], "converged_per_s": base["converged_per_s"],
+                                     "median_updates": float(np.median(base["updates"]))},
+        "speedup_converged_per_s": prod["converged_per_s"] / base["converged_per_s"]
+        if base["converged_per_s"] > 0 else None,
+        "max_abs_dT_vs_plain_fp64_K": {"atmospheres": len(both), "max": max(dT) if dT else None,
+                                       "median": float(np.median(dT)) if dT else None},
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def cpu_baseline(atm: dict, kt: dict, budget_s: float = 10.0):
     """The FP64 oracle as it stands, timed on the host: whole RE iterations
     (profile, opacity, flux with 1 + 4 passes, RE step) of the same
@@ -256,10 +310,16 @@ def main(argv=None):
                     help="precisions to run (profiling runs pick one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["spectral", "batch"], default="spectral",
+    ap.add_argument("--workload", choices=["spectral", "batch", "production"], default="spectral",
                     help="spectral: one 100-layer x 3000-bin atmosphere (the headline line); "
-                         "batch: the uneven 512-atmosphere batch, throughput and solve to convergence")
-    ap.add_argument("--n-atm", type=int, default=512, help="atmospheres in the batch workload")
+                         "batch: the uneven 512-atmosphere batch, throughput and solve to convergence; "
+                         "production: converged atmospheres/s, batched + network + mixed against plain FP64")
+    ap.add_argument("--chunk", type=int, default=256, help="atmospheres per device batch (production)")
+    ap.add_argument("--plain-count", type=int, default=64, help="atmospheres solved by the plain form")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1606_05474_amd", "data", "warmstart_mlp.npz"),
+                    help="trained warm-start network (production)")
+    ap.add_argument("--n-atm", type=int, default=None,
+                    help="atmospheres (batch: 512 by default, production: 4096)")
     ap.add_argument("--max-iter", type=int, default=300, help="update cap of the batch solve")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -288,8 +348,12 @@ def main(argv=None):
         print(json.dumps({"copy_bytes_per_launch": 2 * xs[0].numel() * 4, "launches": len(xs)}))
         return 0
     H.lib()  # fails loudly if the native library is missing
+    if args.n_atm is None:
+        args.n_atm = 4096 if args.workload == "production" else 512
     if args.workload == "batch":
         return batch_main(args)
+    if args.workload == "production":
+        return production_main(args)
     kt = W.table_ktab(2)
     atm, _ = W.spectral_workload(ktab=kt)
     fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt) if args.prec in ("both", "fp64") else None
@@ -318,10 +382,11 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep)", "achieved": fp64["sweep_gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fp64["sweep_gbs"] / HBM_PEAK_GBS,
                      "traffic": tr, "algorithmic_bytes_per_launch": fp64["sweep_bytes"],
-                     "avg_launch_ms": fp64["sweep_ms"]},
+                     "avg_launch_ms": fp64["sweep_ms"], "sweep_shape": fp64["shape"]},
         "mixed_precision": {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
                             "sweep_ms": mixed["sweep_ms"], "sweep_gbs": mixed["sweep_gbs"],
-                            "frac": mixed["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic_entry("mixed")},
+                            "frac": mixed["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic_entry("mixed"),
+                            "sweep_shape": mixed["shape"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(atm, kt, args.cpu_budget)

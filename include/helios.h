@@ -181,10 +181,19 @@ size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec);
  *   w0, g0    [bin x layer] single-scattering albedo and asymmetry
  *   n_scat    additional scattering passes (paper: 4 in the RE loop, 80 post)
  *   D         diffusivity factor (paper: 2)
- *   F_up_g    cell array, in: warm start (zeros first), out: upward fluxes
- *   F_dn_g    cell array, out: downward fluxes (may be NULL)
+ *   F_up_g    cell array, in: warm start, out: upward fluxes of the last pass
+ *   F_dn_g    cell array, out: downward fluxes of the last pass (may be NULL)
  *   F_up_bin, F_dn_bin  [bin x point] double, Gauss-summed fluxes
- *   F_bol     [sum npt][3] double: bolometric up, down, up - down
+ *   F_bol     [sum npt][3] double: bolometric up, down, and net = up - down
+ *             (the net flux is summed from the deviations below, in which
+ *             the Planck term cancels, not by subtracting the two totals)
+ * The per-g arrays hold deviations from the isothermal solution:
+ * value = F - (2 pi / D) B(lambda_bin, T_point), with B the Planck function
+ * at the bin centre and the point's temperature.  A zero array is the
+ * isothermal start F = (2 pi / D) B; between temperature iterations the
+ * warm start therefore keeps each column's deviation from its local Planck
+ * flux (which is also what the sweeps carry: both sources become linear in
+ * the Planck difference across a sublayer). 
  *   ws        workspace of at least helios_workspace_bytes(atm, prec) bytes
  * Downward fluxes carry no state between calls: each pass recomputes them
  * from the TOA condition and the previous upward fluxes. */

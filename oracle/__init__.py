@@ -52,6 +52,7 @@ def _load():
         lib.ref_profile.argtypes = [i, P, P, P]
         lib.ref_planck.argtypes = [d, d]
         lib.ref_planck.restype = d
+        lib.ref_planck_table.argtypes = [i, i, P, P, P]
         lib.ref_boundary.argtypes = [i, P, P, d, d, d, P, P]
         lib.ref_mix_table.argtypes = [i, P, P, i, P, P, d, i, i, d, d, d, d, i, i, P, i, P, P]
         lib.ref_mix_powerlaw.argtypes = [i, P, P, i, P, P, d, i, i, P, d, d, d, d, i, P, P]
@@ -92,6 +93,26 @@ def sigma_sb() -> float:
 
 def planck(lam: float, T: float) -> float:
     return _load().ref_planck(float(lam), float(T))
+
+
+def planck_table(lambda_c, T_pt) -> np.ndarray:
+    """B(lambda_l, T_p) as [bin][point]."""
+    lc, T = _f64(lambda_c), _f64(T_pt)
+    out = np.zeros((lc.size, T.size))
+    _load().ref_planck_table(lc.size, T.size, _p(lc), _p(T), _p(out))
+    return out
+
+
+def isothermal_flux(atm: dict, T_pt, D: float = 2.0) -> np.ndarray:
+    """(2 pi / D) B(lambda_l, T_p) [bin][point]: the flux of both streams in
+    an isothermal column (each sublayer relation maps it to itself)."""
+    return (2.0 * np.pi / D) * planck_table(atm["lambda_c"], T_pt)
+
+
+def isothermal_start(atm: dict, T_pt, D: float = 2.0) -> np.ndarray:
+    """Warm start [bin][g][point] equal to the isothermal flux in every g."""
+    iso = isothermal_flux(atm, T_pt, D)
+    return np.ascontiguousarray(np.broadcast_to(iso[:, None, :], (iso.shape[0], int(atm["ng"]), iso.shape[1])))
 
 
 def gauss_legendre(n: int):
@@ -230,9 +251,15 @@ def radeq(atm: dict, P_pt, F_bol, T_c, m, hist, opts: dict | None = None):
 
 
 def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float = 2.0,
-          opts: dict | None = None, T_init=None, n_threads: int = 0, callback=None):
+          opts: dict | None = None, T_init=None, n_threads: int = 0, callback=None, warm: str = "flux"):
     """Full RE iteration of one atmosphere (Sec. 2.2.3): profile -> opacity ->
     flux -> RE step, until converged or max_iter steps were taken.
+
+    warm = "flux": the scattering warm start is the previous iteration's
+    upward flux, zeros at the first (the paper's description).
+    warm = "deviation": the warm start keeps each column's deviation from the
+    isothermal flux (2 pi / D) B across iterations and starts from that flux;
+    the choice of a warm start changes the trajectory, not the fixed point.
 
     Returns a dict with T_c, iterations, converged flag, resid history and the
     last flux result.
@@ -249,8 +276,13 @@ def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float 
     converged = False
     it = 0
     res = None
+    iso_prev = None
     while True:
         T_pt = profile(P_pt, T_c)
+        if warm == "deviation":
+            iso = isothermal_flux(atm, T_pt, D)
+            F_up += (iso if iso_prev is None else iso - iso_prev)[:, None, :]
+            iso_prev = iso
         kap = mix_opacity(ktab, T_pt, P_pt, atm["vmr"], atm["bin_index"], ng)
         res = flux(atm, kap, T_pt, P_pt, F_up, n_scat=n_scat, D=D, n_threads=n_threads,
                    want_dn=False)

@@ -132,6 +132,12 @@ double ref_planck(double lambda, double T) {
     return 2.0 * REF_H * REF_C * REF_C / pow(lambda, 5) / expm1(x);
 }
 
+/* Planck values of nb bins at npt temperatures: out[l * npt + p]. */
+void ref_planck_table(int nb, int npt, const double* lambda, const double* T, double* out) {
+    for (int l = 0; l < nb; ++l)
+        for (int p = 0; p < npt; ++p) out[(size_t)l * npt + p] = ref_planck(lambda[l], T[p]);
+}
+
 /* Sec. 2.2.2.  TOA: F_down,n = f (R_star/a)^2 pi B_star(lambda); the workloads give the
  * irradiation temperature T_irr with sigma T_irr^4 = f (R_star/a)^2 sigma T_star^4, so
  * f (R_star/a)^2 = (T_irr/T_star)^4.  BOA: the internal flux pi B_int has the shape of

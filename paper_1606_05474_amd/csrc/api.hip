@@ -103,7 +103,7 @@ int check_atm(const helios_atm* atm, Sizes& z) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t B, F_top, F_int, gw, part_up, part_dn, chunk, total;
+    size_t B, F_top, F_int, gw, bin_atm, part_up, part_dn, chunk, total;
 };
 
 // Waves per bin for L lanes per column: each wave holds 64/L columns.
@@ -112,19 +112,21 @@ int waves_per_bin(int n_g, int L) { return (n_g + (64 / L) - 1) / (64 / L); }
 // The workspace is sized for the largest waves-per-bin any sweep shape uses
 // (L = 32), which is also the stride of the partial-sum layout, so the shape
 // can be chosen per call and per size class.
-WsLayout ws_layout(const Sizes& z, int n_g, bool mixed) {
+// Partial sums are 8 bytes in both precisions (a double, or a compensated
+// float pair), so the layout does not depend on the precision.
+WsLayout ws_layout(const Sizes& z, int n_g, bool /*mixed*/) {
     WsLayout w;
-    size_t r = mixed ? sizeof(float) : sizeof(double);
     const size_t wpb = (size_t)waves_per_bin(n_g, 32);
     const size_t n_chunk = (size_t)((z.nb_max + kBolChunk - 1) / kBolChunk);
-    w.B = 0;
-    w.F_top = align256(w.B + (size_t)z.total_pb * r);
+    w.B = 0;  // Planck values in FP64 for both precisions
+    w.F_top = align256(w.B + (size_t)z.total_pb * sizeof(double));
     w.F_int = align256(w.F_top + (size_t)z.total_bin * sizeof(double));
     w.gw = align256(w.F_int + (size_t)z.total_bin * sizeof(double));
-    w.part_up = align256(w.gw + HELIOS_MAX_NG * sizeof(double));
+    w.bin_atm = align256(w.gw + HELIOS_MAX_NG * sizeof(double));
+    w.part_up = align256(w.bin_atm + (size_t)z.total_bin * sizeof(int32_t));
     w.part_dn = align256(w.part_up + (size_t)z.total_pb * wpb * 8);
     w.chunk = align256(w.part_dn + (size_t)z.total_pb * wpb * 8);
-    w.total = align256(w.chunk + (size_t)z.total_pt * n_chunk * 4 * sizeof(double));
+    w.total = align256(w.chunk + (size_t)z.total_pt * n_chunk * 6 * sizeof(double));
     return w;
 }
 
@@ -177,9 +179,9 @@ struct SweepShape {
     int K, L;
 };
 
-bool k_allowed(int K, bool mixed) {
+bool k_allowed(int K, bool /*mixed*/) {
     for (int i = 0; i < kNumSweepK; ++i)
-        if (kSweepK[i] == K) return mixed || K <= 14;
+        if (kSweepK[i] == K) return true;
     return false;
 }
 
@@ -188,8 +190,10 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, SweepShape> g_tuned;
 
 int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
-    for (int L : {16, 32}) {
-        for (int i = 0; i < kNumSweepK; ++i) {
+    // fewest sublayers per lane first (smallest register footprint), then
+    // the narrower column
+    for (int i = 0; i < kNumSweepK; ++i) {
+        for (int L : {16, 32}) {
             int K = kSweepK[i];
             if (!k_allowed(K, mixed)) continue;
             if (K * L >= nsub_max) {
@@ -276,6 +280,7 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
     A.part_up = wsb + p.w.part_up;
     A.part_dn = wsb + p.w.part_dn;
     A.gw = (double*)(wsb + p.w.gw);
+    A.bin_atm = (const int32_t*)(wsb + p.w.bin_atm);
     A.status = atm->status;
     A.n_atm = atm->n_atm;
     A.n_g = atm->n_g;
@@ -303,8 +308,9 @@ hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, i
 
 hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double* T_pt, char* wsb,
                           hipStream_t s) {
-    return launch_planck(atm, p.z.total_pb, T_pt, wsb + p.w.B, (double*)(wsb + p.w.F_top),
-                         (double*)(wsb + p.w.F_int), (double*)(wsb + p.w.gw), gauss_table(atm->n_g), p.mixed, s);
+    return launch_planck(atm, p.z.total_pb, T_pt, (double*)(wsb + p.w.B), (double*)(wsb + p.w.F_top),
+                         (double*)(wsb + p.w.F_int), (double*)(wsb + p.w.gw), (int32_t*)(wsb + p.w.bin_atm),
+                         gauss_table(atm->n_g), p.mixed, s);
 }
 
 // ------------------------------------------------------ warm-start network
@@ -531,6 +537,9 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     Bo.F_dn_bin = F_dn_bin;
     Bo.chunk = (double*)(wsb + p.w.chunk);
     Bo.F_bol = F_bol;
+    Bo.B = (const double*)(wsb + p.w.B);
+    Bo.gw = (const double*)(wsb + p.w.gw);
+    Bo.tpe = 2.0 * kPi / D;
     Bo.wpb_stride = A.wpb_stride;
     Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
     Bo.mixed = p.mixed ? 1 : 0;

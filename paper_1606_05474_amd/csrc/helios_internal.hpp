@@ -85,6 +85,7 @@ struct SweepArgs {
     void* part_dn;
     const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
     const int32_t* status;   // optional: converged atmospheres are skipped
+    const int32_t* bin_atm;  // [sum nb] owning atmosphere of each bin (workspace)
     int64_t w_begin, w_end;  // global wave range covered by the launch
     int32_t n_atm, n_g;
     int32_t wpb;          // waves per bin of this launch's shape
@@ -107,8 +108,11 @@ struct BolArgs {
     const void* part_dn;
     double* F_up_bin;
     double* F_dn_bin;
-    double* chunk;        // [sum npt][n_chunk][4] Neumaier pairs of bin-chunk sums (workspace)
+    double* chunk;        // [sum npt][n_chunk][6] Neumaier pairs of bin-chunk sums (workspace)
     double* F_bol;
+    const double* B;      // [bin x point] Planck values (workspace)
+    const double* gw;     // [n_g] Gauss weights (workspace)
+    double tpe;           // 2 pi eps = 2 pi / D: the sweep's partials are deviations from tpe B
     int32_t wpb_stride, n_chunk, mixed;
     int32_t n_cls;                   // size classes: atmosphere with n <= cls_nhi[k] (first k)
     int32_t cls_nhi[kMaxClasses];    // uses cls_wpb[k] waves per bin
@@ -161,9 +165,9 @@ hipError_t launch_warm_start(const helios_atm* atm, const float* T_net, int n_ou
 hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s);
 hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double* T_c, double* T_pt,
                           hipStream_t s);
-hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, void* B,
-                         double* F_top, double* F_int, double* gw, const GaussTable& gt, bool mixed,
-                         hipStream_t s);
+hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, double* B,
+                         double* F_top, double* F_int, double* gw, int32_t* bin_atm, const GaussTable& gt,
+                         bool mixed, hipStream_t s);
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);

@@ -64,9 +64,8 @@ hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double*
 
 // --------------------------------------------------------------- sources
 // B[bin][pt] at the bin centres, one thread per (bin, point) element.
-template <typename R>
 __global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __restrict__ T_pt,
-                              R* __restrict__ B) {
+                              double* __restrict__ B) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total_pb) return;
     int a = find_atm(atm.pb_off, atm.n_atm, idx);
@@ -76,7 +75,7 @@ __global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __
     int l = (int)(rel / npt);
     int p = (int)(rel - (int64_t)l * npt);
     double lam = atm.lambda_c[atm.bin_off[a] + l];
-    B[idx] = (R)planck_d(lam, T_pt[atm.pt_off[a] + p]);
+    B[idx] = planck_d(lam, T_pt[atm.pt_off[a] + p]);
 }
 
 // Boundary fluxes, one workgroup per atmosphere (Sec. 2.2.2): TOA
@@ -85,13 +84,15 @@ __global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __
 // is a fixed-order tree in LDS.
 __global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* __restrict__ F_top,
                                                        double* __restrict__ F_int, double* __restrict__ gw,
-                                                       GaussTable gt) {
+                                                       int32_t* __restrict__ bin_atm, GaussTable gt) {
     __shared__ double red[256];
     int a = blockIdx.x;
     if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gt.w[threadIdx.x];
-    if (frozen(atm.status, a)) return;  // uniform per workgroup
     int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
     int64_t b0 = atm.bin_off[a];
+    // bin -> atmosphere map for the sweep (one load instead of a search)
+    for (int l = threadIdx.x; l < nb; l += blockDim.x) bin_atm[b0 + l] = a;
+    if (frozen(atm.status, a)) return;  // uniform per workgroup
     double Ts = atm.T_star[a], Ti = atm.T_int[a];
     double r = (Ts > 0.0) ? atm.T_irr[a] / Ts : 0.0;
     double dil = r * r * r * r;
@@ -115,30 +116,27 @@ __global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* _
     for (int l = threadIdx.x; l < nb; l += blockDim.x) F_int[b0 + l] *= scale;
 }
 
-hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, void* B,
-                         double* F_top, double* F_int, double* gw, const GaussTable& gt, bool mixed,
-                         hipStream_t s) {
+hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, double* B,
+                         double* F_top, double* F_int, double* gw, int32_t* bin_atm, const GaussTable& gt,
+                         bool /*mixed*/, hipStream_t s) {
     int block = 256;
     int64_t grid = (total_pb + block - 1) / block;
-    if (mixed)
-        hipLaunchKernelGGL(planck_kernel<float>, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb,
-                           T_pt, (float*)B);
-    else
-        hipLaunchKernelGGL(planck_kernel<double>, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb,
-                           T_pt, (double*)B);
+    hipLaunchKernelGGL(planck_kernel, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb, T_pt, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_top, F_int, gw, gt);
+    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_top, F_int, gw, bin_atm, gt);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------ bolometric sums
 // Stage 1: workgroup = (atmosphere, 64-point tile, chunk of kBolChunk bins);
-// 256 threads = 64 points x 4 sub-chunks of kBolChunk/4 bins.  Each thread
-// combines the sweep's per-wave Gauss partials of a bin (fixed order) into
-// F_up_bin / F_dn_bin, writes them, and accumulates dlambda * F in a
-// Neumaier sum; the 4 sub-chunk sums are combined in order and stored per
-// (point, chunk).  Stage 2: one thread per point sums its chunks in order.
+// 1024 threads = 64 points x 16 groups of kBolChunk/16 bins.  Each thread
+// combines the sweep's per-wave Gauss partials of a bin (fixed order) -- sums
+// of deviations G = F - 2 pi eps B -- adds 2 pi eps B times the sum of the
+// weights to form F_up_bin / F_dn_bin, writes them, and accumulates dlambda
+// times the up, down and net (up - down, from the deviations, where B
+// cancels) fluxes in Neumaier sums; the group sums are combined in order and
+// stored per (point, chunk).  Stage 2 sums a point's chunks in order.
 struct nacc {
     double s, c;
 };
@@ -164,7 +162,7 @@ __device__ inline double combine_partials(const void* part, int64_t base, int wp
 
 // Stage 1 workgroup: 64 points x 16 groups of kBolChunk/16 consecutive bins.
 __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
-    __shared__ double red[16][64][4];
+    __shared__ double red[16][64][6];
     const int a = blockIdx.x;
     const int tile = blockIdx.y, ch = blockIdx.z;
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -176,21 +174,28 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     const int p = tile * 64 + pl;
     constexpr int per = kBolChunk / 16;
     const int l0 = ch * kBolChunk + q * per;
-    nacc au = {0.0, 0.0}, ad = {0.0, 0.0};
+    nacc au = {0.0, 0.0}, ad = {0.0, 0.0}, an = {0.0, 0.0};
     if (p < npt) {
         const double* dl = A.atm.dlambda + A.atm.bin_off[a];
         const int64_t pb = A.atm.pb_off[a];
+        double wsum = 0.0;
+        for (int g = 0; g < A.atm.n_g; ++g) wsum += A.gw[g];
+        const double tw = A.tpe * wsum;
 #pragma unroll
         for (int i = 0; i < per; ++i) {
             const int l = l0 + i;
             if (l < nb) {
                 const int64_t base = pb * A.wpb_stride + ((int64_t)l * A.wpb_stride) * npt + p;
-                const double fu = combine_partials(A.part_up, base, wpb, npt, A.mixed);
-                const double fd = combine_partials(A.part_dn, base, wpb, npt, A.mixed);
-                A.F_up_bin[pb + (int64_t)l * npt + p] = fu;
-                A.F_dn_bin[pb + (int64_t)l * npt + p] = fd;
+                const double gu = combine_partials(A.part_up, base, wpb, npt, A.mixed);
+                const double gd = combine_partials(A.part_dn, base, wpb, npt, A.mixed);
+                const int64_t o = pb + (int64_t)l * npt + p;
+                const double bw = tw * A.B[o];
+                const double fu = bw + gu, fd = bw + gd;
+                A.F_up_bin[o] = fu;
+                A.F_dn_bin[o] = fd;
                 nadd(au, dl[l] * fu);
                 nadd(ad, dl[l] * fd);
+                nadd(an, dl[l] * (gu - gd));
             }
         }
     }
@@ -198,28 +203,28 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     red[q][pl][1] = au.c;
     red[q][pl][2] = ad.s;
     red[q][pl][3] = ad.c;
+    red[q][pl][4] = an.s;
+    red[q][pl][5] = an.c;
     __syncthreads();
     if (q == 0 && p < npt) {
-        nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
-        double cu = 0.0, cd = 0.0;
-        for (int k = 0; k < 16; ++k) {
-            nadd(tu, red[k][pl][0]);
-            nadd(td, red[k][pl][2]);
-            cu += red[k][pl][1];
-            cd += red[k][pl][3];
+        double* o = A.chunk + ((A.atm.pt_off[a] + p) * A.n_chunk + ch) * 6;
+        for (int v = 0; v < 3; ++v) {
+            nacc t = {0.0, 0.0};
+            double cc = 0.0;
+            for (int k = 0; k < 16; ++k) {
+                nadd(t, red[k][pl][2 * v]);
+                cc += red[k][pl][2 * v + 1];
+            }
+            o[2 * v] = t.s;
+            o[2 * v + 1] = t.c + cc;
         }
-        double* o = A.chunk + ((A.atm.pt_off[a] + p) * A.n_chunk + ch) * 4;
-        o[0] = tu.s;
-        o[1] = tu.c + cu;
-        o[2] = td.s;
-        o[3] = td.c + cd;
     }
 }
 
 // Stage 2 workgroup: 64 points x 16 groups; group q sums chunks q, q+16, ...
 // in order, then the 16 group sums are combined in order.
 __global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
-    __shared__ double red[16][64][4];
+    __shared__ double red[16][64][6];
     const int a = blockIdx.x, tile = blockIdx.y;
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int npt = 2 * A.atm.n_layer[a] + 1;
@@ -227,36 +232,32 @@ __global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
     const int p = tile * 64 + pl;
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
     const int nch = (nb + kBolChunk - 1) / kBolChunk;
-    nacc tu = {0.0, 0.0}, td = {0.0, 0.0};
-    double cu = 0.0, cd = 0.0;
+    nacc t[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    double e[3] = {0.0, 0.0, 0.0};
     if (p < npt) {
-        const double* c = A.chunk + (A.atm.pt_off[a] + p) * A.n_chunk * 4;
-        for (int k = q; k < nch; k += 16) {
-            nadd(tu, c[4 * k + 0]);
-            cu += c[4 * k + 1];
-            nadd(td, c[4 * k + 2]);
-            cd += c[4 * k + 3];
-        }
+        const double* c = A.chunk + (A.atm.pt_off[a] + p) * A.n_chunk * 6;
+        for (int k = q; k < nch; k += 16)
+            for (int v = 0; v < 3; ++v) {
+                nadd(t[v], c[6 * k + 2 * v]);
+                e[v] += c[6 * k + 2 * v + 1];
+            }
     }
-    red[q][pl][0] = tu.s;
-    red[q][pl][1] = tu.c + cu;
-    red[q][pl][2] = td.s;
-    red[q][pl][3] = td.c + cd;
+    for (int v = 0; v < 3; ++v) {
+        red[q][pl][2 * v] = t[v].s;
+        red[q][pl][2 * v + 1] = t[v].c + e[v];
+    }
     __syncthreads();
     if (q == 0 && p < npt) {
-        nacc su = {0.0, 0.0}, sd = {0.0, 0.0};
-        double eu = 0.0, ed = 0.0;
-        for (int k = 0; k < 16; ++k) {
-            nadd(su, red[k][pl][0]);
-            eu += red[k][pl][1];
-            nadd(sd, red[k][pl][2]);
-            ed += red[k][pl][3];
-        }
-        const double fu = su.s + (su.c + eu), fd = sd.s + (sd.c + ed);
         double* o = A.F_bol + 3 * (A.atm.pt_off[a] + p);
-        o[0] = fu;
-        o[1] = fd;
-        o[2] = fu - fd;
+        for (int v = 0; v < 3; ++v) {
+            nacc s = {0.0, 0.0};
+            double ee = 0.0;
+            for (int k = 0; k < 16; ++k) {
+                nadd(s, red[k][pl][2 * v]);
+                ee += red[k][pl][2 * v + 1];
+            }
+            o[v] = s.s + (s.c + ee);  // up, down, and net summed from the deviations
+        }
     }
 }
 

@@ -37,6 +37,23 @@
 //   gradient in optical depth measured downward.
 //   eq:purescat ((1 - w0) < 1e-6):  q = gamma dtau/(1 + gamma dtau),
 //   gamma = D (1 - g0)/2, a = 1 - q, c = q, no source.
+//
+// Deviation form.  An isothermal column has F_up = F_dn = 2 pi eps B at every
+// point (for any coefficients), so the sweep carries G = F - 2 pi eps B(point)
+// instead of F.  Substituting leaves a and c unchanged and turns both sources
+// into one term linear in the Planck difference dB = B_lower - B_upper across
+// the sublayer (the part proportional to B cancels exactly):
+//   up:   G_up(upper)   = a G_up(lower) + c G_dn(upper) + sig
+//   down: G_dn(lower)   = a G_dn(upper) + c G_up(lower) - sig
+//   non-isothermal  sig = 2 pi eps f dB om / (dtau (zp - zm T))
+//   isothermal      sig = pi eps (1 + a - c) dB
+//   pure scattering sig = 2 pi eps a dB
+// with the boundary values G_dn(TOA) = F_top - 2 pi eps B(TOA) and
+// G_up(BOA) = G_dn(BOA) + F_int.  Deep in the atmosphere F_up and F_dn are both
+// close to pi B and their difference (the net flux) is small; in this form
+// the rounding of each stream is relative to its deviation from pi B rather
+// than to pi B itself, which is what lets FP32 sweeps resolve net fluxes at
+// depth.  Fluxes are recovered as F = G + 2 pi eps B in FP64 by the bin sum.
 #include "helios_internal.hpp"
 
 namespace helios {
@@ -152,6 +169,32 @@ __device__ inline void sub_coeffs(R dtau, R w0, R g0, R D, R Bu, R Bd, R& Tr, R&
     sub_coeffs_q<R>(q, dtau, tpe, Bu, Bd, Tr, a, c, su, sd);
 }
 
+// The sweep's coefficients of one sublayer in the deviation form: a, c and
+// the source sig for the Planck difference dB = B_lower - B_upper.  One
+// reciprocal of (zp - zm T)(zp + zm T) serves a and c; om / (zp - zm T) is
+// om (zp + zm T) times it.
+template <typename R>
+__device__ inline void sub_coeffs_g(const LayerQ<R>& q, R dtau, R two_pi_eps, R dB, R& a, R& c, R& sig) {
+    const R one = (R)1;
+    R T, om;
+    Prec<R>::t_om(q.kx * dtau, T, om);
+    const R u = q.zp - q.zm * T, v = q.zp + q.zm * T;
+    const R iden = Prec<R>::rcp(u * v);
+    const R omi = om * iden;
+    a = q.r * T * iden;
+    c = q.zpzm * (one + T) * omi;
+    const R s_non = two_pi_eps * q.f * v * omi * Prec<R>::rcp(dtau) * dB;
+    const R s_iso = (R)0.5 * two_pi_eps * (one + a - c) * dB;
+    sig = (dtau < (R)1e-4) ? s_iso : s_non;  // a select: the unused one may be inf at dtau = 0
+    if (__any(q.purescat)) {  // eq:purescat
+        const R gd = q.purescat_gd * dtau;
+        const R qq = gd * Prec<R>::rcp(one + gd);
+        a = q.purescat ? one - qq : a;
+        c = q.purescat ? qq : c;
+        sig = q.purescat ? two_pi_eps * (one - qq) * dB : sig;
+    }
+}
+
 // Shifts within a column's group of L lanes.  For L = 16 the group is one
 // DPP row, so row_shl/row_shr moves (out-of-row sources read 0) replace LDS
 // permutes; wider groups use shuffles (out-of-group sources read the own
@@ -265,8 +308,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     const int npt_max = A.npt_max;
     R* s_kap = reinterpret_cast<R*>(smem_raw);  // [C][npt]   opacities, later partials / F_dn
     R* s_fu = s_kap + C * npt_max;              // [C][npt]   warm start, later F_up
-    R* s_B = s_fu + C * npt_max;                // [npt]
-    R* s_dm = s_B + npt_max;                    // [npt - 1]  sublayer column masses
+    R* s_dB = s_fu + C * npt_max;               // [npt - 1]  Planck difference across each sublayer
+    R* s_dm = s_dB + npt_max;                   // [npt - 1]  sublayer column masses
     R* s_w0 = s_dm + npt_max;                   // [n]
     R* s_g0 = s_w0 + npt_max / 2;               // [n]
 
@@ -274,7 +317,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     const int seg = lane & (L - 1);
     const int cw = lane / L;
     const R* __restrict__ kap_all = static_cast<const R*>(A.kappa);
-    const R* __restrict__ B_all = static_cast<const R*>(A.B);
+    const double* __restrict__ B_all = static_cast<const double*>(A.B);
     R* __restrict__ Fu_all = static_cast<R*>(A.F_up_g);
     R* __restrict__ Fd_all = static_cast<R*>(A.F_dn_g);
     slot* __restrict__ part_up = static_cast<slot*>(A.part_up);
@@ -283,7 +326,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     for (int64_t gwave = A.w_begin + blockIdx.x; gwave < A.w_end; gwave += gridDim.x) {
         const int64_t gb = gwave / A.wpb;
         const int j = (int)(gwave - gb * A.wpb);
-        const int at = find_atm(A.bin_off, A.n_atm, gb);
+        const int at = A.bin_atm[gb];
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
         if (n < A.n_lo || n > A.n_hi || frozen(A.status, at)) continue;  // uniform per wave
@@ -306,62 +349,110 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const R D = (R)A.D;
         const R inv_D = (R)(1.0 / A.D);
         const R tpe = (R)(2.0 * kPi / A.D);
-        const R Ftop = (R)A.F_top[A.bin_off[at] + l];
+        // TOA value of the downward deviation, formed in FP64
+        const R Ftop = (R)(A.F_top[A.bin_off[at] + l] - (2.0 * kPi / A.D) * B_all[pb + nsub]);
         const R Fint = (R)A.F_int[A.bin_off[at] + l];
         R wcol[C];  // Gauss weights of the wave's columns
 #pragma unroll
         for (int c = 0; c < C; ++c) wcol[c] = (c < ncols) ? (R)A.gw[j * C + c] : (R)0;
 
-        // ---- stage the wave's inputs in LDS (coalesced)
+        // ---- stage the wave's inputs in LDS (coalesced).  Every load of the
+        // item is issued before the first one is consumed: the loop bounds are
+        // compile-time (the deepest column this shape serves) and indices are
+        // clamped into the item's own padded columns, so no load is guarded by
+        // a branch and one memory latency covers the whole item.
         {
-            for (int cc = 0; cc < ncols; ++cc) {
-                const R* kb = kap_all + cell0 + (int64_t)cc * cs;
-                const R* fb = Fu_all + cell0 + (int64_t)cc * cs;
-                for (int i = lane; i < npt; i += 64) {
-                    s_kap[cc * npt + i] = kb[i];
-                    s_fu[cc * npt + i] = fb[i];
+            constexpr int NCAP = K * L + 1;         // points of the deepest column served
+            constexpr int PCH = (NCAP + 63) / 64;   // 64-point chunks of a column
+            constexpr int LCH = (K * L / 2 + 63) / 64;
+            R kv[C][PCH], fv[C][PCH];
+            double bv[PCH], pv[PCH], wv[LCH], gv[LCH];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t col = cell0 + (int64_t)min(c, ncols - 1) * cs;
+#pragma unroll
+                for (int j = 0; j < PCH; ++j) {
+                    const int i = min(lane + 64 * j, npt - 1);
+                    kv[c][j] = kap_all[col + i];
+                    fv[c][j] = Fu_all[col + i];
                 }
             }
-            for (int i = lane; i < npt; i += 64) s_B[i] = B_all[pb + i];
-            for (int i = lane; i < nsub; i += 64) s_dm[i] = (R)((P[i] - P[i + 1]) * igrav);
-            for (int i = lane; i < n; i += 64) {
-                s_w0[i] = (R)A.w0[lb + i];
-                s_g0[i] = (R)A.g0[lb + i];
+#pragma unroll
+            for (int j = 0; j < PCH; ++j) {
+                const int i = min(lane + 64 * j, npt - 1);
+                bv[j] = B_all[pb + i];
+                pv[j] = P[i];
+            }
+#pragma unroll
+            for (int j = 0; j < LCH; ++j) {
+                const int i = min(lane + 64 * j, n - 1);
+                wv[j] = A.w0[lb + i];
+                gv[j] = A.g0[lb + i];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+#pragma unroll
+                for (int j = 0; j < PCH; ++j) {
+                    const int i = lane + 64 * j;
+                    if (c < ncols && i < npt) {
+                        s_kap[c * npt + i] = kv[c][j];
+                        s_fu[c * npt + i] = fv[c][j];
+                    }
+                }
+            }
+            // sublayer differences from the next point's value: the next lane,
+            // or lane 0 of the next chunk for lane 63 (sublayer i < npt - 1
+            // never needs a chunk past the last)
+#pragma unroll
+            for (int j = 0; j < PCH; ++j) {
+                double bn = __shfl_down(bv[j], 1u, 64), pn = __shfl_down(pv[j], 1u, 64);
+                if (j + 1 < PCH) {
+                    const double b0 = __shfl(bv[j + 1 < PCH ? j + 1 : j], 0, 64);
+                    const double p0 = __shfl(pv[j + 1 < PCH ? j + 1 : j], 0, 64);
+                    bn = (lane == 63) ? b0 : bn;
+                    pn = (lane == 63) ? p0 : pn;
+                }
+                const int i = lane + 64 * j;
+                if (i < nsub) {
+                    s_dB[i] = (R)(bv[j] - bn);
+                    s_dm[i] = (R)((pv[j] - pn) * igrav);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < LCH; ++j) {
+                const int i = lane + 64 * j;
+                if (i < n) {
+                    s_w0[i] = (R)wv[j];
+                    s_g0[i] = (R)gv[j];
+                }
             }
         }
         __syncthreads();
 
         // ---- sublayer coefficients and warm start (once per call)
-        R ca[K], cc[K], su[K], sd[K], fu[K], bu[K];
+        R ca[K], cc[K], sg[K], fu[K], bu[K];
         {
             const R* kc = s_kap + cw * npt + lo;
             const R* fc = s_fu + cw * npt + lo;
-            const R* Bc = s_B + lo;
+            const R* dBc = s_dB + lo;
             const R* dmc = s_dm + lo;
-            R kp = (R)0, Bp = (R)0;
-            if (cnt > 0) {
-                kp = kc[0];
-                Bp = Bc[0];
-            }
+            R kp = (R)0;
+            if (cnt > 0) kp = kc[0];
             LayerQ<R> q;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 ca[k] = (R)1;
                 cc[k] = (R)0;
-                su[k] = (R)0;
-                sd[k] = (R)0;
+                sg[k] = (R)0;
                 fu[k] = (R)0;
                 bu[k] = (R)0;
                 if (k < cnt) {
                     if ((k & 1) == 0) q = layer_q<R>(s_w0[(lo + k) >> 1], s_g0[(lo + k) >> 1], D, inv_D, tpe);
                     const R kn = kc[k + 1];
-                    const R Bn = Bc[k + 1];
                     const R dtau = (R)0.5 * (kp + kn) * dmc[k];
-                    R Tr;
-                    sub_coeffs_q<R>(q, dtau, tpe, Bn, Bp, Tr, ca[k], cc[k], su[k], sd[k]);
+                    sub_coeffs_g<R>(q, dtau, tpe, dBc[k], ca[k], cc[k], sg[k]);
                     fu[k] = fc[k];
                     kp = kn;
-                    Bp = Bn;
                 }
             }
         }
@@ -405,7 +496,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             // ---------------- downward sweep: compose my segment (top -> bottom)
             R MB = (R)0;
 #pragma unroll
-            for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + (cc[k] * fu[k] + sd[k]);
+            for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + (cc[k] * fu[k] - sg[k]);
             if (seg == L - 1) MB = ftop_fold + MB;
             if constexpr (PRECOMP) {  // suffix scan towards the BOA
                 MB = scan_down_step<L, 0>(MB, mdn[0]);
@@ -419,20 +510,17 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             }
             R x = grp_down<L, 1>(MB);  // F_dn at my segment's top point
             if (seg == L - 1) x = Ftop;
+            // downward fluxes of the final pass go straight to LDS (the staged
+            // warm start is dead by then), then the Gauss partials (column
+            // sums) and, optionally, the per-g values are stored coalesced
+            R* s_out = s_fu;
 #pragma unroll
             for (int k = K - 1; k >= 0; --k) {
-                bu[k] = cc[k] * x + su[k];
-                x = ca[k] * x + (cc[k] * fu[k] + sd[k]);
-                if (last) sd[k] = x;  // sd[k] is dead from here on in the last pass
+                bu[k] = cc[k] * x + sg[k];
+                x = ca[k] * x + (cc[k] * fu[k] - sg[k]);
+                if (last && k < cnt) s_out[cw * npt + lo + k] = x;
             }
             if (last) {
-                // downward fluxes of the final pass: staged in LDS, then the Gauss
-                // partials (column sums) and, optionally, the per-g values are
-                // stored coalesced
-                R* s_out = s_fu;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k < cnt) s_out[cw * npt + lo + k] = sd[k];
                 if (top_seg && colok) s_out[cw * npt + nsub] = Ftop;
                 __syncthreads();
                 for (int i = lane; i < npt; i += 64) part_dn[poff + i] = GS::col_sum(s_out + i, npt, ncols, wcol);
@@ -497,19 +585,19 @@ static size_t sweep_lds(const SweepArgs& a, size_t rbytes) {
 }
 
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills.
-template <int K, bool F64>
+template <int K, int L, bool F64>
 constexpr int sweep_occ() {
-    if (F64) return K <= 4 ? 3 : 2;
+    if (F64) return (K <= 4 && L == 16) ? 3 : (K <= 14 ? 2 : 1);
     return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
 }
 
 template <int K, int L>
 static hipError_t launch_kp(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, false>()>), dim3(grid), dim3(64),
+        hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, L, false>()>), dim3(grid), dim3(64),
                            sweep_lds<L>(a, 4), s, a);
     else
-        hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, true>()>), dim3(grid), dim3(64),
+        hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, L, true>()>), dim3(grid), dim3(64),
                            sweep_lds<L>(a, 8), s, a);
     return hipGetLastError();
 }

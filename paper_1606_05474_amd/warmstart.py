@@ -156,6 +156,98 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
     return out
 
 
+def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 512,
+               n: int = 200, nb: int = 3000, prec: int = H.MIXED, max_iter: int = 400, restart_after: int = 150,
+               check_every: int = 10, keep_T: int = 0, log=print):
+    """The production form: atmospheres start..start+count-1 of a parameter
+    set solved in chunks of `chunk` atmospheres, each chunk one batch on the
+    device (size-class sweeps, graph replay, finished atmospheres skipped),
+    started from the network (isothermal fallback, restart after
+    `restart_after` updates) or, with net=None, isothermally.  The timed
+    region of a chunk starts with its inputs resident on the device and
+    covers the network, the warm start and the whole solve.  Returns totals
+    and the converged profiles of the first `keep_T` atmospheres."""
+    kt = W.table_ktab(2, nbt=3000)
+    ktd = H.KTable(kt)
+    out = {"count": 0, "converged": 0, "seconds": 0.0, "updates": [], "fallbacks": 0, "restarts": 0,
+           "T": [], "conv_flags": []}
+    for c0 in range(start, start + count, chunk):
+        c = min(chunk, start + count - c0)
+        atms, _ = W.learned_workload(seed, c, c0, n=n, nb=nb, ktab=kt)
+        b = H.Batch(atms)
+        s = H.Solver(b, ktd, prec=prec)
+        x = np.stack([a["params"] for a in atms])
+        T0 = np.concatenate([a["T0"] for a in atms])
+        if c0 == start:  # one-time shape tuning for this process, outside the timed region
+            s.reset(T0)
+            s.autotune()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if net is not None:
+            fb = s.warm_reset(net, x, net.logP)
+            conv, it, rs = s.run(max_iter, check_every, graph=True, restart_after=restart_after)
+        else:
+            s.reset(T0)
+            fb = np.zeros(c, np.int32)
+            conv, it, rs = s.run(max_iter, check_every, graph=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["count"] += c
+        out["converged"] += int(conv.sum())
+        out["seconds"] += dt
+        out["updates"].append(it)
+        out["fallbacks"] += int(fb.sum())
+        out["restarts"] += int(rs.sum())
+        out["conv_flags"].append(conv)
+        need = keep_T - sum(len(t) for t in out["T"])
+        if need > 0:
+            Tc = s.T_c.cpu().numpy()
+            out["T"] += [Tc[int(b.lay_off[a]):int(b.lay_off[a + 1])] for a in range(min(need, c))]
+        log(f"chunk {c0}..{c0 + c - 1}: {int(conv.sum())}/{c} converged in {dt:.1f} s, median updates "
+            f"{np.median(it):.0f}, fallbacks {int(fb.sum())}, restarts {int(rs.sum())}")
+        del s, b
+        torch.cuda.empty_cache()
+    out["updates"] = np.concatenate(out["updates"])
+    out["conv_flags"] = np.concatenate(out["conv_flags"])
+    out["converged_per_s"] = out["converged"] / out["seconds"]
+    return out
+
+
+def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int = 3000, max_iter: int = 400,
+          keep_T: int = 0, log=print):
+    """The plain form: the same atmospheres one at a time, FP64, isothermal
+    start, an eager iteration loop (timed per atmosphere with its inputs
+    resident on the device)."""
+    kt = W.table_ktab(2, nbt=3000)
+    ktd = H.KTable(kt)
+    atms, _ = W.learned_workload(seed, count, start, n=n, nb=nb, ktab=kt)
+    out = {"count": count, "converged": 0, "seconds": 0.0, "updates": [], "T": [], "conv_flags": []}
+    for k, atm in enumerate(atms):
+        b = H.Batch([atm])
+        s = H.Solver(b, ktd, prec=H.FP64)
+        if k == 0:
+            s.reset(atm["T0"])
+            s.autotune()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.reset(atm["T0"])
+        conv, it, _ = s.run(max_iter, 10, graph=False)
+        torch.cuda.synchronize()
+        out["seconds"] += time.perf_counter() - t0
+        out["converged"] += int(conv[0])
+        out["updates"].append(int(it[0]))
+        out["conv_flags"].append(bool(conv[0]))
+        if k < keep_T:
+            out["T"].append(s.T_c.cpu().numpy())
+        del s, b
+    out["updates"] = np.array(out["updates"])
+    out["conv_flags"] = np.array(out["conv_flags"])
+    out["converged_per_s"] = out["converged"] / out["seconds"]
+    log(f"plain: {out['converged']}/{count} converged in {out['seconds']:.1f} s, median updates "
+        f"{np.median(out['updates']):.0f}")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)

@@ -35,3 +35,9 @@ def col_rel_error(x, y, axis=-1):
     scale = np.max(np.abs(y), axis=axis, keepdims=True)
     scale = np.where(scale > 0, scale, 1.0)
     return np.abs(x - y) / scale
+
+
+def to_flux(G, iso):
+    """Per-g GPU deviations [bin][g][point] plus the oracle's isothermal flux
+    [bin][point]: the fluxes themselves."""
+    return np.asarray(G, np.float64) + np.asarray(iso, np.float64)[:, None, :]

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle as ref
-from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile
+from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux
 from paper_1606_05474_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -156,13 +156,17 @@ def _gpu_flux(b, kap, T, prec, n_scat=4, F_up0=None, want_dn=True):
     return F_up, F_dn, ub, db, bol
 
 
-def _check_flux_fp64(b, a, res_ref, F_up_ref, F_up, F_dn, ub, db, bol, tol=1e-10):
+def _check_flux_fp64(b, a, T, res_ref, F_up_ref, F_up, F_dn, ub, db, bol, tol=1e-10):
+    """FP64 flux call of atmosphere a (point temperatures T) against the
+    oracle's result; the per-g GPU arrays hold deviations from the
+    isothermal flux, which the oracle's own Planck values turn into fluxes."""
     err_net = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], res_ref["F_bol"])
     assert err_net.max() < tol, err_net.max()
-    gu = b.split_cell(_np(F_up))[a]
+    iso = ref.isothermal_flux(b.atms[a], T)
+    gu = to_flux(b.split_cell(_np(F_up))[a], iso)
     assert col_rel_error(gu, F_up_ref).max() < 1e-11
     if F_dn is not None:
-        gd = b.split_cell(_np(F_dn))[a]
+        gd = to_flux(b.split_cell(_np(F_dn))[a], iso)
         assert col_rel_error(gd, res_ref["F_dn"]).max() < 1e-11
     assert col_rel_error(b.split_pb(_np(ub))[a], res_ref["F_up_bin"]).max() < 1e-11
     assert col_rel_error(b.split_pb(_np(db))[a], res_ref["F_dn_bin"]).max() < 1e-11
@@ -176,15 +180,17 @@ def test_flux_fp64_plain_two_calls_warm_start():
     H.grid(b)
     T_c = smooth_profile(atm)
     P, T, kap = oracle_state(atm, kt, T_c)
-    up_ref = np.zeros(kap.shape)
+    up_ref = ref.isothermal_start(atm, T)
     r1 = ref.flux(atm, kap, T, P, up_ref)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0)
-    _check_flux_fp64(b, 0, r1, up_ref, F_up, F_dn, ub, db, bol)
+    _check_flux_fp64(b, 0, T, r1, up_ref, F_up, F_dn, ub, db, bol)
     # second call warm-started from the first call's upward fluxes, new temperatures
     T2 = T * 1.01
+    # the warm start keeps each column's deviation from the isothermal flux
+    up_ref += (ref.isothermal_flux(atm, T2) - ref.isothermal_flux(atm, T))[:, None, :]
     r2 = ref.flux(atm, kap, T2, P, up_ref)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T2), 0, F_up0=F_up)
-    _check_flux_fp64(b, 0, r2, up_ref, F_up, F_dn, ub, db, bol)
+    _check_flux_fp64(b, 0, T2, r2, up_ref, F_up, F_dn, ub, db, bol)
 
 
 @pytest.mark.parametrize("n,nb,n_scat", [(100, 40, 4), (37, 9, 0), (61, 5, 11), (200, 6, 4)])
@@ -196,10 +202,10 @@ def test_flux_fp64_table_scattering(n, nb, n_scat, small_table):
     H.grid(b)
     T_c = smooth_profile(atm)
     P, T, kap = oracle_state(atm, small_table, T_c)
-    up_ref = np.zeros(kap.shape)
+    up_ref = ref.isothermal_start(atm, T)
     r = ref.flux(atm, kap, T, P, up_ref, n_scat=n_scat)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0, n_scat=n_scat)
-    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+    _check_flux_fp64(b, 0, T, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
 def test_flux_without_downward_output_is_identical():
@@ -219,7 +225,7 @@ def test_flux_mixed_precision_within_tolerance(small_table):
     b = H.Batch([atm])
     H.grid(b)
     P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
-    up_ref = np.zeros(kap.shape)
+    up_ref = ref.isothermal_start(atm, T)
     r = ref.flux(atm, kap, T, P, up_ref)
     # the mixed path computes its own float32 opacities from the same table
     kap_m = torch.zeros(b.total_cell, dtype=torch.float32, device="cuda")
@@ -307,7 +313,7 @@ def test_plain_re_solve_matches_oracle():
     """The plain FP64 workload: same number of temperature updates to reach
     |dF|/sigma T_int^4 < 1e-3 and the same converged profile."""
     atm, kt = W.plain_workload()
-    sol = ref.solve(atm, kt, max_iter=200)
+    sol = ref.solve(atm, kt, max_iter=200, warm="deviation")
     assert sol["converged"]
     b = H.Batch([atm])
     s = H.Solver(b, H.KTable(kt), prec=H.FP64)
@@ -337,9 +343,9 @@ def test_ragged_batch_equals_oracle_per_atmosphere(small_table):
     for a, atm in enumerate(atms):
         P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
         np.testing.assert_allclose(b.split_cell(_np(kap))[a], kap_ref, rtol=1e-13)
-        up_ref = np.zeros(kap_ref.shape)
+        up_ref = ref.isothermal_start(atm, T)
         r = ref.flux(atm, kap_ref, T, P, up_ref)
-        _check_flux_fp64(b, a, r, up_ref, F_up, F_dn, ub, db, bol)
+        _check_flux_fp64(b, a, T, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
 # ------------------------------------------------------------- edge cases
@@ -355,10 +361,10 @@ def test_edge_minimal_atmosphere_one_bin_one_g():
     b = H.Batch([atm])
     H.grid(b)
     P, T, kap = oracle_state(atm, kt, [1300.0, 800.0])
-    up_ref = np.zeros(kap.shape)
+    up_ref = ref.isothermal_start(atm, T)
     r = ref.flux(atm, kap, T, P, up_ref)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0)
-    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+    _check_flux_fp64(b, 0, T, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
 def test_edge_pure_scattering_and_isothermal_layers():
@@ -377,10 +383,10 @@ def test_edge_pure_scattering_and_isothermal_layers():
     b = H.Batch([atm])
     H.grid(b)
     P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
-    up_ref = np.zeros(kap.shape)
+    up_ref = ref.isothermal_start(atm, T)
     r = ref.flux(atm, kap, T, P, up_ref, n_scat=6)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), 0, n_scat=6)
-    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+    _check_flux_fp64(b, 0, T, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
 def test_errors_are_reported_and_nothing_runs():
@@ -399,8 +405,7 @@ def test_errors_are_reported_and_nothing_runs():
     assert e.value.code == -1
 
 
-SHAPES = [(K, L, prec) for K in (4, 8, 14, 26) for L in (16, 32) for prec in (0, 1)
-          if K * L >= 100 and not (prec == 0 and K > 14)]
+SHAPES = [(K, L, prec) for K in (4, 8, 14, 26) for L in (16, 32) for prec in (0, 1) if K * L >= 100]
 
 
 @pytest.mark.parametrize("K,L,prec", SHAPES)
@@ -415,25 +420,24 @@ def test_flux_every_sweep_shape(K, L, prec, small_table, monkeypatch):
     b = H.Batch([atm])
     H.grid(b)
     P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
-    up_ref = np.zeros(kap.shape)
+    up_ref = ref.isothermal_start(atm, T)
     r = ref.flux(atm, kap, T, P, up_ref, n_scat=3)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, b.pack_cell([kap]), _t(T), prec, n_scat=3)
     if prec == 0:
-        _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+        _check_flux_fp64(b, 0, T, r, up_ref, F_up, F_dn, ub, db, bol)
     else:
         assert net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"]).max() < 1e-4
-        assert col_rel_error(b.split_cell(_np(F_up))[0], up_ref).max() < 1e-4
+        assert col_rel_error(to_flux(b.split_cell(_np(F_up))[0], ref.isothermal_flux(atm, T)), up_ref).max() < 1e-4
 
 
 # ------------------------------------------------------- batching features
 @pytest.mark.parametrize("prec", [0, 1])
 def test_ragged_batch_spanning_every_size_class(prec, small_table):
-    """One atmosphere per size class (and the class edges), interleaved so
-    that each class launch skips other classes' bins; FP64 stops at the
-    deepest atmosphere its compiled shapes hold (224 layers)."""
+    """One atmosphere per size class (and the class edges, up to the 400-layer
+    maximum), interleaved so that each class launch skips other classes' bins."""
     lc, dl = W.bins(300)
     rng = np.random.default_rng(31 + prec)
-    ns = [65, 2, 209 if prec else 150, 32, 113, 33, 64] + ([400] if prec else [224])
+    ns = [65, 2, 209, 32, 113, 33, 64, 400]
     atms = [W.spectral_atmosphere(rng, n, lc, dl, 3 + (i % 3)) for i, n in enumerate(ns)]
     b = H.Batch(atms)
     H.grid(b)
@@ -449,10 +453,10 @@ def test_ragged_batch_spanning_every_size_class(prec, small_table):
     F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, prec)
     for a, atm in enumerate(atms):
         P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
-        up_ref = np.zeros(kap_ref.shape)
+        up_ref = ref.isothermal_start(atm, T)
         r = ref.flux(atm, kap_ref, T, P, up_ref)
         if prec == 0:
-            _check_flux_fp64(b, a, r, up_ref, F_up, F_dn, ub, db, bol)
+            _check_flux_fp64(b, a, T, r, up_ref, F_up, F_dn, ub, db, bol)
         else:
             err = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], r["F_bol"])
             assert err.max() < 1e-4, (a, err.max())
@@ -490,9 +494,9 @@ def test_status_skips_atmospheres_that_are_not_running(small_table):
         assert np.all(b.split_pt(_np(bol).reshape(-1, 3))[a] == sentinel)
     P, T, kap_ref = oracle_state(atms[0], small_table, T_cs[0])
     np.testing.assert_allclose(b.split_cell(_np(kap))[0], kap_ref, rtol=1e-13)
-    up_ref = np.zeros(kap_ref.shape)
+    up_ref = ref.isothermal_start(atms[0], T)
     r = ref.flux(atms[0], kap_ref, T, P, up_ref)
-    _check_flux_fp64(b, 0, r, up_ref, F_up, F_dn, ub, db, bol)
+    _check_flux_fp64(b, 0, T, r, up_ref, F_up, F_dn, ub, db, bol)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -518,11 +522,11 @@ def test_autotune_restores_warm_start_and_keeps_parity(prec, small_table):
     assert set(shapes) == {32, 64, 112}
     for hi, (K, L) in shapes.items():
         assert K * L >= 2 * max(a["n"] for a in atms if a["n"] <= hi)
-        assert L in (16, 32) and (prec == 1 or K <= 14)
+        assert L in (16, 32) and K in (4, 8, 14, 26)
     F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, prec)
     for a, atm in enumerate(atms):
         P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
-        up_ref = np.zeros(kap_ref.shape)
+        up_ref = ref.isothermal_start(atm, T)
         r = ref.flux(atm, kap_ref, T, P, up_ref)
         err = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], r["F_bol"])
         assert err.max() < (1e-10 if prec == 0 else 1e-4), (a, err.max())
@@ -548,3 +552,69 @@ def test_graph_replayed_solve_equals_eager_solve():
     # a second solve replays the same graph from a fresh state
     cg2, ig2 = graphed.solve(T0, max_iter=300, check_every=7, graph=True)
     assert np.array_equal(ig2, ie) and torch.equal(graphed.T_c, eager.T_c)
+
+
+# ------------------------------------------------ full-size and converged cases
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_production_atmosphere_against_oracle(prec):
+    """One atmosphere at the production size (200 layers x 3000 bins x 20 g,
+    stand-in chemistry, four float32 tables) in the launch configuration the
+    benchmarks use: the whole flux call against the oracle on the same
+    opacities (FP64 1e-10, mixed 1e-4 relative net flux)."""
+    atms, kt = W.learned_workload(5, 1, 0, n=200, nb=3000)
+    atm = atms[0]
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm, 2300.0, 900.0)
+    P, T, kap_ref = oracle_state(atm, kt, T_c)
+    up_ref = ref.isothermal_start(atm, T)
+    r = ref.flux(atm, kap_ref, T, P, up_ref)
+    T_pt = _t(T)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(kt), T_pt, kap, prec)
+    F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, prec, want_dn=False)
+    err = net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"])
+    assert err.max() < (1e-10 if prec == 0 else 1e-4), err.max()
+
+
+def _well_conditioned_layers(atm, kt, sol, dT=1.0):
+    """Layers whose own temperature moves their net-flux divergence by at
+    least 1% of d(sigma T^4)/dT (oracle finite differences at the oracle's
+    converged profile, same warm start for both evaluations)."""
+    P = sol["P_pt"]
+    sig = 5.670374419e-5
+
+    def divergence(T_c):
+        T = ref.profile(P, T_c)
+        kap = ref.mix_opacity(kt, T, P, atm["vmr"], atm["bin_index"], atm["ng"])
+        F = ref.flux(atm, kap, T, P, sol["F_up"].copy(), want_dn=False)["F_bol"][:, 2]
+        return F[2::2] - F[:-1:2]
+
+    base = divergence(sol["T_c"])
+    ok = np.zeros(atm["n"], bool)
+    for i in range(atm["n"]):
+        Tp = sol["T_c"].copy()
+        Tp[i] += dT
+        d = abs(divergence(Tp)[i] - base[i]) / dT
+        ok[i] = d >= 0.01 * 4.0 * sig * sol["T_c"][i] ** 3
+    return ok
+
+
+def test_mixed_precision_converges_to_the_oracle_profile():
+    """The plain workload solved in mixed precision reaches the oracle's
+    converged profile (same warm-start convention) within 0.1 K over the
+    well-conditioned layers (where a layer's own temperature controls its
+    flux divergence); optically thin upper layers are only weakly
+    determined by the convergence test and are reported, not bounded."""
+    atm, kt = W.plain_workload()
+    sol = ref.solve(atm, kt, max_iter=300, warm="deviation")
+    assert sol["converged"]
+    b = H.Batch([atm])
+    s = H.Solver(b, H.KTable(kt), prec=H.MIXED)
+    conv, iters = s.solve(atm["T0"], max_iter=300)
+    assert conv[0]
+    dT = np.abs(_np(s.T_c) - sol["T_c"])
+    ok = _well_conditioned_layers(atm, kt, sol)
+    assert ok.sum() >= atm["n"] // 2, ok.sum()
+    assert dT[ok].max() < 0.1, (dT[ok].max(), dT.max())
+    assert np.all(np.isfinite(dT))

@@ -490,3 +490,17 @@ def test_printed_nonisothermal_form_is_not_the_twostream_solution(ref):
     up, _ = ode.sublayer(dtau, w0, g0, D, Bu, Bd, Fu, Fd)
     assert abs(printed / up - 1) > 0.05
     assert ref.sub_up(dtau, w0, g0, D, Bu, Bd, Fu, Fd) == pytest.approx(up, rel=1e-12)
+
+
+def test_deviation_warm_start_reaches_the_same_equilibrium(ref, plain_solution):
+    """Carrying the scattering warm start as the deviation from the
+    isothermal flux changes the trajectory, not the fixed point: the same
+    radiative equilibrium (net flux sigma T_int^4 at every interface) and the
+    same profile."""
+    atm, kt, sol = plain_solution
+    dev = ref.solve(atm, kt, max_iter=400, warm="deviation")
+    assert dev["converged"]
+    s4 = SIGMA_CODATA * atm["T_int"] ** 4
+    net = dev["flux"]["F_bol"][::2, 2]
+    assert np.abs(net - s4).max() < atm["n"] * 1e-3 * s4
+    assert np.abs(dev["T_c"] - sol["T_c"]).max() < 0.1, np.abs(dev["T_c"] - sol["T_c"]).max()
