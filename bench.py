@@ -235,12 +235,14 @@ def production_main(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.n_atm} parameter-described atmospheres (seed 5), 200 layers x 3000 bins x "
-                               f"20 g, chunks of {args.chunk}, mixed precision, network warm start with isothermal "
-                               "fallback and restart after 150 updates, tolerance 1e-3 sigma T_int^4",
+                               f"20 g, chunks of {args.chunk}, mixed precision with dead band then FP64 polish, "
+                               "network warm start with isothermal fallback and restart after 150 updates; plain "
+                               "form: FP64, one atmosphere at a time, isothermal start, every layer stepped; "
+                               "tolerance 1e-3 sigma T_int^4 for both",
                    "n_atm": args.n_atm, "chunk": args.chunk},
         "production": {"converged": prod["converged"], "count": prod["count"], "seconds": prod["seconds"],
                        "median_updates": float(np.median(prod["updates"])), "fallbacks": prod["fallbacks"],
-                       "restarts": prod["restarts"],
+                       "restarts": prod["restarts"], "fp64_polished": prod["polished"],
                        "layer_bin_g_per_s": float(prod["updates"].sum()) * units / prod["seconds"]},
         "plain_fp64_one_at_a_time": {"converged": base["converged"], "count": base["count"],
                                      "seconds": base["seconds"], "converged_per_s": base["converged_per_s"],

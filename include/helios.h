@@ -122,7 +122,8 @@ typedef struct helios_re_opts {
     int32_t window;   /* oscillation-control window, 2..16 (paper: 6) */
     int32_t osc_any;  /* 0: oscillation = sign alternated over the whole window;
                          1: any sign change in the window counts */
-    int32_t pad_;
+    int32_t deadband; /* 0: every layer steps (paper); 1: a layer with |dF_i| / norm_i < tol
+                         keeps its temperature, step multiplier and sign history */
     double T_floor;   /* lower temperature bound, K */
     double shrink;    /* multiplier on oscillation (paper: reduce by 33% -> 0.67) */
     double grow;      /* multiplier when monotonic (paper: +10% -> 1.1) */

@@ -66,7 +66,7 @@ def _load():
         lib.ref_flux.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, i, d,
                                  P, P, P, P, P, i]
         lib.ref_flux.restype = i
-        lib.ref_radeq.argtypes = [i, P, P, d, d, d, P, P, P, d, i, d, i, i, d, d, d, d, P]
+        lib.ref_radeq.argtypes = [i, P, P, d, d, d, P, P, P, d, i, d, i, i, d, d, d, d, i, P]
         lib.ref_radeq.restype = i
         for name in ("ref_E1", "ref_exact_trans", "ref_exact_diffusivity"):
             getattr(lib, name).argtypes = [d]
@@ -230,7 +230,7 @@ def flux(atm: dict, kappa, T_pt, P_pt, F_up, n_scat: int = 4, D: float = 2.0,
 
 # ------------------------------------------------------------------ RE step
 RE_DEFAULTS = dict(tol=1e-3, norm_sigma_tint=1, T_floor=10.0, window=6, osc_any=0, shrink=0.67,
-                   grow=1.1, fpre_c=1e5, fpre_p=0.9)
+                   grow=1.1, fpre_c=1e5, fpre_p=0.9, deadband=0)
 
 
 def radeq(atm: dict, P_pt, F_bol, T_c, m, hist, opts: dict | None = None):
@@ -246,7 +246,8 @@ def radeq(atm: dict, P_pt, F_bol, T_c, m, hist, opts: dict | None = None):
                              float(atm.get("mmw", 2.4)) * M_PROTON, float(atm["T_int"]),
                              _p(T_c), _p(m), _p(hist), float(o["tol"]), int(o["norm_sigma_tint"]),
                              float(o["T_floor"]), int(o["window"]), int(o["osc_any"]), float(o["shrink"]),
-                             float(o["grow"]), float(o["fpre_c"]), float(o["fpre_p"]), _p(resid))
+                             float(o["grow"]), float(o["fpre_c"]), float(o["fpre_p"]), int(o["deadband"]),
+                             _p(resid))
     return code, float(resid[0])
 
 

@@ -455,7 +455,7 @@ int ref_flux(int n, int nb, int ng,
 int ref_radeq(int n, const double* P_pt, const double* F_bol, double grav, double mmw_g,
               double T_int, double* T_c, double* m, int32_t* hist,
               double tol, int norm_sigma_tint, double T_floor, int window, int osc_any,
-              double shrink, double grow, double fpre_c, double fpre_p,
+              double shrink, double grow, double fpre_c, double fpre_p, int deadband,
               double* resid) {
     if (window < 2 || window > 16) return -1;
     const double sigma = ref_sigma_sb();
@@ -473,6 +473,12 @@ int ref_radeq(int n, const double* P_pt, const double* F_bol, double grav, doubl
     for (int i = 0; i < n; ++i) {
         double dF = F_bol[3 * (2 * i + 2) + 2] - F_bol[3 * (2 * i) + 2];
         double T = T_c[i], P = P_pt[2 * i + 1];
+        /* optional dead band: a layer already within the tolerance is left
+           as it is (temperature, step multiplier and sign history) */
+        if (deadband) {
+            double norm = norm_sigma_tint ? sigma * pow(T_int, 4) : sigma * pow(T, 4);
+            if (fabs(dF) / norm < tol) continue;
+        }
         double dT = 0.0;
         if (dF != 0.0) {
             double rho = P * mmw_g / (REF_K * T);

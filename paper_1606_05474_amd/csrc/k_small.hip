@@ -335,6 +335,11 @@ __global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         double dF = F[3 * (2 * i + 2) + 2] - F[3 * (2 * i) + 2];
         double T = Tc[i];
+        if (o.deadband) {  // a layer within the tolerance keeps T, m and its history
+            double t2 = T * T;
+            double norm = (o.norm == HELIOS_NORM_SIGMA_TINT4) ? sig * ti2 * ti2 : sig * t2 * t2;
+            if (fabs(dF) / norm < o.tol) continue;
+        }
         double dT = 0.0;
         if (dF != 0.0) {
             double lnR = log(P[2 * i] / P[2 * i + 2]);

@@ -183,9 +183,9 @@ __device__ inline void sub_coeffs_g(const LayerQ<R>& q, R dtau, R two_pi_eps, R 
     const R omi = om * iden;
     a = q.r * T * iden;
     c = q.zpzm * (one + T) * omi;
-    const R s_non = two_pi_eps * q.f * v * omi * Prec<R>::rcp(dtau) * dB;
-    const R s_iso = (R)0.5 * two_pi_eps * (one + a - c) * dB;
-    sig = (dtau < (R)1e-4) ? s_iso : s_non;  // a select: the unused one may be inf at dtau = 0
+    sig = two_pi_eps * q.f * v * omi * Prec<R>::rcp(dtau) * dB;
+    const bool iso = dtau < (R)1e-4;
+    if (__any(iso)) sig = iso ? (R)0.5 * two_pi_eps * (one + a - c) * dB : sig;  // may be inf at dtau = 0
     if (__any(q.purescat)) {  // eq:purescat
         const R gd = q.purescat_gd * dtau;
         const R qq = gd * Prec<R>::rcp(one + gd);
@@ -490,13 +490,24 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         }
         const R ftop_fold = pseg * Ftop;
 
+        // the down sweep's per-sublayer offsets c F_up - sig, kept for the
+        // replay when registers allow
+        constexpr bool KEEP_T = (sizeof(R) == 4) || (K <= 8);
+        R tk[KEEP_T ? K : 1];
         R ftoa = (R)0;
         for (int pass = 0; pass <= A.n_scat; ++pass) {
             const bool last = (pass == A.n_scat);
             // ---------------- downward sweep: compose my segment (top -> bottom)
             R MB = (R)0;
+            if constexpr (KEEP_T) {
 #pragma unroll
-            for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + (cc[k] * fu[k] - sg[k]);
+                for (int k = 0; k < K; ++k) tk[k] = cc[k] * fu[k] - sg[k];
+#pragma unroll
+                for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + tk[k];
+            } else {
+#pragma unroll
+                for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + (cc[k] * fu[k] - sg[k]);
+            }
             if (seg == L - 1) MB = ftop_fold + MB;
             if constexpr (PRECOMP) {  // suffix scan towards the BOA
                 MB = scan_down_step<L, 0>(MB, mdn[0]);
@@ -517,7 +528,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 #pragma unroll
             for (int k = K - 1; k >= 0; --k) {
                 bu[k] = cc[k] * x + sg[k];
-                x = ca[k] * x + (cc[k] * fu[k] - sg[k]);
+                if constexpr (KEEP_T) x = ca[k] * x + tk[k];
+                else x = ca[k] * x + (cc[k] * fu[k] - sg[k]);
                 if (last && k < cnt) s_out[cw * npt + lo + k] = x;
             }
             if (last) {

@@ -53,7 +53,7 @@ class HeliosKtab(ctypes.Structure):
 
 class HeliosReOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("norm", ctypes.c_int32), ("window", ctypes.c_int32),
-                ("osc_any", ctypes.c_int32), ("pad_", ctypes.c_int32), ("T_floor", ctypes.c_double),
+                ("osc_any", ctypes.c_int32), ("deadband", ctypes.c_int32), ("T_floor", ctypes.c_double),
                 ("shrink", ctypes.c_double), ("grow", ctypes.c_double), ("fpre_c", ctypes.c_double),
                 ("fpre_p", ctypes.c_double)]
 
@@ -339,10 +339,11 @@ class REOptions:
     grow: float = 1.1
     fpre_c: float = 1e5
     fpre_p: float = 0.9
+    deadband: int = 0
 
     def c(self) -> HeliosReOpts:
-        return HeliosReOpts(self.tol, self.norm, self.window, self.osc_any, 0, self.T_floor, self.shrink,
-                            self.grow, self.fpre_c, self.fpre_p)
+        return HeliosReOpts(self.tol, self.norm, self.window, self.osc_any, self.deadband, self.T_floor,
+                            self.shrink, self.grow, self.fpre_c, self.fpre_p)
 
 
 def radeq(b: Batch, F_bol, T_c, T_pt, m, hist, status, resid=None, opts: REOptions | None = None,
@@ -555,14 +556,20 @@ class Solver:
         self._warm = None
         self._reset_state()
 
-    def warm_reset(self, net: MLP, x, logP_net, T_iso=1000.0, T_lo=10.0, T_hi=1.0e4):
+    def warm_reset(self, net: MLP, x, logP_net, T_iso=1000.0, T_lo=10.0, T_hi=1.0e4, m0=1.0):
         """Start from the network's profiles (helios_warm_start); atmospheres
-        whose network profile is unusable start isothermal at T_iso.
-        Returns the per-atmosphere fallback flags (numpy)."""
+        whose network profile is unusable start isothermal at T_iso.  The
+        step multipliers of network-started atmospheres start at m0 (a start
+        close to equilibrium needs smaller first steps).  Returns the
+        per-atmosphere fallback flags (numpy)."""
         fb = torch.zeros(self.b.n_atm, dtype=torch.int32, device=self.b.device)
         warm_start(self.b, net, x, logP_net, self.T_c, fb, T_iso=T_iso, T_lo=T_lo, T_hi=T_hi)
         self._reset_state()
         fb = fb.cpu().numpy()
+        if m0 != 1.0:
+            self.m.fill_(m0)
+            for a in np.where(fb != 0)[0]:
+                self.m[int(self.b.lay_off[a]):int(self.b.lay_off[a + 1])] = 1.0
         self._warm = fb == 0
         self._T_iso = float(T_iso)
         return fb

@@ -125,13 +125,14 @@ def load(path: str) -> H.MLP:
 
 
 def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec: int = H.FP64, max_iter: int = 400,
-             restart_after: int = 150, n: int = 100, nb: int = 1000, log=print):
+             restart_after: int = 150, n: int = 100, nb: int = 1000, deadband: int = 0, m0: float = 1.0,
+             log=print):
     """Updates to converge and wall time from the isothermal start and from
     the network's start, same atmospheres, same tolerance."""
     kt = W.table_ktab(2, nbt=3000)
     atms, _ = W.learned_workload(seed, count, start, n=n, nb=nb, ktab=kt)
     b = H.Batch(atms)
-    s = H.Solver(b, H.KTable(kt), prec=prec)
+    s = H.Solver(b, H.KTable(kt), prec=prec, opts=H.REOptions(deadband=deadband))
     x = np.stack([a["params"] for a in atms])
     T0 = np.concatenate([a["T0"] for a in atms])
     out = {}
@@ -143,7 +144,7 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
             conv, it, rs = s.run(max_iter, 10, graph=True)
             fb = np.zeros(count, np.int32)
         else:
-            fb = s.warm_reset(net, x, net.logP)
+            fb = s.warm_reset(net, x, net.logP, m0=m0)
             conv, it, rs = s.run(max_iter, 10, graph=True, restart_after=restart_after)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -156,26 +157,37 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
     return out
 
 
-def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 512,
-               n: int = 200, nb: int = 3000, prec: int = H.MIXED, max_iter: int = 400, restart_after: int = 150,
-               check_every: int = 10, keep_T: int = 0, log=print):
+def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 256,
+               n: int = 200, nb: int = 3000, max_iter: int = 300, restart_after: int = 150,
+               check_every: int = 10, deadband: int = 1, polish_iter: int = 400, m0: float = 1.0, keep_T: int = 0,
+               log=print):
     """The production form: atmospheres start..start+count-1 of a parameter
     set solved in chunks of `chunk` atmospheres, each chunk one batch on the
-    device (size-class sweeps, graph replay, finished atmospheres skipped),
-    started from the network (isothermal fallback, restart after
-    `restart_after` updates) or, with net=None, isothermally.  The timed
-    region of a chunk starts with its inputs resident on the device and
-    covers the network, the warm start and the whole solve.  Returns totals
-    and the converged profiles of the first `keep_T` atmospheres."""
+    device (size-class sweeps, graph replay, finished atmospheres skipped):
+
+    1. start from the network (isothermal where its profile is unusable) or,
+       with net=None, isothermally;
+    2. iterate in mixed precision (FP32 sweeps, FP64 sums and update), with
+       the dead band on by default; a network-started atmosphere still
+       running after `restart_after` updates restarts isothermally;
+    3. atmospheres still running (or non-finite) continue in FP64 from their
+       last finite temperatures (else the isothermal start) for up to
+       `polish_iter` updates, as a batch of their own.
+
+    The convergence test is the same as the plain form's throughout.  The
+    timed region of a chunk starts with its inputs resident on the device and
+    covers all three stages.  Returns totals and the converged profiles of the
+    first `keep_T` atmospheres."""
     kt = W.table_ktab(2, nbt=3000)
     ktd = H.KTable(kt)
+    opts = H.REOptions(deadband=deadband)
     out = {"count": 0, "converged": 0, "seconds": 0.0, "updates": [], "fallbacks": 0, "restarts": 0,
-           "T": [], "conv_flags": []}
+           "polished": 0, "T": [], "conv_flags": []}
     for c0 in range(start, start + count, chunk):
         c = min(chunk, start + count - c0)
         atms, _ = W.learned_workload(seed, c, c0, n=n, nb=nb, ktab=kt)
         b = H.Batch(atms)
-        s = H.Solver(b, ktd, prec=prec)
+        s = H.Solver(b, ktd, prec=H.MIXED, opts=opts)
         x = np.stack([a["params"] for a in atms])
         T0 = np.concatenate([a["T0"] for a in atms])
         if c0 == start:  # one-time shape tuning for this process, outside the timed region
@@ -184,12 +196,26 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if net is not None:
-            fb = s.warm_reset(net, x, net.logP)
+            fb = s.warm_reset(net, x, net.logP, m0=m0)
             conv, it, rs = s.run(max_iter, check_every, graph=True, restart_after=restart_after)
         else:
             s.reset(T0)
             fb = np.zeros(c, np.int32)
             conv, it, rs = s.run(max_iter, check_every, graph=True)
+        Tc = s.T_c.cpu().numpy()
+        T_list = [Tc[int(b.lay_off[a]):int(b.lay_off[a + 1])] for a in range(c)]
+        left = np.where(~conv)[0]
+        if left.size:
+            T_left = [T_list[a] if np.all(np.isfinite(T_list[a])) else atms[a]["T0"] for a in left]
+            sub = H.Batch([atms[a] for a in left])
+            s2 = H.Solver(sub, ktd, prec=H.FP64, opts=opts)
+            c2, it2 = s2.solve(np.concatenate(T_left), max_iter=polish_iter, check_every=check_every, graph=True)
+            conv[left] = c2
+            it[left] = it[left] + it2
+            T2 = s2.T_c.cpu().numpy()
+            for k, a in enumerate(left):
+                T_list[a] = T2[int(sub.lay_off[k]):int(sub.lay_off[k + 1])]
+            del s2, sub
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out["count"] += c
@@ -198,13 +224,13 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         out["updates"].append(it)
         out["fallbacks"] += int(fb.sum())
         out["restarts"] += int(rs.sum())
+        out["polished"] += int(left.size)
         out["conv_flags"].append(conv)
-        need = keep_T - sum(len(t) for t in out["T"])
+        need = keep_T - len(out["T"])
         if need > 0:
-            Tc = s.T_c.cpu().numpy()
-            out["T"] += [Tc[int(b.lay_off[a]):int(b.lay_off[a + 1])] for a in range(min(need, c))]
+            out["T"] += T_list[:need]
         log(f"chunk {c0}..{c0 + c - 1}: {int(conv.sum())}/{c} converged in {dt:.1f} s, median updates "
-            f"{np.median(it):.0f}, fallbacks {int(fb.sum())}, restarts {int(rs.sum())}")
+            f"{np.median(it):.0f}, fallbacks {int(fb.sum())}, restarts {int(rs.sum())}, FP64 polish {left.size}")
         del s, b
         torch.cuda.empty_cache()
     out["updates"] = np.concatenate(out["updates"])
@@ -273,6 +299,8 @@ def main(argv=None):
     e.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
     e.add_argument("--restart-after", type=int, default=150)
     e.add_argument("--max-iter", type=int, default=400)
+    e.add_argument("--deadband", type=int, default=0)
+    e.add_argument("--m0", type=float, default=1.0)
     a = ap.parse_args(argv)
     H.lib()
     log = lambda *v: print(*v, flush=True)  # noqa: E731
@@ -289,7 +317,7 @@ def main(argv=None):
     else:
         net = load(a.weights)
         evaluate(net, a.seed, a.count, prec=H.MIXED if a.prec == "mixed" else H.FP64, max_iter=a.max_iter,
-                 restart_after=a.restart_after, log=log)
+                 restart_after=a.restart_after, deadband=a.deadband, m0=a.m0, log=log)
     return 0
 
 

@@ -41,3 +41,26 @@ def to_flux(G, iso):
     """Per-g GPU deviations [bin][g][point] plus the oracle's isothermal flux
     [bin][point]: the fluxes themselves."""
     return np.asarray(G, np.float64) + np.asarray(iso, np.float64)[:, None, :]
+
+
+def well_conditioned_layers(atm, kt, sol, dT=1.0):
+    """Layers whose own temperature moves their net-flux divergence by at
+    least 1% of d(sigma T^4)/dT (oracle finite differences at the oracle's
+    converged profile, same warm start for both evaluations)."""
+    P = sol["P_pt"]
+    sig = 5.670374419e-5
+
+    def divergence(T_c):
+        T = ref.profile(P, T_c)
+        kap = ref.mix_opacity(kt, T, P, atm["vmr"], atm["bin_index"], atm["ng"])
+        F = ref.flux(atm, kap, T, P, sol["F_up"].copy(), want_dn=False)["F_bol"][:, 2]
+        return F[2::2] - F[:-1:2]
+
+    base = divergence(sol["T_c"])
+    ok = np.zeros(atm["n"], bool)
+    for i in range(atm["n"]):
+        Tp = sol["T_c"].copy()
+        Tp[i] += dT
+        d = abs(divergence(Tp)[i] - base[i]) / dT
+        ok[i] = d >= 0.01 * 4.0 * sig * sol["T_c"][i] ** 3
+    return ok

@@ -10,6 +10,8 @@ flips move an output by far less than 2e-3 of the output range, the bound
 used for outputs; gradients, built from the same activations and rounded
 errors, are held to 1e-2 norm-wise per layer and the loss to 1e-3.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -163,3 +165,36 @@ def test_mlp_errors_are_reported():
         net.forward(np.zeros((0, 6), np.float32))
     bad = H.HeliosMlp(6, 0, 1, 10)
     assert H.lib().helios_mlp_param_count(bad) == 0
+
+
+WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_1606_05474_amd", "data", "warmstart_mlp.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained warm-start network in the tree")
+def test_trained_network_shortens_the_solve():
+    """The committed network (trained on the device by these kernels) starts
+    held-out atmospheres close to their equilibrium: fewer temperature
+    updates to the same tolerance than the isothermal start, and profiles
+    within a few tens of kelvin of the converged ones."""
+    from paper_1606_05474_amd import warmstart as WS
+    from paper_1606_05474_amd import workloads as W
+
+    net = WS.load(WEIGHTS)
+    atms, kt = W.learned_workload(40, 24, 100)
+    b = H.Batch(atms)
+    s = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    T0 = np.concatenate([a["T0"] for a in atms])
+    s.reset(T0)
+    c_iso, it_iso, _ = s.run(400, 10, graph=True)
+    T_conv = s.T_c.cpu().numpy().copy()
+    x = np.stack([a["params"] for a in atms])
+    fb = s.warm_reset(net, x, net.logP)
+    T_start = s.T_c.cpu().numpy().copy()
+    c_nn, it_nn, rs = s.run(400, 10, graph=True, restart_after=150)
+    assert fb.sum() == 0
+    both = c_iso & c_nn
+    assert both.sum() >= len(atms) // 2
+    assert np.median(it_nn[both]) < 0.8 * np.median(it_iso[both]), (np.median(it_nn[both]), np.median(it_iso[both]))
+    err = [np.sqrt(np.mean((T_start[b.lay_off[a]:b.lay_off[a + 1]] - T_conv[b.lay_off[a]:b.lay_off[a + 1]]) ** 2))
+           for a in np.where(c_iso)[0]]
+    assert np.median(err) < 60.0, np.median(err)

@@ -15,7 +15,8 @@ import pytest
 import torch
 
 import oracle as ref
-from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux
+from gpu_helpers import (col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux,
+                         well_conditioned_layers)
 from paper_1606_05474_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -237,7 +238,8 @@ def test_flux_mixed_precision_within_tolerance(small_table):
 
 
 # ----------------------------------------------------------------- RE step
-def test_radeq_matches_oracle_single_update():
+@pytest.mark.parametrize("deadband", [0, 1])
+def test_radeq_matches_oracle_single_update(deadband):
     atms = [W.plain_workload(n=n, nb=8)[0] for n in (50, 23)]
     b = H.Batch(atms)
     H.grid(b)
@@ -246,7 +248,11 @@ def test_radeq_matches_oracle_single_update():
     for atm in atms:
         n = atm["n"]
         P = ref.grid(atm["P_c"])
-        net = 9e4 + np.cumsum(rng.normal(0, 3e4, 2 * n + 1))
+        inc = rng.normal(0, 3e4, 2 * n + 1)
+        if deadband:  # every third layer inside the tolerance band
+            for i in range(0, n, 3):
+                inc[2 * i + 1:2 * i + 3] = rng.normal(0, 1.0, 2)
+        net = 9e4 + np.cumsum(inc)
         F = np.zeros((2 * n + 1, 3))
         F[:, 0] = 5e8 + net
         F[:, 1] = 5e8
@@ -264,11 +270,14 @@ def test_radeq_matches_oracle_single_update():
     status = torch.zeros(b.n_atm, dtype=torch.int32, device="cuda")
     resid = torch.zeros(b.n_atm, dtype=torch.float64, device="cuda")
     iters = torch.zeros(b.n_atm, dtype=torch.int32, device="cuda")
-    H.radeq(b, F_d, T_d, T_pt, m_d, h_d, status, resid, iters=iters)
+    H.radeq(b, F_d, T_d, T_pt, m_d, h_d, status, resid, H.REOptions(deadband=deadband), iters=iters)
     torch.cuda.synchronize()
     for a, atm in enumerate(atms):
         T_ref, m_ref, h_ref = T_cs[a].copy(), ms[a].copy(), hs[a].copy()
-        code, r = ref.radeq(atm, ref.grid(atm["P_c"]), F_bols[a], T_ref, m_ref, h_ref)
+        code, r = ref.radeq(atm, ref.grid(atm["P_c"]), F_bols[a], T_ref, m_ref, h_ref, {"deadband": deadband})
+        if deadband:
+            kept = T_ref == T_cs[a]
+            assert kept[::3].all() and kept.sum() >= len(kept) // 3
         assert code == 0
         np.testing.assert_allclose(b.split_layer(_np(T_d))[a], T_ref, rtol=0, atol=1e-9)
         np.testing.assert_allclose(b.split_layer(_np(m_d))[a], m_ref, rtol=1e-15)
@@ -577,29 +586,6 @@ def test_full_size_production_atmosphere_against_oracle(prec):
     assert err.max() < (1e-10 if prec == 0 else 1e-4), err.max()
 
 
-def _well_conditioned_layers(atm, kt, sol, dT=1.0):
-    """Layers whose own temperature moves their net-flux divergence by at
-    least 1% of d(sigma T^4)/dT (oracle finite differences at the oracle's
-    converged profile, same warm start for both evaluations)."""
-    P = sol["P_pt"]
-    sig = 5.670374419e-5
-
-    def divergence(T_c):
-        T = ref.profile(P, T_c)
-        kap = ref.mix_opacity(kt, T, P, atm["vmr"], atm["bin_index"], atm["ng"])
-        F = ref.flux(atm, kap, T, P, sol["F_up"].copy(), want_dn=False)["F_bol"][:, 2]
-        return F[2::2] - F[:-1:2]
-
-    base = divergence(sol["T_c"])
-    ok = np.zeros(atm["n"], bool)
-    for i in range(atm["n"]):
-        Tp = sol["T_c"].copy()
-        Tp[i] += dT
-        d = abs(divergence(Tp)[i] - base[i]) / dT
-        ok[i] = d >= 0.01 * 4.0 * sig * sol["T_c"][i] ** 3
-    return ok
-
-
 def test_mixed_precision_converges_to_the_oracle_profile():
     """The plain workload solved in mixed precision reaches the oracle's
     converged profile (same warm-start convention) within 0.1 K over the
@@ -614,7 +600,7 @@ def test_mixed_precision_converges_to_the_oracle_profile():
     conv, iters = s.solve(atm["T0"], max_iter=300)
     assert conv[0]
     dT = np.abs(_np(s.T_c) - sol["T_c"])
-    ok = _well_conditioned_layers(atm, kt, sol)
+    ok = well_conditioned_layers(atm, kt, sol)
     assert ok.sum() >= atm["n"] // 2, ok.sum()
     assert dT[ok].max() < 0.1, (dT[ok].max(), dT.max())
     assert np.all(np.isfinite(dT))

@@ -504,3 +504,18 @@ def test_deviation_warm_start_reaches_the_same_equilibrium(ref, plain_solution):
     net = dev["flux"]["F_bol"][::2, 2]
     assert np.abs(net - s4).max() < atm["n"] * 1e-3 * s4
     assert np.abs(dev["T_c"] - sol["T_c"]).max() < 0.1, np.abs(dev["T_c"] - sol["T_c"]).max()
+
+
+def test_dead_band_reaches_the_same_equilibrium(ref, plain_solution):
+    """Leaving layers that are already within the tolerance untouched changes
+    the trajectory, not the fixed point."""
+    atm, kt, sol = plain_solution
+    db = ref.solve(atm, kt, max_iter=400, opts={"deadband": 1})
+    assert db["converged"]
+    s4 = SIGMA_CODATA * atm["T_int"] ** 4
+    assert np.abs(db["flux"]["F_bol"][::2, 2] - s4).max() < atm["n"] * 1e-3 * s4
+    from gpu_helpers import well_conditioned_layers
+
+    ok = well_conditioned_layers(atm, kt, sol)
+    dT = np.abs(db["T_c"] - sol["T_c"])
+    assert ok.sum() >= atm["n"] // 2 and dT[ok].max() < 0.1, (ok.sum(), dT[ok].max())
