@@ -9,7 +9,9 @@
 // ratios are computed once (LDS).  Consecutive points usually fall in the
 // same (T, log P) cell: a thread keeps the cell's corner values of its column
 // in registers and reloads them only when the cell changes (a
-// workgroup-uniform decision).  For a fixed point the threads read
+// workgroup-uniform decision), and it issues the loads of the next cell's
+// corners as soon as a cell is entered, so they are in flight while the
+// current cell's points are computed.  For a fixed point the threads read
 // consecutive (bin, g) entries of each corner row (coalesced).  A thread's
 // kMixPts results are one or two whole aligned 128-byte lines of its column
 // (the column stride is padded to a multiple of kMixPts) and are written
@@ -52,6 +54,7 @@ struct Vec2<double> {
 template <typename R, int NSP>
 __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
     __shared__ int s_cell[kMixPts];
+    __shared__ int s_next[kMixPts];  // at the first point of a run of equal cells: the next run's cell, or -1
     __shared__ R s_w[kMixPts][4];    // bilinear corner weights or power-law scale
     __shared__ R s_x[kMixPts][NSP];  // mass mixing ratios
 
@@ -90,6 +93,15 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
         }
     }
     __syncthreads();
+    if (t == 0) {  // runs of equal cells along the chunk: where each starts, and what follows it
+        int next = -1;
+        for (int j = npts - 1; j >= 0; --j) {
+            const bool start = (j == 0) || (s_cell[j] != s_cell[j - 1]);
+            s_next[j] = start ? next : -2;
+            if (start) next = s_cell[j];
+        }
+    }
+    __syncthreads();
     if (c >= ncol) return;
 
     const int l = c / A.ng, g = c - l * A.ng;
@@ -97,7 +109,19 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
     const int bt = min(max(A.atm.bin_index[A.atm.bin_off[a] + l], 0), A.nbt - 1);
     const size_t row = (size_t)A.nbt * A.ng;  // one (species, T, P) corner row
     const size_t off = (size_t)bt * A.ng + g;
-    R kc[NSP][4];
+    float kc[NSP][4], kn[NSP][4];  // corners of the current cell and of the next one (in flight)
+    auto load_cell = [&](float (&dst)[NSP][4], int cell) {
+#pragma unroll
+        for (int sp = 0; sp < NSP; ++sp) {
+            const float* kb = A.k + ((size_t)sp * A.nT * A.nP + cell) * row + off;
+            const bool ok = sp < A.n_species;
+            dst[sp][0] = ok ? kb[0] : 0.0f;
+            dst[sp][1] = ok ? kb[row] : 0.0f;
+            dst[sp][2] = ok ? kb[(size_t)A.nP * row] : 0.0f;
+            dst[sp][3] = ok ? kb[(size_t)(A.nP + 1) * row] : 0.0f;
+        }
+    };
+    R kp[NSP];  // power-law coefficients
     R vals[kMixPts];
     int cur = -1;
 #pragma unroll
@@ -105,31 +129,31 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
         R acc = (R)0;
         if (j < npts) {
             if (A.mode == HELIOS_KTAB_TABLE) {
-                if (s_cell[j] != cur) {  // uniform: load the new cell's corners
-                    cur = s_cell[j];
+                const int nx = s_next[j];
+                if (nx != -2) {  // uniform: a new run of equal cells starts here
+                    if (j == 0) load_cell(kc, s_cell[0]);
+                    else {
 #pragma unroll
-                    for (int sp = 0; sp < NSP; ++sp) {
-                        const float* kb = A.k + ((size_t)sp * A.nT * A.nP + cur) * row + off;
-                        const bool ok = sp < A.n_species;
-                        kc[sp][0] = ok ? (R)kb[0] : (R)0;
-                        kc[sp][1] = ok ? (R)kb[row] : (R)0;
-                        kc[sp][2] = ok ? (R)kb[(size_t)A.nP * row] : (R)0;
-                        kc[sp][3] = ok ? (R)kb[(size_t)(A.nP + 1) * row] : (R)0;
+                        for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) kc[sp][q] = kn[sp][q];
                     }
+                    if (nx >= 0) load_cell(kn, nx);  // the following run's corners
                 }
                 const R w00 = s_w[j][0], w01 = s_w[j][1], w10 = s_w[j][2], w11 = s_w[j][3];
 #pragma unroll
                 for (int sp = 0; sp < NSP; ++sp)
-                    acc += s_x[j][sp] * (w00 * kc[sp][0] + w01 * kc[sp][1] + w10 * kc[sp][2] + w11 * kc[sp][3]);
+                    acc += s_x[j][sp] * (w00 * (R)kc[sp][0] + w01 * (R)kc[sp][1] + w10 * (R)kc[sp][2] +
+                                         w11 * (R)kc[sp][3]);
             } else {
                 if (cur < 0) {
                     cur = 0;
 #pragma unroll
                     for (int sp = 0; sp < NSP; ++sp)
-                        kc[sp][0] = (sp < A.n_species) ? (R)A.k0[(size_t)sp * row + off] : (R)0;
+                        kp[sp] = (sp < A.n_species) ? (R)A.k0[(size_t)sp * row + off] : (R)0;
                 }
 #pragma unroll
-                for (int sp = 0; sp < NSP; ++sp) acc += s_x[j][sp] * kc[sp][0];
+                for (int sp = 0; sp < NSP; ++sp) acc += s_x[j][sp] * kp[sp];
                 acc *= s_w[j][0];
             }
         }

@@ -82,10 +82,12 @@ __global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __
 // (T_irr/T_star)^4 pi B(T_star); BOA pi B(T_int) scaled so that its
 // width-weighted sum over the model's bins is sigma T_int^4.  The scale's sum
 // is a fixed-order tree in LDS.
-__global__ void __launch_bounds__(256) boundary_kernel(helios_atm atm, double* __restrict__ F_top,
-                                                       double* __restrict__ F_int, double* __restrict__ gw,
-                                                       int32_t* __restrict__ bin_atm, GaussTable gt) {
-    __shared__ double red[256];
+constexpr int kBoundaryThreads = 1024;
+__global__ void __launch_bounds__(kBoundaryThreads) boundary_kernel(helios_atm atm, double* __restrict__ F_top,
+                                                                    double* __restrict__ F_int,
+                                                                    double* __restrict__ gw,
+                                                                    int32_t* __restrict__ bin_atm, GaussTable gt) {
+    __shared__ double red[kBoundaryThreads];
     int a = blockIdx.x;
     if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gt.w[threadIdx.x];
     int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
@@ -124,7 +126,8 @@ hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* 
     hipLaunchKernelGGL(planck_kernel, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb, T_pt, B);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_top, F_int, gw, bin_atm, gt);
+    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(kBoundaryThreads), 0, s, *atm, F_top, F_int, gw,
+                       bin_atm, gt);
     return hipGetLastError();
 }
 

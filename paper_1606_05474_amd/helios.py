@@ -587,6 +587,35 @@ class Solver:
             self.status[a] = ATM_RUNNING
         profile(self.b, self.T_c, self.T_pt)
 
+    def subset(self, keep):
+        """A solver over the atmospheres `keep` (indices into this batch) that
+        continues their iteration: temperatures, step multipliers, sign
+        histories, update counts and per-g warm starts are carried over, every
+        carried atmosphere is running.  Used to compact a batch whose active
+        set has shrunk, so later launches cover only live atmospheres."""
+        keep = np.asarray(keep, np.int64)
+        b0 = self.b
+        nb = Batch([b0.atms[int(a)] for a in keep], device=b0.device)
+        s = Solver(nb, self.kt, prec=self.prec, n_scat=self.n_scat, D=self.D, opts=self.opts)
+        for k, a in enumerate(keep):
+            a = int(a)
+            ls, le = int(b0.lay_off[a]), int(b0.lay_off[a + 1])
+            ns = int(nb.lay_off[k])
+            s.T_c[ns:ns + le - ls] = self.T_c[ls:le]
+            s.m[ns:ns + le - ls] = self.m[ls:le]
+            s.hist[ns:ns + le - ls] = self.hist[ls:le]
+            cs, ce = int(b0.cell_off[a]), int(b0.cell_off[a + 1])
+            nc = int(nb.cell_off[k])
+            s.F_up_g[nc:nc + ce - cs] = self.F_up_g[cs:ce]
+        idx = torch.as_tensor(keep, device=b0.device)
+        s.iters.copy_(self.iters[idx])
+        s.resid.copy_(self.resid[idx])
+        if self._warm is not None:
+            s._warm = self._warm[keep]
+        s._T_iso = self._T_iso
+        profile(s.b, s.T_c, s.T_pt)
+        return s
+
     def step(self, stream=None):
         """One RE iteration for every running atmosphere of the batch (enqueue only)."""
         b = self.b

@@ -124,8 +124,8 @@ def load(path: str) -> H.MLP:
     return net
 
 
-def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec: int = H.FP64, max_iter: int = 400,
-             restart_after: int = 150, n: int = 100, nb: int = 1000, deadband: int = 0, m0: float = 1.0,
+def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec: int = H.FP64, max_iter: int = 600,
+             restart_after: int = 400, n: int = 100, nb: int = 1000, deadband: int = 0, m0: float = 1.0,
              log=print):
     """Updates to converge and wall time from the isothermal start and from
     the network's start, same atmospheres, same tolerance."""
@@ -158,8 +158,8 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
 
 
 def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 256,
-               n: int = 200, nb: int = 3000, max_iter: int = 300, restart_after: int = 150,
-               check_every: int = 10, deadband: int = 1, polish_iter: int = 400, m0: float = 1.0, keep_T: int = 0,
+               n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 900,
+               check_every: int = 10, deadband: int = 1, polish_iter: int = 600, m0: float = 0.3, keep_T: int = 0,
                log=print):
     """The production form: atmospheres start..start+count-1 of a parameter
     set solved in chunks of `chunk` atmospheres, each chunk one batch on the
@@ -197,13 +197,10 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         t0 = time.perf_counter()
         if net is not None:
             fb = s.warm_reset(net, x, net.logP, m0=m0)
-            conv, it, rs = s.run(max_iter, check_every, graph=True, restart_after=restart_after)
         else:
             s.reset(T0)
             fb = np.zeros(c, np.int32)
-            conv, it, rs = s.run(max_iter, check_every, graph=True)
-        Tc = s.T_c.cpu().numpy()
-        T_list = [Tc[int(b.lay_off[a]):int(b.lay_off[a + 1])] for a in range(c)]
+        conv, it, rs, T_list = _run_compacting(s, max_iter, check_every, restart_after if net is not None else None)
         left = np.where(~conv)[0]
         if left.size:
             T_left = [T_list[a] if np.all(np.isfinite(T_list[a])) else atms[a]["T0"] for a in left]
@@ -237,6 +234,60 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
     out["conv_flags"] = np.concatenate(out["conv_flags"])
     out["converged_per_s"] = out["converged"] / out["seconds"]
     return out
+
+
+def _run_compacting(s: H.Solver, max_iter: int, check_every: int, restart_after: int | None,
+                    min_live: int = 8):
+    """Iterate a batch in captured blocks of `check_every` updates; whenever
+    at most half of the atmospheres of the current batch are still running
+    (and more than `min_live`), move the running ones into a smaller batch
+    (Solver.subset) so that later launches cover live atmospheres only.
+    Returns (converged, updates, restarted, final layer temperatures) per
+    atmosphere of the original batch."""
+    n0 = s.b.n_atm
+    conv = np.zeros(n0, bool)
+    its = np.zeros(n0, np.int64)
+    restarted = np.zeros(n0, bool)
+    T_out = [None] * n0
+    live = np.arange(n0)  # original index of each atmosphere of the current batch
+    rs_cur = np.zeros(n0, bool)
+
+    def harvest(sv, which):
+        st = sv.status.cpu().numpy()
+        it = sv.iters.cpu().numpy()
+        Tc = sv.T_c.cpu().numpy()
+        for k in which:
+            a = int(live[k])
+            conv[a] = st[k] == H.ATM_CONVERGED
+            its[a] = it[k]
+            T_out[a] = Tc[int(sv.b.lay_off[k]):int(sv.b.lay_off[k + 1])].copy()
+
+    done = 0
+    s.capture(check_every)
+    while done < max_iter:
+        s.replay()
+        done += check_every
+        st = s.status.cpu().numpy()
+        if restart_after is not None and s._warm is not None:
+            it = s.iters.cpu().numpy()
+            late = np.where(s._warm & ~rs_cur & (st == H.ATM_RUNNING) & (it >= restart_after))[0]
+            if late.size:
+                s.restart(late, s._T_iso)
+                rs_cur[late] = True
+                restarted[live[late]] = True
+                st = s.status.cpu().numpy()
+        running = st == H.ATM_RUNNING
+        if not running.any():
+            break
+        if running.sum() <= len(live) // 2 and len(live) > min_live:
+            harvest(s, np.where(~running)[0])
+            keep = np.where(running)[0]
+            s = s.subset(keep)
+            live = live[keep]
+            rs_cur = rs_cur[keep]
+            s.capture(check_every)
+    harvest(s, range(len(live)))
+    return conv, its, restarted, T_out
 
 
 def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int = 3000, max_iter: int = 400,
@@ -297,10 +348,10 @@ def main(argv=None):
     e.add_argument("--seed", type=int, default=40)
     e.add_argument("--count", type=int, default=256)
     e.add_argument("--prec", choices=["fp64", "mixed"], default="fp64")
-    e.add_argument("--restart-after", type=int, default=150)
-    e.add_argument("--max-iter", type=int, default=400)
+    e.add_argument("--restart-after", type=int, default=400)
+    e.add_argument("--max-iter", type=int, default=600)
     e.add_argument("--deadband", type=int, default=0)
-    e.add_argument("--m0", type=float, default=1.0)
+    e.add_argument("--m0", type=float, default=0.3)
     a = ap.parse_args(argv)
     H.lib()
     log = lambda *v: print(*v, flush=True)  # noqa: E731

@@ -604,3 +604,29 @@ def test_mixed_precision_converges_to_the_oracle_profile():
     assert ok.sum() >= atm["n"] // 2, ok.sum()
     assert dT[ok].max() < 0.1, (dT[ok].max(), dT.max())
     assert np.all(np.isfinite(dT))
+
+
+def test_compacted_batch_continues_the_same_iteration():
+    """Moving the running atmospheres of a batch into a smaller one
+    (Solver.subset) carries their whole state: the continued iteration gives
+    bit-for-bit the temperatures and update counts of the uncompacted run."""
+    atms = [W.plain_workload(n=40, nb=12, seed=s)[0] for s in (1, 2, 3, 4, 5)]
+    kt = W.plain_workload(n=40, nb=12)[1]
+    T0 = np.concatenate([a["T0"] for a in atms])
+    b = H.Batch(atms)
+    full = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    full.reset(T0)
+    for _ in range(120):
+        full.step()
+    part = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    part.reset(T0)
+    for _ in range(50):
+        part.step()
+    keep = np.array([4, 1, 2])
+    sub = part.subset(keep)
+    for _ in range(70):
+        sub.step()
+    torch.cuda.synchronize()
+    for k, a in enumerate(keep):
+        np.testing.assert_array_equal(b.split_layer(_np(full.T_c))[a], sub.b.split_layer(_np(sub.T_c))[k])
+        assert int(_np(full.iters)[a]) == int(_np(sub.iters)[k])
