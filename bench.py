@@ -236,7 +236,7 @@ def production_main(args):
         "data": "synthetic",
         "config": {"workload": f"{args.n_atm} parameter-described atmospheres (seed 5), 200 layers x 3000 bins x "
                                f"20 g, chunks of {args.chunk}, mixed precision with dead band then FP64 polish, "
-                               "network warm start with isothermal fallback and isothermal restart after 900 updates, first step multipliers 0.3; plain "
+                               "network warm start with isothermal fallback and isothermal restart after 1000 updates, first step multipliers 0.3; plain "
                                "form: FP64, one atmosphere at a time, isothermal start, every layer stepped; "
                                "tolerance 1e-3 sigma T_int^4 for both",
                    "n_atm": args.n_atm, "chunk": args.chunk},

@@ -109,14 +109,12 @@ struct WsLayout {
 // Waves per bin for L lanes per column: each wave holds 64/L columns.
 int waves_per_bin(int n_g, int L) { return (n_g + (64 / L) - 1) / (64 / L); }
 
-// The workspace is sized for the largest waves-per-bin any sweep shape uses
-// (L = 32), which is also the stride of the partial-sum layout, so the shape
-// can be chosen per call and per size class.
-// Partial sums are 8 bytes in both precisions (a double, or a compensated
-// float pair), so the layout does not depend on the precision.
-WsLayout ws_layout(const Sizes& z, int n_g, bool /*mixed*/) {
+// One Gauss partial per (bin, point) and direction, sized for doubles (the
+// mixed path stores floats in the first half), so the layout does not depend
+// on the precision or the sweep shape.
+WsLayout ws_layout(const Sizes& z, int /*n_g*/, bool /*mixed*/) {
     WsLayout w;
-    const size_t wpb = (size_t)waves_per_bin(n_g, 32);
+    const size_t wpb = 1;
     const size_t n_chunk = (size_t)((z.nb_max + kBolChunk - 1) / kBolChunk);
     w.B = 0;  // Planck values in FP64 for both precisions
     w.F_top = align256(w.B + (size_t)z.total_pb * sizeof(double));
@@ -284,21 +282,22 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
     A.status = atm->status;
     A.n_atm = atm->n_atm;
     A.n_g = atm->n_g;
-    A.wpb_stride = waves_per_bin(atm->n_g, 32);
+    A.wpb_stride = 1;
     A.n_scat = n_scat;
     A.npt_max = p.z.npt_max;
     A.D = D;
     return A;
 }
 
-// One sweep launch for class k over bins [b_lo, b_hi).
+// One sweep launch for class k over bins [b_lo, b_hi): one wave per bin,
+// looping over the bin's groups of 64/L columns.
 hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, int64_t b_hi, bool mixed,
                        hipStream_t s) {
-    A.wpb = waves_per_bin(A.n_g, sh.L);
+    A.wpb = waves_per_bin(A.n_g, sh.L);  // column groups per bin
     A.n_lo = class_nlo(k);
     A.n_hi = kClassNHi[k];
-    A.w_begin = b_lo * A.wpb;
-    A.w_end = b_hi * A.wpb;
+    A.w_begin = b_lo;
+    A.w_end = b_hi;
     int64_t grid64 = A.w_end - A.w_begin;
     int cap = env_int("HELIOS_SWEEP_GRID", 0);
     if (cap > 0 && grid64 > cap) grid64 = cap;
@@ -546,7 +545,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     Bo.n_cls = kNumClasses;
     for (int k = 0; k < kNumClasses; ++k) {
         Bo.cls_nhi[k] = kClassNHi[k];
-        Bo.cls_wpb[k] = p.sh[k].L ? waves_per_bin(atm->n_g, p.sh[k].L) : 1;
+        Bo.cls_wpb[k] = 1;  // the sweep leaves one partial per (bin, point)
     }
     e = launch_bolometric(Bo, p.z.npt_max, p.z.nb_max, p.z.total_pt, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (bolometric)");

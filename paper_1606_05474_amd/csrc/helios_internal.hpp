@@ -52,17 +52,6 @@ __device__ inline double planck_d(double lambda, double T) {
     return c1 / (l2 * l2 * lambda) / expm1(x);
 }
 
-// Compensated pair (value + error) for float sums.
-struct fpair {
-    float s, c;
-};
-__device__ inline fpair two_sum_add(fpair a, fpair b) {
-    float s = a.s + b.s;
-    float bb = s - a.s;
-    float err = (a.s - (s - bb)) + (b.s - bb);
-    return {s, a.c + b.c + err};
-}
-
 // ----------------------------------------------------------- launch args
 struct SweepArgs {
     const int32_t* n_layer;
@@ -86,10 +75,10 @@ struct SweepArgs {
     const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
     const int32_t* status;   // optional: converged atmospheres are skipped
     const int32_t* bin_atm;  // [sum nb] owning atmosphere of each bin (workspace)
-    int64_t w_begin, w_end;  // global wave range covered by the launch
+    int64_t w_begin, w_end;  // global bin range covered by the launch (one wave per bin)
     int32_t n_atm, n_g;
-    int32_t wpb;          // waves per bin of this launch's shape
-    int32_t wpb_stride;   // waves-per-bin stride of the partial-sum layout (largest shape)
+    int32_t wpb;          // groups of 64/L columns per bin (this launch's shape)
+    int32_t wpb_stride;   // partials per (bin, point) in the workspace (1)
     int32_t n_lo, n_hi;   // this launch serves atmospheres with n_lo <= n <= n_hi
     int32_t n_scat;
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
@@ -104,7 +93,7 @@ struct GaussTable {
 
 struct BolArgs {
     helios_atm atm;
-    const void* part_up;  // partial sums from the sweep (double, or compensated float pairs)
+    const void* part_up;  // per-wave Gauss partials from the sweep (double, or float in mixed precision)
     const void* part_dn;
     double* F_up_bin;
     double* F_dn_bin;

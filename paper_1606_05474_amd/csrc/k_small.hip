@@ -157,10 +157,10 @@ __device__ inline double combine_partials(const void* part, int64_t base, int wp
         for (int j = 0; j < wpb; ++j) s += p[(int64_t)j * npt];
         return s;
     }
-    const fpair* p = static_cast<const fpair*>(part) + base;
-    fpair acc = {0.0f, 0.0f};
-    for (int j = 0; j < wpb; ++j) acc = two_sum_add(acc, p[(int64_t)j * npt]);
-    return (double)acc.s + (double)acc.c;
+    const float* p = static_cast<const float*>(part) + base;
+    double acc = 0.0;
+    for (int j = 0; j < wpb; ++j) acc += (double)p[(int64_t)j * npt];
+    return acc;
 }
 
 // Stage 1 workgroup: 64 points x 16 groups of kBolChunk/16 consecutive bins.

@@ -283,21 +283,25 @@ struct GSum<double> {
 };
 template <>
 struct GSum<float> {
-    using slot = fpair;
+    // a wave's columns are at most 4 g points, so its partial is a sum of <= 4
+    // products; every later sum (over the bin's waves, then over bins) is in
+    // FP64 with compensation
+    using slot = float;
     __device__ static inline slot col_sum(const float* col, int npt, int ncols, const float* w) {
-        fpair acc = {0.0f, 0.0f};
-        for (int c = 0; c < ncols; ++c) acc = two_sum_add(acc, fpair{w[c] * col[c * npt], 0.0f});
+        float acc = 0.0f;
+        for (int c = 0; c < ncols; ++c) acc += w[c] * col[c * npt];
         return acc;
     }
 };
 
-// One workgroup = one wave = C = 64/L columns (consecutive g of one bin) of
-// L lanes.  Wave j of bin l covers g in [j*C, j*C + C); its C columns are
-// contiguous in the [bin][g][point] arrays, so the wave stages them (and
-// the bin's Planck values, sublayer column masses, w0 and g0) in LDS with
-// coalesced loads, and writes its outputs back through LDS the same way.
-// No barrier spans more than the wave; the Gauss partial sums go to the
-// workspace and the bolometric kernel combines a bin's partials in fixed order.
+// One workgroup = one wave, which owns one bin at a time: it stages the
+// bin's Planck differences, sublayer column masses, w0 and g0 in LDS once,
+// then solves the bin's n_g columns C = 64/L at a time (group j covers g in
+// [j*C, j*C + C), contiguous in the [bin][g][point] arrays, staged and
+// written back through LDS with coalesced accesses), and accumulates the
+// Gauss sums of all groups in LDS in a fixed order.  One partial per (bin,
+// point) goes to the workspace, where the bin-sum kernel adds the Planck term
+// and sums over bins.  No barrier spans more than the wave.
 template <int K, int L, typename R, int OCC>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using GS = GSum<R>;
@@ -306,12 +310,14 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     static_assert(K % 2 == 0, "segments hold whole layers");
     extern __shared__ unsigned char smem_raw[];
     const int npt_max = A.npt_max;
-    R* s_kap = reinterpret_cast<R*>(smem_raw);  // [C][npt]   opacities, later partials / F_dn
-    R* s_fu = s_kap + C * npt_max;              // [C][npt]   warm start, later F_up
+    R* s_kap = reinterpret_cast<R*>(smem_raw);  // [C][npt]   opacities of the group
+    R* s_fu = s_kap + C * npt_max;              // [C][npt]   warm start, later F_dn / F_up of the group
     R* s_dB = s_fu + C * npt_max;               // [npt - 1]  Planck difference across each sublayer
     R* s_dm = s_dB + npt_max;                   // [npt - 1]  sublayer column masses
     R* s_w0 = s_dm + npt_max;                   // [n]
     R* s_g0 = s_w0 + npt_max / 2;               // [n]
+    slot* s_pu = reinterpret_cast<slot*>(s_g0 + npt_max / 2 + 1);  // [npt] Gauss sums, up
+    slot* s_pd = s_pu + npt_max;                                     // [npt] Gauss sums, down
 
     const int lane = threadIdx.x;
     const int seg = lane & (L - 1);
@@ -323,27 +329,19 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     slot* __restrict__ part_up = static_cast<slot*>(A.part_up);
     slot* __restrict__ part_dn = static_cast<slot*>(A.part_dn);
 
-    for (int64_t gwave = A.w_begin + blockIdx.x; gwave < A.w_end; gwave += gridDim.x) {
-        const int64_t gb = gwave / A.wpb;
-        const int j = (int)(gwave - gb * A.wpb);
+    for (int64_t gb = A.w_begin + blockIdx.x; gb < A.w_end; gb += gridDim.x) {
         const int at = A.bin_atm[gb];
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
         if (n < A.n_lo || n > A.n_hi || frozen(A.status, at)) continue;  // uniform per wave
         const int nsub = 2 * n, npt = nsub + 1;
         const int nact = (nsub + K - 1) / K;
-        const int g = j * C + cw;
-        const int ncols = min(C, A.n_g - j * C);  // columns of this wave
-        const bool colok = cw < ncols;
         const int lo = seg * K;
         const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // points owned (any column)
         const bool top_seg = (seg == nact - 1);                 // also owns the TOA point
-        const int cnt = colok ? scnt : 0;
         const int cs = col_stride(n);
-        const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * cs;  // first column
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
-        const int64_t poff = (A.pb_off[at] * A.wpb_stride) + ((int64_t)l * A.wpb_stride + j) * npt;
         const double* __restrict__ P = A.P_pt + A.pt_off[at];
         const double igrav = 1.0 / A.grav[at];
         const R D = (R)A.D;
@@ -352,78 +350,94 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // TOA value of the downward deviation, formed in FP64
         const R Ftop = (R)(A.F_top[A.bin_off[at] + l] - (2.0 * kPi / A.D) * B_all[pb + nsub]);
         const R Fint = (R)A.F_int[A.bin_off[at] + l];
-        R wcol[C];  // Gauss weights of the wave's columns
-#pragma unroll
-        for (int c = 0; c < C; ++c) wcol[c] = (c < ncols) ? (R)A.gw[j * C + c] : (R)0;
 
-        // ---- stage the wave's inputs in LDS (coalesced).  Every load of the
-        // item is issued before the first one is consumed: the loop bounds are
-        // compile-time (the deepest column this shape serves) and indices are
-        // clamped into the item's own padded columns, so no load is guarded by
-        // a branch and one memory latency covers the whole item.
+        // ---- the bin's per-sublayer inputs, staged once for all g.  All loads
+        // are issued before the first is consumed (compile-time bounds,
+        // indices clamped into the bin's own rows).
         {
-            constexpr int NCAP = K * L + 1;         // points of the deepest column served
-            constexpr int PCH = (NCAP + 63) / 64;   // 64-point chunks of a column
+            constexpr int NCAP = K * L + 1;
+            constexpr int PCH = (NCAP + 63) / 64;
             constexpr int LCH = (K * L / 2 + 63) / 64;
-            R kv[C][PCH], fv[C][PCH];
             double bv[PCH], pv[PCH], wv[LCH], gv[LCH];
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int64_t col = cell0 + (int64_t)min(c, ncols - 1) * cs;
-#pragma unroll
-                for (int j = 0; j < PCH; ++j) {
-                    const int i = min(lane + 64 * j, npt - 1);
-                    kv[c][j] = kap_all[col + i];
-                    fv[c][j] = Fu_all[col + i];
-                }
+            for (int q = 0; q < PCH; ++q) {
+                const int i = min(lane + 64 * q, npt - 1);
+                bv[q] = B_all[pb + i];
+                pv[q] = P[i];
             }
 #pragma unroll
-            for (int j = 0; j < PCH; ++j) {
-                const int i = min(lane + 64 * j, npt - 1);
-                bv[j] = B_all[pb + i];
-                pv[j] = P[i];
-            }
-#pragma unroll
-            for (int j = 0; j < LCH; ++j) {
-                const int i = min(lane + 64 * j, n - 1);
-                wv[j] = A.w0[lb + i];
-                gv[j] = A.g0[lb + i];
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-#pragma unroll
-                for (int j = 0; j < PCH; ++j) {
-                    const int i = lane + 64 * j;
-                    if (c < ncols && i < npt) {
-                        s_kap[c * npt + i] = kv[c][j];
-                        s_fu[c * npt + i] = fv[c][j];
-                    }
-                }
+            for (int q = 0; q < LCH; ++q) {
+                const int i = min(lane + 64 * q, n - 1);
+                wv[q] = A.w0[lb + i];
+                gv[q] = A.g0[lb + i];
             }
             // sublayer differences from the next point's value: the next lane,
             // or lane 0 of the next chunk for lane 63 (sublayer i < npt - 1
             // never needs a chunk past the last)
 #pragma unroll
-            for (int j = 0; j < PCH; ++j) {
-                double bn = __shfl_down(bv[j], 1u, 64), pn = __shfl_down(pv[j], 1u, 64);
-                if (j + 1 < PCH) {
-                    const double b0 = __shfl(bv[j + 1 < PCH ? j + 1 : j], 0, 64);
-                    const double p0 = __shfl(pv[j + 1 < PCH ? j + 1 : j], 0, 64);
+            for (int q = 0; q < PCH; ++q) {
+                double bn = __shfl_down(bv[q], 1u, 64), pn = __shfl_down(pv[q], 1u, 64);
+                if (q + 1 < PCH) {
+                    const double b0 = __shfl(bv[q + 1 < PCH ? q + 1 : q], 0, 64);
+                    const double p0 = __shfl(pv[q + 1 < PCH ? q + 1 : q], 0, 64);
                     bn = (lane == 63) ? b0 : bn;
                     pn = (lane == 63) ? p0 : pn;
                 }
-                const int i = lane + 64 * j;
+                const int i = lane + 64 * q;
                 if (i < nsub) {
-                    s_dB[i] = (R)(bv[j] - bn);
-                    s_dm[i] = (R)((pv[j] - pn) * igrav);
+                    s_dB[i] = (R)(bv[q] - bn);
+                    s_dm[i] = (R)((pv[q] - pn) * igrav);
+                }
+                if (i < npt) {
+                    s_pu[i] = (slot)0;
+                    s_pd[i] = (slot)0;
                 }
             }
 #pragma unroll
-            for (int j = 0; j < LCH; ++j) {
-                const int i = lane + 64 * j;
+            for (int q = 0; q < LCH; ++q) {
+                const int i = lane + 64 * q;
                 if (i < n) {
-                    s_w0[i] = (R)wv[j];
-                    s_g0[i] = (R)gv[j];
+                    s_w0[i] = (R)wv[q];
+                    s_g0[i] = (R)gv[q];
+                }
+            }
+        }
+
+      for (int j = 0; j < A.wpb; ++j) {  // groups of C columns
+        const int g = j * C + cw;
+        const int ncols = min(C, A.n_g - j * C);  // columns of this group
+        const bool colok = cw < ncols;
+        const int cnt = colok ? scnt : 0;
+        const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * cs;  // first column
+        R wcol[C];  // Gauss weights of the wave's columns
+#pragma unroll
+        for (int c = 0; c < C; ++c) wcol[c] = (c < ncols) ? (R)A.gw[j * C + c] : (R)0;
+
+        // ---- stage the group's opacities and warm start in LDS (coalesced,
+        // all loads issued before the first is consumed)
+        {
+            constexpr int NCAP = K * L + 1;
+            constexpr int PCH = (NCAP + 63) / 64;
+            R kv[C][PCH], fv[C][PCH];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t col = cell0 + (int64_t)min(c, ncols - 1) * cs;
+#pragma unroll
+                for (int q = 0; q < PCH; ++q) {
+                    const int i = min(lane + 64 * q, npt - 1);
+                    kv[c][q] = kap_all[col + i];
+                    fv[c][q] = Fu_all[col + i];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+#pragma unroll
+                for (int q = 0; q < PCH; ++q) {
+                    const int i = lane + 64 * q;
+                    if (c < ncols && i < npt) {
+                        s_kap[c * npt + i] = kv[c][q];
+                        s_fu[c * npt + i] = fv[c][q];
+                    }
                 }
             }
         }
@@ -535,7 +549,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             if (last) {
                 if (top_seg && colok) s_out[cw * npt + nsub] = Ftop;
                 __syncthreads();
-                for (int i = lane; i < npt; i += 64) part_dn[poff + i] = GS::col_sum(s_out + i, npt, ncols, wcol);
+                for (int i = lane; i < npt; i += 64) s_pd[i] += GS::col_sum(s_out + i, npt, ncols, wcol);
                 if (Fd_all) {
                     for (int cc = 0; cc < ncols; ++cc) {
                         R* db = Fd_all + cell0 + (int64_t)cc * cs;
@@ -579,12 +593,18 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 if (k < cnt) s_fu[cw * npt + lo + k] = fu[k];
             if (top_seg && colok) s_fu[cw * npt + nsub] = ftoa;
             __syncthreads();
-            for (int i = lane; i < npt; i += 64) part_up[poff + i] = GS::col_sum(s_fu + i, npt, ncols, wcol);
+            for (int i = lane; i < npt; i += 64) s_pu[i] += GS::col_sum(s_fu + i, npt, ncols, wcol);
             for (int cc = 0; cc < ncols; ++cc) {
                 R* ub = Fu_all + cell0 + (int64_t)cc * cs;
                 for (int i = lane; i < npt; i += 64) ub[i] = s_fu[cc * npt + i];
             }
             __syncthreads();
+        }
+      }  // groups
+        // ---- the bin's Gauss sums (one partial per point)
+        for (int i = lane; i < npt; i += 64) {
+            part_up[pb + i] = s_pu[i];
+            part_dn[pb + i] = s_pd[i];
         }
     }
 }
@@ -593,14 +613,16 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 template <int L>
 static size_t sweep_lds(const SweepArgs& a, size_t rbytes) {
     constexpr int C = 64 / L;
-    return (size_t)(2 * C * a.npt_max + 2 * a.npt_max + a.npt_max) * rbytes + 64;
+    // staging + per-bin inputs + two Gauss-sum accumulators (slot = R)
+    return (size_t)(2 * C * a.npt_max + 2 * a.npt_max + a.npt_max + 1 + 2 * a.npt_max) * rbytes + 64;
 }
 
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills.
 template <int K, int L, bool F64>
 constexpr int sweep_occ() {
-    if (F64) return (K <= 4 && L == 16) ? 3 : (K <= 14 ? 2 : 1);
-    return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
+    if (F64) return (K <= 4 && L == 16) ? 3 : ((K <= 8 || (K <= 14 && L == 16)) ? 2 : 1);
+    if (L == 16) return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
+    return K <= 4 ? 4 : (K <= 8 ? 3 : (K <= 14 ? 2 : 1));
 }
 
 template <int K, int L>

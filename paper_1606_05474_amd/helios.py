@@ -587,16 +587,19 @@ class Solver:
             self.status[a] = ATM_RUNNING
         profile(self.b, self.T_c, self.T_pt)
 
-    def subset(self, keep):
+    def subset(self, keep, prec=None):
         """A solver over the atmospheres `keep` (indices into this batch) that
         continues their iteration: temperatures, step multipliers, sign
         histories, update counts and per-g warm starts are carried over, every
         carried atmosphere is running.  Used to compact a batch whose active
-        set has shrunk, so later launches cover only live atmospheres."""
+        set has shrunk, so later launches cover only live atmospheres, and to
+        continue atmospheres in another precision (the per-g warm start holds
+        deviations from the isothermal flux, which carry over unchanged)."""
         keep = np.asarray(keep, np.int64)
         b0 = self.b
         nb = Batch([b0.atms[int(a)] for a in keep], device=b0.device)
-        s = Solver(nb, self.kt, prec=self.prec, n_scat=self.n_scat, D=self.D, opts=self.opts)
+        s = Solver(nb, self.kt, prec=self.prec if prec is None else prec, n_scat=self.n_scat, D=self.D,
+                   opts=self.opts)
         for k, a in enumerate(keep):
             a = int(a)
             ls, le = int(b0.lay_off[a]), int(b0.lay_off[a + 1])
@@ -606,7 +609,7 @@ class Solver:
             s.hist[ns:ns + le - ls] = self.hist[ls:le]
             cs, ce = int(b0.cell_off[a]), int(b0.cell_off[a + 1])
             nc = int(nb.cell_off[k])
-            s.F_up_g[nc:nc + ce - cs] = self.F_up_g[cs:ce]
+            s.F_up_g[nc:nc + ce - cs] = self.F_up_g[cs:ce].to(s.F_up_g.dtype)
         idx = torch.as_tensor(keep, device=b0.device)
         s.iters.copy_(self.iters[idx])
         s.resid.copy_(self.resid[idx])

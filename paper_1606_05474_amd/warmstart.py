@@ -158,7 +158,7 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
 
 
 def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 256,
-               n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 900,
+               n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 1000,
                check_every: int = 10, deadband: int = 1, polish_iter: int = 600, m0: float = 0.3, keep_T: int = 0,
                log=print):
     """The production form: atmospheres start..start+count-1 of a parameter
@@ -200,19 +200,32 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         else:
             s.reset(T0)
             fb = np.zeros(c, np.int32)
-        conv, it, rs, T_list = _run_compacting(s, max_iter, check_every, restart_after if net is not None else None)
+        conv, it, rs, T_list, s_last, live = _run_compacting(s, max_iter, check_every,
+                                                             restart_after if net is not None else None)
         left = np.where(~conv)[0]
         if left.size:
-            T_left = [T_list[a] if np.all(np.isfinite(T_list[a])) else atms[a]["T0"] for a in left]
-            sub = H.Batch([atms[a] for a in left])
-            s2 = H.Solver(sub, ktd, prec=H.FP64, opts=opts)
-            c2, it2 = s2.solve(np.concatenate(T_left), max_iter=polish_iter, check_every=check_every, graph=True)
-            conv[left] = c2
-            it[left] = it[left] + it2
-            T2 = s2.T_c.cpu().numpy()
-            for k, a in enumerate(left):
-                T_list[a] = T2[int(sub.lay_off[k]):int(sub.lay_off[k + 1])]
-            del s2, sub
+            # continue the stragglers in FP64 from their full state (non-finite
+            # ones restart isothermally)
+            pos = {int(a): k for k, a in enumerate(live)}
+            st_last = s_last.status.cpu().numpy()
+            cont = [a for a in left if a in pos and st_last[pos[a]] == H.ATM_RUNNING]
+            fresh = [a for a in left if a not in cont]
+            if cont:
+                s2 = s_last.subset([pos[a] for a in cont], prec=H.FP64)
+                s2._warm = None
+                c2, it2, _, T2, _, _ = _run_compacting(s2, polish_iter, check_every, None)
+                for k, a in enumerate(cont):
+                    conv[a], it[a], T_list[a] = c2[k], it2[k], T2[k]
+                del s2
+            if fresh:
+                sub = H.Batch([atms[a] for a in fresh])
+                s3 = H.Solver(sub, ktd, prec=H.FP64, opts=opts)
+                s3.reset(np.concatenate([atms[a]["T0"] for a in fresh]))
+                c3, it3, _, T3, _, _ = _run_compacting(s3, polish_iter, check_every, None)
+                for k, a in enumerate(fresh):
+                    conv[a], it[a], T_list[a] = c3[k], it[a] + it3[k], T3[k]
+                del s3, sub
+        del s_last
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out["count"] += c
@@ -242,8 +255,8 @@ def _run_compacting(s: H.Solver, max_iter: int, check_every: int, restart_after:
     at most half of the atmospheres of the current batch are still running
     (and more than `min_live`), move the running ones into a smaller batch
     (Solver.subset) so that later launches cover live atmospheres only.
-    Returns (converged, updates, restarted, final layer temperatures) per
-    atmosphere of the original batch."""
+    Returns (converged, updates, restarted, final layer temperatures, the
+    last solver and the original index of each of its atmospheres)."""
     n0 = s.b.n_atm
     conv = np.zeros(n0, bool)
     its = np.zeros(n0, np.int64)
@@ -287,7 +300,7 @@ def _run_compacting(s: H.Solver, max_iter: int, check_every: int, restart_after:
             rs_cur = rs_cur[keep]
             s.capture(check_every)
     harvest(s, range(len(live)))
-    return conv, its, restarted, T_out
+    return conv, its, restarted, T_out, s, live
 
 
 def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int = 3000, max_iter: int = 400,
@@ -352,6 +365,8 @@ def main(argv=None):
     e.add_argument("--max-iter", type=int, default=600)
     e.add_argument("--deadband", type=int, default=0)
     e.add_argument("--m0", type=float, default=0.3)
+    e.add_argument("--n", type=int, default=100)
+    e.add_argument("--nb", type=int, default=1000)
     a = ap.parse_args(argv)
     H.lib()
     log = lambda *v: print(*v, flush=True)  # noqa: E731
@@ -368,7 +383,7 @@ def main(argv=None):
     else:
         net = load(a.weights)
         evaluate(net, a.seed, a.count, prec=H.MIXED if a.prec == "mixed" else H.FP64, max_iter=a.max_iter,
-                 restart_after=a.restart_after, deadband=a.deadband, m0=a.m0, log=log)
+                 restart_after=a.restart_after, deadband=a.deadband, m0=a.m0, n=a.n, nb=a.nb, log=log)
     return 0
 
 
