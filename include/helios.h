@@ -221,7 +221,8 @@ int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double
  * layer count (n <= 32, 64, 112, 208, 400) and sweeps each class with one
  * launch of its own shape (sublayers per lane x lanes per column).  For each
  * class present in the batch, every compiled shape that holds the class's
- * deepest atmosphere is timed here on up to 1024 bins of that atmosphere
+ * deepest atmosphere, with one or more waves per bin (more than one only for
+ * batches of at most 65536 bins), is timed here on up to 4096 bins of that atmosphere
  * (same arguments as helios_flux, status ignored), and the fastest is used
  * by later helios_flux calls of this process with the same precision and
  * n_g.  Synchronous: returns after the timing.  F_up_g is restored to its

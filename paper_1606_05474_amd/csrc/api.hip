@@ -54,7 +54,7 @@ struct Sizes {
     // per class: deepest member, bin range [bin_lo, bin_hi) spanning its members,
     // and the member with the most bins among the deepest (autotuner sample)
     int cls_nmax[kNumClasses] = {};
-    int64_t cls_bin_lo[kNumClasses] = {}, cls_bin_hi[kNumClasses] = {};
+    int64_t cls_bin_lo[kNumClasses] = {}, cls_bin_hi[kNumClasses] = {}, cls_bins[kNumClasses] = {};
     int cls_rep[kNumClasses] = {};
 };
 
@@ -94,6 +94,7 @@ int check_atm(const helios_atm* atm, Sizes& z) {
         int r = z.cls_rep[k];
         if (n > z.cls_nmax[k] || (n == atm->n_layer_h[r] && nb > atm->n_bin_h[r])) z.cls_rep[k] = a;
         z.cls_nmax[k] = std::max(z.cls_nmax[k], n);
+        z.cls_bins[k] += nb;
         b0 += nb;
         z.cls_bin_hi[k] = b0;
     }
@@ -109,12 +110,23 @@ struct WsLayout {
 // Waves per bin for L lanes per column: each wave holds 64/L columns.
 int waves_per_bin(int n_g, int L) { return (n_g + (64 / L) - 1) / (64 / L); }
 
-// One Gauss partial per (bin, point) and direction, sized for doubles (the
+// A sweep launch gives each bin P waves (each takes a contiguous share of the
+// bin's column groups and leaves its own partial).  P = 1 moves the least
+// data; small launches may fill the device better with P > 1, which the
+// autotuner can choose.  The workspace holds up to waves_per_bin(n_g, 32)
+// partials per (bin, point) for batches of at most kSplitBins bins, one for
+// larger ones.
+constexpr int64_t kSplitBins = 65536;
+int parts_stride(const Sizes& z, int n_g) {
+    return z.total_bin <= kSplitBins ? waves_per_bin(n_g, 32) : 1;
+}
+
+// Gauss partials per (bin, point) and direction, sized for doubles (the
 // mixed path stores floats in the first half), so the layout does not depend
 // on the precision or the sweep shape.
-WsLayout ws_layout(const Sizes& z, int /*n_g*/, bool /*mixed*/) {
+WsLayout ws_layout(const Sizes& z, int n_g, bool /*mixed*/) {
     WsLayout w;
-    const size_t wpb = 1;
+    const size_t wpb = (size_t)parts_stride(z, n_g);
     const size_t n_chunk = (size_t)((z.nb_max + kBolChunk - 1) / kBolChunk);
     w.B = 0;  // Planck values in FP64 for both precisions
     w.F_top = align256(w.B + (size_t)z.total_pb * sizeof(double));
@@ -175,6 +187,7 @@ int env_int(const char* name, int dflt) {
 // atmosphere with L = 16, else L = 32.
 struct SweepShape {
     int K, L;
+    int P = 1;  // waves per bin
 };
 
 bool k_allowed(int K, bool /*mixed*/) {
@@ -256,6 +269,12 @@ int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     return HELIOS_OK;
 }
 
+// Waves per bin of class k's launch (never more than the workspace holds or
+// the bin has column groups).
+int class_parts(const FluxPlan& p, int k, int n_g) {
+    return std::max(1, std::min({p.sh[k].P, parts_stride(p.z, n_g), waves_per_bin(n_g, p.sh[k].L)}));
+}
+
 SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa, const double* w0,
                      const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, char* wsb) {
     SweepArgs A;
@@ -282,7 +301,7 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
     A.status = atm->status;
     A.n_atm = atm->n_atm;
     A.n_g = atm->n_g;
-    A.wpb_stride = 1;
+    A.wpb_stride = parts_stride(p.z, atm->n_g);
     A.n_scat = n_scat;
     A.npt_max = p.z.npt_max;
     A.D = D;
@@ -291,13 +310,14 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
 
 // One sweep launch for class k over bins [b_lo, b_hi): one wave per bin,
 // looping over the bin's groups of 64/L columns.
-hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, int64_t b_hi, bool mixed,
-                       hipStream_t s) {
+hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, int64_t b_hi, int parts,
+                       bool mixed, hipStream_t s) {
     A.wpb = waves_per_bin(A.n_g, sh.L);  // column groups per bin
+    A.parts = parts;
     A.n_lo = class_nlo(k);
     A.n_hi = kClassNHi[k];
-    A.w_begin = b_lo;
-    A.w_end = b_hi;
+    A.w_begin = b_lo * parts;
+    A.w_end = b_hi * parts;
     int64_t grid64 = A.w_end - A.w_begin;
     int cap = env_int("HELIOS_SWEEP_GRID", 0);
     if (cap > 0 && grid64 > cap) grid64 = cap;
@@ -521,7 +541,8 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     }
     for (int k = 0; k < kNumClasses; ++k) {
         if (p.z.cls_nmax[k] == 0) continue;
-        e = sweep_class(A, p.sh[k], k, p.z.cls_bin_lo[k], p.z.cls_bin_hi[k], p.mixed, s);
+        e = sweep_class(A, p.sh[k], k, p.z.cls_bin_lo[k], p.z.cls_bin_hi[k], class_parts(p, k, atm->n_g), p.mixed,
+                        s);
         if (e != hipSuccess) return hip_fail(e, "helios_flux (sweep)");
     }
     if (g_ev_before && g_ev_after) {
@@ -545,7 +566,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     Bo.n_cls = kNumClasses;
     for (int k = 0; k < kNumClasses; ++k) {
         Bo.cls_nhi[k] = kClassNHi[k];
-        Bo.cls_wpb[k] = 1;  // the sweep leaves one partial per (bin, point)
+        Bo.cls_wpb[k] = p.sh[k].L ? class_parts(p, k, atm->n_g) : 1;  // partials per (bin, point)
     }
     e = launch_bolometric(Bo, p.z.npt_max, p.z.nb_max, p.z.total_pt, s);
     if (e != hipSuccess) return hip_fail(e, "helios_flux (bolometric)");
@@ -577,14 +598,14 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
         return cleanup(hip_fail(e, "helios_autotune (events)"));
     for (int k = 0; k < kNumClasses; ++k) {
         if (p.z.cls_nmax[k] == 0) continue;
-        // sample: up to 1024 bins of the class's deepest atmosphere
+        // sample: up to 4096 bins of the class's deepest atmosphere
         const int a = p.z.cls_rep[k];
         int64_t b_lo = 0, c_lo = 0;
         for (int i = 0; i < a; ++i) {
             b_lo += atm->n_bin_h[i];
             c_lo += (int64_t)atm->n_bin_h[i] * atm->n_g * col_stride(atm->n_layer_h[i]);
         }
-        const int64_t nbs = std::min<int64_t>(atm->n_bin_h[a], 1024);
+        const int64_t nbs = std::min<int64_t>(atm->n_bin_h[a], 4096);
         const size_t cells = (size_t)nbs * atm->n_g * col_stride(atm->n_layer_h[a]);
         char* fu = (char*)F_up_g + c_lo * r;
         saved.resize(cells * r);
@@ -595,16 +616,20 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
         SweepShape best = p.sh[k];
         float best_ms = 1e30f;
         for (int L : {16, 32}) {
+          const int groups = waves_per_bin(atm->n_g, L);
+          for (int P : {1, 2, groups}) {
+            if (P > std::min(groups, parts_stride(p.z, atm->n_g)) || (P == groups && P <= 2 && P != 1)) continue;
             for (int i = 0; i < kNumSweepK; ++i) {
-                SweepShape c = {kSweepK[i], L};
+                SweepShape c = {kSweepK[i], L, P};
                 if (!k_allowed(c.K, p.mixed) || c.K * c.L < nsub) continue;
-                if ((e = sweep_class(A, c, k, b_lo, b_lo + nbs, p.mixed, s)) != hipSuccess)  // warm-up
+                const int parts = P;
+                if ((e = sweep_class(A, c, k, b_lo, b_lo + nbs, parts, p.mixed, s)) != hipSuccess)  // warm-up
                     return cleanup(hip_fail(e, "helios_autotune (sweep)"));
                 float ms_min = 1e30f;
                 for (int rep = 0; rep < 3; ++rep) {
                     float ms = 0.f;
                     if ((e = hipEventRecord(ev0, s)) != hipSuccess ||
-                        (e = sweep_class(A, c, k, b_lo, b_lo + nbs, p.mixed, s)) != hipSuccess ||
+                        (e = sweep_class(A, c, k, b_lo, b_lo + nbs, parts, p.mixed, s)) != hipSuccess ||
                         (e = hipEventRecord(ev1, s)) != hipSuccess || (e = hipEventSynchronize(ev1)) != hipSuccess ||
                         (e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess)
                         return cleanup(hip_fail(e, "helios_autotune (timing)"));
@@ -615,6 +640,7 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
                     best = c;
                 }
             }
+          }
         }
         if ((e = hipMemcpyAsync(fu, saved.data(), cells * r, hipMemcpyHostToDevice, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)

@@ -75,10 +75,11 @@ struct SweepArgs {
     const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
     const int32_t* status;   // optional: converged atmospheres are skipped
     const int32_t* bin_atm;  // [sum nb] owning atmosphere of each bin (workspace)
-    int64_t w_begin, w_end;  // global bin range covered by the launch (one wave per bin)
+    int64_t w_begin, w_end;  // global (bin, part) range covered by the launch
     int32_t n_atm, n_g;
     int32_t wpb;          // groups of 64/L columns per bin (this launch's shape)
-    int32_t wpb_stride;   // partials per (bin, point) in the workspace (1)
+    int32_t parts;        // waves per bin in this launch (each a contiguous share of the groups)
+    int32_t wpb_stride;   // partials per (bin, point) the workspace holds (>= parts)
     int32_t n_lo, n_hi;   // this launch serves atmospheres with n_lo <= n <= n_hi
     int32_t n_scat;
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)

@@ -294,14 +294,16 @@ struct GSum<float> {
     }
 };
 
-// One workgroup = one wave, which owns one bin at a time: it stages the
-// bin's Planck differences, sublayer column masses, w0 and g0 in LDS once,
-// then solves the bin's n_g columns C = 64/L at a time (group j covers g in
-// [j*C, j*C + C), contiguous in the [bin][g][point] arrays, staged and
-// written back through LDS with coalesced accesses), and accumulates the
-// Gauss sums of all groups in LDS in a fixed order.  One partial per (bin,
-// point) goes to the workspace, where the bin-sum kernel adds the Planck term
-// and sums over bins.  No barrier spans more than the wave.
+// One workgroup = one wave, which owns one (bin, part) at a time: it stages
+// the bin's Planck differences, sublayer column masses, w0 and g0 in LDS once,
+// then solves its share of the bin's n_g columns C = 64/L at a time (group j
+// covers g in [j*C, j*C + C), contiguous in the [bin][g][point] arrays, staged
+// and written back through LDS with coalesced accesses), and accumulates the
+// Gauss sums of its groups in LDS in a fixed order.  Large launches give a bin
+// one part (one partial per (bin, point)); launches with few bins split a
+// bin's groups over several waves to fill the device.  The bin-sum kernel adds
+// a bin's partials in order, adds the Planck term and sums over bins.  No
+// barrier spans more than the wave.
 template <int K, int L, typename R, int OCC>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using GS = GSum<R>;
@@ -329,7 +331,12 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     slot* __restrict__ part_up = static_cast<slot*>(A.part_up);
     slot* __restrict__ part_dn = static_cast<slot*>(A.part_dn);
 
-    for (int64_t gb = A.w_begin + blockIdx.x; gb < A.w_end; gb += gridDim.x) {
+    for (int64_t item = A.w_begin + blockIdx.x; item < A.w_end; item += gridDim.x) {
+        const int64_t gb = item / A.parts;
+        const int part = (int)(item - gb * A.parts);
+        // one group per wave: its Gauss sums go straight to the workspace
+        // (no LDS accumulators are allocated for such launches)
+        const bool direct = (A.parts >= A.wpb);
         const int at = A.bin_atm[gb];
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
@@ -388,7 +395,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     s_dB[i] = (R)(bv[q] - bn);
                     s_dm[i] = (R)((pv[q] - pn) * igrav);
                 }
-                if (i < npt) {
+                if (i < npt && !direct) {
                     s_pu[i] = (slot)0;
                     s_pd[i] = (slot)0;
                 }
@@ -403,7 +410,9 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             }
         }
 
-      for (int j = 0; j < A.wpb; ++j) {  // groups of C columns
+        const int gpp = (A.wpb + A.parts - 1) / A.parts;  // groups of this wave: [j_lo, j_hi)
+        const int j_lo = part * gpp, j_hi = min(A.wpb, j_lo + gpp);
+      for (int j = j_lo; j < j_hi; ++j) {  // groups of C columns
         const int g = j * C + cw;
         const int ncols = min(C, A.n_g - j * C);  // columns of this group
         const bool colok = cw < ncols;
@@ -549,7 +558,11 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             if (last) {
                 if (top_seg && colok) s_out[cw * npt + nsub] = Ftop;
                 __syncthreads();
-                for (int i = lane; i < npt; i += 64) s_pd[i] += GS::col_sum(s_out + i, npt, ncols, wcol);
+                for (int i = lane; i < npt; i += 64) {
+                    const slot v = GS::col_sum(s_out + i, npt, ncols, wcol);
+                    if (direct) part_dn[pb * A.wpb_stride + (int64_t)part * npt + i] = v;
+                    else s_pd[i] += v;
+                }
                 if (Fd_all) {
                     for (int cc = 0; cc < ncols; ++cc) {
                         R* db = Fd_all + cell0 + (int64_t)cc * cs;
@@ -593,7 +606,11 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 if (k < cnt) s_fu[cw * npt + lo + k] = fu[k];
             if (top_seg && colok) s_fu[cw * npt + nsub] = ftoa;
             __syncthreads();
-            for (int i = lane; i < npt; i += 64) s_pu[i] += GS::col_sum(s_fu + i, npt, ncols, wcol);
+            for (int i = lane; i < npt; i += 64) {
+                const slot v = GS::col_sum(s_fu + i, npt, ncols, wcol);
+                if (direct) part_up[pb * A.wpb_stride + (int64_t)part * npt + i] = v;
+                else s_pu[i] += v;
+            }
             for (int cc = 0; cc < ncols; ++cc) {
                 R* ub = Fu_all + cell0 + (int64_t)cc * cs;
                 for (int i = lane; i < npt; i += 64) ub[i] = s_fu[cc * npt + i];
@@ -601,10 +618,14 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             __syncthreads();
         }
       }  // groups
-        // ---- the bin's Gauss sums (one partial per point)
-        for (int i = lane; i < npt; i += 64) {
-            part_up[pb + i] = s_pu[i];
-            part_dn[pb + i] = s_pd[i];
+        // ---- this wave's Gauss sums over its groups (one partial per point)
+        if (!direct) {
+            // partial slot of this (bin, part): [bin x point][stride] layout
+            const int64_t poff = pb * A.wpb_stride + (int64_t)part * npt;
+            for (int i = lane; i < npt; i += 64) {
+                part_up[poff + i] = s_pu[i];
+                part_dn[poff + i] = s_pd[i];
+            }
         }
     }
 }
@@ -613,8 +634,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 template <int L>
 static size_t sweep_lds(const SweepArgs& a, size_t rbytes) {
     constexpr int C = 64 / L;
-    // staging + per-bin inputs + two Gauss-sum accumulators (slot = R)
-    return (size_t)(2 * C * a.npt_max + 2 * a.npt_max + a.npt_max + 1 + 2 * a.npt_max) * rbytes + 64;
+    // staging + per-bin inputs + two Gauss-sum accumulators (slot = R; not
+    // needed when every wave has a single group)
+    const size_t acc = (a.parts >= a.wpb) ? 0 : 2 * (size_t)a.npt_max;
+    return (size_t)(2 * C * a.npt_max + 2 * a.npt_max + a.npt_max + 1 + acc) * rbytes + 64;
 }
 
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills.

@@ -328,6 +328,29 @@ def flux(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, n_scat=4,
                              prec, _stream(stream)))
 
 
+def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, stream=None):
+    """Post-processing of converged profiles (Sec. 2.6, Sec. 3): one flux
+    call with many scattering passes from the isothermal start; returns the
+    upward flux at the top of each atmosphere per bin (a list of [n_bin]
+    device arrays) and the per-bin upward fluxes at every point."""
+    dev = b.device
+    rd = rdtype(prec)
+    T_c = torch.as_tensor(T_c, dtype=torch.float64, device=dev)
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device=dev)
+    grid(b, stream=stream)
+    profile(b, T_c, T_pt, stream=stream)
+    kap = torch.zeros(b.total_cell, dtype=rd, device=dev)
+    mix_opacity(b, kt, T_pt, kap, prec, stream=stream)
+    F_up = torch.zeros(b.total_cell, dtype=rd, device=dev)
+    ub = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
+    db = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device=dev)
+    ws = torch.zeros(workspace_bytes(b, prec), dtype=torch.uint8, device=dev)
+    flux(b, kap, T_pt, F_up, ub, db, bol, ws, n_scat=n_scat, D=D, prec=prec, stream=stream)
+    per_bin = b.split_pb(ub)
+    return [pb_a[:, -1] for pb_a in per_bin], per_bin
+
+
 @dataclass
 class REOptions:
     tol: float = 1e-3

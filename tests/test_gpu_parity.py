@@ -630,3 +630,22 @@ def test_compacted_batch_continues_the_same_iteration():
     for k, a in enumerate(keep):
         np.testing.assert_array_equal(b.split_layer(_np(full.T_c))[a], sub.b.split_layer(_np(sub.T_c))[k])
         assert int(_np(full.iters)[a]) == int(_np(sub.iters)[k])
+
+
+def test_post_processing_spectrum_with_80_passes():
+    """The post-processing step (many scattering passes on a converged
+    profile): TOA upward flux per bin against the oracle with the same 80
+    passes from the same isothermal start, FP64."""
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(81)
+    atm = W.spectral_atmosphere(rng, 100, lc, dl, 300)
+    kt = W.table_ktab(2, nbt=300)
+    T_c = smooth_profile(atm, 1900.0, 1100.0)
+    b = H.Batch([atm])
+    toa, per_bin = H.emission_spectrum(b, H.KTable(kt), T_c, n_scat=80)
+    P, T, kap = oracle_state(atm, kt, T_c)
+    r = ref.flux(atm, kap, T, P, ref.isothermal_start(atm, T), n_scat=80, want_dn=False)
+    got = _np(toa[0])
+    want = r["F_up_bin"][:, -1]
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    assert col_rel_error(_np(per_bin[0]), r["F_up_bin"]).max() < 1e-11
