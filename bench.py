@@ -204,6 +204,62 @@ def batch_main(args):
     return 0
 
 
+def chunk_main(args):
+    """RE-iteration throughput on one production chunk: N parameter-described
+    atmospheres of 200 layers x 3000 bins x 20 g, mixed precision with the
+    dead band, started from the network (timed steps only, no solve)."""
+    import numpy as np
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import warmstart as WS
+    from paper_1606_05474_amd import workloads as W
+
+    atms, kt = W.learned_workload(5, args.n_atm, 0, n=200, nb=3000)
+    b = H.Batch(atms)
+    s = H.Solver(b, H.KTable(kt), prec=H.MIXED, opts=H.REOptions(deadband=1))
+    x = np.stack([a["params"] for a in atms])
+    s.reset(np.concatenate([a["T0"] for a in atms]))
+    s.autotune()
+    net = WS.load(args.weights)
+    s.warm_reset(net, x, net.logP, m0=0.3)
+    for _ in range(args.warmup):
+        s.step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    e1.record()
+    torch.cuda.synchronize()
+    sweep_ms = 0.0
+    for _ in range(args.steps):
+        H.set_sweep_events(e0, e1)
+        s.step()
+        e1.synchronize()
+        sweep_ms += e0.elapsed_time(e1)
+    H.set_sweep_events(None, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    units = len(atms) * 200 * 3000 * 20
+    alg = len(atms) * sweep_algorithmic_bytes(200, 3000, 20, 4)
+    sweep_ms /= args.steps
+    line = {"metric": "layer*bin*g flux updates/s", "value": units * args.steps / wall, "unit": "layer*bin*g/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": f"production chunk: {len(atms)} parameter-described atmospheres x 200 layers x "
+                                   "3000 bins x 20 g, mixed precision, dead band, network start",
+                       "shapes": {str(k): list(v) for k, v in H.sweep_shapes(s.b, H.MIXED).items()}},
+            "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep)",
+                         "achieved": alg / (sweep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_launch": alg, "avg_launch_ms": sweep_ms}}
+    print(json.dumps(line))
+    return 0
+
+
 def production_main(args):
     """Converged atmospheres per second: the production form (batched chunks,
     network warm start with isothermal fallback, mixed precision) against the
@@ -312,9 +368,10 @@ def main(argv=None):
                     help="precisions to run (profiling runs pick one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["spectral", "batch", "production"], default="spectral",
+    ap.add_argument("--workload", choices=["spectral", "batch", "chunk", "production"], default="spectral",
                     help="spectral: one 100-layer x 3000-bin atmosphere (the headline line); "
                          "batch: the uneven 512-atmosphere batch, throughput and solve to convergence; "
+                         "chunk: RE-iteration throughput of one production chunk; "
                          "production: converged atmospheres/s, batched + network + mixed against plain FP64")
     ap.add_argument("--chunk", type=int, default=256, help="atmospheres per device batch (production)")
     ap.add_argument("--plain-count", type=int, default=64, help="atmospheres solved by the plain form")
@@ -352,13 +409,15 @@ def main(argv=None):
         return 0
     H.lib()  # fails loudly if the native library is missing
     if args.n_atm is None:
-        args.n_atm = 4096 if args.workload == "production" else 512
+        args.n_atm = {"production": 4096, "chunk": 128}.get(args.workload, 512)
     if args.max_iter is None:
         args.max_iter = 1500 if args.workload == "production" else 300
     if args.workload == "batch":
         return batch_main(args)
     if args.workload == "production":
         return production_main(args)
+    if args.workload == "chunk":
+        return chunk_main(args)
     kt = W.table_ktab(2)
     atm, _ = W.spectral_workload(ktab=kt)
     fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt) if args.prec in ("both", "fp64") else None
