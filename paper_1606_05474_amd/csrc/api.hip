@@ -217,7 +217,7 @@ int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
 }
 
 // Shape of class k (deepest member nsub_max sublayers): an environment
-// override (HELIOS_SWEEP_K / HELIOS_SWEEP_L, for measurement), else the
+// override (HELIOS_SWEEP_K / HELIOS_SWEEP_L / HELIOS_SWEEP_P, for measurement), else the
 // autotuned one, else the default.
 int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh) {
     int fk = env_int("HELIOS_SWEEP_K", 0), fl = env_int("HELIOS_SWEEP_L", 0);
@@ -225,7 +225,7 @@ int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh) {
         if (!k_allowed(fk, mixed) || (fl != 16 && fl != 32))
             return fail(HELIOS_EINVAL, "HELIOS_SWEEP_K/L = %d/%d not available", fk, fl);
         if (fk * fl < nsub_max) return fail(HELIOS_ESHAPE, "K*L = %d < %d sublayers", fk * fl, nsub_max);
-        sh = {fk, fl};
+        sh = {fk, fl, std::max(1, env_int("HELIOS_SWEEP_P", 1))};
         return HELIOS_OK;
     }
     {
@@ -316,6 +316,7 @@ hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, i
     A.parts = parts;
     A.n_lo = class_nlo(k);
     A.n_hi = kClassNHi[k];
+    A.npt_max = std::min(A.npt_max, 2 * A.n_hi + 1);  // LDS sized for the class
     A.w_begin = b_lo * parts;
     A.w_end = b_hi * parts;
     int64_t grid64 = A.w_end - A.w_begin;

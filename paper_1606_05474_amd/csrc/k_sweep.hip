@@ -54,6 +54,8 @@
 // the rounding of each stream is relative to its deviation from pi B rather
 // than to pi B itself, which is what lets FP32 sweeps resolve net fluxes at
 // depth.  Fluxes are recovered as F = G + 2 pi eps B in FP64 by the bin sum.
+#include <type_traits>
+
 #include "helios_internal.hpp"
 
 namespace helios {
@@ -62,12 +64,38 @@ template <typename R>
 struct Prec;
 template <>
 struct Prec<double> {
-    // T = exp(-x) and om = 1 - T from one transcendental: om is accurate for
-    // thin layers, T accurate in absolute terms
+    // T = exp(-x) and om = 1 - T for x >= 0.  Cody-Waite reduction
+    // x = n ln2 + s' with |s'| <= ln2/2 (ln2 carried in two parts), the Taylor
+    // series of expm1 to degree 13 on the reduced argument (truncation below
+    // 5e-18) and scaling by 2^-n.  For n = 0 the polynomial gives om directly,
+    // so om keeps full relative accuracy for thin layers; for n >= 1, T <= 0.71
+    // and 1 - T is free of cancellation.  Arguments beyond 1000 (T = 0 in
+    // FP64) are clamped, which keeps n in integer range.
     __device__ static inline void t_om(double x, double& T, double& om) {
-        double em = expm1(-x);
-        om = -em;
-        T = 1.0 + em;
+        constexpr double ln2_hi = 0.6931471805599453;      // ln 2 rounded to double
+        constexpr double ln2_lo = 2.3190468138462996e-17;  // ln 2 - ln2_hi
+        constexpr double inv_ln2 = 1.4426950408889634;
+        x = fmin(x, 1000.0);
+        const double n = rint(x * inv_ln2);
+        double r = fma(-n, ln2_hi, x);
+        r = fma(-n, ln2_lo, r);
+        const double s = -r;  // exp(-x) = 2^-n exp(s)
+        double p = 1.0 / 6227020800.0;  // 1/13!
+        p = fma(p, s, 1.0 / 479001600.0);
+        p = fma(p, s, 1.0 / 39916800.0);
+        p = fma(p, s, 1.0 / 3628800.0);
+        p = fma(p, s, 1.0 / 362880.0);
+        p = fma(p, s, 1.0 / 40320.0);
+        p = fma(p, s, 1.0 / 5040.0);
+        p = fma(p, s, 1.0 / 720.0);
+        p = fma(p, s, 1.0 / 120.0);
+        p = fma(p, s, 1.0 / 24.0);
+        p = fma(p, s, 1.0 / 6.0);
+        p = fma(p, s, 0.5);
+        p = fma(p, s, 1.0);
+        const double q = p * s;  // expm1(s)
+        T = ldexp(1.0 + q, -(int)n);
+        om = (n == 0.0) ? -q : 1.0 - T;
     }
     // reciprocal: hardware estimate refined by two Newton steps (the
     // arguments here are well scaled: no denormals, no overflow)
@@ -169,29 +197,54 @@ __device__ inline void sub_coeffs(R dtau, R w0, R g0, R D, R Bu, R Bd, R& Tr, R&
     sub_coeffs_q<R>(q, dtau, tpe, Bu, Bd, Tr, a, c, su, sd);
 }
 
-// The sweep's coefficients of one sublayer in the deviation form: a, c and
-// the source sig for the Planck difference dB = B_lower - B_upper.  One
-// reciprocal of (zp - zm T)(zp + zm T) serves a and c; om / (zp - zm T) is
-// om (zp + zm T) times it.
+// Per-layer quantities of the sweep, the same for a layer's two sublayers and
+// every g of a bin (staged in LDS once per bin):
+//   r = sqrt((1 - w0)/(1 - w0 g0)),  kx = D sqrt((1 - w0 g0)(1 - w0)),
+//   sf = 2 pi eps f = 2 pi eps / (D (1 - w0 g0)),
+//   gd = D (1 - g0)/2 for a pure scatterer ((1 - w0) < 1e-6), else -1.
 template <typename R>
-__device__ inline void sub_coeffs_g(const LayerQ<R>& q, R dtau, R two_pi_eps, R dB, R& a, R& c, R& sig) {
+__device__ inline void layer_g(R w0, R g0, R D, R inv_D, R tpe, R& r, R& kx, R& sf, R& gd) {
+    const R one = (R)1;
+    const R omg = one - w0 * g0;
+    const R iomg = Prec<R>::rcp(omg);
+    r = Prec<R>::sqrt_((one - w0) * iomg);
+    kx = D * r * omg;
+    sf = tpe * iomg * inv_D;
+    gd = ((one - w0) < (R)1e-6) ? D * (one - g0) * (R)0.5 : (R)-1;
+}
+
+// The sweep's coefficients of one sublayer in the deviation form: a, c and
+// the source sig for the Planck difference dB = B_lower - B_upper, from the
+// layer's quantities (zp = (1 + r)/2, zm = (1 - r)/2).  One reciprocal,
+// rec = 1/((zp - zm T)(zp + zm T) dtau), serves a, c and the gradient term.
+// dtau is floored at a power of two, so that a transparent sublayer stays
+// finite and a padding sublayer (dtau = 0, dB = 0, r = 1, kx = sf = 0) is
+// exactly the identity map (a = 1, c = sig = 0).  Only real sublayers (act)
+// take the eq:isoscat form.
+template <typename R>
+__device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R dtau, R two_pi_eps, R dB,
+                                    bool act, R& a, R& c, R& sig) {
     const R one = (R)1;
     R T, om;
-    Prec<R>::t_om(q.kx * dtau, T, om);
-    const R u = q.zp - q.zm * T, v = q.zp + q.zm * T;
-    const R iden = Prec<R>::rcp(u * v);
+    Prec<R>::t_om(kx * dtau, T, om);
+    const R u = zp - zm * T, v = zp + zm * T;
+    const R den = u * v;
+    const R dd = fmax(dtau, sizeof(R) == 8 ? (R)0x1p-960 : (R)0x1p-100);
+    const R rec = Prec<R>::rcp(den * dd);
+    const R iden = rec * dd;  // 1/den
     const R omi = om * iden;
-    a = q.r * T * iden;
-    c = q.zpzm * (one + T) * omi;
-    sig = two_pi_eps * q.f * v * omi * Prec<R>::rcp(dtau) * dB;
-    const bool iso = dtau < (R)1e-4;
-    if (__any(iso)) sig = iso ? (R)0.5 * two_pi_eps * (one + a - c) * dB : sig;  // may be inf at dtau = 0
-    if (__any(q.purescat)) {  // eq:purescat
-        const R gd = q.purescat_gd * dtau;
-        const R qq = gd * Prec<R>::rcp(one + gd);
-        a = q.purescat ? one - qq : a;
-        c = q.purescat ? qq : c;
-        sig = q.purescat ? two_pi_eps * (one - qq) * dB : sig;
+    a = r * T * iden;
+    c = zpzm * (one + T) * omi;
+    sig = sf * dB * v * om * rec;  // 2 pi eps f dB om / ((zp - zm T) dtau)
+    const bool iso = act && dtau < (R)1e-4;
+    if (__any(iso)) sig = iso ? (R)0.5 * two_pi_eps * (one + a - c) * dB : sig;
+    if (__any(gd >= (R)0)) {  // eq:purescat
+        const bool ps = gd >= (R)0;
+        const R g = gd * dtau;
+        const R qq = g * Prec<R>::rcp(one + g);
+        a = ps ? one - qq : a;
+        c = ps ? qq : c;
+        sig = ps ? two_pi_eps * (one - qq) * dB : sig;
     }
 }
 
@@ -268,103 +321,104 @@ __device__ inline void scan_up_full(R& MA, R& MB, int seg) {
     if constexpr (L > 16) up_pair<L, 16>(MA, MB, seg);
 }
 
-// Gauss partial sum of one point over the wave's ncols columns staged in
-// LDS (column stride npt), in column order; compensated pairs in FP32.
-template <typename R>
-struct GSum;
-template <>
-struct GSum<double> {
-    using slot = double;
-    __device__ static inline slot col_sum(const double* col, int npt, int ncols, const double* w) {
-        double acc = 0.0;
-        for (int c = 0; c < ncols; ++c) acc += w[c] * col[c * npt];
-        return acc;
-    }
-};
-template <>
-struct GSum<float> {
-    // a wave's columns are at most 4 g points, so its partial is a sum of <= 4
-    // products; every later sum (over the bin's waves, then over bins) is in
-    // FP64 with compensation
-    using slot = float;
-    __device__ static inline slot col_sum(const float* col, int npt, int ncols, const float* w) {
-        float acc = 0.0f;
-        for (int c = 0; c < ncols; ++c) acc += w[c] * col[c * npt];
-        return acc;
-    }
+// Sum of v over the wave's C = 64/L columns (lanes seg, seg + L, ...); every
+// column gets the same value, added in the order ((c0 + c1) + (c2 + c3)).
+template <int L, typename R>
+__device__ inline R col_sum(R v) {
+    if constexpr (L <= 16) v += __shfl_xor(v, 16, 64);
+    if constexpr (L <= 32) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// LDS layout of a sweep workgroup of shape (K, L), in elements of R (each
+// block starts on a multiple of 4 elements).  Arrays span the shape's full
+// capacity of K*L sublayers so that every lane can address its K sublayers
+// without bounds tests: sublayers past the column hold the identity.
+//   dB, hdm  [K*L + 1]   Planck difference and half column mass per sublayer
+//   lq       [K*L/2][4]  r, kx, sf, gd per layer
+//   pu, pd   [K*L + 2]   Gauss sums per point; the last slot absorbs writes
+//                        of lanes that own no point
+struct SweepLds {
+    int dB, hdm, lq, pu, pd, junk, total;
+    __host__ __device__ constexpr SweepLds(int KL)
+        : dB(0),
+          hdm((KL + 1 + 3) & ~3),
+          lq(2 * ((KL + 1 + 3) & ~3)),
+          pu(2 * ((KL + 1 + 3) & ~3) + 4 * ((KL / 2 + 3) & ~3)),
+          pd(2 * ((KL + 1 + 3) & ~3) + 4 * ((KL / 2 + 3) & ~3) + ((KL + 2 + 3) & ~3)),
+          junk(KL + 1),
+          total(2 * ((KL + 1 + 3) & ~3) + 4 * ((KL / 2 + 3) & ~3) + 2 * ((KL + 2 + 3) & ~3)) {}
 };
 
-// One workgroup = one wave, which owns one (bin, part) at a time: it stages
-// the bin's Planck differences, sublayer column masses, w0 and g0 in LDS once,
-// then solves its share of the bin's n_g columns C = 64/L at a time (group j
-// covers g in [j*C, j*C + C), contiguous in the [bin][g][point] arrays, staged
-// and written back through LDS with coalesced accesses), and accumulates the
-// Gauss sums of its groups in LDS in a fixed order.  Large launches give a bin
-// one part (one partial per (bin, point)); launches with few bins split a
-// bin's groups over several waves to fill the device.  The bin-sum kernel adds
-// a bin's partials in order, adds the Planck term and sums over bins.  No
-// barrier spans more than the wave.
+// One workgroup = one wave, which owns one (bin, part) at a time.  It stages
+// the bin's Planck differences, half column masses and per-layer quantities
+// in LDS once, then solves its share of the bin's n_g columns C = 64/L at a
+// time (group j covers g in [j*C, j*C + C)).  Each lane reads the opacities
+// and warm start of its own K points straight from HBM (pairs of values, all
+// loads issued before the first is used) and writes its fluxes back the same
+// way.  The Gauss sums over a group's columns are formed with cross-column
+// shuffles and accumulated per point in LDS over the wave's groups, then
+// written out coalesced: one partial per (bin, part, point).  Large launches
+// give a bin one part; launches with few bins split a bin's groups over
+// several waves.  The bin-sum kernel adds a bin's partials in order, adds the
+// Planck term and sums over bins.  No barrier spans more than the wave.
 template <int K, int L, typename R, int OCC>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
-    using GS = GSum<R>;
-    using slot = typename GS::slot;
+    using R2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
     constexpr int C = 64 / L;
+    constexpr int KH = K / 2;
+    constexpr int KL = K * L;
+    constexpr SweepLds lay(KL);
     static_assert(K % 2 == 0, "segments hold whole layers");
     extern __shared__ unsigned char smem_raw[];
-    const int npt_max = A.npt_max;
-    R* s_kap = reinterpret_cast<R*>(smem_raw);  // [C][npt]   opacities of the group
-    R* s_fu = s_kap + C * npt_max;              // [C][npt]   warm start, later F_dn / F_up of the group
-    R* s_dB = s_fu + C * npt_max;               // [npt - 1]  Planck difference across each sublayer
-    R* s_dm = s_dB + npt_max;                   // [npt - 1]  sublayer column masses
-    R* s_w0 = s_dm + npt_max;                   // [n]
-    R* s_g0 = s_w0 + npt_max / 2;               // [n]
-    slot* s_pu = reinterpret_cast<slot*>(s_g0 + npt_max / 2 + 1);  // [npt] Gauss sums, up
-    slot* s_pd = s_pu + npt_max;                                     // [npt] Gauss sums, down
+    R* sm = reinterpret_cast<R*>(smem_raw);
+    R* s_dB = sm + lay.dB;
+    R* s_hdm = sm + lay.hdm;
+    R* s_lq = sm + lay.lq;
+    R* s_pu = sm + lay.pu;
+    R* s_pd = sm + lay.pd;
 
     const int lane = threadIdx.x;
     const int seg = lane & (L - 1);
     const int cw = lane / L;
+    const int lo = seg * K;
     const R* __restrict__ kap_all = static_cast<const R*>(A.kappa);
     const double* __restrict__ B_all = static_cast<const double*>(A.B);
     R* __restrict__ Fu_all = static_cast<R*>(A.F_up_g);
     R* __restrict__ Fd_all = static_cast<R*>(A.F_dn_g);
-    slot* __restrict__ part_up = static_cast<slot*>(A.part_up);
-    slot* __restrict__ part_dn = static_cast<slot*>(A.part_dn);
+    R* __restrict__ part_up = static_cast<R*>(A.part_up);
+    R* __restrict__ part_dn = static_cast<R*>(A.part_dn);
+    const R D = (R)A.D;
+    const R inv_D = (R)(1.0 / A.D);
+    const R tpe = (R)(2.0 * kPi / A.D);
 
     for (int64_t item = A.w_begin + blockIdx.x; item < A.w_end; item += gridDim.x) {
-        const int64_t gb = item / A.parts;
+        const int64_t gb = (A.parts == 1) ? item : item / A.parts;
         const int part = (int)(item - gb * A.parts);
-        // one group per wave: its Gauss sums go straight to the workspace
-        // (no LDS accumulators are allocated for such launches)
-        const bool direct = (A.parts >= A.wpb);
         const int at = A.bin_atm[gb];
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
         if (n < A.n_lo || n > A.n_hi || frozen(A.status, at)) continue;  // uniform per wave
         const int nsub = 2 * n, npt = nsub + 1;
         const int nact = (nsub + K - 1) / K;
-        const int lo = seg * K;
-        const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // points owned (any column)
+        const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // sublayers owned (any column); even
         const bool top_seg = (seg == nact - 1);                 // also owns the TOA point
         const int cs = col_stride(n);
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
         const double* __restrict__ P = A.P_pt + A.pt_off[at];
-        const double igrav = 1.0 / A.grav[at];
-        const R D = (R)A.D;
-        const R inv_D = (R)(1.0 / A.D);
-        const R tpe = (R)(2.0 * kPi / A.D);
+        const double higrav = 0.5 / A.grav[at];
         // TOA value of the downward deviation, formed in FP64
         const R Ftop = (R)(A.F_top[A.bin_off[at] + l] - (2.0 * kPi / A.D) * B_all[pb + nsub]);
         const R Fint = (R)A.F_int[A.bin_off[at] + l];
 
-        // ---- the bin's per-sublayer inputs, staged once for all g.  All loads
-        // are issued before the first is consumed (compile-time bounds,
+        // ---- the bin's per-sublayer and per-layer inputs, staged once for
+        // all g, padded with the identity up to the shape's capacity.  All
+        // loads are issued before the first is consumed (compile-time bounds,
         // indices clamped into the bin's own rows).
         {
-            constexpr int NCAP = K * L + 1;
-            constexpr int PCH = (NCAP + 63) / 64;
-            constexpr int LCH = (K * L / 2 + 63) / 64;
+            constexpr int PCH = (KL + 2 + 63) / 64;
+            constexpr int LCH = (KL / 2 + 63) / 64;
             double bv[PCH], pv[PCH], wv[LCH], gv[LCH];
 #pragma unroll
             for (int q = 0; q < PCH; ++q) {
@@ -379,8 +433,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 gv[q] = A.g0[lb + i];
             }
             // sublayer differences from the next point's value: the next lane,
-            // or lane 0 of the next chunk for lane 63 (sublayer i < npt - 1
-            // never needs a chunk past the last)
+            // or lane 0 of the next chunk for lane 63
 #pragma unroll
             for (int q = 0; q < PCH; ++q) {
                 double bn = __shfl_down(bv[q], 1u, 64), pn = __shfl_down(pv[q], 1u, 64);
@@ -391,92 +444,91 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     pn = (lane == 63) ? p0 : pn;
                 }
                 const int i = lane + 64 * q;
-                if (i < nsub) {
-                    s_dB[i] = (R)(bv[q] - bn);
-                    s_dm[i] = (R)((pv[q] - pn) * igrav);
+                const bool real = i < nsub;
+                if (i <= KL) {
+                    s_dB[i] = real ? (R)(bv[q] - bn) : (R)0;
+                    s_hdm[i] = real ? (R)((pv[q] - pn) * higrav) : (R)0;
                 }
-                if (i < npt && !direct) {
-                    s_pu[i] = (slot)0;
-                    s_pd[i] = (slot)0;
+                if (i <= KL + 1) {
+                    s_pu[i] = (R)0;
+                    s_pd[i] = (R)0;
                 }
             }
 #pragma unroll
             for (int q = 0; q < LCH; ++q) {
                 const int i = lane + 64 * q;
-                if (i < n) {
-                    s_w0[i] = (R)wv[q];
-                    s_g0[i] = (R)gv[q];
-                }
-            }
-        }
-
-        const int gpp = (A.wpb + A.parts - 1) / A.parts;  // groups of this wave: [j_lo, j_hi)
-        const int j_lo = part * gpp, j_hi = min(A.wpb, j_lo + gpp);
-      for (int j = j_lo; j < j_hi; ++j) {  // groups of C columns
-        const int g = j * C + cw;
-        const int ncols = min(C, A.n_g - j * C);  // columns of this group
-        const bool colok = cw < ncols;
-        const int cnt = colok ? scnt : 0;
-        const int64_t cell0 = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * cs;  // first column
-        R wcol[C];  // Gauss weights of the wave's columns
-#pragma unroll
-        for (int c = 0; c < C; ++c) wcol[c] = (c < ncols) ? (R)A.gw[j * C + c] : (R)0;
-
-        // ---- stage the group's opacities and warm start in LDS (coalesced,
-        // all loads issued before the first is consumed)
-        {
-            constexpr int NCAP = K * L + 1;
-            constexpr int PCH = (NCAP + 63) / 64;
-            R kv[C][PCH], fv[C][PCH];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int64_t col = cell0 + (int64_t)min(c, ncols - 1) * cs;
-#pragma unroll
-                for (int q = 0; q < PCH; ++q) {
-                    const int i = min(lane + 64 * q, npt - 1);
-                    kv[c][q] = kap_all[col + i];
-                    fv[c][q] = Fu_all[col + i];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-#pragma unroll
-                for (int q = 0; q < PCH; ++q) {
-                    const int i = lane + 64 * q;
-                    if (c < ncols && i < npt) {
-                        s_kap[c * npt + i] = kv[c][q];
-                        s_fu[c * npt + i] = fv[c][q];
-                    }
+                if (i < KL / 2) {
+                    R r = (R)1, kx = (R)0, sf = (R)0, gd = (R)-1;
+                    if (i < n) layer_g<R>((R)wv[q], (R)gv[q], D, inv_D, tpe, r, kx, sf, gd);
+                    s_lq[4 * i + 0] = r;
+                    s_lq[4 * i + 1] = kx;
+                    s_lq[4 * i + 2] = sf;
+                    s_lq[4 * i + 3] = gd;
                 }
             }
         }
         __syncthreads();
 
-        // ---- sublayer coefficients and warm start (once per call)
-        R ca[K], cc[K], sg[K], fu[K], bu[K];
+        const int gpp = (A.wpb + A.parts - 1) / A.parts;  // groups of this wave: [j_lo, j_hi)
+        const int j_lo = part * gpp, j_hi = min(A.wpb, j_lo + gpp);
+      for (int j = j_lo; j < j_hi; ++j) {  // groups of C columns
+        const int ncols = min(C, A.n_g - j * C);  // columns of this group
+        const bool colok = cw < ncols;
+        const int cnt = colok ? scnt : 0;
+        // the group's first column (uniform) and my column's offset from it
+        // (a surplus column of a short last group reads the group's last
+        // column and writes nothing)
+        const int64_t gcol = A.cell_off[at] + ((int64_t)l * A.n_g + j * C) * cs;
+        const R* __restrict__ kap_g = kap_all + gcol;
+        R* __restrict__ fu_g = Fu_all + gcol;
+        const uint32_t col = (uint32_t)(min(cw, ncols - 1) * cs);
+        const R wg = colok ? (R)A.gw[j * C + cw] : (R)0;  // Gauss weight of my column
+
+        // ---- my points' opacities (lo .. lo + K) and warm start (lo .. lo + K - 1):
+        // pairs starting at even indices, clamped to nsub; a pair at nsub also
+        // reads index nsub + 1 < col_stride (npt is odd), which is not used
+        R kv[K + 2], fu[K];
         {
-            const R* kc = s_kap + cw * npt + lo;
-            const R* fc = s_fu + cw * npt + lo;
-            const R* dBc = s_dB + lo;
-            const R* dmc = s_dm + lo;
-            R kp = (R)0;
-            if (cnt > 0) kp = kc[0];
-            LayerQ<R> q;
+            R2 kp2[KH + 1], fp2[KH];
+#pragma unroll
+            for (int p = 0; p <= KH; ++p)
+                kp2[p] = *reinterpret_cast<const R2*>(kap_g + (col + (uint32_t)min(lo + 2 * p, nsub)));
+#pragma unroll
+            for (int p = 0; p < KH; ++p)
+                fp2[p] = *reinterpret_cast<const R2*>(fu_g + (col + (uint32_t)min(lo + 2 * p, nsub)));
+#pragma unroll
+            for (int p = 0; p <= KH; ++p) {
+                kv[2 * p] = kp2[p].x;
+                kv[2 * p + 1] = kp2[p].y;
+            }
+#pragma unroll
+            for (int p = 0; p < KH; ++p) {
+                fu[2 * p] = fp2[p].x;
+                fu[2 * p + 1] = fp2[p].y;
+            }
+        }
+
+        // ---- sublayer coefficients (once per call); sublayers past my
+        // column's end get dtau = 0 and the LDS padding, i.e. the identity
+        R ca[K], cc[K], sg[K];
+        {
+            R r = (R)1, kx = (R)0, sf = (R)0, gd = (R)-1, zp = (R)1, zm = (R)0, zpzm = (R)0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                ca[k] = (R)1;
-                cc[k] = (R)0;
-                sg[k] = (R)0;
-                fu[k] = (R)0;
-                bu[k] = (R)0;
-                if (k < cnt) {
-                    if ((k & 1) == 0) q = layer_q<R>(s_w0[(lo + k) >> 1], s_g0[(lo + k) >> 1], D, inv_D, tpe);
-                    const R kn = kc[k + 1];
-                    const R dtau = (R)0.5 * (kp + kn) * dmc[k];
-                    sub_coeffs_g<R>(q, dtau, tpe, dBc[k], ca[k], cc[k], sg[k]);
-                    fu[k] = fc[k];
-                    kp = kn;
+                const bool act = k < cnt;
+                if ((k & 1) == 0) {
+                    const R* lq = s_lq + 4 * ((lo + k) >> 1);
+                    r = lq[0];
+                    kx = lq[1];
+                    sf = lq[2];
+                    gd = lq[3];
+                    zp = (R)0.5 + (R)0.5 * r;
+                    zm = (R)0.5 - (R)0.5 * r;
+                    zpzm = zp * zm;
                 }
+                const R dtau = act ? (kv[k] + kv[k + 1]) * s_hdm[lo + k] : (R)0;
+                fu[k] = act ? fu[k] : (R)0;
+                sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], act, ca[k], cc[k], sg[k]);
             }
         }
 
@@ -486,8 +538,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // segments (top: F_dn = F_top; bottom: F_up = F_dn + F_int), so every
         // scanned map ends up constant and only its offset b is scanned.
         constexpr int LOG2L = (L == 16) ? 4 : 5;
-        // keep the multipliers in registers unless that would spill (wide FP64 segments)
-        constexpr bool PRECOMP = (sizeof(R) == 4) || (K <= 8);
+        // keep the scan multipliers in registers unless that would spill
+        constexpr bool PRECOMP = (sizeof(R) == 4) || (K <= 14);
         R pseg = (R)1;
 #pragma unroll
         for (int k = 0; k < K; ++k) pseg *= ca[k];
@@ -513,24 +565,49 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         }
         const R ftop_fold = pseg * Ftop;
 
-        // the down sweep's per-sublayer offsets c F_up - sig, kept for the
-        // replay when registers allow
-        constexpr bool KEEP_T = (sizeof(R) == 4) || (K <= 8);
-        R tk[KEEP_T ? K : 1];
-        R ftoa = (R)0;
-        for (int pass = 0; pass <= A.n_scat; ++pass) {
-            const bool last = (pass == A.n_scat);
-            // ---------------- downward sweep: compose my segment (top -> bottom)
-            R MB = (R)0;
-            if constexpr (KEEP_T) {
+        // Gauss sums of one stream over the group's columns at my points
+        // (v[k] at lo + k, vtop at the TOA for the top segment), added to the
+        // wave's LDS accumulators.  Every column of a point computes the same
+        // sum and writes the same value; points past the column go to the
+        // junk slot.
+        auto emit = [&](const R (&v)[K], R vtop, R* acc) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) tk[k] = cc[k] * fu[k] - sg[k];
-#pragma unroll
-                for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + tk[k];
-            } else {
-#pragma unroll
-                for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + (cc[k] * fu[k] - sg[k]);
+            for (int k = 0; k < K; ++k) {
+                const R sk = col_sum<L>(wg * v[k]);
+                const int idx = (lo + k < nsub) ? lo + k : lay.junk;
+                acc[idx] += sk;
             }
+            const R st = col_sum<L>(wg * vtop);
+            if (top_seg) acc[nsub] += st;
+        };
+        // per-g values of one stream (pairs at my points, the TOA value alone)
+        auto store = [&](const R (&v)[K], R vtop, R* __restrict__ dst_g) {
+            if (!colok) return;
+#pragma unroll
+            for (int p = 0; p < KH; ++p) {
+                if (2 * p < cnt) {
+                    R2 w;
+                    w.x = v[2 * p];
+                    w.y = v[2 * p + 1];
+                    *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(lo + 2 * p))) = w;
+                }
+            }
+            if (top_seg) dst_g[col + (uint32_t)nsub] = vtop;
+        };
+
+        // One scattering pass: downward sweep (top -> bottom), then upward
+        // (bottom -> top).  fu[k] holds sublayer k's stream state in turn:
+        // F_up at its lower point, the downward map offset c F_up - sig, the
+        // upward map offset c F_dn + sig (in the last pass F_dn first), and
+        // the new F_up.
+        R ftoa = (R)0;
+        auto one_pass = [&](auto last_tag) {
+            constexpr bool LAST = decltype(last_tag)::value;
+            R MB = (R)0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) fu[k] = cc[k] * fu[k] - sg[k];
+#pragma unroll
+            for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + fu[k];
             if (seg == L - 1) MB = ftop_fold + MB;
             if constexpr (PRECOMP) {  // suffix scan towards the BOA
                 MB = scan_down_step<L, 0>(MB, mdn[0]);
@@ -544,39 +621,32 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             }
             R x = grp_down<L, 1>(MB);  // F_dn at my segment's top point
             if (seg == L - 1) x = Ftop;
-            // downward fluxes of the final pass go straight to LDS (the staged
-            // warm start is dead by then), then the Gauss partials (column
-            // sums) and, optionally, the per-g values are stored coalesced
-            R* s_out = s_fu;
+            if constexpr (!LAST) {
+                // fu[k] then takes the upward sweep's offset c F_dn + sig
 #pragma unroll
-            for (int k = K - 1; k >= 0; --k) {
-                bu[k] = cc[k] * x + sg[k];
-                if constexpr (KEEP_T) x = ca[k] * x + tk[k];
-                else x = ca[k] * x + (cc[k] * fu[k] - sg[k]);
-                if (last && k < cnt) s_out[cw * npt + lo + k] = x;
-            }
-            if (last) {
-                if (top_seg && colok) s_out[cw * npt + nsub] = Ftop;
-                __syncthreads();
-                for (int i = lane; i < npt; i += 64) {
-                    const slot v = GS::col_sum(s_out + i, npt, ncols, wcol);
-                    if (direct) part_dn[pb * A.wpb_stride + (int64_t)part * npt + i] = v;
-                    else s_pd[i] += v;
+                for (int k = K - 1; k >= 0; --k) {
+                    const R xn = ca[k] * x + fu[k];
+                    fu[k] = cc[k] * x + sg[k];
+                    x = xn;
                 }
-                if (Fd_all) {
-                    for (int cc = 0; cc < ncols; ++cc) {
-                        R* db = Fd_all + cell0 + (int64_t)cc * cs;
-                        for (int i = lane; i < npt; i += 64) db[i] = s_out[cc * npt + i];
-                    }
+            } else {
+                // keep F_dn for the outputs, then form the offsets from it
+                const R xtop = x;
+#pragma unroll
+                for (int k = K - 1; k >= 0; --k) {
+                    x = ca[k] * x + fu[k];
+                    fu[k] = x;
                 }
-                __syncthreads();
+                emit(fu, Ftop, s_pd);
+                if (Fd_all) store(fu, Ftop, Fd_all + gcol);
+#pragma unroll
+                for (int k = 0; k < K; ++k) fu[k] = cc[k] * (k + 1 < K ? fu[k + 1] : xtop) + sg[k];
             }
-            // ---------------- upward sweep: compose (bottom -> top); the BOA
-            // condition F_up(0) = F_dn(0) + F_int lives in segment 0
-            const R y0 = x + Fint;  // meaningful in segment 0 only
+            // the BOA condition F_up(0) = F_dn(0) + F_int lives in segment 0
+            const R y0 = x + Fint;
             MB = (R)0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) MB = ca[k] * MB + bu[k];
+            for (int k = 0; k < K; ++k) MB = ca[k] * MB + fu[k];
             if (seg == 0) MB = pseg * y0 + MB;
             if constexpr (PRECOMP) {  // prefix scan towards the TOA
                 MB = scan_up_step<L, 0>(MB, mup[0]);
@@ -592,70 +662,50 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             if (seg == 0) y = y0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
+                const R yn = ca[k] * y + fu[k];
                 fu[k] = y;
-                y = ca[k] * y + bu[k];
+                y = yn;
             }
             ftoa = y;
-        }
+        };
+        for (int pass = 0; pass < A.n_scat; ++pass) one_pass(std::false_type{});
+        one_pass(std::true_type{});
 
         // ---- outputs: upward fluxes (warm start of the next call) and their
-        // Gauss partials, staged in LDS and stored coalesced
-        {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < cnt) s_fu[cw * npt + lo + k] = fu[k];
-            if (top_seg && colok) s_fu[cw * npt + nsub] = ftoa;
-            __syncthreads();
-            for (int i = lane; i < npt; i += 64) {
-                const slot v = GS::col_sum(s_fu + i, npt, ncols, wcol);
-                if (direct) part_up[pb * A.wpb_stride + (int64_t)part * npt + i] = v;
-                else s_pu[i] += v;
-            }
-            for (int cc = 0; cc < ncols; ++cc) {
-                R* ub = Fu_all + cell0 + (int64_t)cc * cs;
-                for (int i = lane; i < npt; i += 64) ub[i] = s_fu[cc * npt + i];
-            }
-            __syncthreads();
-        }
+        // Gauss sums
+        emit(fu, ftoa, s_pu);
+        store(fu, ftoa, fu_g);
       }  // groups
-        // ---- this wave's Gauss sums over its groups (one partial per point)
-        if (!direct) {
-            // partial slot of this (bin, part): [bin x point][stride] layout
-            const int64_t poff = pb * A.wpb_stride + (int64_t)part * npt;
-            for (int i = lane; i < npt; i += 64) {
-                part_up[poff + i] = s_pu[i];
-                part_dn[poff + i] = s_pd[i];
-            }
+        // ---- this wave's Gauss sums over its groups (one partial per point),
+        // stored coalesced
+        __syncthreads();
+        const int64_t poff = pb * A.wpb_stride + (int64_t)part * npt;
+        for (int i = lane; i < npt; i += 64) {
+            part_up[poff + i] = s_pu[i];
+            part_dn[poff + i] = s_pd[i];
         }
+        __syncthreads();  // the next item restages the LDS arrays
     }
 }
 
-// LDS bytes of one sweep workgroup.
-template <int L>
-static size_t sweep_lds(const SweepArgs& a, size_t rbytes) {
-    constexpr int C = 64 / L;
-    // staging + per-bin inputs + two Gauss-sum accumulators (slot = R; not
-    // needed when every wave has a single group)
-    const size_t acc = (a.parts >= a.wpb) ? 0 : 2 * (size_t)a.npt_max;
-    return (size_t)(2 * C * a.npt_max + 2 * a.npt_max + a.npt_max + 1 + acc) * rbytes + 64;
-}
+// LDS bytes of one sweep workgroup of shape (K, L).
+static size_t sweep_lds(int K, int L, size_t rbytes) { return (size_t)SweepLds(K * L).total * rbytes; }
 
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills.
 template <int K, int L, bool F64>
 constexpr int sweep_occ() {
-    if (F64) return (K <= 4 && L == 16) ? 3 : ((K <= 8 || (K <= 14 && L == 16)) ? 2 : 1);
-    if (L == 16) return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
-    return K <= 4 ? 4 : (K <= 8 ? 3 : (K <= 14 ? 2 : 1));
+    if (F64) return (K <= 4) ? 4 : ((K <= 8) ? 3 : (K <= 14 ? 2 : 1));
+    return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
 }
 
 template <int K, int L>
 static hipError_t launch_kp(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed)
         hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, L, false>()>), dim3(grid), dim3(64),
-                           sweep_lds<L>(a, 4), s, a);
+                           sweep_lds(K, L, 4), s, a);
     else
         hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, L, true>()>), dim3(grid), dim3(64),
-                           sweep_lds<L>(a, 8), s, a);
+                           sweep_lds(K, L, 8), s, a);
     return hipGetLastError();
 }
 
