@@ -50,7 +50,7 @@ int class_nlo(int k) { return k == 0 ? 0 : kClassNHi[k - 1] + 1; }
 // Host view of the batch sizes.
 struct Sizes {
     int64_t total_n = 0, total_pt = 0, total_bin = 0, total_lb = 0, total_pb = 0, total_cell = 0;
-    int n_max = 0, npt_max = 0, nb_max = 0;
+    int n_max = 0, npt_max = 0, nb_max = 0, n_atm = 0;
     // per class: deepest member, bin range [bin_lo, bin_hi) spanning its members,
     // and the member with the most bins among the deepest (autotuner sample)
     int cls_nmax[kNumClasses] = {};
@@ -84,6 +84,7 @@ int check_atm(const helios_atm* atm, Sizes& z) {
         z.npt_max = std::max(z.npt_max, npt);
         z.nb_max = std::max(z.nb_max, nb);
     }
+    z.n_atm = atm->n_atm;
     int64_t b0 = 0;
     for (int a = 0; a < atm->n_atm; ++a) {
         int n = atm->n_layer_h[a], nb = atm->n_bin_h[a], k = class_of(n);
@@ -104,7 +105,8 @@ int check_atm(const helios_atm* atm, Sizes& z) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t B, F_top, F_int, gw, bin_atm, part_up, part_dn, chunk, total;
+    size_t B, F_top, F_int, gw, bin_atm, part_up, part_dn, chunk, bnd_part, total;
+    int bnd_maxch;
 };
 
 // Waves per bin for L lanes per column: each wave holds 64/L columns.
@@ -136,7 +138,9 @@ WsLayout ws_layout(const Sizes& z, int n_g, bool /*mixed*/) {
     w.part_up = align256(w.bin_atm + (size_t)z.total_bin * sizeof(int32_t));
     w.part_dn = align256(w.part_up + (size_t)z.total_pb * wpb * 8);
     w.chunk = align256(w.part_dn + (size_t)z.total_pb * wpb * 8);
-    w.total = align256(w.chunk + (size_t)z.total_pt * n_chunk * 6 * sizeof(double));
+    w.bnd_maxch = (z.nb_max + kBndChunk - 1) / kBndChunk;
+    w.bnd_part = align256(w.chunk + (size_t)z.total_pt * n_chunk * 6 * sizeof(double));
+    w.total = align256(w.bnd_part + (size_t)z.n_atm * w.bnd_maxch * sizeof(double));
     return w;
 }
 
@@ -297,6 +301,9 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
     A.part_up = wsb + p.w.part_up;
     A.part_dn = wsb + p.w.part_dn;
     A.gw = (double*)(wsb + p.w.gw);
+    A.bnd_part = (const double*)(wsb + p.w.bnd_part);
+    A.T_int = atm->T_int;
+    A.bnd_maxch = p.w.bnd_maxch;
     A.bin_atm = (const int32_t*)(wsb + p.w.bin_atm);
     A.status = atm->status;
     A.n_atm = atm->n_atm;
@@ -328,9 +335,18 @@ hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, i
 
 hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double* T_pt, char* wsb,
                           hipStream_t s) {
-    return launch_planck(atm, p.z.total_pb, T_pt, (double*)(wsb + p.w.B), (double*)(wsb + p.w.F_top),
-                         (double*)(wsb + p.w.F_int), (double*)(wsb + p.w.gw), (int32_t*)(wsb + p.w.bin_atm),
-                         gauss_table(atm->n_g), p.mixed, s);
+    SourceArgs sa;
+    sa.B = (double*)(wsb + p.w.B);
+    sa.F_top = (double*)(wsb + p.w.F_top);
+    sa.F_int = (double*)(wsb + p.w.F_int);
+    sa.gw = (double*)(wsb + p.w.gw);
+    sa.bin_atm = (int32_t*)(wsb + p.w.bin_atm);
+    sa.bnd_part = (double*)(wsb + p.w.bnd_part);
+    sa.bnd_maxch = p.w.bnd_maxch;
+    sa.nb_max = p.z.nb_max;
+    sa.npt_max = p.z.npt_max;
+    sa.total_bin = p.z.total_bin;
+    return launch_planck(atm, T_pt, sa, gauss_table(atm->n_g), s);
 }
 
 // ------------------------------------------------------ warm-start network
@@ -557,6 +573,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     Bo.F_up_bin = F_up_bin;
     Bo.F_dn_bin = F_dn_bin;
     Bo.chunk = (double*)(wsb + p.w.chunk);
+    Bo.total_pt = p.z.total_pt;
     Bo.F_bol = F_bol;
     Bo.B = (const double*)(wsb + p.w.B);
     Bo.gw = (const double*)(wsb + p.w.gw);

@@ -43,13 +43,51 @@ __device__ inline int find_atm(const int64_t* __restrict__ off, int n_atm, int64
     return lo;
 }
 
-// Planck function per unit wavelength and steradian at the bin centre.
+// e = exp(-x) and om = 1 - exp(-x) for x >= 0 in FP64.  Cody-Waite
+// reduction x = n ln2 + s' with |s'| <= ln2/2 (ln2 carried in two parts), the
+// Taylor series of expm1 to degree 13 on the reduced argument (truncation
+// below 5e-18) and scaling by 2^-n.  For n = 0 the polynomial gives om
+// directly, so om keeps full relative accuracy for small x; for n >= 1,
+// e <= 0.71 and 1 - e is free of cancellation.  Arguments beyond 1000 (e = 0
+// in FP64) are clamped, which keeps n in integer range.
+__device__ inline void exp_neg_om(double x, double& e, double& om) {
+    constexpr double ln2_hi = 0.6931471805599453;      // ln 2 rounded to double
+    constexpr double ln2_lo = 2.3190468138462996e-17;  // ln 2 - ln2_hi
+    constexpr double inv_ln2 = 1.4426950408889634;
+    x = fmin(x, 1000.0);
+    const double n = rint(x * inv_ln2);
+    double r = fma(-n, ln2_hi, x);
+    r = fma(-n, ln2_lo, r);
+    const double s = -r;  // exp(-x) = 2^-n exp(s)
+    double p = 1.0 / 6227020800.0;  // 1/13!
+    p = fma(p, s, 1.0 / 479001600.0);
+    p = fma(p, s, 1.0 / 39916800.0);
+    p = fma(p, s, 1.0 / 3628800.0);
+    p = fma(p, s, 1.0 / 362880.0);
+    p = fma(p, s, 1.0 / 40320.0);
+    p = fma(p, s, 1.0 / 5040.0);
+    p = fma(p, s, 1.0 / 720.0);
+    p = fma(p, s, 1.0 / 120.0);
+    p = fma(p, s, 1.0 / 24.0);
+    p = fma(p, s, 1.0 / 6.0);
+    p = fma(p, s, 0.5);
+    p = fma(p, s, 1.0);
+    const double q = p * s;  // expm1(s)
+    e = ldexp(1.0 + q, -(int)n);
+    om = (n == 0.0) ? -q : 1.0 - e;
+}
+
+// Planck function per unit wavelength and steradian at the bin centre:
+// 2 h c^2 / lambda^5 / (exp(x) - 1) = 2 h c^2 / lambda^5 * exp(-x) / (1 - exp(-x)),
+// x = h c / (lambda k T).
 __device__ inline double planck_d(double lambda, double T) {
     if (!(T > 0.0)) return 0.0;
     const double c1 = 2.0 * kH * kC * kC;
     const double x = kH * kC / (lambda * kKB * T);
     const double l2 = lambda * lambda;
-    return c1 / (l2 * l2 * lambda) / expm1(x);
+    double e, om;
+    exp_neg_om(x, e, om);
+    return c1 / (l2 * l2 * lambda) * (e / om);
 }
 
 // ----------------------------------------------------------- launch args
@@ -73,6 +111,8 @@ struct SweepArgs {
     void* part_up;        // [bin x wave-of-bin x point] Gauss partial sums (workspace)
     void* part_dn;
     const double* gw;     // [n_g] Gauss weights on [0,1] (workspace)
+    const double* bnd_part;  // [n_atm][bnd_maxch] chunk sums of pi B(T_int) dlambda (workspace)
+    const double* T_int;     // [n_atm]
     const int32_t* status;   // optional: converged atmospheres are skipped
     const int32_t* bin_atm;  // [sum nb] owning atmosphere of each bin (workspace)
     int64_t w_begin, w_end;  // global (bin, part) range covered by the launch
@@ -83,6 +123,7 @@ struct SweepArgs {
     int32_t n_lo, n_hi;   // this launch serves atmospheres with n_lo <= n <= n_hi
     int32_t n_scat;
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
+    int32_t bnd_maxch;    // boundary chunks per atmosphere in bnd_part
     double D;
 };
 
@@ -98,7 +139,8 @@ struct BolArgs {
     const void* part_dn;
     double* F_up_bin;
     double* F_dn_bin;
-    double* chunk;        // [sum npt][n_chunk][6] Neumaier pairs of bin-chunk sums (workspace)
+    double* chunk;        // [n_chunk][6][sum npt] Neumaier pairs of bin-chunk sums (workspace)
+    int64_t total_pt;
     double* F_bol;
     const double* B;      // [bin x point] Planck values (workspace)
     const double* gw;     // [n_g] Gauss weights (workspace)
@@ -155,9 +197,21 @@ hipError_t launch_warm_start(const helios_atm* atm, const float* T_net, int n_ou
 hipError_t launch_grid(const helios_atm* atm, int64_t total_pt, hipStream_t s);
 hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double* T_c, double* T_pt,
                           hipStream_t s);
-hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, double* B,
-                         double* F_top, double* F_int, double* gw, int32_t* bin_atm, const GaussTable& gt,
-                         bool mixed, hipStream_t s);
+// Boundary fluxes (F_int unscaled: the sweep applies sigma T_int^4 / sum of
+// bnd_part), Gauss weights and the bin -> atmosphere map, then the Planck
+// values at the points.
+struct SourceArgs {
+    double* B;
+    double* F_top;
+    double* F_int;
+    double* gw;
+    int32_t* bin_atm;
+    double* bnd_part;
+    int32_t bnd_maxch, nb_max, npt_max;
+    int64_t total_bin;
+};
+hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const SourceArgs& sa, const GaussTable& gt,
+                         hipStream_t s);
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);
@@ -173,6 +227,7 @@ hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c,
 // Sweep instantiations available (sublayers per lane).
 constexpr int kSweepK[] = {4, 8, 14, 26};
 constexpr int kBolChunk = 32;  // bins per bolometric chunk
+constexpr int kBndChunk = 256;  // bins per boundary-flux workgroup
 constexpr int kNumSweepK = 4;
 
 }  // namespace helios

@@ -63,71 +63,68 @@ hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double*
 }
 
 // --------------------------------------------------------------- sources
-// B[bin][pt] at the bin centres, one thread per (bin, point) element.
-__global__ void planck_kernel(helios_atm atm, int64_t total_pb, const double* __restrict__ T_pt,
-                              double* __restrict__ B) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total_pb) return;
-    int a = find_atm(atm.pb_off, atm.n_atm, idx);
-    if (frozen(atm.status, a)) return;
-    int npt = 2 * atm.n_layer[a] + 1;
-    int64_t rel = idx - atm.pb_off[a];
-    int l = (int)(rel / npt);
-    int p = (int)(rel - (int64_t)l * npt);
-    double lam = atm.lambda_c[atm.bin_off[a] + l];
-    B[idx] = planck_d(lam, T_pt[atm.pt_off[a] + p]);
+// B[bin][pt] at the bin centres: workgroup = (bin, tile of 256 points), one
+// thread per point (the bin's atmosphere from the map the boundary kernel
+// wrote earlier in the same call).
+constexpr int kPlanckThreads = 256;
+__global__ void __launch_bounds__(kPlanckThreads) planck_kernel(helios_atm atm, const double* __restrict__ T_pt,
+                                                                const int32_t* __restrict__ bin_atm,
+                                                                double* __restrict__ B) {
+    const int64_t b = blockIdx.x;
+    const int a = bin_atm[b];
+    if (frozen(atm.status, a)) return;  // uniform per workgroup
+    const int npt = 2 * atm.n_layer[a] + 1;
+    const int p = blockIdx.y * kPlanckThreads + threadIdx.x;
+    if (p >= npt) return;
+    const int64_t o = atm.pb_off[a] + (b - atm.bin_off[a]) * npt + p;
+    B[o] = planck_d(atm.lambda_c[b], T_pt[atm.pt_off[a] + p]);
 }
 
-// Boundary fluxes, one workgroup per atmosphere (Sec. 2.2.2): TOA
-// (T_irr/T_star)^4 pi B(T_star); BOA pi B(T_int) scaled so that its
-// width-weighted sum over the model's bins is sigma T_int^4.  The scale's sum
-// is a fixed-order tree in LDS.
-constexpr int kBoundaryThreads = 1024;
-__global__ void __launch_bounds__(kBoundaryThreads) boundary_kernel(helios_atm atm, double* __restrict__ F_top,
-                                                                    double* __restrict__ F_int,
-                                                                    double* __restrict__ gw,
-                                                                    int32_t* __restrict__ bin_atm, GaussTable gt) {
-    __shared__ double red[kBoundaryThreads];
-    int a = blockIdx.x;
-    if (a == 0 && (int)threadIdx.x < atm.n_g) gw[threadIdx.x] = gt.w[threadIdx.x];
-    int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
-    int64_t b0 = atm.bin_off[a];
-    // bin -> atmosphere map for the sweep (one load instead of a search)
-    for (int l = threadIdx.x; l < nb; l += blockDim.x) bin_atm[b0 + l] = a;
-    if (frozen(atm.status, a)) return;  // uniform per workgroup
-    double Ts = atm.T_star[a], Ti = atm.T_int[a];
-    double r = (Ts > 0.0) ? atm.T_irr[a] / Ts : 0.0;
-    double dil = r * r * r * r;
+// Boundary fluxes (Sec. 2.2.2), workgroup = (atmosphere, chunk of kBndChunk
+// bins): TOA (T_irr/T_star)^4 pi B(T_star); BOA pi B(T_int), left unscaled,
+// with the chunk's sum of pi B(T_int) dlambda (a fixed-order tree in LDS) in
+// bnd_part.  The sweep scales the BOA flux so that its width-weighted sum over
+// the atmosphere's bins is sigma T_int^4.  The same workgroups write the
+// Gauss weights and the bin -> atmosphere map.
+__global__ void __launch_bounds__(kBndChunk) boundary_kernel(helios_atm atm, SourceArgs sa, GaussTable gt) {
+    __shared__ double red[kBndChunk];
+    const int a = blockIdx.x, ch = blockIdx.y;
+    const int t = threadIdx.x;
+    if (a == 0 && ch == 0 && t < atm.n_g) sa.gw[t] = gt.w[t];
+    const int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
+    if (ch * kBndChunk >= nb) return;  // uniform
+    const int64_t b0 = atm.bin_off[a];
+    const int l = ch * kBndChunk + t;
+    if (l < nb) sa.bin_atm[b0 + l] = a;
+    if (frozen(atm.status, a)) return;  // uniform
+    const double Ts = atm.T_star[a], Ti = atm.T_int[a];
+    const double r = (Ts > 0.0) ? atm.T_irr[a] / Ts : 0.0;
+    const double dil = r * r * r * r;
     double part = 0.0;
-    for (int l = threadIdx.x; l < nb; l += blockDim.x) {
-        double lam = atm.lambda_c[b0 + l];
-        F_top[b0 + l] = dil * kPi * planck_d(lam, Ts);
-        double fi = kPi * planck_d(lam, Ti);
-        F_int[b0 + l] = fi;
-        part += fi * atm.dlambda[b0 + l];
+    if (l < nb) {
+        const double lam = atm.lambda_c[b0 + l];
+        sa.F_top[b0 + l] = dil * kPi * planck_d(lam, Ts);
+        const double fi = kPi * planck_d(lam, Ti);
+        sa.F_int[b0 + l] = fi;
+        part = fi * atm.dlambda[b0 + l];
     }
-    red[threadIdx.x] = part;
+    red[t] = part;
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    for (int st = kBndChunk / 2; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
         __syncthreads();
     }
-    double sum = red[0];
-    double t2 = Ti * Ti;
-    double scale = (sum > 0.0) ? sigma_sb() * t2 * t2 / sum : 0.0;
-    for (int l = threadIdx.x; l < nb; l += blockDim.x) F_int[b0 + l] *= scale;
+    if (t == 0) sa.bnd_part[(int64_t)a * sa.bnd_maxch + ch] = red[0];
 }
 
-hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* T_pt, double* B,
-                         double* F_top, double* F_int, double* gw, int32_t* bin_atm, const GaussTable& gt,
-                         bool /*mixed*/, hipStream_t s) {
-    int block = 256;
-    int64_t grid = (total_pb + block - 1) / block;
-    hipLaunchKernelGGL(planck_kernel, dim3((unsigned)grid), dim3(block), 0, s, *atm, total_pb, T_pt, B);
+hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const SourceArgs& sa, const GaussTable& gt,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm, sa.bnd_maxch), dim3(kBndChunk), 0, s, *atm, sa, gt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm), dim3(kBoundaryThreads), 0, s, *atm, F_top, F_int, gw,
-                       bin_atm, gt);
+    const int tiles = (sa.npt_max + kPlanckThreads - 1) / kPlanckThreads;
+    hipLaunchKernelGGL(planck_kernel, dim3((unsigned)sa.total_bin, tiles), dim3(kPlanckThreads), 0, s, *atm, T_pt,
+                       sa.bin_atm, sa.B);
     return hipGetLastError();
 }
 
@@ -139,7 +136,8 @@ hipError_t launch_planck(const helios_atm* atm, int64_t total_pb, const double* 
 // weights to form F_up_bin / F_dn_bin, writes them, and accumulates dlambda
 // times the up, down and net (up - down, from the deviations, where B
 // cancels) fluxes in Neumaier sums; the group sums are combined in order and
-// stored per (point, chunk).  Stage 2 sums a point's chunks in order.
+// stored per (chunk, quantity, point) (so both stages access them
+// coalesced).  Stage 2 sums a point's chunks in order.
 struct nacc {
     double s, c;
 };
@@ -163,7 +161,11 @@ __device__ inline double combine_partials(const void* part, int64_t base, int wp
     return acc;
 }
 
-// Stage 1 workgroup: 64 points x 16 groups of kBolChunk/16 consecutive bins.
+// chunk sums: [n_chunk][6][total_pt]
+__device__ inline int64_t chunk_at(const BolArgs& A, int ch, int v, int64_t gpt) {
+    return ((int64_t)ch * 6 + v) * A.total_pt + gpt;
+}
+
 __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     __shared__ double red[16][64][6];
     const int a = blockIdx.x;
@@ -209,18 +211,17 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     red[q][pl][4] = an.s;
     red[q][pl][5] = an.c;
     __syncthreads();
-    if (q == 0 && p < npt) {
-        double* o = A.chunk + ((A.atm.pt_off[a] + p) * A.n_chunk + ch) * 6;
-        for (int v = 0; v < 3; ++v) {
-            nacc t = {0.0, 0.0};
-            double cc = 0.0;
-            for (int k = 0; k < 16; ++k) {
-                nadd(t, red[k][pl][2 * v]);
-                cc += red[k][pl][2 * v + 1];
-            }
-            o[2 * v] = t.s;
-            o[2 * v + 1] = t.c + cc;
+    if (q < 3 && p < npt) {  // wave v combines quantity v
+        const int v = q;
+        const int64_t gpt = A.atm.pt_off[a] + p;
+        nacc t = {0.0, 0.0};
+        double cc = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            nadd(t, red[k][pl][2 * v]);
+            cc += red[k][pl][2 * v + 1];
         }
+        A.chunk[chunk_at(A, ch, 2 * v, gpt)] = t.s;
+        A.chunk[chunk_at(A, ch, 2 * v + 1, gpt)] = t.c + cc;
     }
 }
 
@@ -237,30 +238,44 @@ __global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
     const int nch = (nb + kBolChunk - 1) / kBolChunk;
     nacc t[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     double e[3] = {0.0, 0.0, 0.0};
+    const int64_t gpt = A.atm.pt_off[a] + p;
     if (p < npt) {
-        const double* c = A.chunk + (A.atm.pt_off[a] + p) * A.n_chunk * 6;
-        for (int k = q; k < nch; k += 16)
-            for (int v = 0; v < 3; ++v) {
-                nadd(t[v], c[6 * k + 2 * v]);
-                e[v] += c[6 * k + 2 * v + 1];
+        // U chunks' loads in flight at a time, added in chunk order
+        constexpr int U = 3;
+        for (int k0 = q; k0 < nch; k0 += 16 * U) {
+            double c[U][6];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 16 * u;
+#pragma unroll
+                for (int v = 0; v < 6; ++v) c[u][v] = (k < nch) ? A.chunk[chunk_at(A, k, v, gpt)] : 0.0;
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (k0 + 16 * u < nch) {
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        nadd(t[v], c[u][2 * v]);
+                        e[v] += c[u][2 * v + 1];
+                    }
+                }
+            }
+        }
     }
     for (int v = 0; v < 3; ++v) {
         red[q][pl][2 * v] = t[v].s;
         red[q][pl][2 * v + 1] = t[v].c + e[v];
     }
     __syncthreads();
-    if (q == 0 && p < npt) {
-        double* o = A.F_bol + 3 * (A.atm.pt_off[a] + p);
-        for (int v = 0; v < 3; ++v) {
-            nacc s = {0.0, 0.0};
-            double ee = 0.0;
-            for (int k = 0; k < 16; ++k) {
-                nadd(s, red[k][pl][2 * v]);
-                ee += red[k][pl][2 * v + 1];
-            }
-            o[v] = s.s + (s.c + ee);  // up, down, and net summed from the deviations
+    if (q < 3 && p < npt) {  // wave v combines quantity v: up, down, and net summed from the deviations
+        const int v = q;
+        nacc sacc = {0.0, 0.0};
+        double ee = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            nadd(sacc, red[k][pl][2 * v]);
+            ee += red[k][pl][2 * v + 1];
         }
+        A.F_bol[3 * gpt + v] = sacc.s + (sacc.c + ee);
     }
 }
 
@@ -274,14 +289,20 @@ hipError_t launch_bolometric(const BolArgs& a, int npt_max, int nb_max, int64_t 
 }
 
 // ------------------------------------------------------------- RE update
-// One workgroup per atmosphere; threads over layers.  Always FP64.
-__global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double* __restrict__ F_bol,
-                                                    double* __restrict__ T_c, double* __restrict__ T_pt,
-                                                    double* __restrict__ m, int32_t* __restrict__ hist,
-                                                    int32_t* __restrict__ iter, helios_re_opts o,
-                                                    int32_t* __restrict__ status, double* __restrict__ resid) {
-    __shared__ double red[256];
-    __shared__ int bad[256];
+// One workgroup per atmosphere; threads over layers.  Always FP64.  The
+// points' log P are formed once in LDS (shared by the step sizes and the
+// re-interpolation); the convergence reduction is a wave reduction plus one
+// LDS step.
+constexpr int kRadeqThreads = 256;
+__global__ void __launch_bounds__(kRadeqThreads) radeq_kernel(helios_atm atm, const double* __restrict__ F_bol,
+                                                              double* __restrict__ T_c, double* __restrict__ T_pt,
+                                                              double* __restrict__ m, int32_t* __restrict__ hist,
+                                                              int32_t* __restrict__ iter, helios_re_opts o,
+                                                              int32_t* __restrict__ status,
+                                                              double* __restrict__ resid) {
+    __shared__ double s_lp[2 * HELIOS_MAX_LAYERS + 1];
+    __shared__ double s_red[kRadeqThreads / 64];
+    __shared__ int s_bad[kRadeqThreads / 64];
     const int a = blockIdx.x;
     const int n = atm.n_layer[a];
     const int npt = 2 * n + 1;
@@ -293,6 +314,7 @@ __global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double
     int32_t* ha = hist + atm.lay_off[a];
     const double sig = sigma_sb();
     const double ti2 = atm.T_int[a] * atm.T_int[a];
+    for (int p = threadIdx.x; p < npt; p += blockDim.x) s_lp[p] = log(P[p]);
     // convergence measure (eq:condition), on the fluxes handed in
     double worst = 0.0;
     int nonfinite = 0;
@@ -305,18 +327,21 @@ __global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double
         double r = fabs(dF) / norm;
         worst = fmax(worst, r);
     }
-    red[threadIdx.x] = worst;
-    bad[threadIdx.x] = nonfinite;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
-            bad[threadIdx.x] |= bad[threadIdx.x + st];
-        }
-        __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        worst = fmax(worst, __shfl_xor(worst, off, 64));
+        nonfinite |= __shfl_xor(nonfinite, off, 64);
     }
-    worst = red[0];
-    nonfinite = bad[0];
+    if ((threadIdx.x & 63) == 0) {
+        s_red[threadIdx.x >> 6] = worst;
+        s_bad[threadIdx.x >> 6] = nonfinite;
+    }
+    __syncthreads();
+    worst = 0.0;
+    nonfinite = 0;
+    for (int w = 0; w < kRadeqThreads / 64; ++w) {
+        worst = fmax(worst, s_red[w]);
+        nonfinite |= s_bad[w];
+    }
     if (threadIdx.x == 0 && resid) resid[a] = nonfinite ? __longlong_as_double(0x7ff8000000000000LL) : worst;
     if (nonfinite) {
         if (threadIdx.x == 0) status[a] = HELIOS_ATM_NUMERIC;
@@ -345,7 +370,7 @@ __global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double
         }
         double dT = 0.0;
         if (dF != 0.0) {
-            double lnR = log(P[2 * i] / P[2 * i + 2]);
+            double lnR = s_lp[2 * i] - s_lp[2 * i + 2];
             double mag = pow(fabs(dF), 1.0 - o.fpre_p) * o.fpre_c * ma[i] / (sig * T * T * T * lnR);
             dT = (dF > 0.0) ? -mag : mag;
         }
@@ -363,15 +388,26 @@ __global__ void __launch_bounds__(256) radeq_kernel(helios_atm atm, const double
         Tc[i] = (Tn > o.T_floor) ? Tn : o.T_floor;
     }
     __syncthreads();
-    // re-interpolate the point temperatures of this atmosphere
+    // re-interpolate the point temperatures of this atmosphere (linear in log P)
     double* Tp = T_pt + atm.pt_off[a];
-    for (int p = threadIdx.x; p < npt; p += blockDim.x) Tp[p] = interface_T(P, Tc, n, p);
+    for (int p = threadIdx.x; p < npt; p += blockDim.x) {
+        const int i = p >> 1;
+        double T;
+        if (p & 1) T = Tc[i];
+        else if (i == 0) T = Tc[0];
+        else if (i == n) T = Tc[n - 1];
+        else {
+            const double f = (s_lp[p] - s_lp[p - 1]) / (s_lp[p + 1] - s_lp[p - 1]);
+            T = Tc[i - 1] + f * (Tc[i] - Tc[i - 1]);
+        }
+        Tp[p] = T;
+    }
 }
 
 hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
                         const helios_re_state* st, const helios_re_opts& o, int32_t* status,
                         double* resid, int /*n_max*/, hipStream_t s) {
-    hipLaunchKernelGGL(radeq_kernel, dim3(atm->n_atm), dim3(256), 0, s, *atm, F_bol, T_c, T_pt, st->m,
+    hipLaunchKernelGGL(radeq_kernel, dim3(atm->n_atm), dim3(kRadeqThreads), 0, s, *atm, F_bol, T_c, T_pt, st->m,
                        st->hist, st->iter, o, status, resid);
     return hipGetLastError();
 }

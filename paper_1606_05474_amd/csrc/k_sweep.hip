@@ -64,39 +64,8 @@ template <typename R>
 struct Prec;
 template <>
 struct Prec<double> {
-    // T = exp(-x) and om = 1 - T for x >= 0.  Cody-Waite reduction
-    // x = n ln2 + s' with |s'| <= ln2/2 (ln2 carried in two parts), the Taylor
-    // series of expm1 to degree 13 on the reduced argument (truncation below
-    // 5e-18) and scaling by 2^-n.  For n = 0 the polynomial gives om directly,
-    // so om keeps full relative accuracy for thin layers; for n >= 1, T <= 0.71
-    // and 1 - T is free of cancellation.  Arguments beyond 1000 (T = 0 in
-    // FP64) are clamped, which keeps n in integer range.
-    __device__ static inline void t_om(double x, double& T, double& om) {
-        constexpr double ln2_hi = 0.6931471805599453;      // ln 2 rounded to double
-        constexpr double ln2_lo = 2.3190468138462996e-17;  // ln 2 - ln2_hi
-        constexpr double inv_ln2 = 1.4426950408889634;
-        x = fmin(x, 1000.0);
-        const double n = rint(x * inv_ln2);
-        double r = fma(-n, ln2_hi, x);
-        r = fma(-n, ln2_lo, r);
-        const double s = -r;  // exp(-x) = 2^-n exp(s)
-        double p = 1.0 / 6227020800.0;  // 1/13!
-        p = fma(p, s, 1.0 / 479001600.0);
-        p = fma(p, s, 1.0 / 39916800.0);
-        p = fma(p, s, 1.0 / 3628800.0);
-        p = fma(p, s, 1.0 / 362880.0);
-        p = fma(p, s, 1.0 / 40320.0);
-        p = fma(p, s, 1.0 / 5040.0);
-        p = fma(p, s, 1.0 / 720.0);
-        p = fma(p, s, 1.0 / 120.0);
-        p = fma(p, s, 1.0 / 24.0);
-        p = fma(p, s, 1.0 / 6.0);
-        p = fma(p, s, 0.5);
-        p = fma(p, s, 1.0);
-        const double q = p * s;  // expm1(s)
-        T = ldexp(1.0 + q, -(int)n);
-        om = (n == 0.0) ? -q : 1.0 - T;
-    }
+    // T = exp(-x) and om = 1 - T (om accurate for thin layers)
+    __device__ static inline void t_om(double x, double& T, double& om) { exp_neg_om(x, T, om); }
     // reciprocal: hardware estimate refined by two Newton steps (the
     // arguments here are well scaled: no denormals, no overflow)
     __device__ static inline double rcp(double v) {
@@ -410,7 +379,18 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const double higrav = 0.5 / A.grav[at];
         // TOA value of the downward deviation, formed in FP64
         const R Ftop = (R)(A.F_top[A.bin_off[at] + l] - (2.0 * kPi / A.D) * B_all[pb + nsub]);
-        const R Fint = (R)A.F_int[A.bin_off[at] + l];
+        // BOA flux: pi B(T_int) scaled so that its width-weighted sum over the
+        // atmosphere's bins is sigma T_int^4 (chunk sums added in order)
+        R Fint;
+        {
+            const int nbch = (int)((A.bin_off[at + 1] - A.bin_off[at] + kBndChunk - 1) / kBndChunk);
+            const double* bp = A.bnd_part + (int64_t)at * A.bnd_maxch;
+            double sum = 0.0;
+            for (int c = 0; c < nbch; ++c) sum += bp[c];
+            const double t2 = A.T_int[at] * A.T_int[at];
+            const double scale = (sum > 0.0) ? sigma_sb() * t2 * t2 / sum : 0.0;
+            Fint = (R)(A.F_int[A.bin_off[at] + l] * scale);
+        }
 
         // ---- the bin's per-sublayer and per-layer inputs, staged once for
         // all g, padded with the identity up to the shape's capacity.  All
