@@ -13,14 +13,17 @@
 // corners as soon as a cell is entered, so they are in flight while the
 // current cell's points are computed.  For a fixed point the threads read
 // consecutive (bin, g) entries of each corner row (coalesced).  A thread's
-// kMixPts results are one or two whole aligned 128-byte lines of its column
-// (the column stride is padded to a multiple of kMixPts) and are written
-// with vector stores.
+// kMixPts = 16 results are an aligned 64-byte (FP32) or 128-byte (FP64)
+// piece of its column (the column stride is padded to a multiple of 32
+// points) and are written with vector stores, up to the last valid point.
 #include "helios_internal.hpp"
 
 namespace helios {
 
-constexpr int kMixPts = HELIOS_CELL_ALIGN;
+// points per workgroup (a divisor of the column stride's 32-point alignment;
+// 16 keeps a thread's results in few registers and gives many workgroups)
+template <typename R>
+constexpr int mix_pts() { return 16; }
 constexpr int kMixCols = 256;
 
 struct MixArgs {
@@ -32,7 +35,7 @@ struct MixArgs {
     void* kappa;
     int64_t total_pt;
     int32_t mode, n_species, nT, nP, nbt, ng;
-    int32_t max_chunks;  // chunks of kMixPts points per atmosphere (largest)
+    int32_t max_chunks;  // chunks of mix_pts<R>() points per atmosphere (largest)
     double T_min, T_step, logP_min, logP_step;
     double p_exp, t_exp, P_ref, T_ref;
     double mratio[HELIOS_MAX_SPECIES];  // m_j / mbar
@@ -53,6 +56,7 @@ struct Vec2<double> {
 
 template <typename R, int NSP>
 __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
+    constexpr int kMixPts = mix_pts<R>();
     __shared__ int s_cell[kMixPts];
     __shared__ int s_next[kMixPts];  // at the first point of a run of equal cells: the next run's cell, or -1
     __shared__ R s_w[kMixPts][4];    // bilinear corner weights or power-law scale
@@ -110,6 +114,7 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
     const size_t row = (size_t)A.nbt * A.ng;  // one (species, T, P) corner row
     const size_t off = (size_t)bt * A.ng + g;
     float kc[NSP][4], kn[NSP][4];  // corners of the current cell and of the next one (in flight)
+    R kr[sizeof(R) == 8 ? NSP : 1][4];  // FP64: the current cell's corners converted once per run
     auto load_cell = [&](float (&dst)[NSP][4], int cell) {
 #pragma unroll
         for (int sp = 0; sp < NSP; ++sp) {
@@ -138,13 +143,24 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
 #pragma unroll
                             for (int q = 0; q < 4; ++q) kc[sp][q] = kn[sp][q];
                     }
+                    if constexpr (sizeof(R) == 8) {
+#pragma unroll
+                        for (int sp = 0; sp < NSP; ++sp)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) kr[sp][q] = (R)kc[sp][q];  // once per run
+                    }
                     if (nx >= 0) load_cell(kn, nx);  // the following run's corners
                 }
                 const R w00 = s_w[j][0], w01 = s_w[j][1], w10 = s_w[j][2], w11 = s_w[j][3];
+                if constexpr (sizeof(R) == 8) {
 #pragma unroll
-                for (int sp = 0; sp < NSP; ++sp)
-                    acc += s_x[j][sp] * (w00 * (R)kc[sp][0] + w01 * (R)kc[sp][1] + w10 * (R)kc[sp][2] +
-                                         w11 * (R)kc[sp][3]);
+                    for (int sp = 0; sp < NSP; ++sp)
+                        acc += s_x[j][sp] * (w00 * kr[sp][0] + w01 * kr[sp][1] + w10 * kr[sp][2] + w11 * kr[sp][3]);
+                } else {
+#pragma unroll
+                    for (int sp = 0; sp < NSP; ++sp)
+                        acc += s_x[j][sp] * (w00 * kc[sp][0] + w01 * kc[sp][1] + w10 * kc[sp][2] + w11 * kc[sp][3]);
+                }
             } else {
                 if (cur < 0) {
                     cur = 0;
@@ -162,12 +178,13 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
     using V = typename Vec2<R>::type;
     constexpr int per = Vec2<R>::per;
     V* dst = reinterpret_cast<V*>(static_cast<R*>(A.kappa) + A.atm.cell_off[a] + (int64_t)c * col_stride(n) + p0);
+    // whole vectors covering the valid points (column padding past them is not written)
 #pragma unroll
     for (int v = 0; v < kMixPts / per; ++v) {
         V w;
         if constexpr (per == 4) w = V{vals[4 * v], vals[4 * v + 1], vals[4 * v + 2], vals[4 * v + 3]};
         else w = V{vals[2 * v], vals[2 * v + 1]};
-        dst[v] = w;
+        if (per * v < npts) dst[v] = w;
     }
 }
 
@@ -201,7 +218,7 @@ hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double
     int max_cols = 0, max_chunks = 1;
     for (int a = 0; a < atm->n_atm; ++a) {
         max_cols = max(max_cols, n_bin_h[a] * kt->n_g);
-        max_chunks = max(max_chunks, col_stride(n_layer_h[a]) / kMixPts);
+        max_chunks = max(max_chunks, col_stride(n_layer_h[a]) / (mixed ? mix_pts<float>() : mix_pts<double>()));
     }
     A.max_chunks = max_chunks;
     dim3 grid((unsigned)(atm->n_atm * max_chunks), (unsigned)((max_cols + kMixCols - 1) / kMixCols));
