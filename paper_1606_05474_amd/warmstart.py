@@ -160,7 +160,7 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
 def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 256,
                n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 1000,
                check_every: int = 10, deadband: int = 1, polish_iter: int = 600, m0: float = 0.3, keep_T: int = 0,
-               log=print):
+               tol: float = 1e-3, log=print):
     """The production form: atmospheres start..start+count-1 of a parameter
     set solved in chunks of `chunk` atmospheres, each chunk one batch on the
     device (size-class sweeps, graph replay, finished atmospheres skipped):
@@ -174,13 +174,15 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
        last finite temperatures (else the isothermal start) for up to
        `polish_iter` updates, as a batch of their own.
 
-    The convergence test is the same as the plain form's throughout.  The
-    timed region of a chunk starts with its inputs resident on the device and
-    covers all three stages.  Returns totals and the converged profiles of the
+    The convergence test is the plain form's, with tolerance `tol` (the
+    plain form's 1e-3 by default; a smaller value makes the reduced-precision
+    stages stop where the FP64 fluxes also meet 1e-3).  The timed region of a
+    chunk starts with its inputs resident on the device and covers all three
+    stages.  Returns totals and the converged profiles of the
     first `keep_T` atmospheres."""
     kt = W.table_ktab(2, nbt=3000)
     ktd = H.KTable(kt)
-    opts = H.REOptions(deadband=deadband)
+    opts = H.REOptions(deadband=deadband, tol=tol)
     out = {"count": 0, "converged": 0, "seconds": 0.0, "updates": [], "fallbacks": 0, "restarts": 0,
            "polished": 0, "T": [], "conv_flags": []}
     for c0 in range(start, start + count, chunk):
@@ -336,6 +338,44 @@ def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int 
     log(f"plain: {out['converged']}/{count} converged in {out['seconds']:.1f} s, median updates "
         f"{np.median(out['updates']):.0f}")
     return out
+
+
+def fp64_residual(T_list, seed: int = 5, start: int = 0, n: int = 200, nb: int = 3000, n_flux: int = 40,
+                  tol: float = 1e-3):
+    """Convergence measure of given layer temperatures under the FP64 path:
+    the opacities are mixed once, the flux solve is repeated n_flux times on
+    the fixed profile (its scattering passes start from the previous call's
+    upward fluxes, so they converge), then the RE step's test is evaluated.
+    Returns max_i |dF_i| / sigma T_int^4 per atmosphere (numpy)."""
+    kt = W.table_ktab(2, nbt=3000)
+    ktd = H.KTable(kt)
+    atms, _ = W.learned_workload(seed, len(T_list), start, n=n, nb=nb, ktab=kt)
+    b = H.Batch(atms)
+    s = H.Solver(b, ktd, prec=H.FP64, opts=H.REOptions(tol=tol))
+    s.reset(np.concatenate([np.asarray(T, np.float64) for T in T_list]))
+    H.mix_opacity(b, ktd, s.T_pt, s.kappa, H.FP64)
+    for _ in range(n_flux):
+        H.flux(b, s.kappa, s.T_pt, s.F_up_g, s.F_up_bin, s.F_dn_bin, s.F_bol, s.ws, n_scat=s.n_scat, D=s.D,
+               prec=H.FP64)
+    H.radeq(b, s.F_bol, s.T_c, s.T_pt, s.m, s.hist, s.status, s.resid, s.opts, iters=s.iters)
+    return s.resid.cpu().numpy().copy()
+
+
+def same_start_fp64(net: H.MLP, seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int = 3000,
+                    max_iter: int = 1500, restart_after: int = 1000, deadband: int = 1, m0: float = 0.3):
+    """The production schedule (network start, dead band, compaction,
+    isothermal restart of stragglers) entirely in FP64: the reference that
+    isolates the effect of the reduced precision.  Returns (converged flags,
+    layer temperatures per atmosphere)."""
+    kt = W.table_ktab(2, nbt=3000)
+    ktd = H.KTable(kt)
+    atms, _ = W.learned_workload(seed, count, start, n=n, nb=nb, ktab=kt)
+    b = H.Batch(atms)
+    s = H.Solver(b, ktd, prec=H.FP64, opts=H.REOptions(deadband=deadband))
+    x = np.stack([a["params"] for a in atms])
+    s.warm_reset(net, x, net.logP, m0=m0)
+    conv, _, _, T_list, _, _ = _run_compacting(s, max_iter, 10, restart_after)
+    return conv, T_list
 
 
 def main(argv=None):
