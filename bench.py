@@ -43,7 +43,8 @@ def sweep_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
     the points, the upward-flux warm start in (the TOA point is never read)
     and out, the Planck values per (bin, point) (float64 in both precisions),
     w0 and g0 per (bin, layer), the two boundary fluxes and the Gauss
-    weights, and the two Gauss-summed per-bin outputs (float64)."""
+    weights, and the two Gauss-summed partials per (bin, point) (in the
+    sweep's precision)."""
     npt = 2 * n + 1
     per_bin = (ng * npt * rbytes            # kappa
                + ng * (npt - 1) * rbytes    # F_up warm start in
@@ -51,7 +52,7 @@ def sweep_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
                + npt * 8                    # B
                + 2 * n * 8                  # w0, g0
                + 2 * 8                      # F_top, F_int
-               + 2 * npt * 8)               # F_up_bin, F_dn_bin
+               + 2 * npt * rbytes)          # Gauss partials, up and down
     return nb * per_bin + ng * 8
 
 
@@ -217,7 +218,7 @@ def chunk_main(args):
 
     atms, kt = W.learned_workload(5, args.n_atm, 0, n=200, nb=3000)
     b = H.Batch(atms)
-    s = H.Solver(b, H.KTable(kt), prec=H.MIXED, opts=H.REOptions(deadband=1))
+    s = H.Solver(b, H.KTable(kt), prec=H.MIXED, opts=H.REOptions(deadband=1), bin_fluxes=False)
     x = np.stack([a["params"] for a in atms])
     s.reset(np.concatenate([a["T0"] for a in atms]))
     s.autotune()

@@ -184,7 +184,8 @@ size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec);
  *   D         diffusivity factor (paper: 2)
  *   F_up_g    cell array, in: warm start, out: upward fluxes of the last pass
  *   F_dn_g    cell array, out: downward fluxes of the last pass (may be NULL)
- *   F_up_bin, F_dn_bin  [bin x point] double, Gauss-summed fluxes
+ *   F_up_bin, F_dn_bin  [bin x point] double, Gauss-summed fluxes; either may
+ *             be NULL (not written: the iteration itself needs only F_bol)
  *   F_bol     [sum npt][3] double: bolometric up, down, and net = up - down
  *             (the net flux is summed from the deviations below, in which
  *             the Planck term cancels, not by subtracting the two totals)

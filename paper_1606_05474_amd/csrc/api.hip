@@ -545,7 +545,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     FluxPlan p;
     int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p);
     if (rc) return rc;
-    if (!F_up_bin || !F_dn_bin || !F_bol) return fail(HELIOS_EINVAL, "helios_flux: NULL argument");
+    if (!F_bol) return fail(HELIOS_EINVAL, "helios_flux: NULL argument");
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)ws;
     hipError_t e = launch_sources(atm, p, T_pt, wsb, s);

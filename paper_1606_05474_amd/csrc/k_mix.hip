@@ -23,7 +23,7 @@ namespace helios {
 // points per workgroup (a divisor of the column stride's 32-point alignment;
 // 16 keeps a thread's results in few registers and gives many workgroups)
 template <typename R>
-constexpr int mix_pts() { return 16; }
+constexpr int mix_pts() { return sizeof(R) == 4 ? 32 : 16; }
 constexpr int kMixCols = 256;
 
 struct MixArgs {

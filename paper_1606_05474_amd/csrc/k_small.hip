@@ -133,7 +133,7 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
 // 1024 threads = 64 points x 16 groups of kBolChunk/16 bins.  Each thread
 // combines the sweep's per-wave Gauss partials of a bin (fixed order) -- sums
 // of deviations G = F - 2 pi eps B -- adds 2 pi eps B times the sum of the
-// weights to form F_up_bin / F_dn_bin, writes them, and accumulates dlambda
+// weights to form F_up_bin / F_dn_bin, writes them (when asked for), and accumulates dlambda
 // times the up, down and net (up - down, from the deviations, where B
 // cancels) fluxes in Neumaier sums; the group sums are combined in order and
 // stored per (chunk, quantity, point) (so both stages access them
@@ -196,8 +196,8 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
                 const int64_t o = pb + (int64_t)l * npt + p;
                 const double bw = tw * A.B[o];
                 const double fu = bw + gu, fd = bw + gd;
-                A.F_up_bin[o] = fu;
-                A.F_dn_bin[o] = fd;
+                if (A.F_up_bin) A.F_up_bin[o] = fu;
+                if (A.F_dn_bin) A.F_dn_bin[o] = fd;
                 nadd(au, dl[l] * fu);
                 nadd(ad, dl[l] * fd);
                 nadd(an, dl[l] * (gu - gd));

@@ -541,17 +541,19 @@ class Solver:
     and replays it, so a block of iterations costs one launch from the host.
     """
 
-    def __init__(self, b: Batch, kt: KTable, prec=FP64, n_scat=4, D=2.0, opts: REOptions | None = None):
+    def __init__(self, b: Batch, kt: KTable, prec=FP64, n_scat=4, D=2.0, opts: REOptions | None = None,
+                 bin_fluxes: bool = True):
         dev = b.device
         rd = rdtype(prec)
         self.kt, self.prec, self.n_scat, self.D = kt, prec, n_scat, D
+        self.bin_fluxes = bin_fluxes  # keep the per-bin fluxes of every step (the iteration needs only F_bol)
         self.opts = opts or REOptions()
         self.T_c = torch.zeros(b.total_n, dtype=torch.float64, device=dev)
         self.T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device=dev)
         self.kappa = torch.zeros(b.total_cell, dtype=rd, device=dev)
         self.F_up_g = torch.zeros(b.total_cell, dtype=rd, device=dev)
-        self.F_up_bin = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
-        self.F_dn_bin = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
+        self.F_up_bin = torch.zeros(b.total_pb, dtype=torch.float64, device=dev) if bin_fluxes else None
+        self.F_dn_bin = torch.zeros(b.total_pb, dtype=torch.float64, device=dev) if bin_fluxes else None
         self.F_bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device=dev)
         self.ws = torch.zeros(workspace_bytes(b, prec), dtype=torch.uint8, device=dev)
         self.m = torch.ones(b.total_n, dtype=torch.float64, device=dev)
@@ -622,7 +624,7 @@ class Solver:
         b0 = self.b
         nb = Batch([b0.atms[int(a)] for a in keep], device=b0.device)
         s = Solver(nb, self.kt, prec=self.prec if prec is None else prec, n_scat=self.n_scat, D=self.D,
-                   opts=self.opts)
+                   opts=self.opts, bin_fluxes=self.bin_fluxes)
         for k, a in enumerate(keep):
             a = int(a)
             ls, le = int(b0.lay_off[a]), int(b0.lay_off[a + 1])

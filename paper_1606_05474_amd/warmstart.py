@@ -189,7 +189,7 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         c = min(chunk, start + count - c0)
         atms, _ = W.learned_workload(seed, c, c0, n=n, nb=nb, ktab=kt)
         b = H.Batch(atms)
-        s = H.Solver(b, ktd, prec=H.MIXED, opts=opts)
+        s = H.Solver(b, ktd, prec=H.MIXED, opts=opts, bin_fluxes=False)
         x = np.stack([a["params"] for a in atms])
         T0 = np.concatenate([a["T0"] for a in atms])
         if c0 == start:  # one-time shape tuning for this process, outside the timed region
@@ -221,7 +221,7 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
                 del s2
             if fresh:
                 sub = H.Batch([atms[a] for a in fresh])
-                s3 = H.Solver(sub, ktd, prec=H.FP64, opts=opts)
+                s3 = H.Solver(sub, ktd, prec=H.FP64, opts=opts, bin_fluxes=False)
                 s3.reset(np.concatenate([atms[a]["T0"] for a in fresh]))
                 c3, it3, _, T3, _, _ = _run_compacting(s3, polish_iter, check_every, None)
                 for k, a in enumerate(fresh):

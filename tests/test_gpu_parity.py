@@ -219,6 +219,24 @@ def test_flux_without_downward_output_is_identical():
     assert torch.equal(a[0], c[0]) and torch.equal(a[4], c[4])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_flux_without_per_bin_outputs_is_identical(prec):
+    """NULL per-bin outputs skip only their stores: the bolometric fluxes and
+    the warm start are bitwise those of a call that writes them."""
+    atm, kt = W.plain_workload()
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
+    a = _gpu_flux(b, b.pack_cell([kap]), _t(T), prec)
+    rd = H.rdtype(prec)
+    F_up = torch.zeros(b.total_cell, dtype=rd, device="cuda")
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(H.workspace_bytes(b, prec), dtype=torch.uint8, device="cuda")
+    H.flux(b, b.pack_cell([kap]).to(rd), _t(T), F_up, None, None, bol, ws, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], F_up) and torch.equal(a[4], bol)
+
+
 def test_flux_mixed_precision_within_tolerance(small_table):
     lc, dl = W.bins(300)
     rng = np.random.default_rng(3)
