@@ -262,8 +262,9 @@ def chunk_main(args):
 
 
 def production_main(args):
-    """Converged atmospheres per second: the production form (batched chunks,
-    network warm start with isothermal fallback, mixed precision) against the
+    """Converged atmospheres per second: the production form (a refilled
+    device batch, network warm start with isothermal fallback, mixed
+    precision) against the
     plain form (FP64, one atmosphere at a time, isothermal start) on the same
     parameter set (seed 5: 200 layers x 3000 bins x 20 g), same tolerance."""
     import numpy as np
@@ -277,7 +278,7 @@ def production_main(args):
         return 2
     net = WS.load(args.weights)
     log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
-    prod = WS.production(net, seed=5, count=args.n_atm, chunk=args.chunk, max_iter=args.max_iter,
+    prod = WS.production(net, seed=5, count=args.n_atm, pool=args.chunk, max_iter=args.max_iter,
                          keep_T=args.plain_count, tol=args.prod_tol, log=log)
     base = WS.plain(seed=5, count=args.plain_count, max_iter=args.max_iter, keep_T=args.plain_count, log=log)
     both = [k for k in range(args.plain_count) if base["conv_flags"][k] and prod["conv_flags"][k]]
@@ -286,7 +287,7 @@ def production_main(args):
     # under the FP64 convergence test, and against the same schedule in FP64
     resid = WS.fp64_residual(prod["T"], seed=5)
     ok = [k for k in range(len(prod["T"])) if prod["conv_flags"][k]]
-    c64, T64 = WS.same_start_fp64(net, seed=5, count=len(prod["T"]), max_iter=args.max_iter)
+    c64, T64 = WS.same_start_fp64(net, seed=5, count=len(prod["T"]), max_iter=args.max_iter, tol=args.prod_tol)
     both64 = [k for k in ok if c64[k]]
     dT64 = [float(np.abs(prod["T"][k] - T64[k]).max()) for k in both64]
     log(f"FP64 test of the production profiles: max resid {max(resid[ok]):.3g} (tol 1e-3); "
@@ -301,14 +302,18 @@ def production_main(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.n_atm} parameter-described atmospheres (seed 5), 200 layers x 3000 bins x "
-                               f"20 g, chunks of {args.chunk}, mixed precision with dead band then FP64 polish, "
-                               "network warm start with isothermal fallback and isothermal restart after 1000 updates, first step multipliers 0.3; plain "
-                               "form: FP64, one atmosphere at a time, isothermal start, every layer stepped; "
-                               "tolerance 1e-3 sigma T_int^4 for both",
-                   "n_atm": args.n_atm, "chunk": args.chunk},
+                               f"20 g, one device batch of {args.chunk} refilled as atmospheres finish, mixed "
+                               f"precision with dead band to tolerance {args.prod_tol:g}, network warm start with "
+                               "isothermal fallback, isothermal restart after 1000 updates, first step multipliers "
+                               f"0.3, {args.max_iter} updates at most; plain "
+                               "form: FP64, one atmosphere at a time, isothermal start, every layer stepped, "
+                               "tolerance 1e-3 sigma T_int^4; the production profiles are checked against the FP64 "
+                               "test at 1e-3 (fp64_convergence_test_of_production_profiles)",
+                   "n_atm": args.n_atm, "pool": args.chunk},
         "production": {"converged": prod["converged"], "count": prod["count"], "seconds": prod["seconds"],
                        "median_updates": float(np.median(prod["updates"])), "fallbacks": prod["fallbacks"],
                        "restarts": prod["restarts"], "fp64_polished": prod["polished"],
+                       "input_generation_s_not_timed": prod["input_generation_s"],
                        "layer_bin_g_per_s": float(prod["updates"].sum()) * units / prod["seconds"]},
         "plain_fp64_one_at_a_time": {"converged": base["converged"], "count": base["count"],
                                      "seconds": base["seconds"], "converged_per_s": base["converged_per_s"],
@@ -392,14 +397,15 @@ def main(argv=None):
                          "batch: the uneven 512-atmosphere batch, throughput and solve to convergence; "
                          "chunk: RE-iteration throughput of one production chunk; "
                          "production: converged atmospheres/s, batched + network + mixed against plain FP64")
-    ap.add_argument("--chunk", type=int, default=256, help="atmospheres per device batch (production)")
+    ap.add_argument("--chunk", type=int, default=256, help="atmospheres per device batch (production pool)")
     ap.add_argument("--plain-count", type=int, default=64, help="atmospheres solved by the plain form")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1606_05474_amd", "data", "warmstart_mlp.npz"),
                     help="trained warm-start network (production)")
     ap.add_argument("--n-atm", type=int, default=None,
                     help="atmospheres (batch: 512 by default, production: 4096)")
-    ap.add_argument("--prod-tol", type=float, default=1e-3,
-                    help="convergence tolerance of the production form (the plain form uses 1e-3)")
+    ap.add_argument("--prod-tol", type=float, default=7e-4,
+                    help="convergence tolerance of the production form's reduced-precision stages (the plain "
+                         "form uses 1e-3 in FP64; 7e-4 makes the production profiles pass the FP64 test at 1e-3)")
     ap.add_argument("--max-iter", type=int, default=None,
                     help="update cap (batch: 300; production: 1500 for both forms)")
     args = ap.parse_args(argv)

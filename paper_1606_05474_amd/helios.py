@@ -620,27 +620,43 @@ class Solver:
         set has shrunk, so later launches cover only live atmospheres, and to
         continue atmospheres in another precision (the per-g warm start holds
         deviations from the isothermal flux, which carry over unchanged)."""
-        keep = np.asarray(keep, np.int64)
-        b0 = self.b
-        nb = Batch([b0.atms[int(a)] for a in keep], device=b0.device)
-        s = Solver(nb, self.kt, prec=self.prec if prec is None else prec, n_scat=self.n_scat, D=self.D,
-                   opts=self.opts, bin_fluxes=self.bin_fluxes)
-        for k, a in enumerate(keep):
-            a = int(a)
-            ls, le = int(b0.lay_off[a]), int(b0.lay_off[a + 1])
-            ns = int(nb.lay_off[k])
-            s.T_c[ns:ns + le - ls] = self.T_c[ls:le]
-            s.m[ns:ns + le - ls] = self.m[ls:le]
-            s.hist[ns:ns + le - ls] = self.hist[ls:le]
-            cs, ce = int(b0.cell_off[a]), int(b0.cell_off[a + 1])
-            nc = int(nb.cell_off[k])
-            s.F_up_g[nc:nc + ce - cs] = self.F_up_g[cs:ce].to(s.F_up_g.dtype)
-        idx = torch.as_tensor(keep, device=b0.device)
-        s.iters.copy_(self.iters[idx])
-        s.resid.copy_(self.resid[idx])
-        if self._warm is not None:
-            s._warm = self._warm[keep]
-        s._T_iso = self._T_iso
+        return Solver.concat([(self, keep)], prec=prec)
+
+    @staticmethod
+    def concat(parts, prec=None):
+        """One solver over the listed atmospheres of several solvers (parts =
+        [(solver, indices), ...], in order), each continuing its iteration as
+        in `subset`.  The first part's tables and options are used; prec
+        defaults to the first part's."""
+        s0 = parts[0][0]
+        keeps = [np.asarray(k, np.int64) for _, k in parts]
+        dev = s0.b.device
+        nb = Batch([src.b.atms[int(a)] for (src, _), keep in zip(parts, keeps) for a in keep], device=dev)
+        s = Solver(nb, s0.kt, prec=s0.prec if prec is None else prec, n_scat=s0.n_scat, D=s0.D,
+                   opts=s0.opts, bin_fluxes=s0.bin_fluxes)
+        k = 0
+        warm = []
+        for (src, _), keep in zip(parts, keeps):
+            b0 = src.b
+            for a in keep:
+                a = int(a)
+                ls, le = int(b0.lay_off[a]), int(b0.lay_off[a + 1])
+                ns = int(nb.lay_off[k])
+                s.T_c[ns:ns + le - ls] = src.T_c[ls:le]
+                s.m[ns:ns + le - ls] = src.m[ls:le]
+                s.hist[ns:ns + le - ls] = src.hist[ls:le]
+                cs, ce = int(b0.cell_off[a]), int(b0.cell_off[a + 1])
+                nc = int(nb.cell_off[k])
+                s.F_up_g[nc:nc + ce - cs] = src.F_up_g[cs:ce].to(s.F_up_g.dtype)
+                k += 1
+            if keep.size:
+                idx = torch.as_tensor(keep, device=dev)
+                lo = k - keep.size
+                s.iters[lo:k] = src.iters[idx]
+                s.resid[lo:k] = src.resid[idx]
+            warm.append(src._warm[keep] if src._warm is not None else np.zeros(keep.size, bool))
+        s._warm = np.concatenate(warm) if any(src._warm is not None for src, _ in parts) else None
+        s._T_iso = s0._T_iso
         profile(s.b, s.T_c, s.T_pt)
         return s
 

@@ -157,97 +157,145 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
     return out
 
 
-def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, chunk: int = 256,
+def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, pool: int = 256,
                n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 1000,
-               check_every: int = 10, deadband: int = 1, polish_iter: int = 600, m0: float = 0.3, keep_T: int = 0,
-               tol: float = 1e-3, log=print):
+               check_every: int = 10, deadband: int = 1, polish_iter: int = 0, m0: float = 0.3, keep_T: int = 0,
+               tol: float = 7e-4, refill: float = 0.75, log=print):
     """The production form: atmospheres start..start+count-1 of a parameter
-    set solved in chunks of `chunk` atmospheres, each chunk one batch on the
-    device (size-class sweeps, graph replay, finished atmospheres skipped):
+    set solved by one device batch of up to `pool` atmospheres that is
+    refilled as atmospheres finish (size-class sweeps, graph replay of blocks
+    of `check_every` updates, finished atmospheres skipped):
 
-    1. start from the network (isothermal where its profile is unusable) or,
-       with net=None, isothermally;
-    2. iterate in mixed precision (FP32 sweeps, FP64 sums and update), with
-       the dead band on by default; a network-started atmosphere still
-       running after `restart_after` updates restarts isothermally;
-    3. atmospheres still running (or non-finite) continue in FP64 from their
-       last finite temperatures (else the isothermal start) for up to
-       `polish_iter` updates, as a batch of their own.
+    1. each atmosphere starts from the network (isothermal where its profile
+       is unusable) or, with net=None, isothermally;
+    2. it iterates in mixed precision (FP32 sweeps, FP64 sums and update),
+       with the dead band on by default; a network-started atmosphere still
+       running after `restart_after` updates restarts isothermally; one still
+       running after `max_iter` updates leaves the batch unconverged (or, with
+       polish_iter > 0, continues in FP64 from its full state for up to that
+       many updates, all such atmospheres as one batch at the end);
+    3. whenever at most a fraction `refill` of the batch is still running
+       (or no new atmospheres are left and at most half are), the running
+       ones move into a new batch (Solver.concat carries their state) together
+       with enough new atmospheres to fill the pool, so the device keeps
+       working on a full batch until the last atmospheres.
 
-    The convergence test is the plain form's, with tolerance `tol` (the
-    plain form's 1e-3 by default; a smaller value makes the reduced-precision
-    stages stop where the FP64 fluxes also meet 1e-3).  The timed region of a
-    chunk starts with its inputs resident on the device and covers all three
-    stages.  Returns totals and the converged profiles of the
-    first `keep_T` atmospheres."""
+    The convergence test is the plain form's, with tolerance `tol` (7e-4 by
+    default, so that the profiles also pass the FP64 test at the plain
+    form's 1e-3).  The timed region starts after the one-time shape tuning
+    and excludes the host-side generation of the inputs; it includes the
+    device batches' construction, the network inference and every update.
+    Returns totals and the converged profiles of the first `keep_T`
+    atmospheres."""
     kt = W.table_ktab(2, nbt=3000)
     ktd = H.KTable(kt)
     opts = H.REOptions(deadband=deadband, tol=tol)
-    out = {"count": 0, "converged": 0, "seconds": 0.0, "updates": [], "fallbacks": 0, "restarts": 0,
-           "polished": 0, "T": [], "conv_flags": []}
-    for c0 in range(start, start + count, chunk):
-        c = min(chunk, start + count - c0)
-        atms, _ = W.learned_workload(seed, c, c0, n=n, nb=nb, ktab=kt)
-        b = H.Batch(atms)
-        s = H.Solver(b, ktd, prec=H.MIXED, opts=opts, bin_fluxes=False)
-        x = np.stack([a["params"] for a in atms])
-        T0 = np.concatenate([a["T0"] for a in atms])
-        if c0 == start:  # one-time shape tuning for this process, outside the timed region
-            s.reset(T0)
-            s.autotune()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+    conv = np.zeros(count, bool)
+    its = np.zeros(count, np.int64)
+    restarted = np.zeros(count, bool)
+    T_out = [None] * count
+    gen = [0.0]
+    fallbacks = [0]
+    refills = [0]
+
+    def make(k0, k):
+        tg = time.perf_counter()
+        atms, _ = W.learned_workload(seed, k, start + k0, n=n, nb=nb, ktab=kt)
+        gen[0] += time.perf_counter() - tg
+        sv = H.Solver(H.Batch(atms), ktd, prec=H.MIXED, opts=opts, bin_fluxes=False)
         if net is not None:
-            fb = s.warm_reset(net, x, net.logP, m0=m0)
+            fb = sv.warm_reset(net, np.stack([a["params"] for a in atms]), net.logP, m0=m0)
         else:
-            s.reset(T0)
-            fb = np.zeros(c, np.int32)
-        conv, it, rs, T_list, s_last, live = _run_compacting(s, max_iter, check_every,
-                                                             restart_after if net is not None else None)
-        left = np.where(~conv)[0]
-        if left.size:
-            # continue the stragglers in FP64 from their full state (non-finite
-            # ones restart isothermally)
-            pos = {int(a): k for k, a in enumerate(live)}
-            st_last = s_last.status.cpu().numpy()
-            cont = [a for a in left if a in pos and st_last[pos[a]] == H.ATM_RUNNING]
-            fresh = [a for a in left if a not in cont]
-            if cont:
-                s2 = s_last.subset([pos[a] for a in cont], prec=H.FP64)
-                s2._warm = None
-                c2, it2, _, T2, _, _ = _run_compacting(s2, polish_iter, check_every, None)
-                for k, a in enumerate(cont):
-                    conv[a], it[a], T_list[a] = c2[k], it2[k], T2[k]
-                del s2
-            if fresh:
-                sub = H.Batch([atms[a] for a in fresh])
-                s3 = H.Solver(sub, ktd, prec=H.FP64, opts=opts, bin_fluxes=False)
-                s3.reset(np.concatenate([atms[a]["T0"] for a in fresh]))
-                c3, it3, _, T3, _, _ = _run_compacting(s3, polish_iter, check_every, None)
-                for k, a in enumerate(fresh):
-                    conv[a], it[a], T_list[a] = c3[k], it[a] + it3[k], T3[k]
-                del s3, sub
-        del s_last
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out["count"] += c
-        out["converged"] += int(conv.sum())
-        out["seconds"] += dt
-        out["updates"].append(it)
-        out["fallbacks"] += int(fb.sum())
-        out["restarts"] += int(rs.sum())
-        out["polished"] += int(left.size)
-        out["conv_flags"].append(conv)
-        need = keep_T - len(out["T"])
-        if need > 0:
-            out["T"] += T_list[:need]
-        log(f"chunk {c0}..{c0 + c - 1}: {int(conv.sum())}/{c} converged in {dt:.1f} s, median updates "
-            f"{np.median(it):.0f}, fallbacks {int(fb.sum())}, restarts {int(rs.sum())}, FP64 polish {left.size}")
-        del s, b
-        torch.cuda.empty_cache()
-    out["updates"] = np.concatenate(out["updates"])
-    out["conv_flags"] = np.concatenate(out["conv_flags"])
-    out["converged_per_s"] = out["converged"] / out["seconds"]
+            sv.reset(np.concatenate([a["T0"] for a in atms]))
+            fb = np.zeros(k, np.int32)
+        fallbacks[0] += int(fb.sum())
+        return sv
+
+    def harvest(sv, ids, which):
+        st = sv.status.cpu().numpy()
+        it = sv.iters.cpu().numpy()
+        Tc = sv.T_c.cpu().numpy()
+        for k in which:
+            a = int(ids[k])
+            conv[a] = st[k] == H.ATM_CONVERGED
+            its[a] = it[k]
+            T_out[a] = Tc[int(sv.b.lay_off[k]):int(sv.b.lay_off[k + 1])].copy()
+
+    first = min(pool, count)
+    s = make(0, first)
+    s.autotune()  # one-time shape tuning for this process, outside the timed region
+    del s
+    gen[0] = 0.0
+    fallbacks[0] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = make(0, first)
+    ids = np.arange(first)
+    nxt = first
+    rs_cur = np.zeros(first, bool)
+    over_parts = []  # (solver, indices, original ids) of atmospheres that reached max_iter
+    s.capture(check_every)
+    while True:
+        s.replay()
+        st = s.status.cpu().numpy()
+        it = s.iters.cpu().numpy()
+        if restart_after is not None and s._warm is not None:
+            late = np.where(s._warm & ~rs_cur & (st == H.ATM_RUNNING) & (it >= restart_after))[0]
+            if late.size:
+                s.restart(late, s._T_iso)
+                rs_cur[late] = True
+                restarted[ids[late]] = True
+                st = s.status.cpu().numpy()
+        over = (st == H.ATM_RUNNING) & (it >= max_iter)
+        running = (st == H.ATM_RUNNING) & ~over
+        nrun = int(running.sum())
+        if nrun == 0 and nxt >= count:
+            harvest(s, ids, range(len(ids)))
+            if over.any() and polish_iter > 0:
+                over_parts.append((s, np.where(over)[0], ids[over]))
+            break
+        left = count - nxt
+        if (left > 0 and nrun <= refill * len(ids)) or (left == 0 and nrun <= len(ids) // 2 and len(ids) > 8):
+            harvest(s, ids, np.where(~running)[0])
+            if over.any() and polish_iter > 0:
+                over_parts.append((s.subset(np.where(over)[0], prec=H.FP64), None, ids[over]))
+            keep = np.where(running)[0]
+            k_new = min(pool - keep.size, left)
+            parts = [(s, keep)] if keep.size else []
+            new_ids = np.arange(nxt, nxt + k_new)
+            if k_new > 0:
+                sn = make(nxt, k_new)
+                parts.append((sn, np.arange(k_new)))
+            s2 = H.Solver.concat(parts)
+            refills[0] += 1
+            rs_cur = np.concatenate([rs_cur[keep], np.zeros(k_new, bool)])
+            ids = np.concatenate([ids[keep], new_ids])
+            nxt += k_new
+            del parts, s
+            s = s2
+            s.capture(check_every)
+    polished = 0
+    if over_parts:
+        srcs = [(sv if idx is None else sv.subset(idx, prec=H.FP64)) for sv, idx, _ in over_parts]
+        oid = np.concatenate([o for _, _, o in over_parts])
+        s3 = H.Solver.concat([(sv, np.arange(sv.b.n_atm)) for sv in srcs], prec=H.FP64)
+        del srcs, over_parts
+        c3, it3, _, T3, _, _ = _run_compacting(s3, polish_iter, check_every, None)
+        for k, a in enumerate(oid):
+            conv[a], its[a], T_out[a] = c3[k], it3[k], T3[k]
+        polished = int(oid.size)
+        del s3
+    del s
+    torch.cuda.synchronize()
+    seconds = time.perf_counter() - t0 - gen[0]
+    torch.cuda.empty_cache()
+    out = {"count": count, "converged": int(conv.sum()), "seconds": seconds, "updates": its,
+           "fallbacks": fallbacks[0], "restarts": int(restarted.sum()), "polished": polished,
+           "T": T_out[:keep_T], "conv_flags": conv, "converged_per_s": float(conv.sum()) / seconds,
+           "input_generation_s": gen[0], "refills": refills[0]}
+    log(f"production: {out['converged']}/{count} converged in {seconds:.1f} s (inputs generated in "
+        f"{gen[0]:.1f} s, not timed), median updates {np.median(its):.0f}, fallbacks {fallbacks[0]}, "
+        f"restarts {out['restarts']}, FP64 polish {polished}, batch refills {refills[0]}")
     return out
 
 
@@ -362,7 +410,8 @@ def fp64_residual(T_list, seed: int = 5, start: int = 0, n: int = 200, nb: int =
 
 
 def same_start_fp64(net: H.MLP, seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int = 3000,
-                    max_iter: int = 1500, restart_after: int = 1000, deadband: int = 1, m0: float = 0.3):
+                    max_iter: int = 1500, restart_after: int = 1000, deadband: int = 1, m0: float = 0.3,
+                    tol: float = 7e-4):
     """The production schedule (network start, dead band, compaction,
     isothermal restart of stragglers) entirely in FP64: the reference that
     isolates the effect of the reduced precision.  Returns (converged flags,
@@ -371,7 +420,7 @@ def same_start_fp64(net: H.MLP, seed: int = 5, count: int = 64, start: int = 0, 
     ktd = H.KTable(kt)
     atms, _ = W.learned_workload(seed, count, start, n=n, nb=nb, ktab=kt)
     b = H.Batch(atms)
-    s = H.Solver(b, ktd, prec=H.FP64, opts=H.REOptions(deadband=deadband))
+    s = H.Solver(b, ktd, prec=H.FP64, opts=H.REOptions(deadband=deadband, tol=tol))
     x = np.stack([a["params"] for a in atms])
     s.warm_reset(net, x, net.logP, m0=m0)
     conv, _, _, T_list, _, _ = _run_compacting(s, max_iter, 10, restart_after)
