@@ -66,6 +66,8 @@ def _load():
         lib.ref_flux.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, i, d,
                                  P, P, P, P, P, i]
         lib.ref_flux.restype = i
+        lib.ref_flux_exact.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, P, P, P, i]
+        lib.ref_flux_exact.restype = i
         lib.ref_radeq.argtypes = [i, P, P, d, d, d, P, P, P, d, i, d, i, i, d, d, d, d, i, P]
         lib.ref_radeq.restype = i
         for name in ("ref_E1", "ref_exact_trans", "ref_exact_diffusivity"):
@@ -322,6 +324,33 @@ def exact_up(dtau, B1, B2, F1_up, iso=False) -> float:
 
 def exact_down(dtau, B1, B2, F2_dn, iso=False) -> float:
     return _load().ref_exact_down(float(dtau), float(B1), float(B2), float(F2_dn), int(bool(iso)))
+
+
+def flux_exact(atm: dict, kappa, T_pt, P_pt, n_threads: int = 0):
+    """Pure-absorption solve of one atmosphere with the exact layer relations
+    (Sec. 2.1.2; w0, g0 and D do not enter; one sweep each way).  Returns a
+    dict with F_up, F_dn [bin][g][pt], F_up_bin, F_dn_bin [bin][pt] and F_bol
+    [pt][3]."""
+    n = int(atm["n"])
+    npt = 2 * n + 1
+    lc, dl = _f64(atm["lambda_c"]), _f64(atm["dlambda"])
+    nb = lc.size
+    ng = int(atm["ng"])
+    _, gw = gauss_legendre(ng)
+    kappa = _f64(kappa)
+    assert kappa.shape == (nb, ng, npt)
+    T_pt, P_pt = _f64(T_pt), _f64(P_pt)
+    F_up = np.zeros((nb, ng, npt))
+    F_dn = np.zeros((nb, ng, npt))
+    up_bin = np.zeros((nb, npt))
+    dn_bin = np.zeros((nb, npt))
+    bol = np.zeros((npt, 3))
+    rc = _load().ref_flux_exact(n, nb, ng, _p(P_pt), float(atm["grav"]), _p(T_pt), _p(lc), _p(dl), _p(gw),
+                                float(atm["T_star"]), float(atm["T_irr"]), float(atm["T_int"]), _p(kappa),
+                                _p(F_up), _p(F_dn), _p(up_bin), _p(dn_bin), _p(bol), int(n_threads))
+    if rc != 0:
+        raise MemoryError("oracle exact flux failed")
+    return {"F_up": F_up, "F_dn": F_dn, "F_up_bin": up_bin, "F_dn_bin": dn_bin, "F_bol": bol}
 
 
 # ------------------------------------------------- direct column solution

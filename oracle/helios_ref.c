@@ -342,6 +342,34 @@ static void ref_acc_add(ref_acc* a, double v) {
 }
 
 
+/* Gaussian sum at the end of the propagation, then the bin sum. */
+static void ref_sums(int npt, int nb, int ng, const double* dlambda, const double* g_weight,
+                     const double* F_up, const double* F_dn,
+                     double* F_up_bin, double* F_dn_bin, double* F_bol) {
+    for (int l = 0; l < nb; ++l) {
+        for (int p = 0; p < npt; ++p) {
+            ref_acc au = {0.0, 0.0}, ad = {0.0, 0.0};
+            for (int g = 0; g < ng; ++g) {
+                size_t idx = ((size_t)l * ng + g) * npt + p;
+                ref_acc_add(&au, g_weight[g] * F_up[idx]);
+                ref_acc_add(&ad, g_weight[g] * F_dn[idx]);
+            }
+            F_up_bin[(size_t)l * npt + p] = au.s + au.c;
+            F_dn_bin[(size_t)l * npt + p] = ad.s + ad.c;
+        }
+    }
+    for (int p = 0; p < npt; ++p) {
+        ref_acc au = {0.0, 0.0}, ad = {0.0, 0.0};
+        for (int l = 0; l < nb; ++l) {
+            ref_acc_add(&au, dlambda[l] * F_up_bin[(size_t)l * npt + p]);
+            ref_acc_add(&ad, dlambda[l] * F_dn_bin[(size_t)l * npt + p]);
+        }
+        F_bol[3 * p + 0] = au.s + au.c;
+        F_bol[3 * p + 1] = ad.s + ad.c;
+        F_bol[3 * p + 2] = F_bol[3 * p + 0] - F_bol[3 * p + 1];
+    }
+}
+
 int ref_flux(int n, int nb, int ng,
              const double* P_pt, double grav, const double* T_pt,
              const double* lambda_c, const double* dlambda, const double* g_weight,
@@ -394,29 +422,7 @@ int ref_flux(int n, int nb, int ng,
             }
         }
     }
-    /* Gaussian sum at the end of the propagation, then the bin sum. */
-    for (int l = 0; l < nb; ++l) {
-        for (int p = 0; p < npt; ++p) {
-            ref_acc au = {0.0, 0.0}, ad = {0.0, 0.0};
-            for (int g = 0; g < ng; ++g) {
-                size_t idx = ((size_t)l * ng + g) * npt + p;
-                ref_acc_add(&au, g_weight[g] * F_up[idx]);
-                ref_acc_add(&ad, g_weight[g] * dn_all[idx]);
-            }
-            F_up_bin[(size_t)l * npt + p] = au.s + au.c;
-            F_dn_bin[(size_t)l * npt + p] = ad.s + ad.c;
-        }
-    }
-    for (int p = 0; p < npt; ++p) {
-        ref_acc au = {0.0, 0.0}, ad = {0.0, 0.0};
-        for (int l = 0; l < nb; ++l) {
-            ref_acc_add(&au, dlambda[l] * F_up_bin[(size_t)l * npt + p]);
-            ref_acc_add(&ad, dlambda[l] * F_dn_bin[(size_t)l * npt + p]);
-        }
-        F_bol[3 * p + 0] = au.s + au.c;
-        F_bol[3 * p + 1] = ad.s + ad.c;
-        F_bol[3 * p + 2] = F_bol[3 * p + 0] - F_bol[3 * p + 1];
-    }
+    ref_sums(npt, nb, ng, dlambda, g_weight, F_up, dn_all, F_up_bin, F_dn_bin, F_bol);
     free(F_top); free(F_int); free(B); free(dm);
     if (!F_dn) free(dn_all);
     return 0;
@@ -544,8 +550,9 @@ double ref_E1(double x) {
     return exp(-x) / f;
 }
 
-/* eq:direct_trans */
+/* eq:direct_trans; at dtau = 0 its limit 1 (dtau^2 E1(dtau) -> 0) */
 double ref_exact_trans(double dtau) {
+    if (dtau == 0.0) return 1.0;
     return (1.0 - dtau) * exp(-dtau) + dtau * dtau * ref_E1(dtau);
 }
 
@@ -572,4 +579,67 @@ double ref_exact_down(double dtau, double B1, double B2, double F2_dn, int iso) 
     double Bp = (B1 - B2) / dtau;
     return T * F2_dn + REF_PI * B2 * (1.0 - T)
          + REF_PI * Bp * (-2.0 / 3.0 * (1.0 - exp(-dtau)) + dtau * (1.0 - T / 3.0));
+}
+
+/* Pure-absorption column solve with the exact layer relations (Sec. 2.1.2,
+ * eq:direct_trans, eq:isodirect, eq:nonisodirect), the check mode against
+ * which the diffusivity approximation is judged.  Same grid, boundary fluxes,
+ * opacities and sums as ref_flux; w0 and g0 do not enter and a single
+ * downward and upward sweep is exact (no scattering couples the streams).
+ * Sublayer s joins points s (lower, interface 1) and s+1 (upper, interface
+ * 2); a sublayer with dtau < 1e-4 uses eq:isodirect with the mean of its two
+ * Planck values (as the two-stream path does), others eq:nonisodirect. */
+int ref_flux_exact(int n, int nb, int ng,
+                   const double* P_pt, double grav, const double* T_pt,
+                   const double* lambda_c, const double* dlambda, const double* g_weight,
+                   double T_star, double T_irr, double T_int, const double* kappa,
+                   double* F_up, double* F_dn, double* F_up_bin, double* F_dn_bin, double* F_bol,
+                   int n_threads) {
+    const int npt = 2 * n + 1;
+    double* F_top = (double*)malloc(sizeof(double) * nb);
+    double* F_int = (double*)malloc(sizeof(double) * nb);
+    double* B = (double*)malloc(sizeof(double) * (size_t)nb * npt);
+    double* dm = (double*)malloc(sizeof(double) * 2 * n);
+    if (!F_top || !F_int || !B || !dm) {
+        free(F_top); free(F_int); free(B); free(dm);
+        return -1;
+    }
+    ref_boundary(nb, lambda_c, dlambda, T_star, T_irr, T_int, F_top, F_int);
+    for (int l = 0; l < nb; ++l)
+        for (int p = 0; p < npt; ++p) B[(size_t)l * npt + p] = ref_planck(lambda_c[l], T_pt[p]);
+    for (int s = 0; s < 2 * n; ++s) dm[s] = (P_pt[s] - P_pt[s + 1]) / grav;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int col = 0; col < nb * ng; ++col) {
+        const int l = col / ng;
+        const double* kap = kappa + (size_t)col * npt;
+        const double* Bl = B + (size_t)l * npt;
+        double* up = F_up + (size_t)col * npt;
+        double* dn = F_dn + (size_t)col * npt;
+        dn[2 * n] = F_top[l];
+        for (int s = 2 * n - 1; s >= 0; --s) {
+            double dtau = 0.5 * (kap[s] + kap[s + 1]) * dm[s];
+            if (dtau < 1e-4) {
+                double Bm = 0.5 * (Bl[s] + Bl[s + 1]);
+                dn[s] = ref_exact_down(dtau, Bm, Bm, dn[s + 1], 1);
+            } else {
+                dn[s] = ref_exact_down(dtau, Bl[s], Bl[s + 1], dn[s + 1], 0);
+            }
+        }
+        up[0] = dn[0] + F_int[l];
+        for (int s = 0; s < 2 * n; ++s) {
+            double dtau = 0.5 * (kap[s] + kap[s + 1]) * dm[s];
+            if (dtau < 1e-4) {
+                double Bm = 0.5 * (Bl[s] + Bl[s + 1]);
+                up[s + 1] = ref_exact_up(dtau, Bm, Bm, up[s], 1);
+            } else {
+                up[s + 1] = ref_exact_up(dtau, Bl[s], Bl[s + 1], up[s], 0);
+            }
+        }
+    }
+    ref_sums(npt, nb, ng, dlambda, g_weight, F_up, F_dn, F_up_bin, F_dn_bin, F_bol);
+    free(F_top); free(F_int); free(B); free(dm);
+    return 0;
 }

@@ -309,6 +309,75 @@ def test_isothermal_atmosphere_gives_pi_B_everywhere(ref):
     np.testing.assert_allclose(up, np.broadcast_to(piB[:, None, None], up.shape), rtol=1e-10)
 
 
+def test_exact_column_isothermal_gives_pi_B_everywhere(ref):
+    """Exact pure-absorption mode: a uniform-T column under the stellar flux
+    pi B(T) with no internal flux has F_up = F_dn = pi B at every point."""
+    atm = _small_atm()
+    P = ref.grid(atm["P_c"])
+    T = np.full(P.size, 900.0)
+    kap = _kappa(atm)  # spans dtau << 1e-4 (isothermal form) to dtau >> 1
+    piB = np.array([np.pi * ref.planck(l, 900.0) for l in atm["lambda_c"]])
+    out = ref.flux_exact(atm, kap, T, P)
+    np.testing.assert_allclose(out["F_up"], np.broadcast_to(piB[:, None, None], kap.shape), rtol=1e-13)
+    np.testing.assert_allclose(out["F_dn"], np.broadcast_to(piB[:, None, None], kap.shape), rtol=1e-13)
+
+
+def _planck_inverse(lam, B):
+    h, c, k = 6.62607015e-27, 2.99792458e10, 1.380649e-16
+    return h * c / (lam * k * np.log1p(2.0 * h * c * c / (lam ** 5 * B)))
+
+
+def test_exact_column_diffusion_limit(ref):
+    """Exact pure-absorption mode, every sublayer optically thick and the
+    Planck function linear in optical depth, B = B0 + b tau (tau from the
+    top): the formal solution gives F_up = pi (B + 2b/3) and
+    F_dn = pi (B - 2b/3) at every point below the top (radiative diffusion,
+    net flux 4 pi b / 3), independent of the boundary fluxes."""
+    atm = _small_atm(n=10, nb=1, ng=2)
+    P = ref.grid(atm["P_c"])
+    npt = P.size
+    dm = (P[:-1] - P[1:]) / atm["grav"]
+    # opacities with every sublayer at dtau >= 60
+    kp = np.empty(npt)
+    for p in range(npt):
+        nb_dm = [dm[s] for s in (p - 1, p) if 0 <= s < npt - 1]
+        kp[p] = 60.0 / min(nb_dm)
+    kap = np.broadcast_to(kp, (1, 2, npt)).copy()
+    dtau = 0.5 * (kp[:-1] + kp[1:]) * dm
+    tau = np.concatenate([np.cumsum(dtau[::-1])[::-1], [0.0]])  # from the top
+    lam = atm["lambda_c"][0]
+    B0 = ref.planck(lam, 800.0)
+    b = B0 / tau.max()
+    T = _planck_inverse(lam, B0 + b * tau)
+    atm["T_int"] = 300.0
+    out = ref.flux_exact(atm, kap, T, P)
+    B = np.array([ref.planck(lam, t) for t in T])
+    up, dn = out["F_up"][0], out["F_dn"][0]
+    scale = np.pi * B.max()
+    for g in range(2):
+        assert np.abs(up[g, 1:] - np.pi * (B[1:] + 2 * b / 3)).max() < 1e-12 * scale
+        assert np.abs(dn[g, :-1] - np.pi * (B[:-1] - 2 * b / 3)).max() < 1e-12 * scale
+    net = out["F_bol"][:-1, 2] / atm["dlambda"][0]
+    np.testing.assert_allclose(net[1:], 4 * np.pi * b / 3, rtol=1e-9)
+
+
+def test_exact_column_transparent_limit(ref):
+    """Exact pure-absorption mode with no opacity: the stellar flux reaches
+    the bottom unchanged and the upward flux is the reflected stellar flux
+    plus the internal flux at every point."""
+    atm = _small_atm()
+    atm["T_int"] = 400.0
+    atm["T_irr"] = 600.0
+    P = ref.grid(atm["P_c"])
+    T = np.linspace(1200.0, 700.0, P.size)
+    kap = np.zeros((len(atm["lambda_c"]), atm["ng"], P.size))
+    out = ref.flux_exact(atm, kap, T, P)
+    F_top, F_int = ref.boundary(atm["lambda_c"], atm["dlambda"], atm["T_star"], atm["T_irr"], atm["T_int"])
+    np.testing.assert_allclose(out["F_dn"], np.broadcast_to(F_top[:, None, None], kap.shape), rtol=1e-14)
+    np.testing.assert_allclose(out["F_up"], np.broadcast_to((F_top + F_int)[:, None, None], kap.shape),
+                               rtol=1e-14)
+
+
 def test_zero_albedo_one_pass_is_exact_and_warm_start_free(ref):
     atm = _small_atm()
     atm["w0"][:] = 0.0
