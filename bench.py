@@ -261,6 +261,70 @@ def chunk_main(args):
     return 0
 
 
+def exact_main(args):
+    """The exact pure-absorption mode (Sec. 2.1.2) on the single-atmosphere
+    spectral workload with w0 = 0: throughput of helios_flux_exact, and the
+    two-stream solve (one pass, exact for w0 = 0) for D in {1.66, 1.8, 1.9, 2}
+    against it (the diffusivity study of Sec. 2.1.1)."""
+    import numpy as np
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
+    kt = W.table_ktab(2)
+    atm, _ = W.spectral_workload(ktab=kt)
+    atm = dict(atm)
+    atm["w0"] = np.zeros_like(atm["w0"])
+    atm["g0"] = np.zeros_like(atm["g0"])
+    b = H.Batch([atm])
+    s = H.Solver(b, H.KTable(kt), prec=H.FP64)
+    s.reset(atm["T0"])
+    H.mix_opacity(b, s.kt, s.T_pt, s.kappa, H.FP64)
+    F_dn = torch.zeros_like(s.F_up_g)
+    bol_x = torch.zeros_like(s.F_bol)
+    ub = torch.zeros_like(s.F_up_bin)
+    db = torch.zeros_like(s.F_dn_bin)
+    for _ in range(args.warmup):
+        H.flux_exact(b, s.kappa, s.T_pt, s.F_up_g, F_dn, ub, db, bol_x, s.ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        H.flux_exact(b, s.kappa, s.T_pt, s.F_up_g, F_dn, ub, db, bol_x, s.ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
+    npt = 2 * n + 1
+    ex = bol_x.cpu().numpy().reshape(-1, 3)
+    study = {}
+    for D in (1.66, 1.8, 1.9, 2.0):
+        up = torch.zeros_like(s.F_up_g)
+        bol = torch.zeros_like(s.F_bol)
+        H.flux(b, s.kappa, s.T_pt, up, ub, db, bol, s.ws, n_scat=0, D=D, prec=H.FP64)
+        torch.cuda.synchronize()
+        ts = bol.cpu().numpy().reshape(-1, 3)
+        study[str(D)] = {"toa_up_rel": float(abs(ts[-1, 0] - ex[-1, 0]) / ex[-1, 0]),
+                         "max_up_rel": float(np.max(np.abs(ts[:, 0] - ex[:, 0]) / ex[:, 0])),
+                         "max_net_rel_gross": float(np.max(np.abs(ts[:, 2] - ex[:, 2]) / (ex[:, 0] + ex[:, 1])))}
+    # bytes the exact kernel must move: opacities in, both per-g streams out,
+    # Planck values, the Gauss partials
+    alg = nb * (ng * npt * 8 + 2 * ng * npt * 8 + npt * 8 + 2 * npt * 8)
+    line = {"metric": "layer*bin*g flux updates/s", "value": n * nb * ng / (ms * 1e-3), "unit": "layer*bin*g/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "exact pure-absorption mode: one atmosphere, 100 layers x 3000 bins x 20 g, "
+                                   "w0 = 0, one sweep each way (a step: one helios_flux_exact call)"},
+            "roofline": {"bound": "hbm", "kernel": "exact_kernel and the sums (whole call)",
+                         "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_launch": alg},
+            "diffusivity_study_vs_exact": study}
+    print(json.dumps(line))
+    return 0
+
+
 def production_main(args):
     """Converged atmospheres per second: the production form (a refilled
     device batch, network warm start with isothermal fallback, mixed
@@ -392,11 +456,12 @@ def main(argv=None):
                     help="precisions to run (profiling runs pick one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["spectral", "batch", "chunk", "production"], default="spectral",
+    ap.add_argument("--workload", choices=["spectral", "batch", "chunk", "production", "exact"], default="spectral",
                     help="spectral: one 100-layer x 3000-bin atmosphere (the headline line); "
                          "batch: the uneven 512-atmosphere batch, throughput and solve to convergence; "
                          "chunk: RE-iteration throughput of one production chunk; "
-                         "production: converged atmospheres/s, batched + network + mixed against plain FP64")
+                         "production: converged atmospheres/s, batched + network + mixed against plain FP64; "
+                         "exact: the exact pure-absorption mode and the diffusivity study")
     ap.add_argument("--chunk", type=int, default=256, help="atmospheres per device batch (production pool)")
     ap.add_argument("--plain-count", type=int, default=64, help="atmospheres solved by the plain form")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1606_05474_amd", "data", "warmstart_mlp.npz"),
@@ -445,6 +510,8 @@ def main(argv=None):
         return production_main(args)
     if args.workload == "chunk":
         return chunk_main(args)
+    if args.workload == "exact":
+        return exact_main(args)
     kt = W.table_ktab(2)
     atm, _ = W.spectral_workload(ktab=kt)
     fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt) if args.prec in ("both", "fp64") else None

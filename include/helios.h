@@ -204,6 +204,25 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
                 double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
                 helios_prec prec, void* stream);
 
+/* Pure-absorption flux solve with the exact layer relations (Sec. 2.1.2:
+ * transmission eq:direct_trans = 2 E3(dtau), sources eq:nonisodirect, and
+ * eq:isodirect with the mean of the sublayer's two Planck values where
+ * dtau < 1e-4), the check against which the two-stream diffusivity factor D
+ * is judged.  FP64 only.  Same grid, opacities (double cell array), Planck
+ * values, boundary fluxes and sums as helios_flux; single-scattering albedo,
+ * asymmetry and D do not enter, and one downward and one upward sweep per
+ * (bin, g) column are exact (no scattering couples the streams).
+ *   F_up_g, F_dn_g  cell arrays, out: deviations from pi B at the points
+ *                   (pi B is the isothermal solution of this mode); no warm
+ *                   start is read
+ *   F_up_bin, F_dn_bin, F_bol  as for helios_flux (the per-bin arrays may be
+ *                   NULL)
+ *   ws        workspace of at least helios_workspace_bytes(atm, HELIOS_FP64)
+ * Errors: as helios_flux. */
+int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* T_pt, double* F_up_g,
+                      double* F_dn_g, double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws,
+                      size_t ws_bytes, void* stream);
+
 /* Temperature update (Sec. 2.2.3 eq:step, Sec. 2.2.4, eq:condition), always
  * FP64.  For each atmosphere whose status is not CONVERGED: resid = max over
  * layers of |dF_i| / norm_i with dF_i the net-flux difference across layer i

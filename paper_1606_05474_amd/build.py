@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhelios.so")
-SOURCES = ["api.hip", "k_small.hip", "k_mix.hip", "k_sweep.hip", "k_mlp.hip"]
+SOURCES = ["api.hip", "k_small.hip", "k_mix.hip", "k_sweep.hip", "k_exact.hip", "k_mlp.hip"]
 ARCH = "gfx950"
 
 

@@ -592,6 +592,54 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
     return HELIOS_OK;
 }
 
+int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* T_pt, double* F_up_g,
+                      double* F_dn_g, double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
+                      void* stream) {
+    FluxPlan p;
+    int rc = check_atm(atm, p.z);
+    if (rc) return rc;
+    if (!kappa || !T_pt || !F_up_g || !F_dn_g || !F_bol || !ws)
+        return fail(HELIOS_EINVAL, "helios_flux_exact: NULL argument");
+    p.mixed = false;
+    p.w = ws_layout(p.z, atm->n_g, false);
+    if (ws_bytes < p.w.total)
+        return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, p.w.total);
+    for (int k = 0; k < kNumClasses; ++k) p.sh[k] = {0, 0};
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    hipError_t e = launch_sources(atm, p, T_pt, wsb, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_flux_exact (sources)");
+    SweepArgs A = sweep_args(atm, p, kappa, nullptr, nullptr, 0, 2.0, F_up_g, F_dn_g, wsb);
+    A.w_begin = 0;
+    A.w_end = p.z.total_bin;
+    e = launch_exact(A, p.z.total_bin, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_flux_exact (sweep)");
+    BolArgs Bo;
+    Bo.atm = *atm;
+    Bo.part_up = A.part_up;
+    Bo.part_dn = A.part_dn;
+    Bo.F_up_bin = F_up_bin;
+    Bo.F_dn_bin = F_dn_bin;
+    Bo.chunk = (double*)(wsb + p.w.chunk);
+    Bo.total_pt = p.z.total_pt;
+    Bo.F_bol = F_bol;
+    Bo.B = (const double*)(wsb + p.w.B);
+    Bo.gw = (const double*)(wsb + p.w.gw);
+    Bo.tpe = kPi;  // the deviations are taken from pi B
+    Bo.wpb_stride = A.wpb_stride;
+    Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
+    Bo.mixed = 0;
+    Bo.n_cls = kNumClasses;
+    for (int k = 0; k < kNumClasses; ++k) {
+        Bo.cls_nhi[k] = kClassNHi[k];
+        Bo.cls_wpb[k] = 1;
+    }
+    e = launch_bolometric(Bo, p.z.npt_max, p.z.nb_max, p.z.total_pt, s);
+    if (e != hipSuccess) return hip_fail(e, "helios_flux_exact (bolometric)");
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
 int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                     const double* g0, int32_t n_scat, double D, void* F_up_g, void* ws, size_t ws_bytes,
                     helios_prec prec, void* stream) {

@@ -216,6 +216,7 @@ hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs& a, int K, int L, bool mixed, int grid, hipStream_t s);
+hipError_t launch_exact(const SweepArgs& a, int64_t n_bins, hipStream_t s);
 hipError_t launch_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,
                                const double* w0, const double* g0, double D, double* out,
                                int64_t total_sub, bool mixed, hipStream_t s);

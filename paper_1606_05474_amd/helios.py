@@ -88,6 +88,7 @@ def lib():
         L.helios_workspace_bytes.argtypes = [A, ctypes.c_int]
         L.helios_workspace_bytes.restype = sz
         L.helios_flux.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
+        L.helios_flux_exact.argtypes = [A, _P, _P, _P, _P, _P, _P, _P, _P, sz, _P]
         L.helios_radeq.argtypes = [A, _P, _P, _P, ctypes.POINTER(HeliosReState), ctypes.POINTER(HeliosReOpts),
                                    _P, _P, _P]
         L.helios_autotune.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, sz, ctypes.c_int, _P]
@@ -318,6 +319,14 @@ def sweep_shapes(b: Batch, prec=FP64):
 
 def workspace_bytes(b: Batch, prec=FP64) -> int:
     return int(lib().helios_workspace_bytes(ctypes.byref(b.desc), prec))
+
+
+def flux_exact(b: Batch, kappa, T_pt, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws, stream=None):
+    """helios_flux_exact: pure absorption with the exact layer relations
+    (FP64; the per-g outputs are deviations from pi B)."""
+    _check(lib().helios_flux_exact(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(F_up_g), _ptr(F_dn_g),
+                                   _ptr(F_up_bin), _ptr(F_dn_bin), _ptr(F_bol), _ptr(ws),
+                                   ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def flux(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, n_scat=4, D=2.0, F_dn_g=None,

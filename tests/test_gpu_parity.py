@@ -667,3 +667,65 @@ def test_post_processing_spectrum_with_80_passes():
     want = r["F_up_bin"][:, -1]
     assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
     assert col_rel_error(_np(per_bin[0]), r["F_up_bin"]).max() < 1e-11
+
+
+# ----------------------------------------------------- exact pure absorption
+def _exact_gpu(b, kap, T):
+    F_up = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+    F_dn = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+    ub = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    db = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(H.workspace_bytes(b, 0), dtype=torch.uint8, device="cuda")
+    H.flux_exact(b, kap, T, F_up, F_dn, ub, db, bol, ws)
+    torch.cuda.synchronize()
+    return F_up, F_dn, ub, db, bol
+
+
+@pytest.mark.parametrize("case", ["plain", "table", "transparent"])
+def test_flux_exact_matches_oracle(case, small_table):
+    """Exact pure-absorption mode (Sec. 2.1.2) against the oracle: per-g
+    fluxes, per-bin fluxes and the net flux (1e-10, as the FP64 two-stream
+    path), over isothermal-form, non-isothermal and transparent sublayers."""
+    if case == "plain":
+        atm, kt = W.plain_workload()
+    else:
+        kt = small_table
+        lc, dl = W.bins(300)
+        atm = W.spectral_atmosphere(np.random.default_rng(19), 61, lc, dl, 23)
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap = oracle_state(atm, kt, T_c)
+    if case == "transparent":  # some points without opacity: zero-depth sublayers
+        kap[:, :, 10:20] = 0.0
+        kap[:, :, -3:] = 0.0
+    r = ref.flux_exact(atm, kap, T, P)
+    F_up, F_dn, ub, db, bol = _exact_gpu(b, b.pack_cell([kap]), _t(T))
+    err_net = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[0], r["F_bol"])
+    assert err_net.max() < 1e-10, err_net.max()
+    iso = ref.isothermal_flux(atm, T)  # pi B for D = 2
+    assert col_rel_error(to_flux(b.split_cell(_np(F_up))[0], iso), r["F_up"]).max() < 1e-11
+    assert col_rel_error(to_flux(b.split_cell(_np(F_dn))[0], iso), r["F_dn"]).max() < 1e-11
+    assert col_rel_error(b.split_pb(_np(ub))[0], r["F_up_bin"]).max() < 1e-11
+    assert col_rel_error(b.split_pb(_np(db))[0], r["F_dn_bin"]).max() < 1e-11
+
+
+def test_flux_exact_ragged_batch_equals_single_atmospheres(small_table):
+    """A batch of uneven atmospheres gives each one's single-atmosphere result."""
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(23)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb) for n, nb in ((30, 7), (150, 3), (2, 5))]
+    b = H.Batch(atms)
+    H.grid(b)
+    Ts, kaps = [], []
+    for atm in atms:
+        P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
+        Ts.append(T)
+        kaps.append(kap)
+    out = _exact_gpu(b, b.pack_cell(kaps), _t(np.concatenate(Ts)))
+    bol = b.split_pt(_np(out[4]).reshape(-1, 3))
+    for a, atm in enumerate(atms):
+        P = ref.grid(atm["P_c"])
+        r = ref.flux_exact(atm, kaps[a], Ts[a], P)
+        assert net_flux_error(bol[a], r["F_bol"]).max() < 1e-10
