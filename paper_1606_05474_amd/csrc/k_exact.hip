@@ -30,8 +30,9 @@ __device__ inline double e1_d(double x) {
         double term = 1.0, sum = 0.0;
 #pragma unroll
         for (int k = 1; k <= 34; ++k) {
-            term *= -x / k;
-            sum -= term / k;
+            const double ik = 1.0 / (double)k;  // a compile-time constant per term
+            term *= -x * ik;
+            sum -= term * ik;
         }
         return -euler_gamma - log(x) + sum;
     }
@@ -100,13 +101,15 @@ __global__ void __launch_bounds__(64) exact_kernel(const SweepArgs A) {
                 const double T = exact_trans_d(dtau, om);
                 G = T * G - exact_sig(dtau, T, om, B[s] - B[s + 1]);
                 dn[s] = G;
+                up[s + 1] = T;  // kept for the upward sweep, which overwrites it after use
             }
             G += Fint;
             up[0] = G;
             for (int s = 0; s < nsub; ++s) {
                 const double dtau = 0.5 * (kap[s] + kap[s + 1]) * (P[s] - P[s + 1]) * igrav;
-                double om;
-                const double T = exact_trans_d(dtau, om);
+                double e, om;
+                exp_neg_om(dtau, e, om);
+                const double T = up[s + 1];
                 G = T * G + exact_sig(dtau, T, om, B[s] - B[s + 1]);
                 up[s + 1] = G;
             }
