@@ -343,7 +343,8 @@ def production_main(args):
     net = WS.load(args.weights)
     log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
     prod = WS.production(net, seed=5, count=args.n_atm, pool=args.chunk, max_iter=args.max_iter,
-                         keep_T=args.plain_count, tol=args.prod_tol, log=log)
+                         restart_after=args.restart_after or None, keep_T=args.plain_count, tol=args.prod_tol,
+                         log=log)
     base = WS.plain(seed=5, count=args.plain_count, max_iter=args.max_iter, keep_T=args.plain_count, log=log)
     both = [k for k in range(args.plain_count) if base["conv_flags"][k] and prod["conv_flags"][k]]
     dT = [float(np.abs(prod["T"][k] - base["T"][k]).max()) for k in both]
@@ -368,7 +369,8 @@ def production_main(args):
         "config": {"workload": f"{args.n_atm} parameter-described atmospheres (seed 5), 200 layers x 3000 bins x "
                                f"20 g, one device batch of {args.chunk} refilled as atmospheres finish, mixed "
                                f"precision with dead band to tolerance {args.prod_tol:g}, network warm start with "
-                               "isothermal fallback, isothermal restart after 1000 updates, first step multipliers "
+                               f"isothermal fallback, isothermal restart after {args.restart_after} updates "
+                               "(0: none), first step multipliers "
                                f"0.3, {args.max_iter} updates at most; plain "
                                "form: FP64, one atmosphere at a time, isothermal start, every layer stepped, "
                                "tolerance 1e-3 sigma T_int^4; the production profiles are checked against the FP64 "
@@ -468,16 +470,20 @@ def main(argv=None):
                     help="trained warm-start network (production)")
     ap.add_argument("--n-atm", type=int, default=None,
                     help="atmospheres (batch: 512 by default, production: 4096)")
+    ap.add_argument("--restart-after", type=int, default=1000,
+                    help="production: updates after which a network-started atmosphere restarts isothermally "
+                         "(0: never)")
     ap.add_argument("--prod-tol", type=float, default=7e-4,
                     help="convergence tolerance of the production form's reduced-precision stages (the plain "
                          "form uses 1e-3 in FP64; 7e-4 makes the production profiles pass the FP64 test at 1e-3)")
     ap.add_argument("--max-iter", type=int, default=None,
-                    help="update cap (batch: 300; production: 1500 for both forms)")
+                    help="update cap (batch: 300; production: 2000 for both forms)")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); the "
-              "per-GPU shard of this path is one independent set of atmospheres, see DESIGN.md",
+              "path shards by atmosphere (each GPU runs this library on its own atmospheres, with no "
+              "communication until the profiles are gathered), so one GPU's rate is the figure",
               file=sys.stderr)
         return 2
 
@@ -503,7 +509,7 @@ def main(argv=None):
     if args.n_atm is None:
         args.n_atm = {"production": 4096, "chunk": 128}.get(args.workload, 512)
     if args.max_iter is None:
-        args.max_iter = 1500 if args.workload == "production" else 300
+        args.max_iter = 2000 if args.workload == "production" else 300
     if args.workload == "batch":
         return batch_main(args)
     if args.workload == "production":
