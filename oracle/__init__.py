@@ -66,6 +66,9 @@ def _load():
         lib.ref_flux.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, i, d,
                                  P, P, P, P, P, i]
         lib.ref_flux.restype = i
+        lib.ref_flux_iso.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, i, d,
+                                     P, P, P, P, P, i]
+        lib.ref_flux_iso.restype = i
         lib.ref_flux_exact.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, P, P, P, i]
         lib.ref_flux_exact.restype = i
         lib.ref_radeq.argtypes = [i, P, P, d, d, d, P, P, P, d, i, d, i, i, d, d, d, d, i, P]
@@ -230,6 +233,40 @@ def flux(atm: dict, kappa, T_pt, P_pt, F_up, n_scat: int = 4, D: float = 2.0,
     return {"F_dn": F_dn, "F_up_bin": up_bin, "F_dn_bin": dn_bin, "F_bol": bol}
 
 
+def flux_iso(atm: dict, kappa_lay, T_lay, P_int, F_up, n_scat: int = 4, D: float = 2.0,
+             n_threads: int = 0, want_dn: bool = True):
+    """One flux solve on the isothermal-layer grid (Sec. 2.2.1): n layers
+    with temperatures T_lay [n] and opacities kappa_lay [bin][g][n] between
+    the n + 1 interfaces P_int.  ``F_up`` [bin][g][n+1] is the warm start and
+    is updated in place.  Returns F_dn (if wanted), F_up_bin, F_dn_bin
+    [bin][n+1] and F_bol [n+1][3] on the interfaces."""
+    n = int(atm["n"])
+    nif = n + 1
+    lc, dl = _f64(atm["lambda_c"]), _f64(atm["dlambda"])
+    nb = lc.size
+    ng = int(atm["ng"])
+    _, gw = gauss_legendre(ng)
+    kappa = _f64(kappa_lay)
+    assert kappa.shape == (nb, ng, n)
+    T_lay, P_int = _f64(T_lay), _f64(P_int)
+    assert T_lay.shape == (n,) and P_int.shape == (nif,)
+    w0, g0 = _f64(atm["w0"]), _f64(atm["g0"])
+    assert w0.shape == (nb, n) and g0.shape == (nb, n)
+    assert F_up.dtype == np.float64 and F_up.flags.c_contiguous and F_up.shape == (nb, ng, nif)
+    F_dn = np.zeros((nb, ng, nif)) if want_dn else None
+    up_bin = np.zeros((nb, nif))
+    dn_bin = np.zeros((nb, nif))
+    bol = np.zeros((nif, 3))
+    rc = _load().ref_flux_iso(n, nb, ng, _p(P_int), float(atm["grav"]), _p(T_lay), _p(lc), _p(dl), _p(gw),
+                              float(atm["T_star"]), float(atm["T_irr"]), float(atm["T_int"]),
+                              _p(kappa), _p(w0), _p(g0), int(n_scat), float(D),
+                              _p(F_up), _p(F_dn) if want_dn else None,
+                              _p(up_bin), _p(dn_bin), _p(bol), int(n_threads))
+    if rc != 0:
+        raise MemoryError("oracle isothermal-grid flux failed")
+    return {"F_dn": F_dn, "F_up_bin": up_bin, "F_dn_bin": dn_bin, "F_bol": bol}
+
+
 # ------------------------------------------------------------------ RE step
 RE_DEFAULTS = dict(tol=1e-3, norm_sigma_tint=1, T_floor=10.0, window=6, osc_any=0, shrink=0.67,
                    grow=1.1, fpre_c=1e5, fpre_p=0.9, deadband=0)
@@ -254,7 +291,8 @@ def radeq(atm: dict, P_pt, F_bol, T_c, m, hist, opts: dict | None = None):
 
 
 def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float = 2.0,
-          opts: dict | None = None, T_init=None, n_threads: int = 0, callback=None, warm: str = "flux"):
+          opts: dict | None = None, T_init=None, n_threads: int = 0, callback=None, warm: str = "flux",
+          layers: str = "noniso"):
     """Full RE iteration of one atmosphere (Sec. 2.2.3): profile -> opacity ->
     flux -> RE step, until converged or max_iter steps were taken.
 
@@ -264,9 +302,18 @@ def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float 
     isothermal flux (2 pi / D) B across iterations and starts from that flux;
     the choice of a warm start changes the trajectory, not the fixed point.
 
+    layers = "iso" solves on the isothermal-layer grid (Sec. 2.2.1): the
+    layers keep their centre temperatures and opacities, fluxes live on the
+    interfaces, and the RE step takes the same interface net fluxes (warm must
+    be "flux").
+
     Returns a dict with T_c, iterations, converged flag, resid history and the
     last flux result.
     """
+    if layers not in ("noniso", "iso"):
+        raise ValueError(layers)
+    if layers == "iso" and warm != "flux":
+        raise ValueError("the isothermal-layer grid takes the flux warm start")
     n = int(atm["n"])
     ng = int(atm["ng"])
     nb = len(atm["lambda_c"])
@@ -274,22 +321,31 @@ def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float 
     T_c = _f64(atm["T0"] if T_init is None else T_init).copy()
     m = np.ones(n)
     hist = np.zeros(n, dtype=np.int32)
-    F_up = np.zeros((nb, ng, 2 * n + 1))
+    F_up = np.zeros((nb, ng, (n + 1) if layers == "iso" else (2 * n + 1)))
+    vmr_c = _f64(atm["vmr"])[:, 1::2]
     resids = []
     converged = False
     it = 0
     res = None
     iso_prev = None
     while True:
-        T_pt = profile(P_pt, T_c)
-        if warm == "deviation":
-            iso = isothermal_flux(atm, T_pt, D)
-            F_up += (iso if iso_prev is None else iso - iso_prev)[:, None, :]
-            iso_prev = iso
-        kap = mix_opacity(ktab, T_pt, P_pt, atm["vmr"], atm["bin_index"], ng)
-        res = flux(atm, kap, T_pt, P_pt, F_up, n_scat=n_scat, D=D, n_threads=n_threads,
-                   want_dn=False)
-        code, r = radeq(atm, P_pt, res["F_bol"], T_c, m, hist, opts)
+        if layers == "iso":
+            kap = mix_opacity(ktab, T_c, P_pt[1::2], vmr_c, atm["bin_index"], ng)
+            res = flux_iso(atm, kap, T_c, P_pt[0::2], F_up, n_scat=n_scat, D=D, n_threads=n_threads,
+                           want_dn=False)
+            bol = np.zeros((2 * n + 1, 3))  # interfaces at the even points; the step reads no other
+            bol[0::2] = res["F_bol"]
+        else:
+            T_pt = profile(P_pt, T_c)
+            if warm == "deviation":
+                iso = isothermal_flux(atm, T_pt, D)
+                F_up += (iso if iso_prev is None else iso - iso_prev)[:, None, :]
+                iso_prev = iso
+            kap = mix_opacity(ktab, T_pt, P_pt, atm["vmr"], atm["bin_index"], ng)
+            res = flux(atm, kap, T_pt, P_pt, F_up, n_scat=n_scat, D=D, n_threads=n_threads,
+                       want_dn=False)
+            bol = res["F_bol"]
+        code, r = radeq(atm, P_pt, bol, T_c, m, hist, opts)
         resids.append(r)
         if callback is not None:
             callback(it, T_c, r)

@@ -22,9 +22,10 @@
  *                     oscillation control, eq:condition)
  *   exact solution .. Sec. 2.1.2 eq:isodirect, eq:nonisodirect,
  *                     eq:direct_trans, eq:diff (check mode only)
+ *   isothermal grid . Sec. 2.2.1 (n isothermal layers, n + 1 interfaces)
  *
- * Readings of points the paper leaves open are listed in the design doc; the ones
- * that change arithmetic are repeated at the place they apply.
+ * Where the paper leaves a point open, the reading taken is stated at the
+ * place it applies.
  *
  * Parity unpinned: the oscillation-control window semantics and the
  * temperature floor (nothing in the paper fixes the trajectory), see the RE
@@ -641,5 +642,90 @@ int ref_flux_exact(int n, int nb, int ng,
     }
     ref_sums(npt, nb, ng, dlambda, g_weight, F_up, F_dn, F_up_bin, F_dn_bin, F_bol);
     free(F_top); free(F_int); free(B); free(dm);
+    return 0;
+}
+
+/* ------------------------------------------------ isothermal-layer grid
+ * Sec. 2.2.1, first grid: n isothermal layers between n + 1 interfaces.
+ * Layer i lies between interface i (below) and interface i + 1 (above); it
+ * has one temperature and one opacity (those of its centre) and its optical
+ * thickness is dtau_i = kappa_i (P_int,i - P_int,i+1) / grav (eq:layertau).
+ * Fluxes live on the interfaces only.  Each layer is propagated with
+ * eq:isoscat and the Planck value of its own temperature, for every dtau (no
+ * gradient form exists on this grid), or with eq:purescat when
+ * (1 - w0) < 1e-6 (the same switch as on the sublayered grid).  Boundary
+ * conditions, scattering passes and sums are those of ref_flux.
+ *
+ * Inputs: P_int [n+1] interface pressures, T_lay [n] layer temperatures,
+ * kappa [nb][ng][n] layer opacities, w0, g0 [nb][n].  F_up [nb][ng][n+1] is
+ * the warm start on entry and the result on exit; F_dn [nb][ng][n+1]
+ * (optional), F_up_bin, F_dn_bin [nb][n+1] and F_bol [n+1][3] as in ref_flux
+ * with interfaces in place of points. */
+/* One layer in either direction (eq:isoscat and eq:purescat are symmetric
+ * under exchanging the streams).  Upward: F_in = F_up at the lower interface,
+ * F_other = F_dn at the upper one, result F_up at the upper interface.
+ * Downward: F_in = F_dn at the upper interface, F_other = F_up at the lower
+ * one, result F_dn at the lower interface. */
+static double ref_iso_layer(double dtau, double w0, double g0, double D, double B,
+                            double F_in, double F_other) {
+    if (ref_branch(dtau, w0) == REF_BR_PURESCAT) {
+        double q = D * (1.0 - g0) * dtau;
+        return F_in - q * (F_in - F_other) / (2.0 + q);
+    }
+    ref_coeff c;
+    ref_coeffs(dtau, w0, g0, D, &c);
+    double eps = 1.0 / D;
+    return (c.xi * F_in - c.beta * F_other + 2.0 * REF_PI * eps * B * (c.beta - c.ups)) / c.alpha;
+}
+
+int ref_flux_iso(int n, int nb, int ng,
+                 const double* P_int, double grav, const double* T_lay,
+                 const double* lambda_c, const double* dlambda, const double* g_weight,
+                 double T_star, double T_irr, double T_int,
+                 const double* kappa, const double* w0, const double* g0,
+                 int n_scat, double D,
+                 double* F_up, double* F_dn,
+                 double* F_up_bin, double* F_dn_bin, double* F_bol,
+                 int n_threads) {
+    const int nif = n + 1;
+    const size_t ncell = (size_t)nb * ng * nif;
+    double* F_top = (double*)malloc(sizeof(double) * nb);
+    double* F_int = (double*)malloc(sizeof(double) * nb);
+    double* B = (double*)malloc(sizeof(double) * (size_t)nb * n);
+    double* dm = (double*)malloc(sizeof(double) * n);
+    double* dn_all = F_dn ? F_dn : (double*)malloc(sizeof(double) * ncell);
+    if (!F_top || !F_int || !B || !dm || !dn_all) {
+        free(F_top); free(F_int); free(B); free(dm);
+        if (!F_dn) free(dn_all);
+        return -1;
+    }
+    ref_boundary(nb, lambda_c, dlambda, T_star, T_irr, T_int, F_top, F_int);
+    for (int l = 0; l < nb; ++l)
+        for (int i = 0; i < n; ++i) B[(size_t)l * n + i] = ref_planck(lambda_c[l], T_lay[i]);
+    for (int i = 0; i < n; ++i) dm[i] = (P_int[i] - P_int[i + 1]) / grav; /* eq:layertau */
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int col = 0; col < nb * ng; ++col) {
+        const int l = col / ng;
+        const double* kap = kappa + (size_t)col * n;
+        const double* Bl = B + (size_t)l * n;
+        const double* w0l = w0 + (size_t)l * n;
+        const double* g0l = g0 + (size_t)l * n;
+        double* up = F_up + (size_t)col * nif;
+        double* dn = dn_all + (size_t)col * nif;
+        for (int pass = 0; pass <= n_scat; ++pass) {
+            dn[n] = F_top[l];
+            for (int i = n - 1; i >= 0; --i)
+                dn[i] = ref_iso_layer(kap[i] * dm[i], w0l[i], g0l[i], D, Bl[i], dn[i + 1], up[i]);
+            up[0] = dn[0] + F_int[l];
+            for (int i = 0; i < n; ++i)
+                up[i + 1] = ref_iso_layer(kap[i] * dm[i], w0l[i], g0l[i], D, Bl[i], up[i], dn[i + 1]);
+        }
+    }
+    ref_sums(nif, nb, ng, dlambda, g_weight, F_up, dn_all, F_up_bin, F_dn_bin, F_bol);
+    free(F_top); free(F_int); free(B); free(dm);
+    if (!F_dn) free(dn_all);
     return 0;
 }

@@ -588,3 +588,121 @@ def test_dead_band_reaches_the_same_equilibrium(ref, plain_solution):
     ok = well_conditioned_layers(atm, kt, sol)
     dT = np.abs(db["T_c"] - sol["T_c"])
     assert ok.sum() >= atm["n"] // 2 and dT[ok].max() < 0.1, (ok.sum(), dT[ok].max())
+
+
+# ------------------------------------- Sec. 2.2.1 isothermal-layer grid
+def _iso_column(atm, seed=5):
+    """Interface pressures, layer opacities [bin][g][n] spanning thin to thick
+    layers."""
+    rng = np.random.default_rng(seed)
+    P_int = ref_grid_interfaces(atm)
+    nb, ng, n = len(atm["lambda_c"]), atm["ng"], atm["n"]
+    return P_int, 10.0 ** rng.uniform(-9, -1, (nb, ng, n))
+
+
+def ref_grid_interfaces(atm):
+    import oracle
+
+    return oracle.grid(atm["P_c"])[0::2]
+
+
+def test_iso_grid_isothermal_column_gives_pi_B_everywhere(ref):
+    """Uniform T under the stellar flux pi B(T), no internal flux: every
+    interface of every column carries F_up = F_dn = pi B, from a cold start in
+    one pass at w0 = 0, and as the fixed point of the passes with scattering."""
+    atm = _small_atm(w0_max=0.0)
+    P_int, kap = _iso_column(atm)
+    T = np.full(atm["n"], 900.0)
+    piB = np.array([np.pi * ref.planck(l, 900.0) for l in atm["lambda_c"]])
+    up = np.zeros((len(piB), atm["ng"], atm["n"] + 1))
+    out = ref.flux_iso(atm, kap, T, P_int, up, n_scat=0)
+    np.testing.assert_allclose(up, np.broadcast_to(piB[:, None, None], up.shape), rtol=1e-13)
+    np.testing.assert_allclose(out["F_dn"], up, rtol=1e-13)
+    atm = _small_atm()
+    up = np.zeros(up.shape)
+    out = ref.flux_iso(atm, kap, T, P_int, up, n_scat=400)
+    np.testing.assert_allclose(up, np.broadcast_to(piB[:, None, None], up.shape), rtol=1e-10)
+    np.testing.assert_allclose(out["F_dn"], up, rtol=1e-10)
+
+
+def test_iso_grid_zero_albedo_is_the_discrete_formal_solution(ref):
+    """w0 = 0: each layer transmits exp(-D dtau) of the incoming flux and adds
+    pi B (1 - exp(-D dtau)), so the interface fluxes are sums of layer
+    emissions attenuated by the layers in between (written here as cumulative
+    products), reached in one pass."""
+    atm = _small_atm(n=7, nb=3, ng=2, w0_max=0.0)
+    atm["w0"][:] = 0.0
+    atm["T_int"] = 350.0
+    P_int, kap = _iso_column(atm, seed=3)
+    n = atm["n"]
+    T = np.linspace(1600.0, 400.0, n)
+    up = np.zeros((3, 2, n + 1))
+    out = ref.flux_iso(atm, kap, T, P_int, up, n_scat=0)
+    top, bot = ref.boundary(atm["lambda_c"], atm["dlambda"], atm["T_star"], atm["T_irr"], atm["T_int"])
+    for l in range(3):
+        piB = np.pi * np.array([ref.planck(atm["lambda_c"][l], t) for t in T])
+        for g in range(2):
+            tr = np.exp(-2.0 * kap[l, g] * (P_int[:-1] - P_int[1:]) / atm["grav"])
+            emit = piB * (1.0 - tr)
+            # layers k .. n-1 lie above interface k, layers 0 .. k-1 below it
+            dn = np.array([top[l] * np.prod(tr[k:]) + sum(emit[i] * np.prod(tr[k:i]) for i in range(k, n))
+                           for k in range(n + 1)])
+            upx = np.array([(dn[0] + bot[l]) * np.prod(tr[:k])
+                            + sum(emit[i] * np.prod(tr[i + 1:k]) for i in range(k)) for k in range(n + 1)])
+            np.testing.assert_allclose(out["F_dn"][l, g], dn, rtol=1e-13)
+            np.testing.assert_allclose(up[l, g], upx, rtol=1e-13)
+
+
+def test_iso_grid_converged_column_matches_two_stream_ode(ref):
+    """With scattering, the passes converge to the solution of the two-stream
+    differential equations for a column of homogeneous isothermal layers
+    (matrix exponentials, one two-point problem over the column): eq:isoscat
+    is exact for such a layer at any optical thickness."""
+    atm = _small_atm(n=6, nb=2, ng=2, w0_max=0.85)
+    atm["T_int"] = 300.0
+    n = atm["n"]
+    P_int = ref_grid_interfaces(atm)
+    rng = np.random.default_rng(21)
+    dm = (P_int[:-1] - P_int[1:]) / atm["grav"]
+    kap = 10.0 ** rng.uniform(-3, 1, (2, 2, n)) / dm  # layer dtau from 1e-3 to 10
+    T = np.linspace(1500.0, 500.0, n)
+    up = np.zeros((2, 2, n + 1))
+    out = ref.flux_iso(atm, kap, T, P_int, up, n_scat=3000)
+    top, bot = ref.boundary(atm["lambda_c"], atm["dlambda"], atm["T_star"], atm["T_irr"], atm["T_int"])
+    for l in range(2):
+        B = np.array([ref.planck(atm["lambda_c"][l], t) for t in T])
+        for g in range(2):
+            dtau = kap[l, g] * (P_int[:-1] - P_int[1:]) / atm["grav"]
+            u, d = ode.column_isothermal_layers(dtau, atm["w0"][l], atm["g0"][l], 2.0, B, top[l], bot[l])
+            np.testing.assert_allclose(up[l, g], u, rtol=1e-10)
+            np.testing.assert_allclose(out["F_dn"][l, g], d, rtol=1e-10, atol=1e-12 * u.max())
+
+
+def test_iso_grid_pure_scattering_conserves_net_flux(ref):
+    """w0 = 1 (eq:purescat): at convergence F_up - F_dn = F_int at every
+    interface."""
+    atm = _small_atm(n=5, nb=1, ng=1)
+    atm["w0"][:] = 1.0
+    atm["g0"][:] = 0.25
+    atm["T_int"] = 400.0
+    P_int = ref_grid_interfaces(atm)
+    kap = np.full((1, 1, atm["n"]), 2e-7)
+    up = np.zeros((1, 1, atm["n"] + 1))
+    out = ref.flux_iso(atm, kap, np.linspace(1500, 500, atm["n"]), P_int, up, n_scat=3000)
+    _, bot = ref.boundary(atm["lambda_c"], atm["dlambda"], atm["T_star"], atm["T_irr"], atm["T_int"])
+    np.testing.assert_allclose(up[0, 0] - out["F_dn"][0, 0], bot[0], rtol=1e-9)
+
+
+def test_iso_grid_equilibrium_has_constant_net_flux(ref):
+    """Radiative equilibrium on the isothermal-layer grid: the bolometric net
+    flux is sigma T_int^4 at every interface.  (On this grid the iteration
+    needs several times more steps than on the sublayered one: 584 against
+    about 100 here.)"""
+    atm, kt = W.plain_workload(n=20, nb=12, ng=4)
+    sol = ref.solve(atm, kt, max_iter=1000, layers="iso")
+    assert sol["converged"]
+    s4 = SIGMA_CODATA * atm["T_int"] ** 4
+    net = sol["flux"]["F_bol"][:, 2]
+    assert net.size == atm["n"] + 1
+    np.testing.assert_allclose(net, s4, rtol=0, atol=atm["n"] * 1e-3 * s4)
+    assert net[0] == pytest.approx(s4, rel=1e-9)

@@ -70,3 +70,43 @@ def exact_pure_absorption(dtau, B_top, B_bottom, F_up_bottom, F_dn_top, nmu: int
     src_dn = B_bottom * (1 - e) - Bp * (mu - (dtau + mu) * e)
     dn = 2 * np.pi * np.sum(wm * mu * (I_in_dn * e + src_dn))
     return up, dn
+
+
+def column_isothermal_layers(dtau, w0, g0, D, B, F_top, F_int, M: int = 16):
+    """Both fluxes at the n + 1 interfaces of a column of homogeneous,
+    isothermal layers (index 0 at the bottom), from the two-stream ODE above
+    with a constant source in each layer, solved as one two-point problem over
+    the whole column: F_dn = F_top at the top and F_up = F_dn + F_int at the
+    bottom.  Each layer is cut into M segments; on each, the state (F_up, F_dn,
+    1) advances by the matrix exponential of the augmented generator.
+    Returns (F_up, F_dn) bottom to top."""
+    n = len(dtau)
+    nodes = n * M + 1  # node 0 at the top, node n*M at the bottom
+    N = 2 * nodes
+    mat = np.zeros((N, N))
+    rhs = np.zeros(N)
+    r = 0
+    for q in range(n):  # q-th layer from the top
+        i = n - 1 - q
+        ga = D * (1.0 - w0[i] * (1.0 + g0[i]) / 2.0)
+        gs = D * w0[i] * (1.0 - g0[i]) / 2.0
+        s0 = 2.0 * np.pi * (1.0 - w0[i]) * B[i]
+        A = np.array([[ga, -gs, -s0], [gs, -ga, s0], [0.0, 0.0, 0.0]])
+        E = expm(A * (dtau[i] / M))
+        for k in range(q * M, (q + 1) * M):
+            for comp in (0, 1):
+                mat[r, 2 * (k + 1) + comp] = 1.0
+                mat[r, 2 * k] -= E[comp, 0]
+                mat[r, 2 * k + 1] -= E[comp, 1]
+                rhs[r] = E[comp, 2]
+                r += 1
+    mat[r, 1] = 1.0  # F_dn at the top
+    rhs[r] = F_top
+    r += 1
+    b = nodes - 1
+    mat[r, 2 * b] = 1.0  # F_up - F_dn at the bottom
+    mat[r, 2 * b + 1] = -1.0
+    rhs[r] = F_int
+    x = np.linalg.solve(mat, rhs).reshape(nodes, 2)
+    at_if = x[::M][::-1]  # interfaces bottom to top
+    return at_if[:, 0].copy(), at_if[:, 1].copy()
