@@ -68,6 +68,11 @@ def _load():
         lib.ref_flux.restype = i
         lib.ref_flux_iso.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, i, d,
                                      P, P, P, P, P, i]
+        lib.ref_flux_rayleigh.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, d, i, d,
+                                          P, P, P, P, P, i]
+        lib.ref_flux_rayleigh.restype = i
+        lib.ref_rayleigh_h2.argtypes = [d]
+        lib.ref_rayleigh_h2.restype = d
         lib.ref_flux_iso.restype = i
         lib.ref_flux_exact.argtypes = [i, i, i, P, d, P, P, P, P, d, d, d, P, P, P, P, P, P, i]
         lib.ref_flux_exact.restype = i
@@ -233,6 +238,42 @@ def flux(atm: dict, kappa, T_pt, P_pt, F_up, n_scat: int = 4, D: float = 2.0,
     return {"F_dn": F_dn, "F_up_bin": up_bin, "F_dn_bin": dn_bin, "F_bol": bol}
 
 
+def rayleigh_h2(lam: float) -> float:
+    """H2 Rayleigh cross-section per molecule (cm^2) at wavelength lam (cm)."""
+    return _load().ref_rayleigh_h2(float(lam))
+
+
+def flux_rayleigh(atm: dict, kappa, T_pt, P_pt, F_up, n_scat: int = 4, D: float = 2.0,
+                  n_threads: int = 0, want_dn: bool = True):
+    """``flux`` with H2 Rayleigh scattering added to the absorption
+    opacities ``kappa`` (Sec. 2.1.4): per sublayer and g-point the albedo is
+    the scattering share of the extinction and g0 = 0; atm["w0"], atm["g0"]
+    are not used."""
+    n = int(atm["n"])
+    npt = 2 * n + 1
+    lc, dl = _f64(atm["lambda_c"]), _f64(atm["dlambda"])
+    nb = lc.size
+    ng = int(atm["ng"])
+    _, gw = gauss_legendre(ng)
+    kappa = _f64(kappa)
+    assert kappa.shape == (nb, ng, npt)
+    T_pt, P_pt = _f64(T_pt), _f64(P_pt)
+    assert F_up.dtype == np.float64 and F_up.flags.c_contiguous and F_up.shape == (nb, ng, npt)
+    F_dn = np.zeros((nb, ng, npt)) if want_dn else None
+    up_bin = np.zeros((nb, npt))
+    dn_bin = np.zeros((nb, npt))
+    bol = np.zeros((npt, 3))
+    mbar = float(atm.get("mmw", 2.4)) * M_PROTON
+    rc = _load().ref_flux_rayleigh(n, nb, ng, _p(P_pt), float(atm["grav"]), _p(T_pt), _p(lc), _p(dl), _p(gw),
+                                   float(atm["T_star"]), float(atm["T_irr"]), float(atm["T_int"]),
+                                   _p(kappa), mbar, int(n_scat), float(D),
+                                   _p(F_up), _p(F_dn) if want_dn else None,
+                                   _p(up_bin), _p(dn_bin), _p(bol), int(n_threads))
+    if rc != 0:
+        raise MemoryError("oracle Rayleigh flux failed")
+    return {"F_dn": F_dn, "F_up_bin": up_bin, "F_dn_bin": dn_bin, "F_bol": bol}
+
+
 def flux_iso(atm: dict, kappa_lay, T_lay, P_int, F_up, n_scat: int = 4, D: float = 2.0,
              n_threads: int = 0, want_dn: bool = True):
     """One flux solve on the isothermal-layer grid (Sec. 2.2.1): n layers
@@ -292,7 +333,7 @@ def radeq(atm: dict, P_pt, F_bol, T_c, m, hist, opts: dict | None = None):
 
 def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float = 2.0,
           opts: dict | None = None, T_init=None, n_threads: int = 0, callback=None, warm: str = "flux",
-          layers: str = "noniso"):
+          layers: str = "noniso", rayleigh: bool = False):
     """Full RE iteration of one atmosphere (Sec. 2.2.3): profile -> opacity ->
     flux -> RE step, until converged or max_iter steps were taken.
 
@@ -304,16 +345,20 @@ def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float 
 
     layers = "iso" solves on the isothermal-layer grid (Sec. 2.2.1): the
     layers keep their centre temperatures and opacities, fluxes live on the
-    interfaces, and the RE step takes the same interface net fluxes (warm must
-    be "flux").
+    interfaces, and the RE step takes the same interface net fluxes.  There
+    the deviation warm start refers interface i to the layer above it (the
+    top interface to the top layer).
+
+    rayleigh = True adds H2 Rayleigh scattering (``flux_rayleigh``; the
+    sublayered grid only).
 
     Returns a dict with T_c, iterations, converged flag, resid history and the
     last flux result.
     """
+    if rayleigh and layers != "noniso":
+        raise ValueError("Rayleigh scattering is solved on the sublayered grid")
     if layers not in ("noniso", "iso"):
         raise ValueError(layers)
-    if layers == "iso" and warm != "flux":
-        raise ValueError("the isothermal-layer grid takes the flux warm start")
     n = int(atm["n"])
     ng = int(atm["ng"])
     nb = len(atm["lambda_c"])
@@ -330,6 +375,10 @@ def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float 
     iso_prev = None
     while True:
         if layers == "iso":
+            if warm == "deviation":
+                iso = isothermal_flux(atm, T_c[np.minimum(np.arange(n + 1), n - 1)], D)
+                F_up += (iso if iso_prev is None else iso - iso_prev)[:, None, :]
+                iso_prev = iso
             kap = mix_opacity(ktab, T_c, P_pt[1::2], vmr_c, atm["bin_index"], ng)
             res = flux_iso(atm, kap, T_c, P_pt[0::2], F_up, n_scat=n_scat, D=D, n_threads=n_threads,
                            want_dn=False)
@@ -342,8 +391,8 @@ def solve(atm: dict, ktab: dict, max_iter: int = 200, n_scat: int = 4, D: float 
                 F_up += (iso if iso_prev is None else iso - iso_prev)[:, None, :]
                 iso_prev = iso
             kap = mix_opacity(ktab, T_pt, P_pt, atm["vmr"], atm["bin_index"], ng)
-            res = flux(atm, kap, T_pt, P_pt, F_up, n_scat=n_scat, D=D, n_threads=n_threads,
-                       want_dn=False)
+            fn = flux_rayleigh if rayleigh else flux
+            res = fn(atm, kap, T_pt, P_pt, F_up, n_scat=n_scat, D=D, n_threads=n_threads, want_dn=False)
             bol = res["F_bol"]
         code, r = radeq(atm, P_pt, bol, T_c, m, hist, opts)
         resids.append(r)

@@ -23,6 +23,7 @@
  *   exact solution .. Sec. 2.1.2 eq:isodirect, eq:nonisodirect,
  *                     eq:direct_trans, eq:diff (check mode only)
  *   isothermal grid . Sec. 2.2.1 (n isothermal layers, n + 1 interfaces)
+ *   Rayleigh ........ Sec. 2.1.4 (H2 cross-section, scattering albedo)
  *
  * Where the paper leaves a point open, the reading taken is stated at the
  * place it applies.
@@ -371,15 +372,36 @@ static void ref_sums(int npt, int nb, int ng, const double* dlambda, const doubl
     }
 }
 
-int ref_flux(int n, int nb, int ng,
-             const double* P_pt, double grav, const double* T_pt,
-             const double* lambda_c, const double* dlambda, const double* g_weight,
-             double T_star, double T_irr, double T_int,
-             const double* kappa, const double* w0, const double* g0,
-             int n_scat, double D,
-             double* F_up, double* F_dn,
-             double* F_up_bin, double* F_dn_bin, double* F_bol,
-             int n_threads) {
+/* Optical depth, single-scattering albedo and asymmetry of sublayer s of
+ * column (l, g).  Without Rayleigh scattering (kappa_R == NULL): the mean of
+ * the two point opacities, and the layer's w0 and g0.  With it (Sec. 2.1.4):
+ * the H2 scattering opacity kappa_R[l] is added to that mean, and the
+ * sublayer scatters the fraction kappa_R / (total) of its extinction,
+ * isotropically (g0 = 0); the given w0, g0 do not enter. */
+static void ref_sub_optics(const double* kap, int s, double dm_s, const double* w0l, const double* g0l,
+                           const double* kappa_R, int l, double* dtau, double* w0, double* g0) {
+    double k_abs = 0.5 * (kap[s] + kap[s + 1]);
+    if (!kappa_R) {
+        *dtau = k_abs * dm_s;
+        *w0 = w0l[s / 2];
+        *g0 = g0l[s / 2];
+        return;
+    }
+    double k_tot = k_abs + kappa_R[l];
+    *dtau = k_tot * dm_s;
+    *w0 = kappa_R[l] / k_tot;
+    *g0 = 0.0;
+}
+
+static int ref_flux_core(int n, int nb, int ng,
+                         const double* P_pt, double grav, const double* T_pt,
+                         const double* lambda_c, const double* dlambda, const double* g_weight,
+                         double T_star, double T_irr, double T_int,
+                         const double* kappa, const double* w0, const double* g0, const double* kappa_R,
+                         int n_scat, double D,
+                         double* F_up, double* F_dn,
+                         double* F_up_bin, double* F_dn_bin, double* F_bol,
+                         int n_threads) {
     const int npt = 2 * n + 1;
     const size_t ncell = (size_t)nb * ng * npt;
     double* F_top = (double*)malloc(sizeof(double) * nb);
@@ -404,22 +426,22 @@ int ref_flux(int n, int nb, int ng,
         const int l = col / ng;
         const double* kap = kappa + (size_t)col * npt;
         const double* Bl = B + (size_t)l * npt;
-        const double* w0l = w0 + (size_t)l * n;
-        const double* g0l = g0 + (size_t)l * n;
+        const double* w0l = w0 ? w0 + (size_t)l * n : NULL;
+        const double* g0l = g0 ? g0 + (size_t)l * n : NULL;
         double* up = F_up + (size_t)col * npt;
         double* dn = dn_all + (size_t)col * npt;
         for (int pass = 0; pass <= n_scat; ++pass) {
             dn[2 * n] = F_top[l]; /* TOA boundary condition */
             for (int s = 2 * n - 1; s >= 0; --s) {
-                double dtau = 0.5 * (kap[s] + kap[s + 1]) * dm[s];
-                dn[s] = ref_sub_down(dtau, w0l[s / 2], g0l[s / 2], D,
-                                     Bl[s + 1], Bl[s], up[s], dn[s + 1]);
+                double dtau, ws, gs;
+                ref_sub_optics(kap, s, dm[s], w0l, g0l, kappa_R, l, &dtau, &ws, &gs);
+                dn[s] = ref_sub_down(dtau, ws, gs, D, Bl[s + 1], Bl[s], up[s], dn[s + 1]);
             }
             up[0] = dn[0] + F_int[l]; /* BOA: pi B_int = F_up,0 - F_dn,0 */
             for (int s = 0; s < 2 * n; ++s) {
-                double dtau = 0.5 * (kap[s] + kap[s + 1]) * dm[s];
-                up[s + 1] = ref_sub_up(dtau, w0l[s / 2], g0l[s / 2], D,
-                                       Bl[s + 1], Bl[s], up[s], dn[s + 1]);
+                double dtau, ws, gs;
+                ref_sub_optics(kap, s, dm[s], w0l, g0l, kappa_R, l, &dtau, &ws, &gs);
+                up[s + 1] = ref_sub_up(dtau, ws, gs, D, Bl[s + 1], Bl[s], up[s], dn[s + 1]);
             }
         }
     }
@@ -427,6 +449,55 @@ int ref_flux(int n, int nb, int ng,
     free(F_top); free(F_int); free(B); free(dm);
     if (!F_dn) free(dn_all);
     return 0;
+}
+
+int ref_flux(int n, int nb, int ng,
+             const double* P_pt, double grav, const double* T_pt,
+             const double* lambda_c, const double* dlambda, const double* g_weight,
+             double T_star, double T_irr, double T_int,
+             const double* kappa, const double* w0, const double* g0,
+             int n_scat, double D,
+             double* F_up, double* F_dn,
+             double* F_up_bin, double* F_dn_bin, double* F_bol,
+             int n_threads) {
+    return ref_flux_core(n, nb, ng, P_pt, grav, T_pt, lambda_c, dlambda, g_weight, T_star, T_irr, T_int,
+                         kappa, w0, g0, NULL, n_scat, D, F_up, F_dn, F_up_bin, F_dn_bin, F_bol, n_threads);
+}
+
+/* ------------------------------------------- Rayleigh scattering by H2
+ * Sec. 2.1.4.  Cross-section per molecule
+ *   sigma = 24 pi^3 / (n_ref^2 lambda^4) ((n^2 - 1) / (n^2 + 2))^2 K
+ * with, for H2, n_ref = 2.68678e19 cm^-3, King factor K = 1 and refractive
+ * index n = 13.58e-5 (1 + 7.52e-11 cm^2 / lambda^2) + 1 (lambda in cm). */
+double ref_rayleigh_h2(double lambda) {
+    const double n_ref = 2.68678e19, K = 1.0;
+    double nl = 13.58e-5 * (1.0 + 7.52e-11 / (lambda * lambda)) + 1.0;
+    double f = (nl * nl - 1.0) / (nl * nl + 2.0);
+    double l2 = lambda * lambda;
+    return 24.0 * REF_PI * REF_PI * REF_PI / (n_ref * n_ref * l2 * l2) * f * f * K;
+}
+
+/* The flux solve of ref_flux with Rayleigh scattering by H2 added to the
+ * given (absorption) opacities: kappa_R = sigma(lambda_c) / mbar per bin
+ * (mbar in g), scattering albedo of each sublayer and g-point from the
+ * ratio of scattering to total opacity, isotropic scattering (Sec. 2.1.4);
+ * the pure-scattering form applies where (1 - w0) < 1e-6. */
+int ref_flux_rayleigh(int n, int nb, int ng,
+                      const double* P_pt, double grav, const double* T_pt,
+                      const double* lambda_c, const double* dlambda, const double* g_weight,
+                      double T_star, double T_irr, double T_int,
+                      const double* kappa, double mbar,
+                      int n_scat, double D,
+                      double* F_up, double* F_dn,
+                      double* F_up_bin, double* F_dn_bin, double* F_bol,
+                      int n_threads) {
+    double* kR = (double*)malloc(sizeof(double) * nb);
+    if (!kR) return -1;
+    for (int l = 0; l < nb; ++l) kR[l] = ref_rayleigh_h2(lambda_c[l]) / mbar;
+    int rc = ref_flux_core(n, nb, ng, P_pt, grav, T_pt, lambda_c, dlambda, g_weight, T_star, T_irr, T_int,
+                           kappa, NULL, NULL, kR, n_scat, D, F_up, F_dn, F_up_bin, F_dn_bin, F_bol, n_threads);
+    free(kR);
+    return rc;
 }
 
 /* ---------------------------------------------------------------- RE step

@@ -706,3 +706,102 @@ def test_iso_grid_equilibrium_has_constant_net_flux(ref):
     assert net.size == atm["n"] + 1
     np.testing.assert_allclose(net, s4, rtol=0, atol=atm["n"] * 1e-3 * s4)
     assert net[0] == pytest.approx(s4, rel=1e-9)
+
+
+# ------------------------------------------ Sec. 2.1.4 Rayleigh scattering
+def test_rayleigh_cross_section_equals_dipole_scattering(ref):
+    """The printed cross-section is the scattering of an induced dipole,
+    sigma = (8 pi / 3) k^4 alpha^2 with k = 2 pi / lambda, whose
+    polarizability follows from the refractive index by Lorentz-Lorenz,
+    alpha = 3 / (4 pi n_ref) (n^2 - 1) / (n^2 + 2); n from the printed H2
+    dispersion formula."""
+    n_ref = 2.68678e19
+    for lam_um in (0.3, 0.5, 1.0, 4.0, 30.0):
+        lam = lam_um * 1e-4
+        n = 1.0 + 13.58e-5 * (1.0 + 7.52e-11 / lam ** 2)
+        alpha = 3.0 / (4.0 * np.pi * n_ref) * (n * n - 1.0) / (n * n + 2.0)
+        k = 2.0 * np.pi / lam
+        assert ref.rayleigh_h2(lam) == pytest.approx(8.0 * np.pi / 3.0 * k ** 4 * alpha ** 2, rel=1e-12)
+
+
+def test_rayleigh_cross_section_falls_as_inverse_fourth_power(ref):
+    """Far above the dispersion scale sqrt(7.52e-11 cm^2) (about 0.09 micron)
+    the cross-section scales as lambda^-4; at 0.3 micron the dispersion term
+    raises sigma lambda^4 by about 17% over its long-wavelength value."""
+    assert ref.rayleigh_h2(0.2) / ref.rayleigh_h2(0.1) == pytest.approx(1.0 / 16.0, rel=1e-7)
+    assert ref.rayleigh_h2(20e-4) / ref.rayleigh_h2(10e-4) == pytest.approx(1.0 / 16.0, rel=2e-4)
+    lim = ref.rayleigh_h2(1.0)  # lambda = 1 cm
+    assert ref.rayleigh_h2(0.3e-4) * 0.3e-4 ** 4 / lim == pytest.approx(1.17, abs=0.01)
+
+
+def test_rayleigh_flux_equals_two_stream_with_equivalent_albedo(ref):
+    """With an absorption opacity uniform along each column, adding Rayleigh
+    scattering is the plain solve with total opacity kappa + sigma/mbar,
+    albedo (sigma/mbar)/(kappa + sigma/mbar) and g0 = 0."""
+    atm = _small_atm(n=9, nb=6, ng=1)
+    atm["T_int"] = 250.0
+    P = ref.grid(atm["P_c"])
+    T = np.linspace(1400.0, 600.0, P.size)
+    mbar = 2.4 * ref.M_PROTON
+    kR = np.array([ref.rayleigh_h2(l) / mbar for l in atm["lambda_c"]])
+    k_abs = kR * np.array([1e-3, 0.1, 1.0, 10.0, 1e3, 1e6])  # albedo from ~1 to ~0
+    kap = np.repeat(k_abs[:, None, None], P.size, axis=2)
+    up_a = np.zeros((6, 1, P.size))
+    out_a = ref.flux_rayleigh(atm, kap, T, P, up_a, n_scat=7)
+    eq = dict(atm)
+    eq["w0"] = np.repeat((kR / (k_abs + kR))[:, None], atm["n"], axis=1)
+    eq["g0"] = np.zeros((6, atm["n"]))
+    up_b = np.zeros((6, 1, P.size))
+    out_b = ref.flux(eq, kap + kR[:, None, None], T, P, up_b, n_scat=7)
+    np.testing.assert_allclose(up_a, up_b, rtol=1e-12)
+    np.testing.assert_allclose(out_a["F_dn"], out_b["F_dn"], rtol=1e-12, atol=1e-12 * up_b.max())
+    np.testing.assert_allclose(out_a["F_bol"], out_b["F_bol"], rtol=1e-12)
+
+
+def test_pure_rayleigh_column_conserves_net_flux(ref):
+    """No absorption: every sublayer scatters all it intercepts (eq:purescat
+    with g0 = 0); at convergence F_up - F_dn = F_int everywhere and F_dn grows
+    linearly with the Rayleigh optical depth from the TOA (slope D/2 F_int)."""
+    atm = _small_atm(n=5, nb=2, ng=2)
+    atm["T_int"] = 400.0
+    atm["grav"] = 1e5  # Rayleigh optical depth about 3.5 in the short-wave bin
+    P = ref.grid(atm["P_c"])
+    T = np.linspace(1500.0, 500.0, P.size)
+    kap = np.zeros((2, 2, P.size))
+    up = np.zeros(kap.shape)
+    out = ref.flux_rayleigh(atm, kap, T, P, up, n_scat=4000)
+    top, bot = ref.boundary(atm["lambda_c"], atm["dlambda"], atm["T_star"], atm["T_irr"], atm["T_int"])
+    mbar = 2.4 * ref.M_PROTON
+    for l in range(2):
+        kR = ref.rayleigh_h2(atm["lambda_c"][l]) / mbar
+        tau = np.concatenate([[0.0], np.cumsum((kR * (P[:-1] - P[1:]) / atm["grav"])[::-1])])[::-1]
+        assert 1e-4 < tau[0] < 10, tau[0]
+        for g in range(2):
+            gross = up[l, g] + out["F_dn"][l, g]  # the net flux is a small difference here
+            np.testing.assert_allclose(up[l, g] - out["F_dn"][l, g], bot[l], rtol=0, atol=1e-12 * gross.max())
+            np.testing.assert_allclose(out["F_dn"][l, g], top[l] + bot[l] * tau, rtol=1e-9)
+
+
+def test_rayleigh_isothermal_atmosphere_gives_pi_B_everywhere(ref):
+    """pi B at every point is a fixed point of the passes whatever the
+    scattering share (thin to thick, absorbing to almost conservative)."""
+    atm = _small_atm()
+    P = ref.grid(atm["P_c"])
+    T = np.full(P.size, 900.0)
+    kap = _kappa(atm)
+    piB = np.array([np.pi * ref.planck(l, 900.0) for l in atm["lambda_c"]])
+    up = np.broadcast_to(piB[:, None, None], kap.shape).copy()
+    out = ref.flux_rayleigh(atm, kap, T, P, up, n_scat=4)
+    np.testing.assert_allclose(up, np.broadcast_to(piB[:, None, None], up.shape), rtol=1e-13)
+    np.testing.assert_allclose(out["F_dn"], up, rtol=1e-13)
+
+
+def test_rayleigh_equilibrium_has_constant_net_flux(ref):
+    """Radiative equilibrium with Rayleigh scattering: net flux sigma T_int^4
+    at every interface."""
+    atm, kt = W.plain_workload(n=30, nb=20, ng=4)
+    sol = ref.solve(atm, kt, max_iter=600, rayleigh=True)
+    assert sol["converged"]
+    s4 = SIGMA_CODATA * atm["T_int"] ** 4
+    net = sol["flux"]["F_bol"][::2, 2]
+    np.testing.assert_allclose(net, s4, rtol=0, atol=atm["n"] * 1e-3 * s4)
