@@ -56,14 +56,24 @@ def sweep_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
     return nb * per_bin + ng * 8
 
 
-def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict):
+def iso_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
+    """As sweep_algorithmic_bytes for n isothermal layers: one opacity per
+    layer, the warm start at the n + 1 interfaces (the top one is never
+    read), one Planck value per layer, w0 and g0, the boundary fluxes and the
+    Gauss-summed partials at the interfaces."""
+    per_bin = (ng * n * rbytes + ng * n * rbytes + ng * (n + 1) * rbytes + n * 8 + 2 * n * 8 + 2 * 8
+               + 2 * (n + 1) * rbytes)
+    return nb * per_bin + ng * 8
+
+
+def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict, **solver_kw):
     import torch
 
     from paper_1606_05474_amd import helios as H
 
     b = H.Batch([atm])
     ktd = H.KTable(kt)
-    s = H.Solver(b, ktd, prec=prec)
+    s = H.Solver(b, ktd, prec=prec, **solver_kw)
     s.reset(atm["T0"])
     s.autotune()  # the library's sweep-shape autotuner (kept for the process)
     shape = H.sweep_shapes(s.b, prec)
@@ -257,6 +267,133 @@ def chunk_main(args):
                          "achieved": alg / (sweep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": alg / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                          "algorithmic_bytes_per_launch": alg, "avg_launch_ms": sweep_ms}}
+    print(json.dumps(line))
+    return 0
+
+
+def layers_main(args):
+    """The layer-resolution study of Sec. 3.3 on a synthetic stand-in: one
+    physical atmosphere solved to radiative equilibrium on sublayered grids
+    of 21, 51, 101 and 400 layers and on isothermal-layer grids of 51, 101,
+    201 and 400 layers (FP64, all 3000 bins, tolerance 1e-3 sigma T_int^4),
+    then post-processed (80 scattering passes) to TOA emission spectra.
+    Reported: each profile against the 400-layer sublayered one (linear in
+    log P at the model's layer centres), each spectrum's deviation from that
+    model's spectrum, the updates to converge and the time per update.  The
+    step control counts any sign change within the 6-step window as an
+    oscillation: with the strict-alternation reading the 400-layer model
+    oscillates with period 4 and its step multipliers never shrink."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
+    kt = W.table_ktab(2)
+    KT = H.KTable(kt)
+    lc, dl = W.bins(3000)
+    grids = {"noniso": (21, 51, 101, 400), "iso": (51, 101, 201, 400)}
+    res = {}
+    log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
+    for layers, ns in grids.items():
+        atms = [W.resolution_atmosphere(6, n, lc, dl) for n in ns]
+        b = H.Batch(atms)
+        s = H.Solver(b, KT, prec=H.FP64, layers=layers, bin_fluxes=False, opts=H.REOptions(osc_any=1))
+        s.reset(b.cat_layer([a["T0"] for a in atms]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, block = 0, 2000
+        while done < args.max_iter:
+            conv, iters, _ = s.run(block - 1, check_every=100, graph=True)
+            done += block
+            log(f"{layers}: {done} updates, converged {conv.tolist()}, updates {iters.tolist()}, "
+                f"{time.perf_counter() - t0:.1f} s")
+            if conv.all():
+                break
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        T = [t.cpu().numpy() for t in b.split_layer(s.T_c)]
+        toa, _ = H.emission_spectrum(b, KT, s.T_c, n_scat=80, layers=layers)
+        # one RE update's time on this batch with every member running
+        s2 = H.Solver(b, KT, prec=H.FP64, layers=layers, bin_fluxes=False, opts=H.REOptions(osc_any=1))
+        s2.reset(s.T_c)
+        for _ in range(3):
+            s2.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            s2.step()
+        e1.record()
+        torch.cuda.synchronize()
+        for k, n in enumerate(ns):
+            res[f"{layers}{n}"] = {"P_c": atms[k]["P_c"], "T": T[k], "spec": toa[k].cpu().numpy(),
+                                   "converged": bool(conv[k]), "updates": int(iters[k])}
+        res[layers] = {"seconds": sec, "ms_per_update_all_running": e0.elapsed_time(e1) / 10}
+    ref_m = res["noniso400"]
+    lp_ref = np.log(ref_m["P_c"])[::-1]
+    out = {}
+    for key, m in res.items():
+        if "T" not in m:
+            continue
+        T_ref = np.interp(np.log(m["P_c"]), lp_ref, ref_m["T"][::-1])
+        dT = np.abs(m["T"] - T_ref)
+        dev = np.abs(m["spec"] / ref_m["spec"] - 1.0)
+        out[key] = {"converged": m["converged"], "updates": m["updates"],
+                    "max_abs_dT_vs_noniso400_K": float(dT.max()),
+                    "median_abs_dT_vs_noniso400_K": float(np.median(dT)),
+                    "spectrum_median_rel_dev": float(np.median(dev)),
+                    "spectrum_max_rel_dev": float(dev.max()),
+                    "spectrum_bins_above_1pct": float(np.mean(dev > 0.01))}
+    line = {"metric": "layer resolution study", "value": None, "unit": None, "n_gpus": 1, "dtype": "f64",
+            "data": "synthetic", "higher_is_better": None,
+            "config": {"workload": "one atmosphere (stellar 3026 K, irradiation 780 K, T_int 200 K, g 893 cm s^-2, "
+                                   "synthetic 4-species tables, w0 and g0 per bin), 3000 bins x 20 g, P centres "
+                                   "1e-6 .. 1e3 bar; RE to 1e-3 sigma T_int^4 in FP64 from 1000 K (any sign change in the "
+                                   "6-step window shrinks the step), spectra with 80 "
+                                   "scattering passes on each model's own grid; reference: 400 sublayered layers"},
+            "models": out,
+            "time": {k: res[k] for k in grids}}
+    print(json.dumps(line))
+    return 0
+
+
+def modes_main(args):
+    """The solver flavours on the single-atmosphere spectral workload (100
+    layers x 3000 bins x 20 g): the sublayered two-stream solve, the same on
+    isothermal layers (helios_flux_iso) and with H2 Rayleigh scattering
+    (helios_flux_rayleigh), each in FP64 and mixed precision; per mode the
+    RE-iteration rate and the sweep's time and rate of algorithmic bytes."""
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
+    atm, kt = W.spectral_workload()
+    n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
+    modes = {"two-stream": {}, "isothermal layers": {"layers": "iso"},
+             "Rayleigh H2": {"rayleigh_mbar": 2.4 * 1.67262192369e-24}}
+    out = {}
+    for prec, pname in ((H.FP64, "fp64"), (H.MIXED, "mixed")):
+        rb = 8 if prec == H.FP64 else 4
+        for mode, kw in modes.items():
+            r = run_gpu(prec, args.steps, args.warmup, atm, kt, **kw)
+            if mode == "isothermal layers":
+                alg = iso_algorithmic_bytes(n, nb, ng, rb)
+            elif mode == "Rayleigh H2":
+                alg = sweep_algorithmic_bytes(n, nb, ng, rb) - nb * 2 * n * 8  # no w0, g0
+            else:
+                alg = r["sweep_bytes"]
+            gbs = alg / (r["sweep_ms"] * 1e-3) / 1e9
+            out[f"{mode} {pname}"] = {"layer*bin*g/s": r["value"], "ms_per_iteration": r["ms_per_step"],
+                                      "sweep_ms": r["sweep_ms"], "sweep_alg_GBs": gbs,
+                                      "sweep_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "running": r["status"] == H.ATM_RUNNING}
+            print("#", mode, pname, json.dumps(out[f"{mode} {pname}"]), file=sys.stderr, flush=True)
+    line = {"metric": "layer*bin*g flux updates/s per solver mode", "value": None, "unit": "layer*bin*g/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "one atmosphere, 100 layers x 3000 bins x 20 g, table opacities, 1 + 4 "
+                                   "scattering passes; a step: opacity mixing, flux call, RE update"},
+            "modes": out}
     print(json.dumps(line))
     return 0
 
@@ -458,12 +595,15 @@ def main(argv=None):
                     help="precisions to run (profiling runs pick one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["spectral", "batch", "chunk", "production", "exact"], default="spectral",
+    ap.add_argument("--workload", choices=["spectral", "batch", "chunk", "production", "exact", "layers", "modes"],
+                    default="spectral",
                     help="spectral: one 100-layer x 3000-bin atmosphere (the headline line); "
                          "batch: the uneven 512-atmosphere batch, throughput and solve to convergence; "
                          "chunk: RE-iteration throughput of one production chunk; "
                          "production: converged atmospheres/s, batched + network + mixed against plain FP64; "
-                         "exact: the exact pure-absorption mode and the diffusivity study")
+                         "exact: the exact pure-absorption mode and the diffusivity study; "
+                         "layers: the layer-resolution study (sublayered against isothermal layers); "
+                         "modes: the two-stream, isothermal-layer and Rayleigh solves side by side")
     ap.add_argument("--chunk", type=int, default=256, help="atmospheres per device batch (production pool)")
     ap.add_argument("--plain-count", type=int, default=64, help="atmospheres solved by the plain form")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1606_05474_amd", "data", "warmstart_mlp.npz"),
@@ -509,13 +649,17 @@ def main(argv=None):
     if args.n_atm is None:
         args.n_atm = {"production": 4096, "chunk": 128}.get(args.workload, 512)
     if args.max_iter is None:
-        args.max_iter = 2000 if args.workload == "production" else 300
+        args.max_iter = {"production": 2000, "layers": 60000}.get(args.workload, 300)
     if args.workload == "batch":
         return batch_main(args)
     if args.workload == "production":
         return production_main(args)
     if args.workload == "chunk":
         return chunk_main(args)
+    if args.workload == "layers":
+        return layers_main(args)
+    if args.workload == "modes":
+        return modes_main(args)
     if args.workload == "exact":
         return exact_main(args)
     kt = W.table_ktab(2)

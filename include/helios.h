@@ -204,6 +204,46 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
                 double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
                 helios_prec prec, void* stream);
 
+/* The same two-stream solve on the isothermal-layer grid (Sec. 2.2.1): the
+ * atmosphere is n isothermal layers between the n + 1 interfaces at the even
+ * points (P_pt[2i]); layer i has the temperature and opacity of its centre
+ * (T_pt[2i+1] and the kappa values at point 2i+1), optical thickness
+ * kappa (P_pt[2i] - P_pt[2i+2]) / g (eq:layertau), and is propagated with
+ * eq:isoscat and B(T_i) at every optical thickness (eq:purescat where
+ * (1 - w0) < 1e-6).  Boundary conditions, scattering passes, precision and
+ * sums as helios_flux.  Only the centre values of T_pt and kappa are read.
+ *   F_up_g, F_dn_g  cell arrays in the point layout: at point 2i the fluxes at
+ *                   interface i, at point 2i+1 those at interface i+1 (the top
+ *                   of layer i), stored as deviations from (2 pi / D) B(T_i)
+ *                   at points 2i and 2i+1 and from (2 pi / D) B(T_{n-1}) at the
+ *                   TOA point; a zero array is the isothermal start
+ *   F_up_bin, F_dn_bin, F_bol  at the points as for helios_flux; even points
+ *                   are the interfaces and point 2i+1 repeats interface i+1,
+ *                   so helios_radeq takes F_bol unchanged
+ * Errors: as helios_flux. */
+int helios_flux_iso(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                    const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g,
+                    double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
+                    helios_prec prec, void* stream);
+
+/* helios_flux with Rayleigh scattering by H2 (Sec. 2.1.4).  kappa holds
+ * the absorption opacities; the library adds the scattering opacity
+ * sigma(lambda_c) / mbar of each bin, with the H2 cross-section
+ * sigma = 24 pi^3 / (n_ref^2 lambda^4) ((n^2 - 1)/(n^2 + 2))^2 (n_ref =
+ * 2.68678e19 cm^-3, King factor 1, n - 1 = 13.58e-5 (1 + 7.52e-11 cm^2 /
+ * lambda^2)), to every sublayer, and each sublayer and g-point scatters the
+ * scattering share of its extinction isotropically: w0 = kappa_scat /
+ * (kappa_abs + kappa_scat), g0 = 0 (eq:purescat where 1 - w0 < 1e-6).  No
+ * w0 or g0 array is read.
+ *   mbar      mean molecular mass in g (2.4 m_p for the paper's hydrogen
+ *             atmospheres), > 0
+ * Everything else, including the warm-start convention and the outputs, as
+ * helios_flux.  Errors: as helios_flux; -1 if mbar <= 0. */
+int helios_flux_rayleigh(const helios_atm* atm, const void* kappa, const double* T_pt, double mbar,
+                         int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
+                         double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec,
+                         void* stream);
+
 /* Pure-absorption flux solve with the exact layer relations (Sec. 2.1.2:
  * transmission eq:direct_trans = 2 E3(dtau), sources eq:nonisodirect, and
  * eq:isodirect with the mean of the sublayer's two Planck values where

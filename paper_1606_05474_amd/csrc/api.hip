@@ -253,10 +253,11 @@ struct FluxPlan {
 
 int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0, const double* g0,
               int32_t n_scat, double D, const void* F_up_g, const void* ws, size_t ws_bytes, helios_prec prec,
-              FluxPlan& p) {
+              FluxPlan& p, bool need_optics = true) {
     int rc = check_atm(atm, p.z);
     if (rc) return rc;
-    if (!kappa || !T_pt || !w0 || !g0 || !F_up_g || !ws) return fail(HELIOS_EINVAL, "flux: NULL argument");
+    if (!kappa || !T_pt || (need_optics && (!w0 || !g0)) || !F_up_g || !ws)
+        return fail(HELIOS_EINVAL, "flux: NULL argument");
     if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
     if (n_scat < 0 || n_scat > 100000) return fail(HELIOS_EINVAL, "n_scat = %d", n_scat);
     if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
@@ -311,7 +312,10 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
     A.wpb_stride = parts_stride(p.z, atm->n_g);
     A.n_scat = n_scat;
     A.npt_max = p.z.npt_max;
+    A.iso_grid = 0;
     A.D = D;
+    A.lambda_c = atm->lambda_c;
+    A.inv_mbar = 0.0;
     return A;
 }
 
@@ -334,8 +338,9 @@ hipError_t sweep_class(SweepArgs A, const SweepShape& sh, int k, int64_t b_lo, i
 }
 
 hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double* T_pt, char* wsb,
-                          hipStream_t s) {
+                          hipStream_t s, bool iso_grid = false) {
     SourceArgs sa;
+    sa.iso_grid = iso_grid ? 1 : 0;
     sa.B = (double*)(wsb + p.w.B);
     sa.F_top = (double*)(wsb + p.w.F_top);
     sa.F_int = (double*)(wsb + p.w.F_int);
@@ -451,6 +456,65 @@ hipError_t net_forward(const helios_mlp* net, const NetLayout& L, const NetWs& w
     return hipSuccess;
 }
 
+// The two-stream solve of helios_flux on either grid: iso_grid selects the
+// isothermal-layer grid (the Planck kernel's and the sweep's flag);
+// inv_mbar > 0 adds H2 Rayleigh scattering (w0, g0 then unused).
+int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0, const double* g0,
+              int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin, double* F_dn_bin,
+              double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream, bool iso_grid,
+              double inv_mbar, const char* name) {
+    FluxPlan p;
+    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p, !(inv_mbar > 0.0));
+    if (rc) return rc;
+    if (!F_bol) return fail(HELIOS_EINVAL, "%s: NULL argument", name);
+    hipStream_t s = (hipStream_t)stream;
+    char* wsb = (char*)ws;
+    hipError_t e = launch_sources(atm, p, T_pt, wsb, s, iso_grid);
+    if (e != hipSuccess) return hip_fail(e, name);
+
+    SweepArgs A = sweep_args(atm, p, kappa, w0, g0, n_scat, D, F_up_g, F_dn_g, wsb);
+    A.iso_grid = iso_grid ? 1 : 0;
+    A.inv_mbar = inv_mbar;
+    if (g_ev_before && g_ev_after) {
+        e = hipEventRecord(g_ev_before, s);
+        if (e != hipSuccess) return hip_fail(e, name);
+    }
+    for (int k = 0; k < kNumClasses; ++k) {
+        if (p.z.cls_nmax[k] == 0) continue;
+        e = sweep_class(A, p.sh[k], k, p.z.cls_bin_lo[k], p.z.cls_bin_hi[k], class_parts(p, k, atm->n_g), p.mixed,
+                        s);
+        if (e != hipSuccess) return hip_fail(e, name);
+    }
+    if (g_ev_before && g_ev_after) {
+        e = hipEventRecord(g_ev_after, s);
+        if (e != hipSuccess) return hip_fail(e, name);
+    }
+    BolArgs Bo;
+    Bo.atm = *atm;
+    Bo.part_up = A.part_up;
+    Bo.part_dn = A.part_dn;
+    Bo.F_up_bin = F_up_bin;
+    Bo.F_dn_bin = F_dn_bin;
+    Bo.chunk = (double*)(wsb + p.w.chunk);
+    Bo.total_pt = p.z.total_pt;
+    Bo.F_bol = F_bol;
+    Bo.B = (const double*)(wsb + p.w.B);
+    Bo.gw = (const double*)(wsb + p.w.gw);
+    Bo.tpe = 2.0 * kPi / D;
+    Bo.wpb_stride = A.wpb_stride;
+    Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
+    Bo.mixed = p.mixed ? 1 : 0;
+    Bo.n_cls = kNumClasses;
+    for (int k = 0; k < kNumClasses; ++k) {
+        Bo.cls_nhi[k] = kClassNHi[k];
+        Bo.cls_wpb[k] = p.sh[k].L ? class_parts(p, k, atm->n_g) : 1;  // partials per (bin, point)
+    }
+    e = launch_bolometric(Bo, p.z.npt_max, p.z.nb_max, p.z.total_pt, s);
+    if (e != hipSuccess) return hip_fail(e, name);
+    g_err[0] = 0;
+    return HELIOS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -542,54 +606,24 @@ size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec) {
 int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                 const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
                 double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream) {
-    FluxPlan p;
-    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p);
-    if (rc) return rc;
-    if (!F_bol) return fail(HELIOS_EINVAL, "helios_flux: NULL argument");
-    hipStream_t s = (hipStream_t)stream;
-    char* wsb = (char*)ws;
-    hipError_t e = launch_sources(atm, p, T_pt, wsb, s);
-    if (e != hipSuccess) return hip_fail(e, "helios_flux (sources)");
+    return flux_impl(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws, ws_bytes,
+                     prec, stream, false, 0.0, "helios_flux");
+}
 
-    SweepArgs A = sweep_args(atm, p, kappa, w0, g0, n_scat, D, F_up_g, F_dn_g, wsb);
-    if (g_ev_before && g_ev_after) {
-        e = hipEventRecord(g_ev_before, s);
-        if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
-    }
-    for (int k = 0; k < kNumClasses; ++k) {
-        if (p.z.cls_nmax[k] == 0) continue;
-        e = sweep_class(A, p.sh[k], k, p.z.cls_bin_lo[k], p.z.cls_bin_hi[k], class_parts(p, k, atm->n_g), p.mixed,
-                        s);
-        if (e != hipSuccess) return hip_fail(e, "helios_flux (sweep)");
-    }
-    if (g_ev_before && g_ev_after) {
-        e = hipEventRecord(g_ev_after, s);
-        if (e != hipSuccess) return hip_fail(e, "helios_flux (event)");
-    }
-    BolArgs Bo;
-    Bo.atm = *atm;
-    Bo.part_up = A.part_up;
-    Bo.part_dn = A.part_dn;
-    Bo.F_up_bin = F_up_bin;
-    Bo.F_dn_bin = F_dn_bin;
-    Bo.chunk = (double*)(wsb + p.w.chunk);
-    Bo.total_pt = p.z.total_pt;
-    Bo.F_bol = F_bol;
-    Bo.B = (const double*)(wsb + p.w.B);
-    Bo.gw = (const double*)(wsb + p.w.gw);
-    Bo.tpe = 2.0 * kPi / D;
-    Bo.wpb_stride = A.wpb_stride;
-    Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
-    Bo.mixed = p.mixed ? 1 : 0;
-    Bo.n_cls = kNumClasses;
-    for (int k = 0; k < kNumClasses; ++k) {
-        Bo.cls_nhi[k] = kClassNHi[k];
-        Bo.cls_wpb[k] = p.sh[k].L ? class_parts(p, k, atm->n_g) : 1;  // partials per (bin, point)
-    }
-    e = launch_bolometric(Bo, p.z.npt_max, p.z.nb_max, p.z.total_pt, s);
-    if (e != hipSuccess) return hip_fail(e, "helios_flux (bolometric)");
-    g_err[0] = 0;
-    return HELIOS_OK;
+int helios_flux_iso(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                    const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
+                    double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream) {
+    return flux_impl(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws, ws_bytes,
+                     prec, stream, true, 0.0, "helios_flux_iso");
+}
+
+int helios_flux_rayleigh(const helios_atm* atm, const void* kappa, const double* T_pt, double mbar,
+                         int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
+                         double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec,
+                         void* stream) {
+    if (!(mbar > 0.0)) return fail(HELIOS_EINVAL, "helios_flux_rayleigh: mbar = %g must be > 0", mbar);
+    return flux_impl(atm, kappa, T_pt, nullptr, nullptr, n_scat, D, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws,
+                     ws_bytes, prec, stream, false, 1.0 / mbar, "helios_flux_rayleigh");
 }
 
 int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* T_pt, double* F_up_g,

@@ -77,6 +77,19 @@ __device__ inline void exp_neg_om(double x, double& e, double& om) {
     om = (n == 0.0) ? -q : 1.0 - e;
 }
 
+// H2 Rayleigh cross-section per molecule (cm^2) at wavelength lambda (cm),
+// Sec. 2.1.4: 24 pi^3 / (n_ref^2 lambda^4) ((n^2 - 1)/(n^2 + 2))^2 K with
+// n_ref = 2.68678e19 cm^-3, K = 1 and n - 1 = 13.58e-5 (1 + 7.52e-11 cm^2 /
+// lambda^2); n^2 - 1 is formed as (n - 1)(n + 1), free of cancellation.
+__host__ __device__ inline double rayleigh_h2(double lambda) {
+    const double l2 = lambda * lambda;
+    const double nm1 = 13.58e-5 * (1.0 + 7.52e-11 / l2);
+    const double n = 1.0 + nm1;
+    const double f = nm1 * (n + 1.0) / (n * n + 2.0);
+    const double nr = 2.68678e19;
+    return 24.0 * kPi * kPi * kPi / (nr * nr * l2 * l2) * f * f;
+}
+
 // Planck function per unit wavelength and steradian at the bin centre:
 // 2 h c^2 / lambda^5 / (exp(x) - 1) = 2 h c^2 / lambda^5 * exp(-x) / (1 - exp(-x)),
 // x = h c / (lambda k T).
@@ -124,7 +137,10 @@ struct SweepArgs {
     int32_t n_scat;
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
     int32_t bnd_maxch;    // boundary chunks per atmosphere in bnd_part
+    int32_t iso_grid;     // 1: isothermal-layer grid (layer i = sublayer slot 2i, slot 2i+1 the identity)
     double D;
+    const double* lambda_c;  // [sum nb] bin centres (Rayleigh scattering)
+    double inv_mbar;         // > 0: add H2 Rayleigh scattering with this 1/mbar (g^-1); w0, g0 unused
 };
 
 constexpr int kMaxClasses = 8;
@@ -208,6 +224,7 @@ struct SourceArgs {
     int32_t* bin_atm;
     double* bnd_part;
     int32_t bnd_maxch, nb_max, npt_max;
+    int32_t iso_grid;  // 1: Planck values of the isothermal-layer grid (see planck_kernel)
     int64_t total_bin;
 };
 hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const SourceArgs& sa, const GaussTable& gt,
@@ -215,7 +232,7 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);
-hipError_t launch_sweep(const SweepArgs& a, int K, int L, bool mixed, int grid, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs& a, int K, int L, bool mixed, int grid, hipStream_t s);  // Rayleigh if a.inv_mbar > 0
 hipError_t launch_exact(const SweepArgs& a, int64_t n_bins, hipStream_t s);
 hipError_t launch_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,
                                const double* w0, const double* g0, double D, double* out,

@@ -66,18 +66,26 @@ hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double*
 // B[bin][pt] at the bin centres: workgroup = (bin, tile of 256 points), one
 // thread per point (the bin's atmosphere from the map the boundary kernel
 // wrote earlier in the same call).
+//
+// On the isothermal-layer grid (Sec. 2.2.1) layer i has the single
+// temperature of its centre (point 2i+1), and the sweep's reference values
+// are B(T_i) at points 2i and 2i+1 and B(T_{n-1}) at the TOA point 2n.  The
+// sweep then sees a Planck difference of zero across the layer itself (slot
+// 2i) and the step B(T_i) - B(T_{i+1}) across the identity slot 2i+1, which
+// moves the deviation from one layer's reference to the next one's.
 constexpr int kPlanckThreads = 256;
 __global__ void __launch_bounds__(kPlanckThreads) planck_kernel(helios_atm atm, const double* __restrict__ T_pt,
                                                                 const int32_t* __restrict__ bin_atm,
-                                                                double* __restrict__ B) {
+                                                                double* __restrict__ B, int iso_grid) {
     const int64_t b = blockIdx.x;
     const int a = bin_atm[b];
     if (frozen(atm.status, a)) return;  // uniform per workgroup
     const int npt = 2 * atm.n_layer[a] + 1;
     const int p = blockIdx.y * kPlanckThreads + threadIdx.x;
     if (p >= npt) return;
+    const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
     const int64_t o = atm.pb_off[a] + (b - atm.bin_off[a]) * npt + p;
-    B[o] = planck_d(atm.lambda_c[b], T_pt[atm.pt_off[a] + p]);
+    B[o] = planck_d(atm.lambda_c[b], T_pt[atm.pt_off[a] + pt]);
 }
 
 // Boundary fluxes (Sec. 2.2.2), workgroup = (atmosphere, chunk of kBndChunk
@@ -124,7 +132,7 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
     if (e != hipSuccess) return e;
     const int tiles = (sa.npt_max + kPlanckThreads - 1) / kPlanckThreads;
     hipLaunchKernelGGL(planck_kernel, dim3((unsigned)sa.total_bin, tiles), dim3(kPlanckThreads), 0, s, *atm, T_pt,
-                       sa.bin_atm, sa.B);
+                       sa.bin_atm, sa.B, (int)sa.iso_grid);
     return hipGetLastError();
 }
 

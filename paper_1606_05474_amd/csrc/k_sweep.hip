@@ -54,6 +54,22 @@
 // the rounding of each stream is relative to its deviation from pi B rather
 // than to pi B itself, which is what lets FP32 sweeps resolve net fluxes at
 // depth.  Fluxes are recovered as F = G + 2 pi eps B in FP64 by the bin sum.
+//
+// Isothermal-layer grid (Sec. 2.2.1).  The same kernel solves n isothermal
+// layers between n + 1 interfaces on the sublayered point layout: interface i
+// is point 2i, layer i occupies slot 2i (dtau = kappa(centre) times the layer's
+// column mass, reference B(T_i) at both ends, so dB = 0 and eq:isoscat needs
+// no source in the deviation form) and slot 2i+1 has dtau = 0, i.e. a = 1,
+// c = 0: it carries the flux unchanged from point 2i+1 to the next interface
+// while sig = 2 pi eps (B(T_i) - B(T_i+1)) moves the deviation to the next
+// layer's reference.  Point 2i+1 then holds the flux at interface i+1.
+//
+// Rayleigh scattering (Sec. 2.1.4, template flag RAY).  The bin's H2
+// scattering opacity sigma/mbar is added to every sublayer and the albedo
+// follows per sublayer and g-point from the scattering share of the
+// extinction (g0 = 0), so r, kx and the pure-scattering switch are formed per
+// sublayer in the coefficient set-up instead of per layer in LDS; the passes
+// are unchanged.
 #include <type_traits>
 
 #include "helios_internal.hpp"
@@ -331,7 +347,7 @@ struct SweepLds {
 // give a bin one part; launches with few bins split a bin's groups over
 // several waves.  The bin-sum kernel adds a bin's partials in order, adds the
 // Planck term and sums over bins.  No barrier spans more than the wave.
-template <int K, int L, typename R, int OCC>
+template <int K, int L, typename R, int OCC, bool RAY>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using R2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
     constexpr int C = 64 / L;
@@ -391,6 +407,11 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             const double scale = (sum > 0.0) ? sigma_sb() * t2 * t2 / sum : 0.0;
             Fint = (R)(A.F_int[A.bin_off[at] + l] * scale);
         }
+        // Rayleigh scattering (Sec. 2.1.4): twice the bin's H2 scattering
+        // opacity sigma / mbar, so that its sublayer depth is kR2 times the
+        // half column mass
+        R kR2 = (R)0;
+        if constexpr (RAY) kR2 = (R)(2.0 * rayleigh_h2(A.lambda_c[A.bin_off[at] + l]) * A.inv_mbar);
 
         // ---- the bin's per-sublayer and per-layer inputs, staged once for
         // all g, padded with the identity up to the shape's capacity.  All
@@ -406,11 +427,13 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 bv[q] = B_all[pb + i];
                 pv[q] = P[i];
             }
+            if constexpr (!RAY) {
 #pragma unroll
-            for (int q = 0; q < LCH; ++q) {
-                const int i = min(lane + 64 * q, n - 1);
-                wv[q] = A.w0[lb + i];
-                gv[q] = A.g0[lb + i];
+                for (int q = 0; q < LCH; ++q) {
+                    const int i = min(lane + 64 * q, n - 1);
+                    wv[q] = A.w0[lb + i];
+                    gv[q] = A.g0[lb + i];
+                }
             }
             // sublayer differences from the next point's value: the next lane,
             // or lane 0 of the next chunk for lane 63
@@ -434,16 +457,18 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     s_pd[i] = (R)0;
                 }
             }
+            if constexpr (!RAY) {
 #pragma unroll
-            for (int q = 0; q < LCH; ++q) {
-                const int i = lane + 64 * q;
-                if (i < KL / 2) {
-                    R r = (R)1, kx = (R)0, sf = (R)0, gd = (R)-1;
-                    if (i < n) layer_g<R>((R)wv[q], (R)gv[q], D, inv_D, tpe, r, kx, sf, gd);
-                    s_lq[4 * i + 0] = r;
-                    s_lq[4 * i + 1] = kx;
-                    s_lq[4 * i + 2] = sf;
-                    s_lq[4 * i + 3] = gd;
+                for (int q = 0; q < LCH; ++q) {
+                    const int i = lane + 64 * q;
+                    if (i < KL / 2) {
+                        R r = (R)1, kx = (R)0, sf = (R)0, gd = (R)-1;
+                        if (i < n) layer_g<R>((R)wv[q], (R)gv[q], D, inv_D, tpe, r, kx, sf, gd);
+                        s_lq[4 * i + 0] = r;
+                        s_lq[4 * i + 1] = kx;
+                        s_lq[4 * i + 2] = sf;
+                        s_lq[4 * i + 3] = gd;
+                    }
                 }
             }
         }
@@ -496,6 +521,24 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool act = k < cnt;
+                if constexpr (RAY) {
+                    // the sublayer's own optics: absorption (mean of its end
+                    // opacities) plus H2 scattering; albedo w0 = scattering
+                    // share, 1 - w0 formed as the absorption share; g0 = 0
+                    const R dabs = act ? (kv[k] + kv[k + 1]) * s_hdm[lo + k] : (R)0;
+                    const R dtau = act ? dabs + kR2 * s_hdm[lo + k] : (R)0;
+                    const R omw = (dtau > (R)0) ? dabs * Prec<R>::rcp(dtau) : (R)1;
+                    r = Prec<R>::sqrt_(omw);
+                    kx = D * r;
+                    sf = tpe * inv_D;
+                    gd = (omw < (R)1e-6) ? D * (R)0.5 : (R)-1;
+                    zp = (R)0.5 + (R)0.5 * r;
+                    zm = (R)0.5 - (R)0.5 * r;
+                    zpzm = zp * zm;
+                    fu[k] = act ? fu[k] : (R)0;
+                    sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], act, ca[k], cc[k], sg[k]);
+                    continue;
+                }
                 if ((k & 1) == 0) {
                     const R* lq = s_lq + 4 * ((lo + k) >> 1);
                     r = lq[0];
@@ -506,7 +549,17 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     zm = (R)0.5 - (R)0.5 * r;
                     zpzm = zp * zm;
                 }
-                const R dtau = act ? (kv[k] + kv[k + 1]) * s_hdm[lo + k] : (R)0;
+                // sublayer: mean of its end opacities times its column mass.
+                // Isothermal-layer grid: the even slot spans the whole layer
+                // with the centre's opacity, the odd slot is the identity.
+                R dtau;
+                if ((k & 1) == 0) {
+                    const R k_lo = A.iso_grid ? kv[k + 1] : kv[k];
+                    const R hm = A.iso_grid ? s_hdm[lo + k] + s_hdm[lo + k + 1] : s_hdm[lo + k];
+                    dtau = act ? (k_lo + kv[k + 1]) * hm : (R)0;
+                } else {
+                    dtau = (act && !A.iso_grid) ? (kv[k] + kv[k + 1]) * s_hdm[lo + k] : (R)0;
+                }
                 fu[k] = act ? fu[k] : (R)0;
                 sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], act, ca[k], cc[k], sg[k]);
             }
@@ -678,15 +731,21 @@ constexpr int sweep_occ() {
     return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
 }
 
-template <int K, int L>
-static hipError_t launch_kp(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
+template <int K, int L, bool RAY>
+static hipError_t launch_kpr(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, L, false>()>), dim3(grid), dim3(64),
+        hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, L, false>(), RAY>), dim3(grid), dim3(64),
                            sweep_lds(K, L, 4), s, a);
     else
-        hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, L, true>()>), dim3(grid), dim3(64),
+        hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, L, true>(), RAY>), dim3(grid), dim3(64),
                            sweep_lds(K, L, 8), s, a);
     return hipGetLastError();
+}
+
+template <int K, int L>
+static hipError_t launch_kp(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
+    if (a.inv_mbar > 0.0) return launch_kpr<K, L, true>(a, mixed, grid, s);
+    return launch_kpr<K, L, false>(a, mixed, grid, s);
 }
 
 template <int K>

@@ -88,6 +88,8 @@ def lib():
         L.helios_workspace_bytes.argtypes = [A, ctypes.c_int]
         L.helios_workspace_bytes.restype = sz
         L.helios_flux.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
+        L.helios_flux_iso.argtypes = L.helios_flux.argtypes
+        L.helios_flux_rayleigh.argtypes = [A, _P, _P, dbl, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
         L.helios_flux_exact.argtypes = [A, _P, _P, _P, _P, _P, _P, _P, _P, sz, _P]
         L.helios_radeq.argtypes = [A, _P, _P, _P, ctypes.POINTER(HeliosReState), ctypes.POINTER(HeliosReOpts),
                                    _P, _P, _P]
@@ -329,19 +331,39 @@ def flux_exact(b: Batch, kappa, T_pt, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol,
                                    ws.numel() * ws.element_size(), _stream(stream)))
 
 
+LAYERS = ("noniso", "iso")
+
+
 def flux(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, n_scat=4, D=2.0, F_dn_g=None,
-         prec=FP64, stream=None):
-    _check(lib().helios_flux(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
-                             int(n_scat), float(D), _ptr(F_up_g), _ptr(F_dn_g), _ptr(F_up_bin),
-                             _ptr(F_dn_bin), _ptr(F_bol), _ptr(ws), ws.numel() * ws.element_size(),
-                             prec, _stream(stream)))
+         prec=FP64, stream=None, layers="noniso"):
+    """helios_flux (layers="noniso", the sublayered grid) or helios_flux_iso
+    (layers="iso", the isothermal-layer grid)."""
+    if layers not in LAYERS:
+        raise ValueError(f"layers must be one of {LAYERS}")
+    fn = lib().helios_flux if layers == "noniso" else lib().helios_flux_iso
+    _check(fn(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
+              int(n_scat), float(D), _ptr(F_up_g), _ptr(F_dn_g), _ptr(F_up_bin),
+              _ptr(F_dn_bin), _ptr(F_bol), _ptr(ws), ws.numel() * ws.element_size(),
+              prec, _stream(stream)))
 
 
-def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, stream=None):
+def flux_rayleigh(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, mbar, n_scat=4, D=2.0,
+                  F_dn_g=None, prec=FP64, stream=None):
+    """helios_flux_rayleigh: ``kappa`` holds absorption opacities; H2
+    Rayleigh scattering (mean molecular mass ``mbar`` in g) sets the
+    per-sublayer, per-g albedo; the batch's w0, g0 are not used."""
+    _check(lib().helios_flux_rayleigh(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), float(mbar), int(n_scat),
+                                      float(D), _ptr(F_up_g), _ptr(F_dn_g), _ptr(F_up_bin), _ptr(F_dn_bin),
+                                      _ptr(F_bol), _ptr(ws), ws.numel() * ws.element_size(), prec,
+                                      _stream(stream)))
+
+
+def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, stream=None, layers="noniso"):
     """Post-processing of converged profiles (Sec. 2.6, Sec. 3): one flux
     call with many scattering passes from the isothermal start; returns the
     upward flux at the top of each atmosphere per bin (a list of [n_bin]
-    device arrays) and the per-bin upward fluxes at every point."""
+    device arrays) and the per-bin upward fluxes at every point.  The paper
+    post-processes on isothermal layers (layers="iso", Sec. 3.3)."""
     dev = b.device
     rd = rdtype(prec)
     T_c = torch.as_tensor(T_c, dtype=torch.float64, device=dev)
@@ -355,7 +377,7 @@ def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, st
     db = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
     bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device=dev)
     ws = torch.zeros(workspace_bytes(b, prec), dtype=torch.uint8, device=dev)
-    flux(b, kap, T_pt, F_up, ub, db, bol, ws, n_scat=n_scat, D=D, prec=prec, stream=stream)
+    flux(b, kap, T_pt, F_up, ub, db, bol, ws, n_scat=n_scat, D=D, prec=prec, stream=stream, layers=layers)
     per_bin = b.split_pb(ub)
     return [pb_a[:, -1] for pb_a in per_bin], per_bin
 
@@ -551,10 +573,16 @@ class Solver:
     """
 
     def __init__(self, b: Batch, kt: KTable, prec=FP64, n_scat=4, D=2.0, opts: REOptions | None = None,
-                 bin_fluxes: bool = True):
+                 bin_fluxes: bool = True, layers: str = "noniso", rayleigh_mbar: float | None = None):
         dev = b.device
         rd = rdtype(prec)
+        if layers not in LAYERS:
+            raise ValueError(f"layers must be one of {LAYERS}")
+        if rayleigh_mbar is not None and layers != "noniso":
+            raise ValueError("Rayleigh scattering is solved on the sublayered grid")
         self.kt, self.prec, self.n_scat, self.D = kt, prec, n_scat, D
+        self.layers = layers  # "iso": the isothermal-layer grid (helios_flux_iso)
+        self.rayleigh_mbar = rayleigh_mbar  # H2 Rayleigh scattering with this mean molecular mass (g)
         self.bin_fluxes = bin_fluxes  # keep the per-bin fluxes of every step (the iteration needs only F_bol)
         self.opts = opts or REOptions()
         self.T_c = torch.zeros(b.total_n, dtype=torch.float64, device=dev)
@@ -642,7 +670,7 @@ class Solver:
         dev = s0.b.device
         nb = Batch([src.b.atms[int(a)] for (src, _), keep in zip(parts, keeps) for a in keep], device=dev)
         s = Solver(nb, s0.kt, prec=s0.prec if prec is None else prec, n_scat=s0.n_scat, D=s0.D,
-                   opts=s0.opts, bin_fluxes=s0.bin_fluxes)
+                   opts=s0.opts, bin_fluxes=s0.bin_fluxes, layers=s0.layers, rayleigh_mbar=s0.rayleigh_mbar)
         k = 0
         warm = []
         for (src, _), keep in zip(parts, keeps):
@@ -673,8 +701,12 @@ class Solver:
         """One RE iteration for every running atmosphere of the batch (enqueue only)."""
         b = self.b
         mix_opacity(b, self.kt, self.T_pt, self.kappa, self.prec, stream=stream)
-        flux(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol, self.ws,
-             n_scat=self.n_scat, D=self.D, prec=self.prec, stream=stream)
+        if self.rayleigh_mbar is not None:
+            flux_rayleigh(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol,
+                          self.ws, self.rayleigh_mbar, n_scat=self.n_scat, D=self.D, prec=self.prec, stream=stream)
+        else:
+            flux(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol, self.ws,
+                 n_scat=self.n_scat, D=self.D, prec=self.prec, stream=stream, layers=self.layers)
         radeq(b, self.F_bol, self.T_c, self.T_pt, self.m, self.hist, self.status, self.resid, self.opts,
               iters=self.iters, stream=stream)
 

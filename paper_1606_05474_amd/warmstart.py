@@ -225,6 +225,7 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
     s = make(0, first)
     s.autotune()  # one-time shape tuning for this process, outside the timed region
     del s
+    log(f"production: sweep shapes tuned, solving {count} atmospheres")
     gen[0] = 0.0
     fallbacks[0] = 0
     torch.cuda.synchronize()
@@ -268,6 +269,9 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
                 parts.append((sn, np.arange(k_new)))
             s2 = H.Solver.concat(parts)
             refills[0] += 1
+            if refills[0] % 8 == 0:  # progress: finished so far, elapsed
+                log(f"production: {nxt - keep.size} of {count} finished or stopped, "
+                    f"{time.perf_counter() - t0 - gen[0]:.0f} s")
             rs_cur = np.concatenate([rs_cur[keep], np.zeros(k_new, bool)])
             ids = np.concatenate([ids[keep], new_ids])
             nxt += k_new

@@ -171,6 +171,29 @@ def spectral_workload(seed: int = 2, n: int = 100, nb: int = 3000, ng: int = N_G
     return atm, ktab
 
 
+def resolution_atmosphere(seed: int, n: int, lambda_c_full: np.ndarray, dlambda_full: np.ndarray,
+                          ng: int = N_G, T_star: float = 3026.0, T_irr: float = 780.0, T_int: float = 200.0,
+                          grav: float = 893.0) -> dict:
+    """One physical atmosphere sampled on n layers, the same for every n: the
+    mixing-ratio parameters come from rng [seed, 1] and are evaluated at this
+    grid's points; w0 ~ U(0, 0.9) and g0 ~ U(0, 0.5) are drawn per bin from
+    rng [seed, 2] and constant with height.  Scalars of a cool sub-Neptune
+    around an M dwarf (stellar 3026 K, irradiation 780 K, g = 893 cm s^-2),
+    all bins of the table."""
+    nb = lambda_c_full.size
+    vmr = smooth_vmr(np.random.default_rng([seed, 1]), point_log10p_bar(n))
+    rng = np.random.default_rng([seed, 2])
+    w0 = np.repeat(rng.uniform(0.0, 0.9, size=(nb, 1)), n, axis=1)
+    g0 = np.repeat(rng.uniform(0.0, 0.5, size=(nb, 1)), n, axis=1)
+    return {
+        "n": n, "ng": ng, "P_c": pressure_centres(n), "grav": grav,
+        "T_star": T_star, "T_irr": T_irr, "T_int": T_int, "mmw": MMW,
+        "lambda_c": lambda_c_full.copy(), "dlambda": dlambda_full.copy(),
+        "bin_index": np.arange(nb, dtype=np.int32), "w0": w0, "g0": g0, "vmr": vmr,
+        "T0": np.full(n, 1000.0),
+    }
+
+
 def batch_workload(seed: int = 3, n_atm: int = 512, n_range=(50, 200), nb_range=(400, 3000),
                    ng: int = N_G, ktab: dict | None = None):
     """Uneven batch: per atmosphere n ~ U{n_range}, bins ~ U{nb_range} (strided

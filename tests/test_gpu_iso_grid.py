@@ -1,0 +1,224 @@
+"""Isothermal-layer grid (Sec. 2.2.1): helios_flux_iso against the oracle's
+solve on n isothermal layers between n + 1 interfaces, on the same seeded
+inputs.
+
+The GPU keeps the sublayered point layout: point 2i holds interface i and
+point 2i+1 the top of layer i (interface i+1); its per-g arrays are
+deviations from (2 pi / D) B(T_i) at points 2i and 2i+1 and from
+(2 pi / D) B(T_{n-1}) at the TOA point.  Tolerances as for helios_flux: FP64
+net flux within 1e-10 of the gross flux at every point, per-g and per-bin
+fluxes within 1e-11 of their column's largest value; MIXED within 1e-4.
+All calls go through the C ABI.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as ref
+from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux
+from paper_1606_05474_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+H = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global H
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1606_05474_amd import helios
+
+    H = helios
+    H.lib()
+    yield
+
+
+@pytest.fixture(scope="module")
+def small_table():
+    return W.table_ktab(2, nbt=300)
+
+
+def _t(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _np(x):
+    return x.detach().cpu().numpy()
+
+
+def _iface(npt):
+    """Oracle interface held by each GPU point."""
+    return (np.arange(npt) + 1) // 2
+
+
+def _ref_T(T_c, count):
+    """Temperature of the reference Planck value at each of `count` GPU
+    points (count = 2n+1) or oracle interfaces (count = n+1)."""
+    n = len(T_c)
+    idx = np.arange(count) // 2 if count == 2 * n + 1 else np.arange(count)
+    return np.asarray(T_c)[np.minimum(idx, n - 1)]
+
+
+def _iso_start(atm, T_c):
+    """Oracle warm start equal to the GPU's zero deviations."""
+    iso = ref.isothermal_flux(atm, _ref_T(T_c, atm["n"] + 1))
+    return np.ascontiguousarray(np.broadcast_to(iso[:, None, :], (iso.shape[0], atm["ng"], iso.shape[1])))
+
+
+def _gpu_iso(b, kap, T_pt, prec, n_scat=4, F_up0=None):
+    rd = H.rdtype(prec)
+    F_up = torch.zeros(b.total_cell, dtype=rd, device="cuda") if F_up0 is None else F_up0
+    F_dn = torch.zeros(b.total_cell, dtype=rd, device="cuda")
+    ub = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    db = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(H.workspace_bytes(b, prec), dtype=torch.uint8, device="cuda")
+    H.flux(b, kap.to(rd), T_pt, F_up, ub, db, bol, ws, n_scat=n_scat, F_dn_g=F_dn, prec=prec, layers="iso")
+    torch.cuda.synchronize()
+    return F_up, F_dn, ub, db, bol
+
+
+def _check(b, a, T_c, r, up_ref, out, tol=1e-10, tol_g=1e-11):
+    F_up, F_dn, ub, db, bol = out
+    atm = b.atms[a]
+    npt = 2 * atm["n"] + 1
+    j = _iface(npt)
+    bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
+    err = net_flux_error(bol_a, r["F_bol"][j])
+    assert err.max() < tol, err.max()
+    iso = ref.isothermal_flux(atm, _ref_T(T_c, npt))
+    if tol_g is None:
+        return
+    gu = to_flux(b.split_cell(_np(F_up))[a], iso)
+    assert col_rel_error(gu, up_ref[:, :, j]).max() < tol_g
+    gd = to_flux(b.split_cell(_np(F_dn))[a], iso)
+    assert col_rel_error(gd, r["F_dn"][:, :, j]).max() < tol_g
+    assert col_rel_error(b.split_pb(_np(ub))[a], r["F_up_bin"][:, j]).max() < tol_g
+    assert col_rel_error(b.split_pb(_np(db))[a], r["F_dn_bin"][:, j]).max() < tol_g
+
+
+def _case(name, small_table):
+    if name == "plain":
+        atm, kt = W.plain_workload()
+        return atm, kt, 4
+    lc, dl = W.bins(300)
+    n, nb, n_scat = {"table": (61, 23, 11), "cold": (100, 40, 0), "deep": (200, 6, 4)}[name]
+    atm = W.spectral_atmosphere(np.random.default_rng(n + 7), n, lc, dl, nb)
+    return atm, small_table, n_scat
+
+
+@pytest.mark.parametrize("name", ["plain", "table", "cold", "deep"])
+def test_flux_iso_matches_oracle(name, small_table):
+    """FP64 per point, per g and per bin, n_scat = 0, 4 and 11."""
+    atm, kt, n_scat = _case(name, small_table)
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap = oracle_state(atm, kt, T_c)
+    up_ref = _iso_start(atm, T_c)
+    r = ref.flux_iso(atm, kap[:, :, 1::2], T_c, P[0::2], up_ref, n_scat=n_scat)
+    out = _gpu_iso(b, b.pack_cell([kap]), _t(T), 0, n_scat=n_scat)
+    _check(b, 0, T_c, r, up_ref, out)
+
+
+def test_flux_iso_warm_start_second_call():
+    """A second call at new temperatures continues from the first call's
+    deviations (the oracle's warm start moves with the reference Planck
+    values)."""
+    atm, kt = W.plain_workload()
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap = oracle_state(atm, kt, T_c)
+    up_ref = _iso_start(atm, T_c)
+    ref.flux_iso(atm, kap[:, :, 1::2], T_c, P[0::2], up_ref)
+    out = _gpu_iso(b, b.pack_cell([kap]), _t(T), 0)
+    T_c2 = T_c * 1.02
+    P, T2, kap2 = oracle_state(atm, kt, T_c2)
+    n = atm["n"]
+    up_ref += (ref.isothermal_flux(atm, _ref_T(T_c2, n + 1)) - ref.isothermal_flux(atm, _ref_T(T_c, n + 1)))[:, None]
+    r2 = ref.flux_iso(atm, kap2[:, :, 1::2], T_c2, P[0::2], up_ref)
+    out2 = _gpu_iso(b, b.pack_cell([kap2]), _t(T2), 0, F_up0=out[0])
+    _check(b, 0, T_c2, r2, up_ref, out2)
+
+
+def test_flux_iso_mixed_precision_within_tolerance(small_table):
+    lc, dl = W.bins(300)
+    atm = W.spectral_atmosphere(np.random.default_rng(3), 100, lc, dl, 60)
+    b = H.Batch([atm])
+    H.grid(b)
+    T_c = smooth_profile(atm)
+    P, T, kap = oracle_state(atm, small_table, T_c)
+    up_ref = _iso_start(atm, T_c)
+    r = ref.flux_iso(atm, kap[:, :, 1::2], T_c, P[0::2], up_ref)
+    kap_m = torch.zeros(b.total_cell, dtype=torch.float32, device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), _t(T), kap_m, 1)
+    out = _gpu_iso(b, kap_m, _t(T), 1)
+    _check(b, 0, T_c, r, up_ref, out, tol=1e-4, tol_g=None)
+    j = _iface(2 * atm["n"] + 1)
+    assert col_rel_error(b.split_pb(_np(out[2]))[0], r["F_up_bin"][:, j]).max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_flux_iso_ragged_batch_spanning_size_classes(prec, small_table):
+    """Atmospheres of every size class (2 to 400 layers) in one call, each
+    against its own oracle solve; the opacities are the library's own."""
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(41)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb, T_irr=ti, T_int=tint)
+            for n, nb, ti, tint in [(2, 5, 1200.0, 150.0), (40, 9, 2500.0, 500.0), (64, 4, 900.0, 0.0),
+                                    (111, 6, 1800.0, 300.0), (208, 3, 1500.0, 200.0), (400, 2, 2000.0, 400.0)]]
+    b = H.Batch(atms)
+    H.grid(b)
+    T_cs = [smooth_profile(a, 1500 + 100 * i, 700 + 50 * i) for i, a in enumerate(atms)]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, prec)
+    out = _gpu_iso(b, kap, T_pt, prec)
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
+        up_ref = _iso_start(atm, T_cs[a])
+        r = ref.flux_iso(atm, kap_ref[:, :, 1::2], T_cs[a], P[0::2], up_ref)
+        if prec == 0:
+            _check(b, a, T_cs[a], r, up_ref, out)
+        else:
+            _check(b, a, T_cs[a], r, up_ref, out, tol=1e-4, tol_g=None)
+
+
+def test_iso_re_solve_matches_oracle():
+    """Radiative equilibrium on the isothermal-layer grid (FP64): the same
+    number of updates and the same converged profile as the oracle with the
+    same (deviation) warm start."""
+    atm, kt = W.plain_workload(n=12, nb=12, ng=4)
+    sol = ref.solve(atm, kt, max_iter=1000, layers="iso", warm="deviation")
+    assert sol["converged"]
+    b = H.Batch([atm])
+    s = H.Solver(b, H.KTable(kt), prec=H.FP64, layers="iso")
+    conv, iters = s.solve(atm["T0"], max_iter=1000)
+    assert conv[0]
+    dT = np.abs(_np(s.T_c) - sol["T_c"])
+    assert dT.max() < 0.1, dT.max()
+    assert abs(int(iters[0]) - sol["iterations"]) <= 10, (iters[0], sol["iterations"])
+    net = _np(s.F_bol).reshape(-1, 3)[0::2, 2]
+    s4 = ref.sigma_sb() * atm["T_int"] ** 4
+    assert np.abs(net - s4).max() < atm["n"] * 1e-3 * s4
+
+
+def test_iso_post_processing_spectrum_with_80_passes():
+    """The paper's post-processing form: isothermal layers, 80 scattering
+    passes from the isothermal start; TOA upward flux per bin, FP64."""
+    lc, dl = W.bins(300)
+    atm = W.spectral_atmosphere(np.random.default_rng(82), 101, lc, dl, 300)
+    kt = W.table_ktab(2, nbt=300)
+    T_c = smooth_profile(atm, 1900.0, 1100.0)
+    b = H.Batch([atm])
+    toa, per_bin = H.emission_spectrum(b, H.KTable(kt), T_c, n_scat=80, layers="iso")
+    P, T, kap = oracle_state(atm, kt, T_c)
+    r = ref.flux_iso(atm, kap[:, :, 1::2], T_c, P[0::2], _iso_start(atm, T_c), n_scat=80, want_dn=False)
+    want = r["F_up_bin"][:, -1]
+    got = _np(toa[0])
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    j = _iface(2 * atm["n"] + 1)
+    assert col_rel_error(_np(per_bin[0]), r["F_up_bin"][:, j]).max() < 1e-11

@@ -1,0 +1,162 @@
+"""Rayleigh scattering by H2 (Sec. 2.1.4): helios_flux_rayleigh against the
+oracle on the same seeded inputs.  The opacities passed are absorption
+opacities; both sides add sigma/mbar per bin and take the albedo per sublayer
+and g-point.  Tolerances as for helios_flux: FP64 net flux within 1e-10 of
+the gross flux at every point, per-g and per-bin fluxes within 1e-11 of
+their column's largest value; MIXED within 1e-4.  All calls go through the
+C ABI.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as ref
+from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux
+from paper_1606_05474_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+H = None
+MBAR = 2.4 * 1.67262192369e-24
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global H
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1606_05474_amd import helios
+
+    H = helios
+    H.lib()
+    yield
+
+
+@pytest.fixture(scope="module")
+def small_table():
+    return W.table_ktab(2, nbt=300)
+
+
+def _t(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _np(x):
+    return x.detach().cpu().numpy()
+
+
+def _gpu_ray(b, kap, T_pt, prec, n_scat=4):
+    rd = H.rdtype(prec)
+    F_up = torch.zeros(b.total_cell, dtype=rd, device="cuda")
+    F_dn = torch.zeros(b.total_cell, dtype=rd, device="cuda")
+    ub = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    db = torch.zeros(b.total_pb, dtype=torch.float64, device="cuda")
+    bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(H.workspace_bytes(b, prec), dtype=torch.uint8, device="cuda")
+    H.flux_rayleigh(b, kap.to(rd), T_pt, F_up, ub, db, bol, ws, MBAR, n_scat=n_scat, F_dn_g=F_dn, prec=prec)
+    torch.cuda.synchronize()
+    return F_up, F_dn, ub, db, bol
+
+
+def _check(b, a, T, r, up_ref, out, tol=1e-10, tol_g=1e-11):
+    F_up, F_dn, ub, db, bol = out
+    bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
+    err = net_flux_error(bol_a, r["F_bol"])
+    assert err.max() < tol, err.max()
+    if tol_g is None:
+        return
+    iso = ref.isothermal_flux(b.atms[a], T)
+    assert col_rel_error(to_flux(b.split_cell(_np(F_up))[a], iso), up_ref).max() < tol_g
+    assert col_rel_error(to_flux(b.split_cell(_np(F_dn))[a], iso), r["F_dn"]).max() < tol_g
+    assert col_rel_error(b.split_pb(_np(ub))[a], r["F_up_bin"]).max() < tol_g
+    assert col_rel_error(b.split_pb(_np(db))[a], r["F_dn_bin"]).max() < tol_g
+
+
+@pytest.mark.parametrize("name", ["plain", "table", "cold"])
+def test_flux_rayleigh_matches_oracle(name, small_table):
+    if name == "plain":
+        atm, kt = W.plain_workload()
+        n_scat = 4
+    else:
+        lc, dl = W.bins(300)
+        n, nb, n_scat = {"table": (61, 23, 11), "cold": (100, 40, 0)}[name]
+        atm = W.spectral_atmosphere(np.random.default_rng(n + 3), n, lc, dl, nb)
+        kt = small_table
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, kt, smooth_profile(atm))
+    up_ref = ref.isothermal_start(atm, T)
+    r = ref.flux_rayleigh(atm, kap, T, P, up_ref, n_scat=n_scat)
+    out = _gpu_ray(b, b.pack_cell([kap]), _t(T), 0, n_scat=n_scat)
+    _check(b, 0, T, r, up_ref, out)
+
+
+def test_flux_rayleigh_without_absorption_takes_the_pure_scattering_form(small_table):
+    """Points and bins without absorption: sublayers that only scatter
+    (w0 = 1, eq:purescat) next to absorbing ones."""
+    lc, dl = W.bins(300)
+    atm = W.spectral_atmosphere(np.random.default_rng(5), 40, lc, dl, 12)
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
+    kap[:, :, 20:40] = 0.0
+    kap[3] = 0.0
+    up_ref = ref.isothermal_start(atm, T)
+    r = ref.flux_rayleigh(atm, kap, T, P, up_ref, n_scat=9)
+    out = _gpu_ray(b, b.pack_cell([kap]), _t(T), 0, n_scat=9)
+    _check(b, 0, T, r, up_ref, out)
+
+
+def test_flux_rayleigh_mixed_precision_within_tolerance(small_table):
+    lc, dl = W.bins(300)
+    atm = W.spectral_atmosphere(np.random.default_rng(4), 100, lc, dl, 60)
+    b = H.Batch([atm])
+    H.grid(b)
+    P, T, kap = oracle_state(atm, small_table, smooth_profile(atm))
+    up_ref = ref.isothermal_start(atm, T)
+    r = ref.flux_rayleigh(atm, kap, T, P, up_ref)
+    kap_m = torch.zeros(b.total_cell, dtype=torch.float32, device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), _t(T), kap_m, 1)
+    out = _gpu_ray(b, kap_m, _t(T), 1)
+    _check(b, 0, T, r, up_ref, out, tol=1e-4, tol_g=None)
+    assert col_rel_error(b.split_pb(_np(out[2]))[0], r["F_up_bin"]).max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_flux_rayleigh_ragged_batch_spanning_size_classes(prec, small_table):
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(43)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb, T_irr=ti, T_int=tint)
+            for n, nb, ti, tint in [(2, 5, 1200.0, 150.0), (40, 9, 2500.0, 500.0), (64, 4, 900.0, 0.0),
+                                    (111, 6, 1800.0, 300.0), (208, 3, 1500.0, 200.0), (400, 2, 2000.0, 400.0)]]
+    b = H.Batch(atms)
+    H.grid(b)
+    T_cs = [smooth_profile(a, 1500 + 100 * i, 700 + 50 * i) for i, a in enumerate(atms)]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, prec)
+    out = _gpu_ray(b, kap, T_pt, prec)
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
+        up_ref = ref.isothermal_start(atm, T)
+        r = ref.flux_rayleigh(atm, kap_ref, T, P, up_ref)
+        if prec == 0:
+            _check(b, a, T, r, up_ref, out)
+        else:
+            _check(b, a, T, r, up_ref, out, tol=1e-4, tol_g=None)
+
+
+def test_rayleigh_re_solve_matches_oracle():
+    """Radiative equilibrium with Rayleigh scattering (FP64): the same
+    number of updates and the same converged profile as the oracle with the
+    same (deviation) warm start."""
+    atm, kt = W.plain_workload(n=30, nb=20, ng=4)
+    sol = ref.solve(atm, kt, max_iter=600, rayleigh=True, warm="deviation")
+    assert sol["converged"]
+    b = H.Batch([atm])
+    s = H.Solver(b, H.KTable(kt), prec=H.FP64, rayleigh_mbar=MBAR)
+    conv, iters = s.solve(atm["T0"], max_iter=600)
+    assert conv[0]
+    dT = np.abs(_np(s.T_c) - sol["T_c"])
+    assert dT.max() < 0.1, dT.max()
+    assert abs(int(iters[0]) - sol["iterations"]) <= 10, (iters[0], sol["iterations"])
