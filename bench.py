@@ -317,7 +317,8 @@ def layers_main(args):
         T = [t.cpu().numpy() for t in b.split_layer(s.T_c)]
         toa, _ = H.emission_spectrum(b, KT, s.T_c, n_scat=80, layers=layers)
         # one RE update's time on this batch with every member running
-        s2 = H.Solver(b, KT, prec=H.FP64, layers=layers, bin_fluxes=False, opts=H.REOptions(osc_any=1))
+        # tolerance 0: no member can freeze while the update is timed
+        s2 = H.Solver(b, KT, prec=H.FP64, layers=layers, bin_fluxes=False, opts=H.REOptions(osc_any=1, tol=0.0))
         s2.reset(s.T_c)
         for _ in range(3):
             s2.step()
@@ -341,12 +342,18 @@ def layers_main(args):
         T_ref = np.interp(np.log(m["P_c"]), lp_ref, ref_m["T"][::-1])
         dT = np.abs(m["T"] - T_ref)
         dev = np.abs(m["spec"] / ref_m["spec"] - 1.0)
+        bright = ref_m["spec"] >= 1e-3 * ref_m["spec"].max()  # bins that carry the emitted flux
+        k_max = int(np.argmax(dT))
         out[key] = {"converged": m["converged"], "updates": m["updates"],
                     "max_abs_dT_vs_noniso400_K": float(dT.max()),
+                    "max_abs_dT_at_bar": float(m["P_c"][k_max] / 1e6),
                     "median_abs_dT_vs_noniso400_K": float(np.median(dT)),
+                    "max_abs_dT_between_1e-4_and_10_bar_K": float(dT[(m["P_c"] >= 1e2) & (m["P_c"] <= 1e7)].max()),
                     "spectrum_median_rel_dev": float(np.median(dev)),
                     "spectrum_max_rel_dev": float(dev.max()),
-                    "spectrum_bins_above_1pct": float(np.mean(dev > 0.01))}
+                    "spectrum_bins_above_1pct": float(np.mean(dev > 0.01)),
+                    "spectrum_max_rel_dev_bright_bins": float(dev[bright].max()),
+                    "spectrum_bright_bins_above_1pct": float(np.mean(dev[bright] > 0.01))}
     line = {"metric": "layer resolution study", "value": None, "unit": None, "n_gpus": 1, "dtype": "f64",
             "data": "synthetic", "higher_is_better": None,
             "config": {"workload": "one atmosphere (stellar 3026 K, irradiation 780 K, T_int 200 K, g 893 cm s^-2, "
