@@ -274,14 +274,14 @@ def chunk_main(args):
 def layers_main(args):
     """The layer-resolution study of Sec. 3.3 on a synthetic stand-in: one
     physical atmosphere solved to radiative equilibrium on sublayered grids
-    of 21, 51, 101 and 400 layers and on isothermal-layer grids of 51, 101,
+    of 21, 51, 101 and 501 layers and on isothermal-layer grids of 51, 101,
     201 and 400 layers (FP64, all 3000 bins, tolerance 1e-3 sigma T_int^4),
     then post-processed (80 scattering passes) to TOA emission spectra.
-    Reported: each profile against the 400-layer sublayered one (linear in
+    Reported: each profile against the 501-layer sublayered one (linear in
     log P at the model's layer centres), each spectrum's deviation from that
     model's spectrum, the updates to converge and the time per update.  The
     step control counts any sign change within the 6-step window as an
-    oscillation: with the strict-alternation reading the 400-layer model
+    oscillation: with the strict-alternation reading a 400-layer model
     oscillates with period 4 and its step multipliers never shrink."""
     import time
 
@@ -294,7 +294,7 @@ def layers_main(args):
     kt = W.table_ktab(2)
     KT = H.KTable(kt)
     lc, dl = W.bins(3000)
-    grids = {"noniso": (21, 51, 101, 400), "iso": (51, 101, 201, 400)}
+    grids = {"noniso": (21, 51, 101, 501), "iso": (51, 101, 201, 400)}
     res = {}
     log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
     for layers, ns in grids.items():
@@ -333,7 +333,7 @@ def layers_main(args):
             res[f"{layers}{n}"] = {"P_c": atms[k]["P_c"], "T": T[k], "spec": toa[k].cpu().numpy(),
                                    "converged": bool(conv[k]), "updates": int(iters[k])}
         res[layers] = {"seconds": sec, "ms_per_update_all_running": e0.elapsed_time(e1) / 10}
-    ref_m = res["noniso400"]
+    ref_m = res["noniso501"]
     lp_ref = np.log(ref_m["P_c"])[::-1]
     out = {}
     for key, m in res.items():
@@ -345,9 +345,9 @@ def layers_main(args):
         bright = ref_m["spec"] >= 1e-3 * ref_m["spec"].max()  # bins that carry the emitted flux
         k_max = int(np.argmax(dT))
         out[key] = {"converged": m["converged"], "updates": m["updates"],
-                    "max_abs_dT_vs_noniso400_K": float(dT.max()),
+                    "max_abs_dT_vs_noniso501_K": float(dT.max()),
                     "max_abs_dT_at_bar": float(m["P_c"][k_max] / 1e6),
-                    "median_abs_dT_vs_noniso400_K": float(np.median(dT)),
+                    "median_abs_dT_vs_noniso501_K": float(np.median(dT)),
                     "max_abs_dT_between_1e-4_and_10_bar_K": float(dT[(m["P_c"] >= 1e2) & (m["P_c"] <= 1e7)].max()),
                     "spectrum_median_rel_dev": float(np.median(dev)),
                     "spectrum_max_rel_dev": float(dev.max()),
@@ -360,7 +360,7 @@ def layers_main(args):
                                    "synthetic 4-species tables, w0 and g0 per bin), 3000 bins x 20 g, P centres "
                                    "1e-6 .. 1e3 bar; RE to 1e-3 sigma T_int^4 in FP64 from 1000 K (any sign change in the "
                                    "6-step window shrinks the step), spectra with 80 "
-                                   "scattering passes on each model's own grid; reference: 400 sublayered layers"},
+                                   "scattering passes on each model's own grid; reference: 501 sublayered layers"},
             "models": out,
             "time": {k: res[k] for k in grids}}
     print(json.dumps(line))
@@ -624,7 +624,7 @@ def main(argv=None):
                     help="convergence tolerance of the production form's reduced-precision stages (the plain "
                          "form uses 1e-3 in FP64; 7e-4 makes the production profiles pass the FP64 test at 1e-3)")
     ap.add_argument("--max-iter", type=int, default=None,
-                    help="update cap (batch: 300; production: 2000 for both forms)")
+                    help="update cap (batch: 300; production: 1500 for both forms; layers: 60000)")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -656,7 +656,7 @@ def main(argv=None):
     if args.n_atm is None:
         args.n_atm = {"production": 4096, "chunk": 128}.get(args.workload, 512)
     if args.max_iter is None:
-        args.max_iter = {"production": 2000, "layers": 60000}.get(args.workload, 300)
+        args.max_iter = {"production": 1500, "layers": 60000}.get(args.workload, 300)
     if args.workload == "batch":
         return batch_main(args)
     if args.workload == "production":

@@ -59,7 +59,7 @@ extern "C" {
 
 #define HELIOS_MAX_SPECIES 8
 #define HELIOS_MAX_NG 32
-#define HELIOS_MAX_LAYERS 400
+#define HELIOS_MAX_LAYERS 832
 #define HELIOS_CELL_ALIGN 32
 
 typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;

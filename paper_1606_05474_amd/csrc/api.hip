@@ -36,8 +36,8 @@ int hip_fail(hipError_t e, const char* where) {
 // Size classes of the batched sweep, by layer count: atmospheres of one
 // class share a sweep launch and its shape, so a short atmosphere does not
 // run with the lane count of the deepest one.
-constexpr int kNumClasses = 5;
-constexpr int kClassNHi[kNumClasses] = {32, 64, 112, 208, HELIOS_MAX_LAYERS};
+constexpr int kNumClasses = 6;
+constexpr int kClassNHi[kNumClasses] = {32, 64, 112, 208, 400, HELIOS_MAX_LAYERS};
 static_assert(kNumClasses <= kMaxClasses, "class table");
 
 int class_of(int n) {
@@ -200,6 +200,13 @@ bool k_allowed(int K, bool /*mixed*/) {
     return false;
 }
 
+// Instantiated shapes: every K with L = 16 and 32, and the long-column
+// shape (kLongK, 64).
+bool shape_allowed(int K, int L, bool mixed) {
+    if (!k_allowed(K, mixed)) return false;
+    return L == 16 || L == 32 || (L == 64 && K == kLongK);
+}
+
 // Shapes chosen by helios_autotune, per (precision, n_g, size class).
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, SweepShape> g_tuned;
@@ -208,9 +215,9 @@ int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
     // fewest sublayers per lane first (smallest register footprint), then
     // the narrower column
     for (int i = 0; i < kNumSweepK; ++i) {
-        for (int L : {16, 32}) {
+        for (int L : {16, 32, 64}) {
             int K = kSweepK[i];
-            if (!k_allowed(K, mixed)) continue;
+            if (!shape_allowed(K, L, mixed)) continue;
             if (K * L >= nsub_max) {
                 sh = {K, L};
                 return HELIOS_OK;
@@ -226,7 +233,7 @@ int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
 int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh) {
     int fk = env_int("HELIOS_SWEEP_K", 0), fl = env_int("HELIOS_SWEEP_L", 0);
     if (fk || fl) {
-        if (!k_allowed(fk, mixed) || (fl != 16 && fl != 32))
+        if (!shape_allowed(fk, fl, mixed))
             return fail(HELIOS_EINVAL, "HELIOS_SWEEP_K/L = %d/%d not available", fk, fl);
         if (fk * fl < nsub_max) return fail(HELIOS_ESHAPE, "K*L = %d < %d sublayers", fk * fl, nsub_max);
         sh = {fk, fl, std::max(1, env_int("HELIOS_SWEEP_P", 1))};
@@ -715,13 +722,14 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
         const int nsub = 2 * p.z.cls_nmax[k];
         SweepShape best = p.sh[k];
         float best_ms = 1e30f;
-        for (int L : {16, 32}) {
+        for (int L : {16, 32, 64}) {
           const int groups = waves_per_bin(atm->n_g, L);
           for (int P : {1, 2, groups}) {
             if (P > std::min(groups, parts_stride(p.z, atm->n_g)) || (P == groups && P <= 2 && P != 1)) continue;
             for (int i = 0; i < kNumSweepK; ++i) {
                 SweepShape c = {kSweepK[i], L, P};
-                if (!k_allowed(c.K, p.mixed) || c.K * c.L < nsub) continue;
+                if (!shape_allowed(c.K, c.L, p.mixed) || c.K * c.L < nsub) continue;
+                if (c.L == 64 && nsub <= kLongK * 32) continue;  // the long shape only where nothing else fits
                 const int parts = P;
                 if ((e = sweep_class(A, c, k, b_lo, b_lo + nbs, parts, p.mixed, s)) != hipSuccess)  // warm-up
                     return cleanup(hip_fail(e, "helios_autotune (sweep)"));

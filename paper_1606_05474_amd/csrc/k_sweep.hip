@@ -3,7 +3,8 @@
 // scattering passes, and the Gauss sum over g.
 //
 // Mapping.  One workgroup owns one wavelength bin of one atmosphere: n_g
-// columns (one per Gauss point) of L lanes each.  Lane `seg` of a column owns
+// columns (one per Gauss point) of L lanes each (L = 16 or 32; the
+// long-column shape K = 26, L = 64 gives one column the whole wave).  Lane `seg` of a column owns
 // K consecutive sublayers [seg*K, seg*K + K) and the K points at their lower
 // ends.  Its sublayer coefficients and its upward fluxes stay in VGPRs for
 // all passes, so a call reads kappa, B, w0/g0 and the warm start once and
@@ -296,6 +297,7 @@ __device__ inline void scan_down_full(R& MA, R& MB, int seg) {
     down_pair<L, 4>(MA, MB, seg);
     down_pair<L, 8>(MA, MB, seg);
     if constexpr (L > 16) down_pair<L, 16>(MA, MB, seg);
+    if constexpr (L > 32) down_pair<L, 32>(MA, MB, seg);
 }
 template <int L, typename R>
 __device__ inline void scan_up_full(R& MA, R& MB, int seg) {
@@ -304,6 +306,7 @@ __device__ inline void scan_up_full(R& MA, R& MB, int seg) {
     up_pair<L, 4>(MA, MB, seg);
     up_pair<L, 8>(MA, MB, seg);
     if constexpr (L > 16) up_pair<L, 16>(MA, MB, seg);
+    if constexpr (L > 32) up_pair<L, 32>(MA, MB, seg);
 }
 
 // Sum of v over the wave's C = 64/L columns (lanes seg, seg + L, ...); every
@@ -570,7 +573,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // and every pass).  The boundary values are folded into the end
         // segments (top: F_dn = F_top; bottom: F_up = F_dn + F_int), so every
         // scanned map ends up constant and only its offset b is scanned.
-        constexpr int LOG2L = (L == 16) ? 4 : 5;
+        constexpr int LOG2L = (L == 16) ? 4 : (L == 32 ? 5 : 6);
         // keep the scan multipliers in registers unless that would spill
         constexpr bool PRECOMP = (sizeof(R) == 4) || (K <= 14);
         R pseg = (R)1;
@@ -588,7 +591,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 else if (t == 1) { a2 = grp_down<L, 2>(ma); b2 = grp_up<L, 2>(mb); }
                 else if (t == 2) { a2 = grp_down<L, 4>(ma); b2 = grp_up<L, 4>(mb); }
                 else if (t == 3) { a2 = grp_down<L, 8>(ma); b2 = grp_up<L, 8>(mb); }
-                else { a2 = grp_down<L, 16>(ma); b2 = grp_up<L, 16>(mb); }
+                else if (t == 4) { a2 = grp_down<L, 16>(ma); b2 = grp_up<L, 16>(mb); }
+                else { a2 = grp_down<L, 32>(ma); b2 = grp_up<L, 32>(mb); }
                 const bool okd = seg + d < L, oku = seg >= d;
                 mdn[t] = okd ? ma : (R)0;
                 mup[t] = oku ? mb : (R)0;
@@ -647,7 +651,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 MB = scan_down_step<L, 1>(MB, mdn[1]);
                 MB = scan_down_step<L, 2>(MB, mdn[2]);
                 MB = scan_down_step<L, 3>(MB, mdn[3]);
-                if constexpr (LOG2L > 4) MB = scan_down_step<L, 4>(MB, mdn[LOG2L - 1]);
+                if constexpr (LOG2L > 4) MB = scan_down_step<L, 4>(MB, mdn[4 < LOG2L ? 4 : 0]);
+                if constexpr (LOG2L > 5) MB = scan_down_step<L, 5>(MB, mdn[5 < LOG2L ? 5 : 0]);
             } else {
                 R MA = (seg == L - 1) ? (R)0 : pseg;
                 scan_down_full<L>(MA, MB, seg);
@@ -686,7 +691,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 MB = scan_up_step<L, 1>(MB, mup[1]);
                 MB = scan_up_step<L, 2>(MB, mup[2]);
                 MB = scan_up_step<L, 3>(MB, mup[3]);
-                if constexpr (LOG2L > 4) MB = scan_up_step<L, 4>(MB, mup[LOG2L - 1]);
+                if constexpr (LOG2L > 4) MB = scan_up_step<L, 4>(MB, mup[4 < LOG2L ? 4 : 0]);
+                if constexpr (LOG2L > 5) MB = scan_up_step<L, 5>(MB, mup[5 < LOG2L ? 5 : 0]);
             } else {
                 R MA = (seg == 0) ? (R)0 : pseg;
                 scan_up_full<L>(MA, MB, seg);
@@ -727,18 +733,33 @@ static size_t sweep_lds(int K, int L, size_t rbytes) { return (size_t)SweepLds(K
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills.
 template <int K, int L, bool F64>
 constexpr int sweep_occ() {
+    if (L == 64) return 1;  // the long-column shape: whole register file, large LDS staging
     if (F64) return (K <= 4) ? 4 : ((K <= 8) ? 3 : (K <= 14 ? 2 : 1));
     return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
 }
 
+// Dynamic LDS beyond 64 KB (the FP64 long-column shape) is declared to the
+// runtime once per instantiation before its first launch.
+template <typename Kern>
+static hipError_t allow_lds(Kern kern, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
 template <int K, int L, bool RAY>
 static hipError_t launch_kpr(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
-    if (mixed)
-        hipLaunchKernelGGL((sweep_kernel<K, L, float, sweep_occ<K, L, false>(), RAY>), dim3(grid), dim3(64),
-                           sweep_lds(K, L, 4), s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<K, L, double, sweep_occ<K, L, true>(), RAY>), dim3(grid), dim3(64),
-                           sweep_lds(K, L, 8), s, a);
+    if (mixed) {
+        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false>(), RAY>;
+        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 4));
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 4), s, a);
+    } else {
+        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true>(), RAY>;
+        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 8));
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 8), s, a);
+    }
     return hipGetLastError();
 }
 
@@ -752,6 +773,9 @@ template <int K>
 static hipError_t launch_kl(const SweepArgs& a, int L, bool mixed, int grid, hipStream_t s) {
     if (L == 16) return launch_kp<K, 16>(a, mixed, grid, s);
     if (L == 32) return launch_kp<K, 32>(a, mixed, grid, s);
+    if constexpr (K == kLongK) {
+        if (L == 64) return launch_kp<K, 64>(a, mixed, grid, s);
+    }
     return hipErrorInvalidValue;
 }
 

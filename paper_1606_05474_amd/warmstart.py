@@ -158,7 +158,7 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
 
 
 def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, pool: int = 256,
-               n: int = 200, nb: int = 3000, max_iter: int = 2000, restart_after: int = 1000,
+               n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 1000,
                check_every: int = 10, deadband: int = 1, polish_iter: int = 0, m0: float = 0.3, keep_T: int = 0,
                tol: float = 7e-4, refill: float = 0.75, log=print):
     """The production form: atmospheres start..start+count-1 of a parameter

@@ -162,13 +162,14 @@ def test_flux_iso_mixed_precision_within_tolerance(small_table):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_flux_iso_ragged_batch_spanning_size_classes(prec, small_table):
-    """Atmospheres of every size class (2 to 400 layers) in one call, each
+    """Atmospheres of every size class (2 to 600 layers) in one call, each
     against its own oracle solve; the opacities are the library's own."""
     lc, dl = W.bins(300)
     rng = np.random.default_rng(41)
     atms = [W.spectral_atmosphere(rng, n, lc, dl, nb, T_irr=ti, T_int=tint)
             for n, nb, ti, tint in [(2, 5, 1200.0, 150.0), (40, 9, 2500.0, 500.0), (64, 4, 900.0, 0.0),
-                                    (111, 6, 1800.0, 300.0), (208, 3, 1500.0, 200.0), (400, 2, 2000.0, 400.0)]]
+                                    (111, 6, 1800.0, 300.0), (208, 3, 1500.0, 200.0), (400, 2, 2000.0, 400.0),
+                                    (600, 2, 1300.0, 250.0)]]
     b = H.Batch(atms)
     H.grid(b)
     T_cs = [smooth_profile(a, 1500 + 100 * i, 700 + 50 * i) for i, a in enumerate(atms)]
@@ -222,3 +223,26 @@ def test_iso_post_processing_spectrum_with_80_passes():
     assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
     j = _iface(2 * atm["n"] + 1)
     assert col_rel_error(_np(per_bin[0]), r["F_up_bin"][:, j]).max() < 1e-11
+
+
+@pytest.mark.parametrize("mode", ["iso", "rayleigh"])
+def test_graph_replayed_solve_equals_eager_solve_in_other_modes(mode):
+    """The isothermal grid and the Rayleigh variant inside captured HIP
+    graphs: replayed blocks of RE iterations reach bit-for-bit the eager
+    loop's temperatures, update counts and fluxes, also on a second solve
+    that replays the same graph from a fresh state."""
+    atms = [W.plain_workload(n=n, nb=16)[0] for n in (20, 12, 16)]
+    kt = W.plain_workload(n=20, nb=16)[1]
+    T0 = np.concatenate([a["T0"] for a in atms])
+    b = H.Batch(atms)
+    kw = {"layers": "iso"} if mode == "iso" else {"rayleigh_mbar": 2.4 * 1.67262192369e-24}
+    eager = H.Solver(b, H.KTable(kt), prec=H.FP64, **kw)
+    ce, ie = eager.solve(T0, max_iter=1000, check_every=7)
+    graphed = H.Solver(b, H.KTable(kt), prec=H.FP64, **kw)
+    cg, ig = graphed.solve(T0, max_iter=1000, check_every=7, graph=True)
+    assert ce.all() and cg.all()
+    assert np.array_equal(ie, ig)
+    assert torch.equal(eager.T_c, graphed.T_c)
+    assert torch.equal(eager.F_bol, graphed.F_bol)
+    cg2, ig2 = graphed.solve(T0, max_iter=1000, check_every=7, graph=True)
+    assert np.array_equal(ig2, ie) and torch.equal(graphed.T_c, eager.T_c)

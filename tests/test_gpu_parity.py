@@ -432,7 +432,8 @@ def test_errors_are_reported_and_nothing_runs():
     assert e.value.code == -1
 
 
-SHAPES = [(K, L, prec) for K in (4, 8, 14, 26) for L in (16, 32) for prec in (0, 1) if K * L >= 100]
+SHAPES = [(K, L, prec) for K in (4, 8, 14, 26) for L in (16, 32) for prec in (0, 1) if K * L >= 100] + [
+    (26, 64, 0), (26, 64, 1)]  # the long-column shape
 
 
 @pytest.mark.parametrize("K,L,prec", SHAPES)
@@ -460,16 +461,16 @@ def test_flux_every_sweep_shape(K, L, prec, small_table, monkeypatch):
 # ------------------------------------------------------- batching features
 @pytest.mark.parametrize("prec", [0, 1])
 def test_ragged_batch_spanning_every_size_class(prec, small_table):
-    """One atmosphere per size class (and the class edges, up to the 400-layer
+    """One atmosphere per size class (and the class edges, up to the 832-layer
     maximum), interleaved so that each class launch skips other classes' bins."""
     lc, dl = W.bins(300)
     rng = np.random.default_rng(31 + prec)
-    ns = [65, 2, 209, 32, 113, 33, 64, 400]
+    ns = [65, 2, 209, 32, 832, 113, 33, 401, 64, 400]
     atms = [W.spectral_atmosphere(rng, n, lc, dl, 3 + (i % 3)) for i, n in enumerate(ns)]
     b = H.Batch(atms)
     H.grid(b)
     shapes = H.sweep_shapes(b, prec)
-    assert len(shapes) == 5
+    assert len(shapes) == 6
     for hi, (K, L) in shapes.items():
         assert K * L >= 2 * max(n for n in ns if n <= hi)
     T_cs = [smooth_profile(a) for a in atms]

@@ -127,7 +127,8 @@ def test_flux_rayleigh_ragged_batch_spanning_size_classes(prec, small_table):
     rng = np.random.default_rng(43)
     atms = [W.spectral_atmosphere(rng, n, lc, dl, nb, T_irr=ti, T_int=tint)
             for n, nb, ti, tint in [(2, 5, 1200.0, 150.0), (40, 9, 2500.0, 500.0), (64, 4, 900.0, 0.0),
-                                    (111, 6, 1800.0, 300.0), (208, 3, 1500.0, 200.0), (400, 2, 2000.0, 400.0)]]
+                                    (111, 6, 1800.0, 300.0), (208, 3, 1500.0, 200.0), (400, 2, 2000.0, 400.0),
+                                    (600, 2, 1300.0, 250.0)]]
     b = H.Batch(atms)
     H.grid(b)
     T_cs = [smooth_profile(a, 1500 + 100 * i, 700 + 50 * i) for i, a in enumerate(atms)]
