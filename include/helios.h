@@ -278,10 +278,11 @@ int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double
 
 /* Autotuner of the flux sweep (a batching aid; the paper runs one
  * atmosphere at a time).  helios_flux groups atmospheres into size classes by
- * layer count (n <= 32, 64, 112, 208, 400) and sweeps each class with one
- * launch of its own shape (sublayers per lane x lanes per column).  For each
- * class present in the batch, every compiled shape that holds the class's
- * deepest atmosphere, with one or more waves per bin (more than one only for
+ * layer count (n <= 32, 64, 112, 208, 400, 832) and sweeps each class with
+ * one launch of its own shape (sublayers per lane x lanes per column).  For
+ * each class present in the batch, every compiled shape that holds the
+ * class's deepest atmosphere (the 64-lane long-column shape only where no
+ * other one does), with one or more waves per bin (more than one only for
  * batches of at most 65536 bins), is timed here on up to 4096 bins of that atmosphere
  * (same arguments as helios_flux, status ignored), and the fastest is used
  * by later helios_flux calls of this process with the same precision and
