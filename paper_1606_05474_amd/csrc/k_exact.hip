@@ -58,78 +58,100 @@ __device__ inline double exact_sig(double dtau, double T, double om, double dB) 
     return kPi * (dB / dtau) * (2.0 * om / 3.0 + dtau * T / 3.0);
 }
 
-// Workgroup = one bin (a grid-stride loop over the bins of the launch);
-// thread g walks column g down and up, storing its deviations in the
-// per-g arrays; the workgroup then forms the Gauss partials of each point
-// in g order (one partial per (bin, point)).
+// Workgroup = 64 / n_g bins side by side (a grid-stride loop over groups of
+// bins of the launch): lane t walks column t % n_g of bin slot t / n_g down
+// and up, storing its deviations in the per-g arrays; the workgroup then
+// forms the Gauss partials of each of its bins' points in g order (one
+// partial per (bin, point)).  The bins of a workgroup may belong to
+// different atmospheres, so everything per bin is per lane; the barriers
+// and the partial loops are uniform.
+__device__ inline int exact_bins_per_wave(int n_g) { return 64 / n_g; }
+
 __global__ void __launch_bounds__(64) exact_kernel(const SweepArgs A) {
-    const int g = threadIdx.x;
     const double* __restrict__ kap_all = static_cast<const double*>(A.kappa);
     const double* __restrict__ B_all = static_cast<const double*>(A.B);
     double* __restrict__ Fu = static_cast<double*>(A.F_up_g);
     double* __restrict__ Fd = static_cast<double*>(A.F_dn_g);
     double* __restrict__ part_up = static_cast<double*>(A.part_up);
     double* __restrict__ part_dn = static_cast<double*>(A.part_dn);
-    for (int64_t gb = A.w_begin + blockIdx.x; gb < A.w_end; gb += gridDim.x) {
-        const int at = A.bin_atm[gb];
-        const int l = (int)(gb - A.bin_off[at]);
-        const int n = A.n_layer[at];
-        if (frozen(A.status, at)) continue;  // uniform per workgroup
-        const int nsub = 2 * n, npt = nsub + 1;
-        const int cs = col_stride(n);
-        const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
-        const double* __restrict__ P = A.P_pt + A.pt_off[at];
-        const double* __restrict__ B = B_all + pb;
-        const double igrav = 1.0 / A.grav[at];
-        const int64_t bin = A.bin_off[at] + l;
-        const int64_t cell0 = A.cell_off[at] + (int64_t)l * A.n_g * cs;
-        // BOA flux scale: sigma T_int^4 over the atmosphere's in-band sum (chunk sums in order)
-        double sum = 0.0;
-        const int nbch = (int)((A.bin_off[at + 1] - A.bin_off[at] + kBndChunk - 1) / kBndChunk);
-        for (int c = 0; c < nbch; ++c) sum += A.bnd_part[(int64_t)at * A.bnd_maxch + c];
-        const double t2 = A.T_int[at] * A.T_int[at];
-        const double Fint = A.F_int[bin] * ((sum > 0.0) ? sigma_sb() * t2 * t2 / sum : 0.0);
-        if (g < A.n_g) {
-            const double* kap = kap_all + cell0 + (int64_t)g * cs;
-            double* up = Fu + cell0 + (int64_t)g * cs;
-            double* dn = Fd + cell0 + (int64_t)g * cs;
-            double G = A.F_top[bin] - kPi * B[nsub];
-            dn[nsub] = G;
-            for (int s = nsub - 1; s >= 0; --s) {
-                const double dtau = 0.5 * (kap[s] + kap[s + 1]) * (P[s] - P[s + 1]) * igrav;
-                double om;
-                const double T = exact_trans_d(dtau, om);
-                G = T * G - exact_sig(dtau, T, om, B[s] - B[s + 1]);
-                dn[s] = G;
-                up[s + 1] = T;  // kept for the upward sweep, which overwrites it after use
-            }
-            G += Fint;
-            up[0] = G;
-            for (int s = 0; s < nsub; ++s) {
-                const double dtau = 0.5 * (kap[s] + kap[s + 1]) * (P[s] - P[s + 1]) * igrav;
-                double e, om;
-                exp_neg_om(dtau, e, om);
-                const double T = up[s + 1];
-                G = T * G + exact_sig(dtau, T, om, B[s] - B[s + 1]);
-                up[s + 1] = G;
+    const int bpw = exact_bins_per_wave(A.n_g);
+    const int slot = threadIdx.x / A.n_g, g = threadIdx.x - slot * A.n_g;
+    for (int64_t base = A.w_begin + (int64_t)blockIdx.x * bpw; base < A.w_end; base += (int64_t)gridDim.x * bpw) {
+        const int64_t gb = base + slot;
+        if (slot < bpw && gb < A.w_end) {
+            const int at = A.bin_atm[gb];
+            if (!frozen(A.status, at)) {
+                const int l = (int)(gb - A.bin_off[at]);
+                const int n = A.n_layer[at];
+                const int nsub = 2 * n, npt = nsub + 1;
+                const int cs = col_stride(n);
+                const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
+                const double* __restrict__ P = A.P_pt + A.pt_off[at];
+                const double* __restrict__ B = B_all + pb;
+                const double igrav = 1.0 / A.grav[at];
+                const int64_t bin = A.bin_off[at] + l;
+                const int64_t cell0 = A.cell_off[at] + (int64_t)l * A.n_g * cs;
+                // BOA flux scale: sigma T_int^4 over the atmosphere's in-band sum (chunk sums in order)
+                double sum = 0.0;
+                const int nbch = (int)((A.bin_off[at + 1] - A.bin_off[at] + kBndChunk - 1) / kBndChunk);
+                for (int c = 0; c < nbch; ++c) sum += A.bnd_part[(int64_t)at * A.bnd_maxch + c];
+                const double t2 = A.T_int[at] * A.T_int[at];
+                const double Fint = A.F_int[bin] * ((sum > 0.0) ? sigma_sb() * t2 * t2 / sum : 0.0);
+                const double* kap = kap_all + cell0 + (int64_t)g * cs;
+                double* up = Fu + cell0 + (int64_t)g * cs;
+                double* dn = Fd + cell0 + (int64_t)g * cs;
+                double G = A.F_top[bin] - kPi * B[nsub];
+                dn[nsub] = G;
+                for (int s = nsub - 1; s >= 0; --s) {
+                    const double dtau = 0.5 * (kap[s] + kap[s + 1]) * (P[s] - P[s + 1]) * igrav;
+                    double om;
+                    const double T = exact_trans_d(dtau, om);
+                    G = T * G - exact_sig(dtau, T, om, B[s] - B[s + 1]);
+                    dn[s] = G;
+                    up[s + 1] = T;  // kept for the upward sweep, which overwrites it after use
+                }
+                G += Fint;
+                up[0] = G;
+                for (int s = 0; s < nsub; ++s) {
+                    const double dtau = 0.5 * (kap[s] + kap[s + 1]) * (P[s] - P[s + 1]) * igrav;
+                    double e, om;
+                    exp_neg_om(dtau, e, om);
+                    const double T = up[s + 1];
+                    G = T * G + exact_sig(dtau, T, om, B[s] - B[s + 1]);
+                    up[s + 1] = G;
+                }
             }
         }
         __syncthreads();
-        for (int p = threadIdx.x; p < npt; p += blockDim.x) {
-            double su = 0.0, sd = 0.0;
-            for (int c = 0; c < A.n_g; ++c) {
-                su += A.gw[c] * Fu[cell0 + (int64_t)c * cs + p];
-                sd += A.gw[c] * Fd[cell0 + (int64_t)c * cs + p];
+        for (int k = 0; k < bpw; ++k) {  // uniform: the bins of this group in turn
+            const int64_t gk = base + k;
+            if (gk >= A.w_end) break;
+            const int at = A.bin_atm[gk];
+            if (frozen(A.status, at)) continue;
+            const int l = (int)(gk - A.bin_off[at]);
+            const int n = A.n_layer[at];
+            const int npt = 2 * n + 1;
+            const int cs = col_stride(n);
+            const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
+            const int64_t cell0 = A.cell_off[at] + (int64_t)l * A.n_g * cs;
+            for (int p = threadIdx.x; p < npt; p += blockDim.x) {
+                double su = 0.0, sd = 0.0;
+                for (int c = 0; c < A.n_g; ++c) {
+                    su += A.gw[c] * Fu[cell0 + (int64_t)c * cs + p];
+                    sd += A.gw[c] * Fd[cell0 + (int64_t)c * cs + p];
+                }
+                part_up[pb * A.wpb_stride + p] = su;
+                part_dn[pb * A.wpb_stride + p] = sd;
             }
-            part_up[pb * A.wpb_stride + p] = su;
-            part_dn[pb * A.wpb_stride + p] = sd;
         }
         __syncthreads();
     }
 }
 
 hipError_t launch_exact(const SweepArgs& a, int64_t n_bins, hipStream_t s) {
-    const int64_t grid = n_bins < 0x7fffffff ? n_bins : 0x7fffffff;
+    const int bpw = 64 / a.n_g;
+    const int64_t groups = (n_bins + bpw - 1) / bpw;
+    const int64_t grid = groups < 0x7fffffff ? groups : 0x7fffffff;
     hipLaunchKernelGGL(exact_kernel, dim3((unsigned)grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }
