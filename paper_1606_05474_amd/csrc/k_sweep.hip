@@ -237,7 +237,10 @@ __device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R
 // Shifts within a column's group of L lanes.  For L = 16 the group is one
 // DPP row, so row_shl/row_shr moves (out-of-row sources read 0) replace LDS
 // permutes; wider groups use shuffles (out-of-group sources read the own
-// value, which the callers never use).
+// value, which the callers never use).  (Composing the 32-lane shifts from
+// row moves and a permlane16 swap costs four VALU operations per dword where
+// the shuffle costs one LDS permute, and measured 3% slower in this
+// VALU-bound kernel.)
 template <int CTRL>
 __device__ inline float dpp_mov(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
@@ -309,12 +312,45 @@ __device__ inline void scan_up_full(R& MA, R& MB, int seg) {
     if constexpr (L > 32) up_pair<L, 32>(MA, MB, seg);
 }
 
+// v(lane) + v(lane ^ S) for S = 16 or 32 with gfx950's permlane swaps (VALU
+// lane exchanges, no LDS round trip): given v as both operands, the swap
+// returns in every lane the lower and the upper member of its lane pair, so
+// both lanes of a pair form the same sum (lower + upper).
+template <int S>
+__device__ inline unsigned pair_lo_hi(unsigned u, unsigned& hi) {
+    if constexpr (S == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        hi = r[1];
+        return r[0];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        hi = r[1];
+        return r[0];
+    }
+}
+template <int S>
+__device__ inline float xor_pair_sum(float v) {
+    unsigned hi;
+    const unsigned lo = pair_lo_hi<S>(__float_as_uint(v), hi);
+    return __uint_as_float(lo) + __uint_as_float(hi);
+}
+template <int S>
+__device__ inline double xor_pair_sum(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    unsigned lo_h, hi_h, lo_l, hi_l;
+    lo_l = pair_lo_hi<S>((unsigned)b, hi_l);
+    lo_h = pair_lo_hi<S>((unsigned)(b >> 32), hi_h);
+    const double lo = __longlong_as_double((long long)(((unsigned long long)lo_h << 32) | lo_l));
+    const double hi = __longlong_as_double((long long)(((unsigned long long)hi_h << 32) | hi_l));
+    return lo + hi;
+}
+
 // Sum of v over the wave's C = 64/L columns (lanes seg, seg + L, ...); every
 // column gets the same value, added in the order ((c0 + c1) + (c2 + c3)).
 template <int L, typename R>
 __device__ inline R col_sum(R v) {
-    if constexpr (L <= 16) v += __shfl_xor(v, 16, 64);
-    if constexpr (L <= 32) v += __shfl_xor(v, 32, 64);
+    if constexpr (L <= 16) v = xor_pair_sum<16>(v);
+    if constexpr (L <= 32) v = xor_pair_sum<32>(v);
     return v;
 }
 
