@@ -396,11 +396,22 @@ def modes_main(args):
                                       "sweep_ms": r["sweep_ms"], "sweep_alg_GBs": gbs,
                                       "sweep_frac_of_hbm_peak": gbs / HBM_PEAK_GBS, "running": r["status"] == H.ATM_RUNNING}
             print("#", mode, pname, json.dumps(out[f"{mode} {pname}"]), file=sys.stderr, flush=True)
+    # post-processing (Sec. 2.6, Sec. 3.3): 1 + 80 passes, the paper's 101 isothermal layers and the
+    # sublayered grid, FP64; a step is one such flux call plus its opacity mixing and RE update
+    spectra = {}
+    for layers, n_sp in (("iso", 101), ("noniso", 100)):
+        atm_s, _ = W.spectral_workload(n=n_sp, ktab=kt)
+        r = run_gpu(H.FP64, max(10, args.steps // 10), 3, atm_s, kt, n_scat=80, layers=layers)
+        alg = (iso_algorithmic_bytes if layers == "iso" else sweep_algorithmic_bytes)(n_sp, nb, ng, 8)
+        spectra[f"{n_sp} {'isothermal' if layers == 'iso' else 'sublayered'} layers, 81 passes, fp64"] = {
+            "ms_per_spectrum_flux_call": r["sweep_ms"], "ms_per_step": r["ms_per_step"],
+            "sweep_alg_GBs": alg / (r["sweep_ms"] * 1e-3) / 1e9}
+        print("# spectrum", layers, json.dumps(spectra), file=sys.stderr, flush=True)
     line = {"metric": "layer*bin*g flux updates/s per solver mode", "value": None, "unit": "layer*bin*g/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
             "config": {"workload": "one atmosphere, 100 layers x 3000 bins x 20 g, table opacities, 1 + 4 "
                                    "scattering passes; a step: opacity mixing, flux call, RE update"},
-            "modes": out}
+            "modes": out, "post_processing_spectrum": spectra}
     print(json.dumps(line))
     return 0
 
