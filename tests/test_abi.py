@@ -116,3 +116,31 @@ def test_validation_rejects_bad_descriptors_without_a_device(H):
     assert lib.helios_radeq(ctypes.byref(d), fake, fake, fake, ctypes.byref(st), ctypes.byref(opts), fake,
                             None, None) == -1
     assert lib.helios_version() >= 1
+
+
+def test_mode_entry_points_validate_before_any_device_work(H):
+    """helios_flux_iso and helios_flux_rayleigh reject bad arguments on the
+    host (nothing is enqueued); the layer limit is the long-column shape's."""
+    import numpy as np
+
+    lib = H.lib()
+    n_layer = np.array([50], np.int32)
+    n_bin = np.array([3], np.int32)
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    d = H.HeliosAtm(1, 20, n_layer.ctypes.data, n_bin.ctypes.data, *([fake] * 17))
+    args = (fake, fake, fake, fake, 4, 2.0, fake, None, None, None, fake, fake, 1 << 30, 0, None)
+    assert lib.helios_flux_iso(ctypes.byref(d), None, *args[1:]) == -1  # NULL opacities
+    assert lib.helios_flux_iso(ctypes.byref(d), fake, fake, fake, fake, 4, 2.0, fake, None, None, None, None,
+                               fake, 1 << 30, 0, None) == -1  # NULL F_bol
+    assert lib.helios_flux_rayleigh(ctypes.byref(d), fake, fake, 0.0, 4, 2.0, fake, None, None, None, fake, fake,
+                                    1 << 30, 0, None) == -1
+    assert b"mbar" in lib.helios_last_error()
+    assert lib.helios_flux_rayleigh(ctypes.byref(d), None, fake, 4e-24, 4, 2.0, fake, None, None, None, fake,
+                                    fake, 1 << 30, 0, None) == -1
+    assert lib.helios_flux_rayleigh(ctypes.byref(d), fake, fake, 4e-24, -1, 2.0, fake, None, None, None, fake,
+                                    fake, 1 << 30, 0, None) == -1  # negative scattering-pass count
+    n_layer[0] = 833
+    assert lib.helios_grid(ctypes.byref(d), None) == -2
+    assert b"2..832" in lib.helios_last_error()
+    n_layer[0] = 832
+    assert lib.helios_workspace_bytes(ctypes.byref(d), 0) > 0
