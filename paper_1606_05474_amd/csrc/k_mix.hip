@@ -13,9 +13,11 @@
 // corners as soon as a cell is entered, so they are in flight while the
 // current cell's points are computed.  For a fixed point the threads read
 // consecutive (bin, g) entries of each corner row (coalesced).  A thread's
-// kMixPts = 16 results are an aligned 64-byte (FP32) or 128-byte (FP64)
-// piece of its column (the column stride is padded to a multiple of 32
-// points) and are written with vector stores, up to the last valid point.
+// kMixPts results (32 in FP32, 16 in FP64) are an aligned 128-byte piece of
+// its column (the column stride is padded to a multiple of 32 points); the
+// workgroup passes them through LDS so that consecutive lanes store
+// consecutive 16-byte vectors of one piece (whole cache lines per store),
+// up to the last valid point.
 #include "helios_internal.hpp"
 
 namespace helios {
@@ -61,6 +63,7 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
     __shared__ int s_next[kMixPts];  // at the first point of a run of equal cells: the next run's cell, or -1
     __shared__ R s_w[kMixPts][4];    // bilinear corner weights or power-law scale
     __shared__ R s_x[kMixPts][NSP];  // mass mixing ratios
+    __shared__ R s_out[kMixCols][kMixPts + 1];  // the workgroup's results, re-read for coalesced stores
 
     const int t = threadIdx.x;
     const int a = blockIdx.x / A.max_chunks;
@@ -106,9 +109,10 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
         }
     }
     __syncthreads();
-    if (c >= ncol) return;
+    const bool colv = c < ncol;  // threads past the columns still take part in the barrier below
+    const int cq = colv ? c : ncol - 1;
 
-    const int l = c / A.ng, g = c - l * A.ng;
+    const int l = cq / A.ng, g = cq - l * A.ng;
     // a bad caller index must not read outside the table
     const int bt = min(max(A.atm.bin_index[A.atm.bin_off[a] + l], 0), A.nbt - 1);
     const size_t row = (size_t)A.nbt * A.ng;  // one (species, T, P) corner row
@@ -175,16 +179,31 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
         }
         vals[j] = acc;
     }
+    // stores through LDS: each column's piece of the chunk (kMixPts points,
+    // 128 bytes) is written by kMixPts/per consecutive lanes, so a wave's
+    // vector store covers whole 128-byte lines instead of one 16-byte piece
+    // of 64 different lines
+#pragma unroll
+    for (int j = 0; j < kMixPts; ++j) s_out[t][j] = vals[j];
+    __syncthreads();
     using V = typename Vec2<R>::type;
     constexpr int per = Vec2<R>::per;
-    V* dst = reinterpret_cast<V*>(static_cast<R*>(A.kappa) + A.atm.cell_off[a] + (int64_t)c * col_stride(n) + p0);
-    // whole vectors covering the valid points (column padding past them is not written)
+    constexpr int vpc = kMixPts / per;  // vectors per column piece
+    const int cs = col_stride(n);
+    R* __restrict__ kap = static_cast<R*>(A.kappa) + A.atm.cell_off[a] + (int64_t)blockIdx.y * kMixCols * cs + p0;
 #pragma unroll
-    for (int v = 0; v < kMixPts / per; ++v) {
-        V w;
-        if constexpr (per == 4) w = V{vals[4 * v], vals[4 * v + 1], vals[4 * v + 2], vals[4 * v + 3]};
-        else w = V{vals[2 * v], vals[2 * v + 1]};
-        if (per * v < npts) dst[v] = w;
+    for (int r = 0; r < vpc; ++r) {
+        const int q = r * kMixCols + t;
+        const int cc = q / vpc, v = q - cc * vpc;
+        // whole vectors covering the valid points (column padding past them is not written)
+        if ((int)blockIdx.y * kMixCols + cc < ncol && per * v < npts) {
+            V w;
+            if constexpr (per == 4)
+                w = V{s_out[cc][4 * v], s_out[cc][4 * v + 1], s_out[cc][4 * v + 2], s_out[cc][4 * v + 3]};
+            else
+                w = V{s_out[cc][2 * v], s_out[cc][2 * v + 1]};
+            *reinterpret_cast<V*>(kap + (int64_t)cc * cs + per * v) = w;
+        }
     }
 }
 
