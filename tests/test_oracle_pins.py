@@ -805,3 +805,44 @@ def test_rayleigh_equilibrium_has_constant_net_flux(ref):
     s4 = SIGMA_CODATA * atm["T_int"] ** 4
     net = sol["flux"]["F_bol"][::2, 2]
     np.testing.assert_allclose(net, s4, rtol=0, atol=atm["n"] * 1e-3 * s4)
+
+
+# --------------------------------------------- printed parameters (golden)
+def _golden():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if len(line) >= 2:
+            out[line[0]] = float(line[1])
+    return out
+
+
+def test_oracle_uses_the_printed_parameters(ref):
+    """The oracle's RE defaults, branch switches, Rayleigh constants and mean
+    molecular mass are the values the paper prints (tests/golden)."""
+    g = _golden()
+    d = ref.RE_DEFAULTS
+    assert d["fpre_c"] == g["fpre_constant"] and d["fpre_p"] == g["fpre_exponent"]
+    assert d["window"] == g["oscillation_window"]
+    assert d["shrink"] == g["step_shrink"] and d["grow"] == g["step_grow"]
+    eps = 1e-12
+    # eq:isoscat strictly below the printed optical depth, eq:nonisoscat at and above it
+    assert ref.branch(g["isothermal_switch_dtau"] * (1 - eps), 0.3) == 1
+    assert ref.branch(g["isothermal_switch_dtau"], 0.3) == 2
+    # eq:purescat strictly below the printed 1 - w0
+    assert ref.branch(1.0, 1.0 - g["pure_scattering_switch"] * 0.5) == 0
+    assert ref.branch(1.0, 1.0 - g["pure_scattering_switch"] * 2.0) == 2
+    lam = 0.55e-4
+    n = 1.0 + g["rayleigh_index_a"] * (1.0 + g["rayleigh_index_b_cm2"] / lam ** 2)
+    f = (n * n - 1.0) / (n * n + 2.0)
+    sigma = 24.0 * np.pi ** 3 / (g["rayleigh_n_ref"] ** 2 * lam ** 4) * f * f * g["rayleigh_king_factor"]
+    assert ref.rayleigh_h2(lam) == pytest.approx(sigma, rel=1e-13)
+    atm, _ = W.plain_workload()
+    assert atm["mmw"] == g["mean_molecular_mass_mp"] and W.N_G == g["gauss_points"]
+    import inspect
+
+    for fn in (ref.flux, ref.flux_iso, ref.flux_rayleigh, ref.solve):
+        assert inspect.signature(fn).parameters["D"].default == g["diffusivity_D"]
