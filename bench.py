@@ -265,7 +265,8 @@ def chunk_main(args):
                        "shapes": {str(k): list(v) for k, v in H.sweep_shapes(s.b, H.MIXED).items()}},
             "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep)",
                          "achieved": alg / (sweep_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": alg / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "frac": alg / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic_entry("chunk") if len(atms) == 128 else None,
                          "algorithmic_bytes_per_launch": alg, "avg_launch_ms": sweep_ms}}
     print(json.dumps(line))
     return 0
