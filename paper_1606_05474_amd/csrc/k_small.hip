@@ -63,9 +63,9 @@ hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double*
 }
 
 // --------------------------------------------------------------- sources
-// B[bin][pt] at the bin centres: workgroup = (bin, tile of 256 points), one
-// thread per point (the bin's atmosphere from the map the boundary kernel
-// wrote earlier in the same call).
+// B[bin][pt] at the bin centres: workgroup = one bin, its threads stride over
+// the bin's points (the bin's atmosphere from the map the boundary kernel
+// wrote earlier in the same call; the per-bin lookups are paid once per bin).
 //
 // On the isothermal-layer grid (Sec. 2.2.1) layer i has the single
 // temperature of its centre (point 2i+1), and the sweep's reference values
@@ -73,7 +73,7 @@ hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double*
 // sweep then sees a Planck difference of zero across the layer itself (slot
 // 2i) and the step B(T_i) - B(T_{i+1}) across the identity slot 2i+1, which
 // moves the deviation from one layer's reference to the next one's.
-constexpr int kPlanckThreads = 256;
+constexpr int kPlanckThreads = 128;
 __global__ void __launch_bounds__(kPlanckThreads) planck_kernel(helios_atm atm, const double* __restrict__ T_pt,
                                                                 const int32_t* __restrict__ bin_atm,
                                                                 double* __restrict__ B, int iso_grid) {
@@ -81,11 +81,14 @@ __global__ void __launch_bounds__(kPlanckThreads) planck_kernel(helios_atm atm, 
     const int a = bin_atm[b];
     if (frozen(atm.status, a)) return;  // uniform per workgroup
     const int npt = 2 * atm.n_layer[a] + 1;
-    const int p = blockIdx.y * kPlanckThreads + threadIdx.x;
-    if (p >= npt) return;
-    const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
-    const int64_t o = atm.pb_off[a] + (b - atm.bin_off[a]) * npt + p;
-    B[o] = planck_d(atm.lambda_c[b], T_pt[atm.pt_off[a] + pt]);
+    const double lam = atm.lambda_c[b];
+    const double* __restrict__ T = T_pt + atm.pt_off[a];
+    double* __restrict__ Bb = B + atm.pb_off[a] + (b - atm.bin_off[a]) * npt;
+#pragma unroll 4
+    for (int p = threadIdx.x; p < npt; p += kPlanckThreads) {
+        const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
+        Bb[p] = planck_d(lam, T[pt]);
+    }
 }
 
 // Boundary fluxes (Sec. 2.2.2), workgroup = (atmosphere, chunk of kBndChunk
@@ -130,8 +133,7 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
     hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm, sa.bnd_maxch), dim3(kBndChunk), 0, s, *atm, sa, gt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int tiles = (sa.npt_max + kPlanckThreads - 1) / kPlanckThreads;
-    hipLaunchKernelGGL(planck_kernel, dim3((unsigned)sa.total_bin, tiles), dim3(kPlanckThreads), 0, s, *atm, T_pt,
+    hipLaunchKernelGGL(planck_kernel, dim3((unsigned)sa.total_bin), dim3(kPlanckThreads), 0, s, *atm, T_pt,
                        sa.bin_atm, sa.B, (int)sa.iso_grid);
     return hipGetLastError();
 }
