@@ -181,6 +181,14 @@ const GaussTable& gauss_table(int n) {
     return tab[n];
 }
 
+// Sum of the Gauss weights in g order (the bin sum scales B by 2 pi eps times it).
+double gauss_weight_sum(int n) {
+    const GaussTable& t = gauss_table(n);
+    double w = 0.0;
+    for (int g = 0; g < n; ++g) w += t.w[g];
+    return w;
+}
+
 int env_int(const char* name, int dflt) {
     const char* v = getenv(name);
     return (v && *v) ? atoi(v) : dflt;
@@ -508,6 +516,7 @@ int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     Bo.B = (const double*)(wsb + p.w.B);
     Bo.gw = (const double*)(wsb + p.w.gw);
     Bo.tpe = 2.0 * kPi / D;
+    Bo.tw = Bo.tpe * gauss_weight_sum(atm->n_g);
     Bo.wpb_stride = A.wpb_stride;
     Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
     Bo.mixed = p.mixed ? 1 : 0;
@@ -667,6 +676,7 @@ int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* 
     Bo.B = (const double*)(wsb + p.w.B);
     Bo.gw = (const double*)(wsb + p.w.gw);
     Bo.tpe = kPi;  // the deviations are taken from pi B
+    Bo.tw = Bo.tpe * gauss_weight_sum(atm->n_g);
     Bo.wpb_stride = A.wpb_stride;
     Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
     Bo.mixed = 0;

@@ -161,6 +161,7 @@ struct BolArgs {
     const double* B;      // [bin x point] Planck values (workspace)
     const double* gw;     // [n_g] Gauss weights (workspace)
     double tpe;           // 2 pi eps = 2 pi / D: the sweep's partials are deviations from tpe B
+    double tw;            // tpe times the sum of the Gauss weights (in g order), formed on the host
     int32_t wpb_stride, n_chunk, mixed;
     int32_t n_cls;                   // size classes: atmosphere with n <= cls_nhi[k] (first k)
     int32_t cls_nhi[kMaxClasses];    // uses cls_wpb[k] waves per bin

@@ -193,9 +193,7 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     if (p < npt) {
         const double* dl = A.atm.dlambda + A.atm.bin_off[a];
         const int64_t pb = A.atm.pb_off[a];
-        double wsum = 0.0;
-        for (int g = 0; g < A.atm.n_g; ++g) wsum += A.gw[g];
-        const double tw = A.tpe * wsum;
+        const double tw = A.tw;
 #pragma unroll
         for (int i = 0; i < per; ++i) {
             const int l = l0 + i;
