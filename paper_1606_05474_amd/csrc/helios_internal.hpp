@@ -246,7 +246,7 @@ hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c,
 // Sweep instantiations available (sublayers per lane).
 constexpr int kSweepK[] = {4, 8, 14, 26};
 constexpr int kLongK = 26;  // the only K instantiated with L = 64 (columns of up to 1664 sublayers)
-constexpr int kBolChunk = 32;  // bins per bolometric chunk
+constexpr int kBolChunk = 64;  // bins per bolometric chunk
 constexpr int kBndChunk = 256;  // bins per boundary-flux workgroup
 constexpr int kNumSweepK = 4;
 
