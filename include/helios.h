@@ -211,7 +211,7 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
  * kappa (P_pt[2i] - P_pt[2i+2]) / g (eq:layertau), and is propagated with
  * eq:isoscat and B(T_i) at every optical thickness (eq:purescat where
  * (1 - w0) < 1e-6).  Boundary conditions, scattering passes, precision and
- * sums as helios_flux.  Only the centre values of T_pt and kappa are read.
+ * sums as helios_flux.  Only the centre values of T_pt and kappa are used.
  *   F_up_g, F_dn_g  cell arrays in the point layout: at point 2i the fluxes at
  *                   interface i, at point 2i+1 those at interface i+1 (the top
  *                   of layer i), stored as deviations from (2 pi / D) B(T_i)
