@@ -144,3 +144,14 @@ def test_mode_entry_points_validate_before_any_device_work(H):
     assert b"2..832" in lib.helios_last_error()
     n_layer[0] = 832
     assert lib.helios_workspace_bytes(ctypes.byref(d), 0) > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and
+    says why, before touching a device."""
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
