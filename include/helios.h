@@ -47,7 +47,7 @@ extern "C" {
 #define HELIOS_OK 0
 #define HELIOS_NOT_CONVERGED 1
 #define HELIOS_EINVAL (-1)     /* null pointer, non-positive size, unknown enum */
-#define HELIOS_ESHAPE (-2)     /* inconsistent sizes / offsets / table shape */
+#define HELIOS_ESHAPE (-2)     /* inconsistent sizes / offsets / table shape, bin index outside the table */
 #define HELIOS_EDEVICE (-3)    /* a HIP call failed */
 #define HELIOS_EWORKSPACE (-4) /* workspace smaller than helios_workspace_bytes() */
 #define HELIOS_ENUMERIC (-5)   /* non-finite flux or temperature (per-atmosphere status) */
@@ -55,6 +55,7 @@ extern "C" {
 /* per-atmosphere status words written by helios_radeq */
 #define HELIOS_ATM_RUNNING 0
 #define HELIOS_ATM_CONVERGED 1
+#define HELIOS_ATM_BADGRID (-2)  /* point pressures not positive, finite and strictly decreasing upward */
 #define HELIOS_ATM_NUMERIC (-5)
 
 #define HELIOS_MAX_SPECIES 8
@@ -63,6 +64,24 @@ extern "C" {
 #define HELIOS_CELL_ALIGN 32
 
 typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;
+
+/* Convention of the per-g flux arrays (F_up_g, F_dn_g) of the flux calls,
+ * OR'ed into their `prec` argument:
+ *   HELIOS_STATE_DEVIATION (default): each value is the deviation
+ *     G = F - (2 pi / D) B(lambda_bin, T_point) of the flux from the
+ *     isothermal solution at the bin centre and the point's temperature (for
+ *     helios_flux_exact: from pi B).  The sweeps carry exactly this
+ *     quantity; in FP32 it keeps the net flux resolved at depth, where F_up
+ *     and F_dn both approach pi B and differ by ~1e-6 of it.  A zero array is
+ *     the isothermal start.
+ *   HELIOS_STATE_FLUX: each value is the flux F itself (Sec. 2.2.3: the
+ *     scattering iteration starts from zero fluxes, and later temperature
+ *     steps start from the previous step's fluxes).  A zero array is the
+ *     paper's cold start.  The library converts on load and store, in the
+ *     sweep's precision; meant for HELIOS_FP64.
+ * helios_state_convert() converts an array between the two. */
+#define HELIOS_STATE_DEVIATION 0x000
+#define HELIOS_STATE_FLUX 0x100
 typedef enum { HELIOS_KTAB_TABLE = 0, HELIOS_KTAB_POWERLAW = 1 } helios_ktab_mode;
 typedef enum { HELIOS_NORM_SIGMA_T4 = 0, HELIOS_NORM_SIGMA_TINT4 = 1 } helios_norm;
 
@@ -82,6 +101,7 @@ typedef struct helios_atm {
     const int64_t* pb_off;       /* [n_atm+1] */
     const int64_t* cell_off;     /* [n_atm+1] */
     const int32_t* bin_index;    /* [sum nb] k-table bin of each model bin */
+    const int32_t* bin_index_h;  /* [host][sum nb] the same values (validated against the table) */
     const double* lambda_c;      /* [sum nb] bin centre wavelength, cm */
     const double* dlambda;       /* [sum nb] bin width, cm */
     const double* P_c;           /* [sum n] layer-centre pressure, bottom -> top */
@@ -153,7 +173,9 @@ int helios_profile(const helios_atm* atm, const double* T_c, double* T_pt, void*
 /* Opacity at the points (eq:kappa_gauss, eq:mixing, Sec. 2.3):
  * kappa[cell] = sum_j X_j m_j/mbar k_j(T_pt, P_pt, bin_index, g).
  * vmr: [n_species][sum npt] volume mixing ratios.  kappa: cell array, double
- * (HELIOS_FP64) or float (HELIOS_MIXED). */
+ * (HELIOS_FP64) or float (HELIOS_MIXED).
+ * Errors: -2 (nothing enqueued) if a bin_index_h entry lies outside
+ * 0 .. n_bin_table - 1 or the table's n_g differs from the batch's. */
 int helios_mix_opacity(const helios_atm* atm, const helios_ktab* kt, const double* T_pt,
                        const double* vmr, void* kappa, helios_prec prec, void* stream);
 
@@ -183,19 +205,22 @@ size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec);
  *   n_scat    additional scattering passes (paper: 4 in the RE loop, 80 post)
  *   D         diffusivity factor (paper: 2)
  *   F_up_g    cell array, in: warm start, out: upward fluxes of the last pass
+ *             (zeros on the first call of an RE iteration with
+ *             HELIOS_STATE_FLUX: the paper's start)
  *   F_dn_g    cell array, out: downward fluxes of the last pass (may be NULL)
  *   F_up_bin, F_dn_bin  [bin x point] double, Gauss-summed fluxes; either may
  *             be NULL (not written: the iteration itself needs only F_bol)
  *   F_bol     [sum npt][3] double: bolometric up, down, and net = up - down
  *             (the net flux is summed from the deviations below, in which
  *             the Planck term cancels, not by subtracting the two totals)
- * The per-g arrays hold deviations from the isothermal solution:
- * value = F - (2 pi / D) B(lambda_bin, T_point), with B the Planck function
- * at the bin centre and the point's temperature.  A zero array is the
- * isothermal start F = (2 pi / D) B; between temperature iterations the
- * warm start therefore keeps each column's deviation from its local Planck
- * flux (which is also what the sweeps carry: both sources become linear in
- * the Planck difference across a sublayer). 
+ *   prec      HELIOS_FP64 or HELIOS_MIXED (element type of kappa and the
+ *             per-g arrays), OR'ed with the per-g convention
+ *             HELIOS_STATE_DEVIATION (default) or HELIOS_STATE_FLUX.  With
+ *             deviations, F = value + (2 pi / D) B(lambda_bin, T_point) and a
+ *             zero array is the isothermal start; across temperature steps
+ *             the warm start then keeps each column's deviation from its local
+ *             Planck flux.  With fluxes the warm start is the previous fluxes
+ *             themselves (Sec. 2.2.3).  helios_state_convert() converts.
  *   ws        workspace of at least helios_workspace_bytes(atm, prec) bytes
  * Downward fluxes carry no state between calls: each pass recomputes them
  * from the TOA condition and the previous upward fluxes. */
@@ -253,15 +278,41 @@ int helios_flux_rayleigh(const helios_atm* atm, const void* kappa, const double*
  * asymmetry and D do not enter, and one downward and one upward sweep per
  * (bin, g) column are exact (no scattering couples the streams).
  *   F_up_g, F_dn_g  cell arrays, out: deviations from pi B at the points
- *                   (pi B is the isothermal solution of this mode); no warm
- *                   start is read
+ *                   (pi B is the isothermal solution of this mode), or the
+ *                   fluxes with HELIOS_STATE_FLUX in `state`; no warm start is
+ *                   read
  *   F_up_bin, F_dn_bin, F_bol  as for helios_flux (the per-bin arrays may be
  *                   NULL)
  *   ws        workspace of at least helios_workspace_bytes(atm, HELIOS_FP64)
  * Errors: as helios_flux. */
 int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* T_pt, double* F_up_g,
                       double* F_dn_g, double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws,
-                      size_t ws_bytes, void* stream);
+                      size_t ws_bytes, int32_t state, void* stream);
+
+/* Conversion of a per-g cell array between the two conventions of the flux
+ * calls, with the reference (2 pi / D) B(lambda_bin, T_point) formed on the
+ * device from T_pt (the Planck function at the bin centre, as in the flux
+ * solve):
+ *   HELIOS_CONVERT_TO_DEVIATION  F_g <- F_g - (2 pi / D) B
+ *   HELIOS_CONVERT_TO_FLUX       F_g <- F_g + (2 pi / D) B
+ *   HELIOS_CONVERT_ZERO_FLUX     F_g <- -(2 pi / D) B: the zero-flux start of
+ *                                the scattering iteration (Sec. 2.2.3) in
+ *                                deviation form; the input is not read
+ *   layers    HELIOS_LAYERS_SUBLAYERED (helios_flux, helios_flux_rayleigh) or
+ *             HELIOS_LAYERS_ISOTHERMAL (helios_flux_iso: reference B(T_i) at
+ *             points 2i and 2i+1, B(T_{n-1}) at the TOA point).  The exact
+ *             mode's reference pi B is the sublayered one with D = 2.
+ *   prec      element type of F_g (double for HELIOS_FP64, float for
+ *             HELIOS_MIXED); values are formed in FP64 and rounded once.
+ * Atmospheres whose status is not RUNNING are left unchanged.
+ * Errors: -1 for a NULL pointer, an unknown mode, layers or prec, D <= 0. */
+#define HELIOS_CONVERT_TO_DEVIATION 0
+#define HELIOS_CONVERT_TO_FLUX 1
+#define HELIOS_CONVERT_ZERO_FLUX 2
+#define HELIOS_LAYERS_SUBLAYERED 0
+#define HELIOS_LAYERS_ISOTHERMAL 1
+int helios_state_convert(const helios_atm* atm, const double* T_pt, double D, void* F_g, int32_t mode,
+                         int32_t layers, helios_prec prec, void* stream);
 
 /* Temperature update (Sec. 2.2.3 eq:step, Sec. 2.2.4, eq:condition), always
  * FP64.  For each atmosphere whose status is not CONVERGED: resid = max over
@@ -270,7 +321,9 @@ int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* 
  * CONVERGED and nothing moves; otherwise every layer takes
  * dT_i = -sgn(dF_i) |dF_i|^(1-fpre_p) fpre_c m_i / (sigma T_i^3 ln(P_2i/P_2i+2)),
  * T is floored, the step multipliers are adapted and T_pt is re-interpolated.
- * Non-finite input sets the status to NUMERIC (nothing moves).
+ * Non-finite input sets the status to NUMERIC, point pressures that are not
+ * positive, finite and strictly decreasing from the bottom up (Sec. 2.2.1)
+ * set it to BADGRID; nothing moves then, and both are kept by later calls.
  *   status [n_atm] in/out, resid [n_atm] out (may be NULL). */
 int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double* T_pt,
                  const helios_re_state* st, const helios_re_opts* opt, int32_t* status,
@@ -295,8 +348,13 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
                     const double* g0, int32_t n_scat, double D, void* F_up_g, void* ws, size_t ws_bytes,
                     helios_prec prec, void* stream);
 
-/* The sweep shapes helios_flux would use for this batch: for each of the 5
- * size classes (out holds 3 x max_classes int32, max_classes >= 5) the
+/* Forgets every shape helios_autotune chose in this process: later flux
+ * calls use the default shapes until the autotuner runs again.  Host only;
+ * never fails. */
+int helios_autotune_reset(void);
+
+/* The sweep shapes helios_flux would use for this batch: for each of the 6
+ * size classes (out holds 3 x max_classes int32, max_classes >= 6) the
  * class's upper layer-count bound, then K (sublayers per lane) and L (lanes
  * per column), both 0 for a class with no member.  Returns the number of
  * classes (> 0) or an error code. */

@@ -314,7 +314,9 @@ RE_DEFAULTS = dict(tol=1e-3, norm_sigma_tint=1, T_floor=10.0, window=6, osc_any=
 
 
 def radeq(atm: dict, P_pt, F_bol, T_c, m, hist, opts: dict | None = None):
-    """One RE step (updates T_c, m, hist in place).  Returns (code, resid)."""
+    """One RE step (updates T_c, m, hist in place).  Returns (code, resid):
+    code 1 converged (nothing moves), 0 stepped, -5 non-finite input, -2 a
+    point grid whose pressures do not decrease upward (nothing moves)."""
     o = dict(RE_DEFAULTS)
     if opts:
         o.update(opts)

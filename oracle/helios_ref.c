@@ -536,6 +536,14 @@ int ref_radeq(int n, const double* P_pt, const double* F_bol, double grav, doubl
               double shrink, double grow, double fpre_c, double fpre_p, int deadband,
               double* resid) {
     if (window < 2 || window > 16) return -1;
+    /* the grid of Sec. 2.2.1 runs from the bottom (highest pressure) to the
+       top: a point pressure that is not positive, finite and below the one
+       beneath it is no such grid, and the step refuses it */
+    for (int p = 0; p < 2 * n + 1; ++p)
+        if (!(P_pt[p] > 0.0) || !isfinite(P_pt[p]) || (p > 0 && !(P_pt[p] < P_pt[p - 1]))) {
+            *resid = NAN;
+            return -2;
+        }
     const double sigma = ref_sigma_sb();
     double worst = 0.0;
     for (int i = 0; i < n; ++i) {

@@ -64,7 +64,7 @@ int check_atm(const helios_atm* atm, Sizes& z) {
     if (atm->n_g < 1 || atm->n_g > HELIOS_MAX_NG)
         return fail(HELIOS_EINVAL, "n_g = %d outside 1..%d", atm->n_g, HELIOS_MAX_NG);
     if (!atm->n_layer_h || !atm->n_bin_h || !atm->n_layer || !atm->n_bin || !atm->lay_off || !atm->pt_off ||
-        !atm->bin_off || !atm->lb_off || !atm->pb_off || !atm->cell_off || !atm->bin_index ||
+        !atm->bin_off || !atm->lb_off || !atm->pb_off || !atm->cell_off || !atm->bin_index || !atm->bin_index_h ||
         !atm->lambda_c || !atm->dlambda || !atm->P_c || !atm->P_pt || !atm->grav || !atm->T_star ||
         !atm->T_irr || !atm->T_int)
         return fail(HELIOS_EINVAL, "a helios_atm array pointer is NULL");
@@ -263,8 +263,19 @@ struct FluxPlan {
     Sizes z;
     WsLayout w;
     bool mixed;
+    bool flux_state;  // the per-g arrays hold fluxes (HELIOS_STATE_FLUX)
     SweepShape sh[kNumClasses];
 };
+
+// Splits a flux call's prec argument into the element type and the per-g
+// convention; false for unknown bits.
+bool split_prec(int prec_arg, bool& mixed, bool& flux_state) {
+    const int base = prec_arg & 0xff, flags = prec_arg & ~0xff;
+    if ((base != HELIOS_FP64 && base != HELIOS_MIXED) || (flags & ~HELIOS_STATE_FLUX)) return false;
+    mixed = base == HELIOS_MIXED;
+    flux_state = (flags & HELIOS_STATE_FLUX) != 0;
+    return true;
+}
 
 int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0, const double* g0,
               int32_t n_scat, double D, const void* F_up_g, const void* ws, size_t ws_bytes, helios_prec prec,
@@ -273,10 +284,10 @@ int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     if (rc) return rc;
     if (!kappa || !T_pt || (need_optics && (!w0 || !g0)) || !F_up_g || !ws)
         return fail(HELIOS_EINVAL, "flux: NULL argument");
-    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    if (!split_prec((int)prec, p.mixed, p.flux_state))
+        return fail(HELIOS_EINVAL, "unknown precision / state flags 0x%x", (int)prec);
     if (n_scat < 0 || n_scat > 100000) return fail(HELIOS_EINVAL, "n_scat = %d", n_scat);
     if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
-    p.mixed = prec == HELIOS_MIXED;
     p.w = ws_layout(p.z, atm->n_g, p.mixed);
     if (ws_bytes < p.w.total)
         return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, p.w.total);
@@ -328,6 +339,7 @@ SweepArgs sweep_args(const helios_atm* atm, const FluxPlan& p, const void* kappa
     A.n_scat = n_scat;
     A.npt_max = p.z.npt_max;
     A.iso_grid = 0;
+    A.flux_state = p.flux_state ? 1 : 0;
     A.D = D;
     A.lambda_c = atm->lambda_c;
     A.inv_mbar = 0.0;
@@ -581,6 +593,10 @@ int helios_mix_opacity(const helios_atm* atm, const helios_ktab* kt, const doubl
         return fail(HELIOS_EINVAL, "n_species = %d outside 1..%d", kt->n_species, HELIOS_MAX_SPECIES);
     if (kt->n_g != atm->n_g) return fail(HELIOS_ESHAPE, "table n_g %d != batch n_g %d", kt->n_g, atm->n_g);
     if (kt->n_bin_table < 1) return fail(HELIOS_ESHAPE, "n_bin_table = %d", kt->n_bin_table);
+    for (int64_t b = 0; b < z.total_bin; ++b)  // the table lookup (Sec. 2.3) needs a bin of the table
+        if (atm->bin_index_h[b] < 0 || atm->bin_index_h[b] >= kt->n_bin_table)
+            return fail(HELIOS_ESHAPE, "bin %lld: bin_index %d outside the table's 0..%d", (long long)b,
+                        atm->bin_index_h[b], kt->n_bin_table - 1);
     if (!kt->species_mass || !(kt->mmw > 0.0)) return fail(HELIOS_EINVAL, "species masses / mmw missing");
     if (kt->mode == HELIOS_KTAB_TABLE) {
         if (!kt->k) return fail(HELIOS_EINVAL, "TABLE mode without k");
@@ -615,8 +631,28 @@ int helios_transmission(const helios_atm* atm, const void* kappa, const double* 
 
 size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec) {
     Sizes z;
-    if (check_atm(atm, z)) return 0;
-    return ws_layout(z, atm->n_g, prec == HELIOS_MIXED).total;
+    bool mixed = false, fstate = false;
+    if (check_atm(atm, z) || !split_prec((int)prec, mixed, fstate)) return 0;
+    return ws_layout(z, atm->n_g, mixed).total;
+}
+
+int helios_state_convert(const helios_atm* atm, const double* T_pt, double D, void* F_g, int32_t mode,
+                         int32_t layers, helios_prec prec, void* stream) {
+    Sizes z;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!T_pt || !F_g) return fail(HELIOS_EINVAL, "helios_state_convert: NULL argument");
+    if (mode != HELIOS_CONVERT_TO_DEVIATION && mode != HELIOS_CONVERT_TO_FLUX && mode != HELIOS_CONVERT_ZERO_FLUX)
+        return fail(HELIOS_EINVAL, "helios_state_convert: unknown mode %d", mode);
+    if (layers != HELIOS_LAYERS_SUBLAYERED && layers != HELIOS_LAYERS_ISOTHERMAL)
+        return fail(HELIOS_EINVAL, "helios_state_convert: unknown layers %d", layers);
+    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    if (!(D > 0.0)) return fail(HELIOS_EINVAL, "D = %g must be > 0", D);
+    hipError_t e = launch_state(atm, T_pt, 2.0 * kPi / D, F_g, mode, layers == HELIOS_LAYERS_ISOTHERMAL ? 1 : 0,
+                                prec == HELIOS_MIXED, z.total_bin, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "helios_state_convert");
+    g_err[0] = 0;
+    return HELIOS_OK;
 }
 
 int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
@@ -644,13 +680,16 @@ int helios_flux_rayleigh(const helios_atm* atm, const void* kappa, const double*
 
 int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* T_pt, double* F_up_g,
                       double* F_dn_g, double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
-                      void* stream) {
+                      int32_t state, void* stream) {
     FluxPlan p;
     int rc = check_atm(atm, p.z);
     if (rc) return rc;
     if (!kappa || !T_pt || !F_up_g || !F_dn_g || !F_bol || !ws)
         return fail(HELIOS_EINVAL, "helios_flux_exact: NULL argument");
+    if (state != HELIOS_STATE_DEVIATION && state != HELIOS_STATE_FLUX)
+        return fail(HELIOS_EINVAL, "helios_flux_exact: unknown state 0x%x", state);
     p.mixed = false;
+    p.flux_state = state == HELIOS_STATE_FLUX;
     p.w = ws_layout(p.z, atm->n_g, false);
     if (ws_bytes < p.w.total)
         return fail(HELIOS_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, p.w.total);
@@ -770,16 +809,23 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
     return cleanup(HELIOS_OK);
 }
 
+int helios_autotune_reset(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned.clear();
+    return HELIOS_OK;
+}
+
 int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, int32_t max_classes) {
     Sizes z;
     int rc = check_atm(atm, z);
     if (rc) return rc;
     if (!out || max_classes < kNumClasses) return fail(HELIOS_EINVAL, "out needs %d classes", kNumClasses);
-    if (prec != HELIOS_FP64 && prec != HELIOS_MIXED) return fail(HELIOS_EINVAL, "unknown precision %d", prec);
+    bool mixed = false, fstate = false;
+    if (!split_prec((int)prec, mixed, fstate)) return fail(HELIOS_EINVAL, "unknown precision 0x%x", (int)prec);
     for (int k = 0; k < kNumClasses; ++k) {
         SweepShape sh = {0, 0};
         if (z.cls_nmax[k]) {
-            rc = pick_shape(k, 2 * z.cls_nmax[k], atm->n_g, prec == HELIOS_MIXED, sh);
+            rc = pick_shape(k, 2 * z.cls_nmax[k], atm->n_g, mixed, sh);
             if (rc) return rc;
         }
         out[3 * k] = kClassNHi[k];

@@ -138,6 +138,7 @@ struct SweepArgs {
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
     int32_t bnd_maxch;    // boundary chunks per atmosphere in bnd_part
     int32_t iso_grid;     // 1: isothermal-layer grid (layer i = sublayer slot 2i, slot 2i+1 the identity)
+    int32_t flux_state;   // 1: F_up_g / F_dn_g hold fluxes; 0: deviations from (2 pi / D) B
     double D;
     const double* lambda_c;  // [sum nb] bin centres (Rayleigh scattering)
     double inv_mbar;         // > 0: add H2 Rayleigh scattering with this 1/mbar (g^-1); w0, g0 unused
@@ -233,6 +234,8 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
 hipError_t launch_mix(const helios_atm* atm, const helios_ktab* kt, const double* T_pt, const double* vmr,
                       void* kappa, bool mixed, int64_t total_pt, const int32_t* n_layer_h,
                       const int32_t* n_bin_h, hipStream_t s);
+hipError_t launch_state(const helios_atm* atm, const double* T_pt, double tpe, void* F, int mode, int iso_grid,
+                        bool mixed, int64_t total_bin, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs& a, int K, int L, bool mixed, int grid, hipStream_t s);  // Rayleigh if a.inv_mbar > 0
 hipError_t launch_exact(const SweepArgs& a, int64_t n_bins, hipStream_t s);
 hipError_t launch_transmission(const helios_atm* atm, const void* kappa, const double* T_pt,

@@ -146,11 +146,19 @@ __global__ void __launch_bounds__(64) exact_kernel(const SweepArgs A) {
             const int cs = col_stride(n);
             const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
             const int64_t cell0 = A.cell_off[at] + (int64_t)l * A.n_g * cs;
+            const double* __restrict__ B = static_cast<const double*>(A.B) + pb;
             for (int p = threadIdx.x; p < npt; p += blockDim.x) {
                 double su = 0.0, sd = 0.0;
+                const double piB = kPi * B[p];
                 for (int c = 0; c < A.n_g; ++c) {
-                    su += A.gw[c] * Fu[cell0 + (int64_t)c * cs + p];
-                    sd += A.gw[c] * Fd[cell0 + (int64_t)c * cs + p];
+                    const int64_t cell = cell0 + (int64_t)c * cs + p;
+                    const double u = Fu[cell], d = Fd[cell];
+                    su += A.gw[c] * u;
+                    sd += A.gw[c] * d;
+                    if (A.flux_state) {  // the caller keeps fluxes, not deviations from pi B
+                        Fu[cell] = u + piB;
+                        Fd[cell] = d + piB;
+                    }
                 }
                 part_up[pb * A.wpb_stride + p] = su;
                 part_dn[pb * A.wpb_stride + p] = sd;

@@ -128,6 +128,45 @@ __global__ void __launch_bounds__(kBndChunk) boundary_kernel(helios_atm atm, Sou
     if (t == 0) sa.bnd_part[(int64_t)a * sa.bnd_maxch + ch] = red[0];
 }
 
+// Conversion of a per-g cell array between fluxes and deviations from the
+// isothermal flux (2 pi / D) B (Sec. 2.2.3; see helios_state_convert):
+// workgroup = one bin, threads over its points; each point's reference is
+// formed once in FP64 and applied to the bin's n_g columns (coalesced along
+// the points of a column).  mode 0: F - tpe B, 1: G + tpe B, 2: -tpe B.
+template <typename R>
+__global__ void __launch_bounds__(kPlanckThreads) state_kernel(helios_atm atm, const double* __restrict__ T_pt,
+                                                               double tpe, R* __restrict__ F, int mode,
+                                                               int iso_grid) {
+    const int64_t b = blockIdx.x;
+    const int a = find_atm(atm.bin_off, atm.n_atm, b);
+    if (frozen(atm.status, a)) return;  // uniform per workgroup
+    const int n = atm.n_layer[a];
+    const int npt = 2 * n + 1, cs = col_stride(n);
+    const double lam = atm.lambda_c[b];
+    const double* __restrict__ T = T_pt + atm.pt_off[a];
+    R* __restrict__ col0 = F + atm.cell_off[a] + (b - atm.bin_off[a]) * atm.n_g * cs;
+    for (int p = threadIdx.x; p < npt; p += kPlanckThreads) {
+        const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
+        const double ref = tpe * planck_d(lam, T[pt]);
+        for (int g = 0; g < atm.n_g; ++g) {
+            R* c = col0 + (int64_t)g * cs + p;
+            const double v = (mode == 2) ? -ref : (mode == 1 ? (double)*c + ref : (double)*c - ref);
+            *c = (R)v;
+        }
+    }
+}
+
+hipError_t launch_state(const helios_atm* atm, const double* T_pt, double tpe, void* F, int mode, int iso_grid,
+                        bool mixed, int64_t total_bin, hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL(state_kernel<float>, dim3((unsigned)total_bin), dim3(kPlanckThreads), 0, s, *atm, T_pt,
+                           tpe, (float*)F, mode, iso_grid);
+    else
+        hipLaunchKernelGGL(state_kernel<double>, dim3((unsigned)total_bin), dim3(kPlanckThreads), 0, s, *atm, T_pt,
+                           tpe, (double*)F, mode, iso_grid);
+    return hipGetLastError();
+}
+
 hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const SourceArgs& sa, const GaussTable& gt,
                          hipStream_t s) {
     hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm, sa.bnd_maxch), dim3(kBndChunk), 0, s, *atm, sa, gt);
@@ -314,7 +353,8 @@ __global__ void __launch_bounds__(kRadeqThreads) radeq_kernel(helios_atm atm, co
     const int a = blockIdx.x;
     const int n = atm.n_layer[a];
     const int npt = 2 * n + 1;
-    if (status[a] == HELIOS_ATM_CONVERGED) return;  // frozen (uniform per workgroup)
+    // frozen (uniform per workgroup); a bad grid stays flagged
+    if (status[a] == HELIOS_ATM_CONVERGED || status[a] == HELIOS_ATM_BADGRID) return;
     const double* F = F_bol + 3 * atm.pt_off[a];
     const double* P = atm.P_pt + atm.pt_off[a];
     double* Tc = T_c + atm.lay_off[a];
@@ -323,6 +363,11 @@ __global__ void __launch_bounds__(kRadeqThreads) radeq_kernel(helios_atm atm, co
     const double sig = sigma_sb();
     const double ti2 = atm.T_int[a] * atm.T_int[a];
     for (int p = threadIdx.x; p < npt; p += blockDim.x) s_lp[p] = log(P[p]);
+    __syncthreads();
+    // the grid (Sec. 2.2.1): pressures positive, finite and strictly decreasing upward
+    int badgrid = 0;
+    for (int p = threadIdx.x; p < npt; p += blockDim.x)
+        if (!isfinite(s_lp[p]) || (p > 0 && !(s_lp[p] < s_lp[p - 1]))) badgrid = 1;
     // convergence measure (eq:condition), on the fluxes handed in
     double worst = 0.0;
     int nonfinite = 0;
@@ -338,17 +383,27 @@ __global__ void __launch_bounds__(kRadeqThreads) radeq_kernel(helios_atm atm, co
     for (int off = 32; off > 0; off >>= 1) {
         worst = fmax(worst, __shfl_xor(worst, off, 64));
         nonfinite |= __shfl_xor(nonfinite, off, 64);
+        badgrid |= __shfl_xor(badgrid, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         s_red[threadIdx.x >> 6] = worst;
-        s_bad[threadIdx.x >> 6] = nonfinite;
+        s_bad[threadIdx.x >> 6] = nonfinite | (badgrid << 1);
     }
     __syncthreads();
     worst = 0.0;
     nonfinite = 0;
+    badgrid = 0;
     for (int w = 0; w < kRadeqThreads / 64; ++w) {
         worst = fmax(worst, s_red[w]);
-        nonfinite |= s_bad[w];
+        nonfinite |= s_bad[w] & 1;
+        badgrid |= s_bad[w] >> 1;
+    }
+    if (badgrid) {
+        if (threadIdx.x == 0) {
+            status[a] = HELIOS_ATM_BADGRID;
+            if (resid) resid[a] = __longlong_as_double(0x7ff8000000000000LL);
+        }
+        return;
     }
     if (threadIdx.x == 0 && resid) resid[a] = nonfinite ? __longlong_as_double(0x7ff8000000000000LL) : worst;
     if (nonfinite) {

@@ -359,19 +359,22 @@ __device__ inline R col_sum(R v) {
 // capacity of K*L sublayers so that every lane can address its K sublayers
 // without bounds tests: sublayers past the column hold the identity.
 //   dB, hdm  [K*L + 1]   Planck difference and half column mass per sublayer
+//   tB       [K*L + 1]   (2 pi / D) B per point (flux-state conversion)
 //   lq       [K*L/2][4]  r, kx, sf, gd per layer
 //   pu, pd   [K*L + 2]   Gauss sums per point; the last slot absorbs writes
 //                        of lanes that own no point
 struct SweepLds {
-    int dB, hdm, lq, pu, pd, junk, total;
+    int dB, hdm, tB, lq, pu, pd, junk, total;
+    static constexpr int r4(int v) { return (v + 3) & ~3; }
     __host__ __device__ constexpr SweepLds(int KL)
         : dB(0),
-          hdm((KL + 1 + 3) & ~3),
-          lq(2 * ((KL + 1 + 3) & ~3)),
-          pu(2 * ((KL + 1 + 3) & ~3) + 4 * ((KL / 2 + 3) & ~3)),
-          pd(2 * ((KL + 1 + 3) & ~3) + 4 * ((KL / 2 + 3) & ~3) + ((KL + 2 + 3) & ~3)),
+          hdm(r4(KL + 1)),
+          tB(2 * r4(KL + 1)),
+          lq(3 * r4(KL + 1)),
+          pu(3 * r4(KL + 1) + 4 * r4(KL / 2)),
+          pd(3 * r4(KL + 1) + 4 * r4(KL / 2) + r4(KL + 2)),
           junk(KL + 1),
-          total(2 * ((KL + 1 + 3) & ~3) + 4 * ((KL / 2 + 3) & ~3) + 2 * ((KL + 2 + 3) & ~3)) {}
+          total(3 * r4(KL + 1) + 4 * r4(KL / 2) + 2 * r4(KL + 2)) {}
 };
 
 // One workgroup = one wave, which owns one (bin, part) at a time.  It stages
@@ -398,6 +401,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     R* sm = reinterpret_cast<R*>(smem_raw);
     R* s_dB = sm + lay.dB;
     R* s_hdm = sm + lay.hdm;
+    R* s_tB = sm + lay.tB;
     R* s_lq = sm + lay.lq;
     R* s_pu = sm + lay.pu;
     R* s_pd = sm + lay.pd;
@@ -415,6 +419,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     const R D = (R)A.D;
     const R inv_D = (R)(1.0 / A.D);
     const R tpe = (R)(2.0 * kPi / A.D);
+    const double tpe_d = 2.0 * kPi / A.D;
+    const bool fstate = A.flux_state != 0;  // per-g arrays hold F, not F - (2 pi / D) B
 
     for (int64_t item = A.w_begin + blockIdx.x; item < A.w_end; item += gridDim.x) {
         const int64_t gb = (A.parts == 1) ? item : item / A.parts;
@@ -490,6 +496,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 if (i <= KL) {
                     s_dB[i] = real ? (R)(bv[q] - bn) : (R)0;
                     s_hdm[i] = real ? (R)((pv[q] - pn) * higrav) : (R)0;
+                    s_tB[i] = (i < npt) ? (R)(tpe_d * bv[q]) : (R)0;
                 }
                 if (i <= KL + 1) {
                     s_pu[i] = (R)0;
@@ -549,6 +556,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             for (int p = 0; p < KH; ++p) {
                 fu[2 * p] = fp2[p].x;
                 fu[2 * p + 1] = fp2[p].y;
+            }
+            if (fstate) {  // the sweep carries deviations from the isothermal flux
+#pragma unroll
+                for (int k = 0; k < K; ++k) fu[k] -= s_tB[lo + k];
             }
         }
 
@@ -653,7 +664,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             const R st = col_sum<L>(wg * vtop);
             if (top_seg) acc[nsub] += st;
         };
-        // per-g values of one stream (pairs at my points, the TOA value alone)
+        // per-g values of one stream (pairs at my points, the TOA value
+        // alone), as fluxes when the caller keeps the flux state
         auto store = [&](const R (&v)[K], R vtop, R* __restrict__ dst_g) {
             if (!colok) return;
 #pragma unroll
@@ -662,10 +674,14 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     R2 w;
                     w.x = v[2 * p];
                     w.y = v[2 * p + 1];
+                    if (fstate) {
+                        w.x += s_tB[lo + 2 * p];
+                        w.y += s_tB[lo + 2 * p + 1];
+                    }
                     *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(lo + 2 * p))) = w;
                 }
             }
-            if (top_seg) dst_g[col + (uint32_t)nsub] = vtop;
+            if (top_seg) dst_g[col + (uint32_t)nsub] = fstate ? vtop + s_tB[nsub] : vtop;
         };
 
         // One scattering pass: downward sweep (top -> bottom), then upward

@@ -27,7 +27,10 @@ HELIOS_NOT_CONVERGED = 1
 FP64, MIXED = 0, 1
 KTAB_TABLE, KTAB_POWERLAW = 0, 1
 NORM_SIGMA_T4, NORM_SIGMA_TINT4 = 0, 1
-ATM_RUNNING, ATM_CONVERGED, ATM_NUMERIC = 0, 1, -5
+ATM_RUNNING, ATM_CONVERGED, ATM_BADGRID, ATM_NUMERIC = 0, 1, -2, -5
+STATE_DEVIATION, STATE_FLUX = 0x000, 0x100  # per-g convention, OR'ed into prec
+CONVERT_TO_DEVIATION, CONVERT_TO_FLUX, CONVERT_ZERO_FLUX = 0, 1, 2
+LAYERS_SUBLAYERED, LAYERS_ISOTHERMAL = 0, 1
 MAX_SPECIES = 8
 CELL_ALIGN = 32  # column stride of the cell arrays: 2n+1 rounded up to this
 
@@ -38,7 +41,7 @@ class HeliosAtm(ctypes.Structure):
     _fields_ = [("n_atm", ctypes.c_int32), ("n_g", ctypes.c_int32),
                 ("n_layer_h", _P), ("n_bin_h", _P), ("n_layer", _P), ("n_bin", _P),
                 ("lay_off", _P), ("pt_off", _P), ("bin_off", _P), ("lb_off", _P), ("pb_off", _P),
-                ("cell_off", _P), ("bin_index", _P), ("lambda_c", _P), ("dlambda", _P), ("P_c", _P),
+                ("cell_off", _P), ("bin_index", _P), ("bin_index_h", _P), ("lambda_c", _P), ("dlambda", _P), ("P_c", _P),
                 ("P_pt", _P), ("grav", _P), ("T_star", _P), ("T_irr", _P), ("T_int", _P), ("status", _P)]
 
 
@@ -90,7 +93,9 @@ def lib():
         L.helios_flux.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
         L.helios_flux_iso.argtypes = L.helios_flux.argtypes
         L.helios_flux_rayleigh.argtypes = [A, _P, _P, dbl, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
-        L.helios_flux_exact.argtypes = [A, _P, _P, _P, _P, _P, _P, _P, _P, sz, _P]
+        L.helios_flux_exact.argtypes = [A, _P, _P, _P, _P, _P, _P, _P, _P, sz, i32, _P]
+        L.helios_state_convert.argtypes = [A, _P, dbl, _P, i32, i32, ctypes.c_int, _P]
+        L.helios_autotune_reset.argtypes = []
         L.helios_radeq.argtypes = [A, _P, _P, _P, ctypes.POINTER(HeliosReState), ctypes.POINTER(HeliosReOpts),
                                    _P, _P, _P]
         L.helios_autotune.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, sz, ctypes.c_int, _P]
@@ -110,7 +115,9 @@ def lib():
         L.helios_last_error.restype = ctypes.c_char_p
         L.helios_version.restype = i32
         for f in ("helios_grid", "helios_profile", "helios_mix_opacity", "helios_transmission",
-                  "helios_flux", "helios_radeq", "helios_autotune", "helios_sweep_shapes", "helios_mlp_sync",
+                  "helios_flux", "helios_flux_iso", "helios_flux_rayleigh", "helios_flux_exact",
+                  "helios_state_convert", "helios_autotune_reset",
+                  "helios_radeq", "helios_autotune", "helios_sweep_shapes", "helios_mlp_sync",
                   "helios_mlp_forward", "helios_mlp_backward", "helios_mlp_adam", "helios_warm_start"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -180,11 +187,12 @@ class Batch:
         cat = lambda key: np.concatenate([np.ravel(np.asarray(a[key], np.float64)) for a in atms])  # noqa: E731
         self.h_n_layer = np.ascontiguousarray(n, np.int32)
         self.h_n_bin = np.ascontiguousarray(nb, np.int32)
+        self.h_bin_index = np.ascontiguousarray(np.concatenate([np.asarray(a["bin_index"], np.int32) for a in atms]))
         self.d = {
             "n_layer": i32(n), "n_bin": i32(nb), "lay_off": i64(self.lay_off), "pt_off": i64(self.pt_off),
             "bin_off": i64(self.bin_off), "lb_off": i64(self.lb_off), "pb_off": i64(self.pb_off),
             "cell_off": i64(self.cell_off),
-            "bin_index": i32(np.concatenate([np.asarray(a["bin_index"], np.int32) for a in atms])),
+            "bin_index": i32(self.h_bin_index),
             "lambda_c": f64(cat("lambda_c")), "dlambda": f64(cat("dlambda")), "P_c": f64(cat("P_c")),
             "P_pt": torch.zeros(self.total_pt, dtype=torch.float64, device=dev),
             "grav": f64([a["grav"] for a in atms]), "T_star": f64([a["T_star"] for a in atms]),
@@ -194,11 +202,14 @@ class Batch:
         self.g0 = f64(cat("g0"))
         vmr = np.concatenate([np.asarray(a["vmr"], np.float64) for a in atms], axis=1)
         self.vmr = f64(vmr)  # [nsp][total_pt]
+        d = self.d
         self.desc = HeliosAtm(
             self.n_atm, self.ng, self.h_n_layer.ctypes.data, self.h_n_bin.ctypes.data,
-            *[_ptr(self.d[k]) for k in ("n_layer", "n_bin", "lay_off", "pt_off", "bin_off", "lb_off",
-                                         "pb_off", "cell_off", "bin_index", "lambda_c", "dlambda", "P_c",
-                                         "P_pt", "grav", "T_star", "T_irr", "T_int")], None)
+            *[_ptr(d[k]) for k in ("n_layer", "n_bin", "lay_off", "pt_off", "bin_off", "lb_off", "pb_off",
+                                   "cell_off", "bin_index")],
+            self.h_bin_index.ctypes.data,
+            *[_ptr(d[k]) for k in ("lambda_c", "dlambda", "P_c", "P_pt", "grav", "T_star", "T_irr", "T_int")],
+            None)
         self.device = dev
 
     def with_status(self, status):
@@ -268,7 +279,7 @@ class KTable:
 
 
 def rdtype(prec: int):
-    return torch.float32 if prec == MIXED else torch.float64
+    return torch.float32 if (prec & 0xff) == MIXED else torch.float64
 
 
 # --------------------------------------------------------------- the calls
@@ -303,6 +314,23 @@ def set_sweep_events(before=None, after=None):
     _check(lib().helios_set_sweep_events(hb, ha))
 
 
+def autotune_reset():
+    """Forget the shapes the autotuner chose in this process."""
+    _check(lib().helios_autotune_reset())
+
+
+def state_convert(b: Batch, T_pt, F_g, mode, D=2.0, prec=FP64, layers="noniso", stream=None):
+    """helios_state_convert: a per-g cell array between fluxes and deviations
+    from (2 pi / D) B (mode CONVERT_TO_DEVIATION / CONVERT_TO_FLUX), or the
+    zero-flux start in deviation form (CONVERT_ZERO_FLUX)."""
+    if layers not in LAYERS:
+        raise ValueError(f"layers must be one of {LAYERS}")
+    lay = LAYERS_SUBLAYERED if layers == "noniso" else LAYERS_ISOTHERMAL
+    _check(lib().helios_state_convert(ctypes.byref(b.desc), _ptr(T_pt), float(D), _ptr(F_g), int(mode), lay,
+                                      int(prec), _stream(stream)))
+    return F_g
+
+
 def autotune(b: Batch, kappa, T_pt, F_up_g, ws, n_scat=4, D=2.0, prec=FP64, stream=None):
     """Time the compiled sweep shapes per size class of the batch and keep
     the fastest for later flux calls (synchronous; F_up_g is restored)."""
@@ -323,12 +351,14 @@ def workspace_bytes(b: Batch, prec=FP64) -> int:
     return int(lib().helios_workspace_bytes(ctypes.byref(b.desc), prec))
 
 
-def flux_exact(b: Batch, kappa, T_pt, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws, stream=None):
+def flux_exact(b: Batch, kappa, T_pt, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws, state=STATE_DEVIATION,
+               stream=None):
     """helios_flux_exact: pure absorption with the exact layer relations
-    (FP64; the per-g outputs are deviations from pi B)."""
+    (FP64; the per-g outputs are deviations from pi B, or the fluxes with
+    state=STATE_FLUX)."""
     _check(lib().helios_flux_exact(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(F_up_g), _ptr(F_dn_g),
                                    _ptr(F_up_bin), _ptr(F_dn_bin), _ptr(F_bol), _ptr(ws),
-                                   ws.numel() * ws.element_size(), _stream(stream)))
+                                   ws.numel() * ws.element_size(), int(state), _stream(stream)))
 
 
 LAYERS = ("noniso", "iso")
@@ -358,12 +388,17 @@ def flux_rayleigh(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, 
                                       _stream(stream)))
 
 
-def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, stream=None, layers="noniso"):
+def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, stream=None, layers="noniso",
+                      start="zero"):
     """Post-processing of converged profiles (Sec. 2.6, Sec. 3): one flux
-    call with many scattering passes from the isothermal start; returns the
-    upward flux at the top of each atmosphere per bin (a list of [n_bin]
-    device arrays) and the per-bin upward fluxes at every point.  The paper
-    post-processes on isothermal layers (layers="iso", Sec. 3.3)."""
+    call with many scattering passes, from zero fluxes (start="zero", the
+    paper's start of the scattering iteration) or from the isothermal flux
+    (start="isothermal"); returns the upward flux at the top of each
+    atmosphere per bin (a list of [n_bin] device arrays) and the per-bin
+    upward fluxes at every point.  The paper post-processes on isothermal
+    layers (layers="iso", Sec. 3.3)."""
+    if start not in ("zero", "isothermal"):
+        raise ValueError("start must be 'zero' or 'isothermal'")
     dev = b.device
     rd = rdtype(prec)
     T_c = torch.as_tensor(T_c, dtype=torch.float64, device=dev)
@@ -373,6 +408,8 @@ def emission_spectrum(b: Batch, kt: KTable, T_c, n_scat=80, D=2.0, prec=FP64, st
     kap = torch.zeros(b.total_cell, dtype=rd, device=dev)
     mix_opacity(b, kt, T_pt, kap, prec, stream=stream)
     F_up = torch.zeros(b.total_cell, dtype=rd, device=dev)
+    if start == "zero":  # zero fluxes in deviation form
+        state_convert(b, T_pt, F_up, CONVERT_ZERO_FLUX, D=D, prec=prec, layers=layers, stream=stream)
     ub = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
     db = torch.zeros(b.total_pb, dtype=torch.float64, device=dev)
     bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device=dev)
@@ -570,16 +607,32 @@ class Solver:
     while the rest of the batch iterates on.  ``graph=True`` in ``solve``
     captures ``check_every`` iterations into one HIP graph (torch.cuda.CUDAGraph)
     and replays it, so a block of iterations costs one launch from the host.
+
+    ``state`` is the convention of the per-g warm start kept between
+    iterations: "flux" (the fluxes themselves, the paper's reading of
+    Sec. 2.2.3; the FP64 default) or "deviation" (deviations from the
+    isothermal flux, which keep FP32 sweeps accurate at depth; the mixed
+    default).  ``start`` is the scattering iteration's state at the first
+    iteration: "zero" (zero fluxes, the paper's start) or "isothermal"
+    (F = (2 pi / D) B).
     """
 
     def __init__(self, b: Batch, kt: KTable, prec=FP64, n_scat=4, D=2.0, opts: REOptions | None = None,
-                 bin_fluxes: bool = True, layers: str = "noniso", rayleigh_mbar: float | None = None):
+                 bin_fluxes: bool = True, layers: str = "noniso", rayleigh_mbar: float | None = None,
+                 state: str | None = None, start: str = "zero"):
         dev = b.device
         rd = rdtype(prec)
         if layers not in LAYERS:
             raise ValueError(f"layers must be one of {LAYERS}")
         if rayleigh_mbar is not None and layers != "noniso":
             raise ValueError("Rayleigh scattering is solved on the sublayered grid")
+        if prec not in (FP64, MIXED):
+            raise ValueError("prec must be FP64 or MIXED (the state convention is its own argument)")
+        state = state or ("flux" if prec == FP64 else "deviation")
+        if state not in ("flux", "deviation") or start not in ("zero", "isothermal"):
+            raise ValueError("state must be 'flux' or 'deviation', start 'zero' or 'isothermal'")
+        self.state, self.start = state, start
+        self.pflags = prec | (STATE_FLUX if state == "flux" else STATE_DEVIATION)
         self.kt, self.prec, self.n_scat, self.D = kt, prec, n_scat, D
         self.layers = layers  # "iso": the isothermal-layer grid (helios_flux_iso)
         self.rayleigh_mbar = rayleigh_mbar  # H2 Rayleigh scattering with this mean molecular mass (g)
@@ -604,6 +657,23 @@ class Solver:
         self._T_iso = 1000.0
         grid(b)
 
+    def _start_fluxes(self, b=None):
+        """Write the first iteration's per-g state of the running atmospheres
+        of ``b`` (default: the solver's batch view) in the solver's
+        convention: zero fluxes or the isothermal flux."""
+        b = self.b if b is None else b
+        lay = "iso" if self.layers == "iso" else "noniso"
+        if self.start == "zero" and self.state == "deviation":
+            state_convert(b, self.T_pt, self.F_up_g, CONVERT_ZERO_FLUX, D=self.D, prec=self.prec, layers=lay)
+        elif self.start == "isothermal" and self.state == "flux":
+            state_convert(b, self.T_pt, self.F_up_g, CONVERT_TO_FLUX, D=self.D, prec=self.prec, layers=lay)
+
+    def _only(self, which):
+        """A view of the batch in which only the listed atmospheres run."""
+        st = torch.full((self.b.n_atm,), ATM_CONVERGED, dtype=torch.int32, device=self.b.device)
+        st[torch.as_tensor(np.asarray(which, np.int64), device=self.b.device)] = ATM_RUNNING
+        return self.b.with_status(st)
+
     def _reset_state(self):
         self.F_up_g.zero_()
         self.m.fill_(1.0)
@@ -611,6 +681,7 @@ class Solver:
         self.status.zero_()
         self.iters.zero_()
         profile(self.b, self.T_c, self.T_pt)
+        self._start_fluxes()
 
     def reset(self, T_init):
         """Start every atmosphere from the given layer temperatures."""
@@ -648,6 +719,8 @@ class Solver:
             self.F_up_g[int(b.cell_off[a]):int(b.cell_off[a + 1])] = 0
             self.status[a] = ATM_RUNNING
         profile(self.b, self.T_c, self.T_pt)
+        if len(which):
+            self._start_fluxes(self._only(which))
 
     def subset(self, keep, prec=None):
         """A solver over the atmospheres `keep` (indices into this batch) that
@@ -655,8 +728,8 @@ class Solver:
         histories, update counts and per-g warm starts are carried over, every
         carried atmosphere is running.  Used to compact a batch whose active
         set has shrunk, so later launches cover only live atmospheres, and to
-        continue atmospheres in another precision (the per-g warm start holds
-        deviations from the isothermal flux, which carry over unchanged)."""
+        continue atmospheres in another precision (the per-g warm start is
+        converted where the two solvers keep different conventions)."""
         return Solver.concat([(self, keep)], prec=prec)
 
     @staticmethod
@@ -669,10 +742,13 @@ class Solver:
         keeps = [np.asarray(k, np.int64) for _, k in parts]
         dev = s0.b.device
         nb = Batch([src.b.atms[int(a)] for (src, _), keep in zip(parts, keeps) for a in keep], device=dev)
-        s = Solver(nb, s0.kt, prec=s0.prec if prec is None else prec, n_scat=s0.n_scat, D=s0.D,
-                   opts=s0.opts, bin_fluxes=s0.bin_fluxes, layers=s0.layers, rayleigh_mbar=s0.rayleigh_mbar)
+        p_new = s0.prec if prec is None else prec
+        s = Solver(nb, s0.kt, prec=p_new, n_scat=s0.n_scat, D=s0.D, opts=s0.opts, bin_fluxes=s0.bin_fluxes,
+                   layers=s0.layers, rayleigh_mbar=s0.rayleigh_mbar,
+                   state=s0.state if p_new == s0.prec else None, start=s0.start)
         k = 0
         warm = []
+        to_flux, to_dev = [], []  # carried atmospheres whose convention changes
         for (src, _), keep in zip(parts, keeps):
             b0 = src.b
             for a in keep:
@@ -685,6 +761,8 @@ class Solver:
                 cs, ce = int(b0.cell_off[a]), int(b0.cell_off[a + 1])
                 nc = int(nb.cell_off[k])
                 s.F_up_g[nc:nc + ce - cs] = src.F_up_g[cs:ce].to(s.F_up_g.dtype)
+                if src.state != s.state:
+                    (to_flux if s.state == "flux" else to_dev).append(k)
                 k += 1
             if keep.size:
                 idx = torch.as_tensor(keep, device=dev)
@@ -695,6 +773,10 @@ class Solver:
         s._warm = np.concatenate(warm) if any(src._warm is not None for src, _ in parts) else None
         s._T_iso = s0._T_iso
         profile(s.b, s.T_c, s.T_pt)
+        lay = "iso" if s.layers == "iso" else "noniso"
+        for idx, mode in ((to_flux, CONVERT_TO_FLUX), (to_dev, CONVERT_TO_DEVIATION)):
+            if idx:
+                state_convert(s._only(idx), s.T_pt, s.F_up_g, mode, D=s.D, prec=s.prec, layers=lay)
         return s
 
     def step(self, stream=None):
@@ -703,10 +785,11 @@ class Solver:
         mix_opacity(b, self.kt, self.T_pt, self.kappa, self.prec, stream=stream)
         if self.rayleigh_mbar is not None:
             flux_rayleigh(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol,
-                          self.ws, self.rayleigh_mbar, n_scat=self.n_scat, D=self.D, prec=self.prec, stream=stream)
+                          self.ws, self.rayleigh_mbar, n_scat=self.n_scat, D=self.D, prec=self.pflags,
+                          stream=stream)
         else:
             flux(b, self.kappa, self.T_pt, self.F_up_g, self.F_up_bin, self.F_dn_bin, self.F_bol, self.ws,
-                 n_scat=self.n_scat, D=self.D, prec=self.prec, stream=stream, layers=self.layers)
+                 n_scat=self.n_scat, D=self.D, prec=self.pflags, stream=stream, layers=self.layers)
         radeq(b, self.F_bol, self.T_c, self.T_pt, self.m, self.hist, self.status, self.resid, self.opts,
               iters=self.iters, stream=stream)
 
@@ -716,7 +799,7 @@ class Solver:
         apart from kappa."""
         mix_opacity(self.b, self.kt, self.T_pt, self.kappa, self.prec)
         autotune(self.b, self.kappa, self.T_pt, self.F_up_g, self.ws, n_scat=self.n_scat, D=self.D,
-                 prec=self.prec)
+                 prec=self.pflags)
 
     def capture(self, n_steps):
         """Capture n_steps iterations into a HIP graph (replayed by

@@ -25,3 +25,14 @@ def ref():
     import oracle
 
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _fresh_sweep_shapes(request):
+    """Every GPU test starts from the default sweep shapes: shapes another
+    test tuned (helios_autotune keeps them for the process) are forgotten."""
+    if request.node.get_closest_marker("gpu") is not None:
+        from paper_1606_05474_amd import helios
+
+        helios.autotune_reset()
+    yield

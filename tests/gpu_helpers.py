@@ -29,6 +29,16 @@ def net_flux_error(F_bol_gpu, F_bol_ref):
     return np.abs(F_bol_gpu[:, 2] - F_bol_ref[:, 2]) / gross
 
 
+def net_flux_error_sigma(F_bol_gpu, F_bol_ref, T_int):
+    """Per-point |net_gpu - net_ref| / max(|net_ref|, sigma T_int^4): the
+    error against the net flux itself, or against the flux the atmosphere
+    carries at equilibrium where the net flux is smaller than that."""
+    F_bol_gpu = np.asarray(F_bol_gpu).reshape(-1, 3)
+    F_bol_ref = np.asarray(F_bol_ref).reshape(-1, 3)
+    floor = 5.670374419e-5 * float(T_int) ** 4
+    return np.abs(F_bol_gpu[:, 2] - F_bol_ref[:, 2]) / np.maximum(np.abs(F_bol_ref[:, 2]), floor)
+
+
 def col_rel_error(x, y, axis=-1):
     """|x - y| relative to the largest |y| along `axis` (per column)."""
     x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)

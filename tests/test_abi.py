@@ -56,7 +56,7 @@ int main(void) {
   printf("helios_re_state %zu\\n", sizeof(helios_re_state));
   printf("helios_mlp %zu\\n", sizeof(helios_mlp));
   P(helios_mlp, params) P(helios_mlp, out_scale)
-  P(helios_atm, T_int) P(helios_atm, status) P(helios_atm, P_pt) P(helios_ktab, k) P(helios_ktab, mmw) P(helios_ktab, species_mass)
+  P(helios_atm, T_int) P(helios_atm, status) P(helios_atm, P_pt) P(helios_atm, bin_index_h) P(helios_ktab, k) P(helios_ktab, mmw) P(helios_ktab, species_mass)
   P(helios_re_opts, T_floor) P(helios_re_opts, fpre_p) P(helios_re_state, iter)
   return 0;
 }
@@ -74,6 +74,7 @@ int main(void) {
     assert int(got["helios_atm.T_int"]) == H.HeliosAtm.T_int.offset
     assert int(got["helios_atm.status"]) == H.HeliosAtm.status.offset
     assert int(got["helios_atm.P_pt"]) == H.HeliosAtm.P_pt.offset
+    assert int(got["helios_atm.bin_index_h"]) == H.HeliosAtm.bin_index_h.offset
     assert int(got["helios_ktab.k"]) == H.HeliosKtab.k.offset
     assert int(got["helios_ktab.mmw"]) == H.HeliosKtab.mmw.offset
     assert int(got["helios_ktab.species_mass"]) == H.HeliosKtab.species_mass.offset
@@ -91,7 +92,7 @@ def test_validation_rejects_bad_descriptors_without_a_device(H):
     n_layer = np.array([1], np.int32)   # fewer than 2 layers
     n_bin = np.array([3], np.int32)
     fake = ctypes.c_void_p(16)           # never dereferenced: validation fails first
-    d = H.HeliosAtm(1, 20, n_layer.ctypes.data, n_bin.ctypes.data, *([fake] * 17))
+    d = H.HeliosAtm(1, 20, n_layer.ctypes.data, n_bin.ctypes.data, *([fake] * 18))
     assert lib.helios_grid(ctypes.byref(d), None) == -2
     assert b"n_layer" in lib.helios_last_error()
     d.n_g = 0
@@ -127,7 +128,7 @@ def test_mode_entry_points_validate_before_any_device_work(H):
     n_layer = np.array([50], np.int32)
     n_bin = np.array([3], np.int32)
     fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
-    d = H.HeliosAtm(1, 20, n_layer.ctypes.data, n_bin.ctypes.data, *([fake] * 17))
+    d = H.HeliosAtm(1, 20, n_layer.ctypes.data, n_bin.ctypes.data, *([fake] * 18))
     args = (fake, fake, fake, fake, 4, 2.0, fake, None, None, None, fake, fake, 1 << 30, 0, None)
     assert lib.helios_flux_iso(ctypes.byref(d), None, *args[1:]) == -1  # NULL opacities
     assert lib.helios_flux_iso(ctypes.byref(d), fake, fake, fake, fake, 4, 2.0, fake, None, None, None, None,
@@ -155,3 +156,74 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _desc(H, n=50, nb=3, bin_index=None):
+    """A descriptor whose device pointers are never dereferenced (validation
+    fails first) and whose host mirrors are real arrays."""
+    import numpy as np
+
+    fake = ctypes.c_void_p(16)
+    keep = {"n_layer": np.array([n], np.int32), "n_bin": np.array([nb], np.int32),
+            "bin_index": np.ascontiguousarray(np.arange(nb) if bin_index is None else bin_index, np.int32)}
+    d = H.HeliosAtm(1, 20, keep["n_layer"].ctypes.data, keep["n_bin"].ctypes.data, *([fake] * 18))
+    d.bin_index_h = keep["bin_index"].ctypes.data
+    return d, keep, fake
+
+
+def test_mix_opacity_rejects_a_bin_outside_the_table(H):
+    """A model bin whose table index lies outside the table (Sec. 2.3 looks
+    up the k-distribution of the bin) is -2 with nothing enqueued, checked on
+    the host mirror of bin_index."""
+    import numpy as np
+
+    lib = H.lib()
+    mass = np.array([18.0], np.float64)
+    kt = H.HeliosKtab(H.KTAB_TABLE, 1, 2, 2, 3, 20, 100.0, 100.0, 0.0, 1.0, ctypes.c_void_p(16), None, 0.0, 0.0,
+                      1.0, 1.0, mass.ctypes.data, 2.4)
+    for bad in ([0, 1, 3], [0, -1, 2]):
+        d, keep, fake = _desc(H, bin_index=bad)
+        assert lib.helios_mix_opacity(ctypes.byref(d), ctypes.byref(kt), fake, fake, fake, 0, None) == -2
+        assert b"bin_index" in lib.helios_last_error()
+    d, keep, fake = _desc(H, bin_index=[0, 1, 2])
+    kt.mmw = 0.0  # the bins are fine now: the next check (masses) fails instead
+    assert lib.helios_mix_opacity(ctypes.byref(d), ctypes.byref(kt), fake, fake, fake, 0, None) == -1
+    d.bin_index_h = None
+    assert lib.helios_mix_opacity(ctypes.byref(d), ctypes.byref(kt), fake, fake, fake, 0, None) == -1
+
+
+def test_state_flags_and_conversion_validate_on_the_host(H):
+    """The per-g convention flag is accepted in a flux call's prec argument
+    and nowhere else; unknown flags, modes and layers are -1 before any
+    device work."""
+    lib = H.lib()
+    d, keep, fake = _desc(H)
+    big = 1 << 40
+    args = lambda prec: (ctypes.byref(d), fake, fake, fake, fake, 4, 2.0, fake, None, None, None, fake, fake,  # noqa
+                         big, prec, None)
+    assert lib.helios_flux(*args(0x200)) == -1 and b"flags" in lib.helios_last_error()
+    assert lib.helios_flux(*args(H.FP64 | H.STATE_FLUX | 0x400)) == -1
+    assert lib.helios_workspace_bytes(ctypes.byref(d), H.MIXED | H.STATE_FLUX) == \
+        lib.helios_workspace_bytes(ctypes.byref(d), H.MIXED)
+    assert lib.helios_state_convert(ctypes.byref(d), fake, 2.0, fake, 3, 0, 0, None) == -1
+    assert lib.helios_state_convert(ctypes.byref(d), fake, 2.0, fake, 0, 2, 0, None) == -1
+    assert lib.helios_state_convert(ctypes.byref(d), fake, 0.0, fake, 0, 0, 0, None) == -1
+    assert lib.helios_state_convert(ctypes.byref(d), None, 2.0, fake, 0, 0, 0, None) == -1
+    assert lib.helios_state_convert(ctypes.byref(d), fake, 2.0, fake, 0, 0, H.FP64 | H.STATE_FLUX, None) == -1
+    assert lib.helios_flux_exact(ctypes.byref(d), fake, fake, fake, fake, None, None, fake, fake, big, 0x300,
+                                 None) == -1
+    out = (ctypes.c_int32 * 18)()
+    assert lib.helios_sweep_shapes(ctypes.byref(d), 0, out, 5) == -1  # six classes need room for six
+    assert lib.helios_sweep_shapes(ctypes.byref(d), H.MIXED | H.STATE_FLUX, out, 6) == 6
+
+
+def test_autotune_reset_returns_to_the_default_shapes(H):
+    """helios_autotune_reset is host-only and always succeeds; afterwards
+    helios_sweep_shapes reports the default shapes."""
+    lib = H.lib()
+    d, keep, fake = _desc(H, n=100)
+    out = (ctypes.c_int32 * 18)()
+    assert lib.helios_autotune_reset() == 0
+    assert lib.helios_sweep_shapes(ctypes.byref(d), 0, out, 6) == 6
+    # 100 layers (200 sublayers): class n <= 112, fewest sublayers per lane that hold them
+    assert (out[3 * 2], out[3 * 2 + 1], out[3 * 2 + 2]) == (112, 8, 32)

@@ -189,11 +189,11 @@ def test_flux_iso_ragged_batch_spanning_size_classes(prec, small_table):
 
 
 def test_iso_re_solve_matches_oracle():
-    """Radiative equilibrium on the isothermal-layer grid (FP64): the same
-    number of updates and the same converged profile as the oracle with the
-    same (deviation) warm start."""
+    """Radiative equilibrium on the isothermal-layer grid (FP64) from the
+    paper's start (zero fluxes, then the previous step's fluxes) on both
+    sides: the same number of updates and the same converged profile."""
     atm, kt = W.plain_workload(n=12, nb=12, ng=4)
-    sol = ref.solve(atm, kt, max_iter=1000, layers="iso", warm="deviation")
+    sol = ref.solve(atm, kt, max_iter=1000, layers="iso")
     assert sol["converged"]
     b = H.Batch([atm])
     s = H.Solver(b, H.KTable(kt), prec=H.FP64, layers="iso")
@@ -209,7 +209,7 @@ def test_iso_re_solve_matches_oracle():
 
 def test_iso_post_processing_spectrum_with_80_passes():
     """The paper's post-processing form: isothermal layers, 80 scattering
-    passes from the isothermal start; TOA upward flux per bin, FP64."""
+    passes from zero fluxes (Sec. 2.2.3); TOA upward flux per bin, FP64."""
     lc, dl = W.bins(300)
     atm = W.spectral_atmosphere(np.random.default_rng(82), 101, lc, dl, 300)
     kt = W.table_ktab(2, nbt=300)
@@ -217,7 +217,8 @@ def test_iso_post_processing_spectrum_with_80_passes():
     b = H.Batch([atm])
     toa, per_bin = H.emission_spectrum(b, H.KTable(kt), T_c, n_scat=80, layers="iso")
     P, T, kap = oracle_state(atm, kt, T_c)
-    r = ref.flux_iso(atm, kap[:, :, 1::2], T_c, P[0::2], _iso_start(atm, T_c), n_scat=80, want_dn=False)
+    r = ref.flux_iso(atm, kap[:, :, 1::2], T_c, P[0::2], np.zeros((300, atm["ng"], atm["n"] + 1)), n_scat=80,
+                     want_dn=False)
     want = r["F_up_bin"][:, -1]
     got = _np(toa[0])
     assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()

@@ -337,10 +337,11 @@ def test_radeq_converged_and_numeric_status():
 
 # ---------------------------------------------------------- end to end
 def test_plain_re_solve_matches_oracle():
-    """The plain FP64 workload: same number of temperature updates to reach
-    |dF|/sigma T_int^4 < 1e-3 and the same converged profile."""
+    """The plain FP64 workload from the paper's start (zero fluxes, then the
+    previous step's fluxes) on both sides: same number of temperature updates
+    to reach |dF|/sigma T_int^4 < 1e-3 and the same converged profile."""
     atm, kt = W.plain_workload()
-    sol = ref.solve(atm, kt, max_iter=200, warm="deviation")
+    sol = ref.solve(atm, kt, max_iter=200)
     assert sol["converged"]
     b = H.Batch([atm])
     s = H.Solver(b, H.KTable(kt), prec=H.FP64)
@@ -606,13 +607,14 @@ def test_full_size_production_atmosphere_against_oracle(prec):
 
 
 def test_mixed_precision_converges_to_the_oracle_profile():
-    """The plain workload solved in mixed precision reaches the oracle's
-    converged profile (same warm-start convention) within 0.1 K over the
-    well-conditioned layers (where a layer's own temperature controls its
-    flux divergence); optically thin upper layers are only weakly
-    determined by the convergence test and are reported, not bounded."""
+    """The plain workload solved in mixed precision (deviation convention
+    between steps, zero-flux start) reaches the oracle's converged profile
+    (the paper's reading) within 0.1 K over the well-conditioned layers
+    (where a layer's own temperature controls its flux divergence);
+    optically thin upper layers are only weakly determined by the
+    convergence test and are bounded at 1 K."""
     atm, kt = W.plain_workload()
-    sol = ref.solve(atm, kt, max_iter=300, warm="deviation")
+    sol = ref.solve(atm, kt, max_iter=300)
     assert sol["converged"]
     b = H.Batch([atm])
     s = H.Solver(b, H.KTable(kt), prec=H.MIXED)
@@ -622,7 +624,7 @@ def test_mixed_precision_converges_to_the_oracle_profile():
     ok = well_conditioned_layers(atm, kt, sol)
     assert ok.sum() >= atm["n"] // 2, ok.sum()
     assert dT[ok].max() < 0.1, (dT[ok].max(), dT.max())
-    assert np.all(np.isfinite(dT))
+    assert dT.max() < 1.0, (dT.max(), np.argmax(dT))
 
 
 def test_compacted_batch_continues_the_same_iteration():
@@ -654,7 +656,7 @@ def test_compacted_batch_continues_the_same_iteration():
 def test_post_processing_spectrum_with_80_passes():
     """The post-processing step (many scattering passes on a converged
     profile): TOA upward flux per bin against the oracle with the same 80
-    passes from the same isothermal start, FP64."""
+    passes from the same zero-flux start (Sec. 2.2.3), FP64."""
     lc, dl = W.bins(300)
     rng = np.random.default_rng(81)
     atm = W.spectral_atmosphere(rng, 100, lc, dl, 300)
@@ -663,7 +665,7 @@ def test_post_processing_spectrum_with_80_passes():
     b = H.Batch([atm])
     toa, per_bin = H.emission_spectrum(b, H.KTable(kt), T_c, n_scat=80)
     P, T, kap = oracle_state(atm, kt, T_c)
-    r = ref.flux(atm, kap, T, P, ref.isothermal_start(atm, T), n_scat=80, want_dn=False)
+    r = ref.flux(atm, kap, T, P, np.zeros((300, atm["ng"], 2 * atm["n"] + 1)), n_scat=80, want_dn=False)
     got = _np(toa[0])
     want = r["F_up_bin"][:, -1]
     assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()

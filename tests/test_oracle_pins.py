@@ -541,6 +541,30 @@ def test_re_step_control_and_convergence_flag(ref):
     assert ref.radeq(atm, P, F, T, m, h)[0] == -5
 
 
+def test_re_step_floor_and_grid_check(ref):
+    """Reading R10: a step that would take a layer below 10 K leaves it at
+    exactly 10 K (its step multiplier and sign history still advance); and
+    the step refuses a point grid whose pressures do not decrease upward
+    (Sec. 2.2.1 orders the grid from the bottom to the top), moving nothing."""
+    n = 4
+    P = ref.grid(W.pressure_centres(n))
+    T = np.array([1500.0, 12.0, 900.0, 800.0])
+    net = np.array([3e4, 3e4, 1.0, 9e4, 9e4, 3e2, 2e3, 7.0, 9e3])  # layer 1: dF = +9e4, it cools
+    F = np.zeros((2 * n + 1, 3))
+    F[:, 2] = net
+    m, h = np.ones(n), np.zeros(n, np.int32)
+    Tn = T.copy()
+    code, _ = ref.radeq({"grav": 1000.0, "T_int": 200.0}, P, F, Tn, m, h)
+    assert code == 0 and Tn[1] == 10.0 and Tn[0] != T[0]
+    assert (h[1] >> 16) == 1 and (h[1] & 1) == 0  # one sign recorded: cooling
+    P_bad = P.copy()
+    P_bad[[3, 4]] = P_bad[[4, 3]]
+    Tb, mb, hb = T.copy(), m.copy(), h.copy()
+    code, r = ref.radeq({"grav": 1000.0, "T_int": 200.0}, P_bad, F, Tb, mb, hb)
+    assert code == -2 and np.isnan(r)
+    assert np.array_equal(Tb, T) and np.array_equal(mb, m) and np.array_equal(hb, h)
+
+
 def test_printed_nonisothermal_form_is_not_the_twostream_solution(ref):
     """Why eq:nonisoscat needs the two readings: taken literally (B_1 at the
     lower end, eps/(1 + w0 g0) on B') it misses the exact two-stream solution
