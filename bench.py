@@ -8,16 +8,21 @@ passes, Gauss and bin sums) and the FP64 temperature update with the
 interface re-interpolation (helios_radeq), all in the library's HIP kernels,
 with inputs resident in HBM.
 
-Workload: one atmosphere at full spectral size -- 100 layers (201 points)
-over 1e-6..1e3 bar, 3000 bins over 0.3-30 micron, 20 Gauss points, four
-species k-tables on a 20 T x 20 log P grid (float32, 384 MB), seeded
-synthetic inputs (paper_1606_05474_amd.workloads), FP64.  The same loop in
-mixed precision is reported alongside.
+Default workload (the largest one that fits one GPU): one production chunk
+of 256 parameter-described atmospheres x 200 layers (401 points) x 3000
+bins x 20 Gauss points, four float32 k-tables on a 20 T x 20 log P grid
+(384 MB), mixed precision (FP32 sweeps, FP64 sums and update), started from
+the warm-start network, seeded synthetic inputs
+(paper_1606_05474_amd.workloads).  The single-atmosphere spectral workload
+(100 layers x 3000 bins x 20 g, FP64 and mixed) and the uneven 512-atmosphere
+batch are reported alongside, and the FP64 oracle's rate on one of the
+chunk's atmospheres on the host cores.
 
 Metric: layer*bin*g flux updates per second (one unit = one layer, both
 sublayers, one bin, one g point, through one complete flux call).
 
 Usage:  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+        python bench.py --workload {spectral,batch,chunk,production,exact,layers,modes}
 """
 from __future__ import annotations
 
@@ -31,6 +36,13 @@ import time
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+# Algorithmic bytes one layer*bin*g unit must move through one flux call
+# (opacities at the sublayer's two points read; upward and downward per-g
+# state at two points read and written; Planck values, w0 and g0 amortised
+# over the 20 g-points): 16 + 64 + 0.8 + 0.8 in FP64, 8 + 32 + 0.4 + 0.4 in
+# FP32.  The roofline fraction is quoted against these, whatever the kernel
+# itself moves (it keeps no downward state between calls).
+UNIT_BYTES = {"fp64": 81.6, "mixed": 40.8}
 
 
 def sweep_source_hash() -> str:
@@ -66,24 +78,21 @@ def iso_algorithmic_bytes(n: int, nb: int, ng: int, rbytes: int) -> int:
     return nb * per_bin + ng * 8
 
 
-def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict, **solver_kw):
+def timed_steps(s, steps: int, warmup: int):
+    """W untimed steps, then exactly K timed ones: wall clock between two
+    device synchronisations, and HIP events recorded by the library around
+    the flux sweep launches of every timed step, on the stream the sweep runs
+    on.  Returns (wall seconds, sweep milliseconds per step)."""
     import torch
 
     from paper_1606_05474_amd import helios as H
 
-    b = H.Batch([atm])
-    ktd = H.KTable(kt)
-    s = H.Solver(b, ktd, prec=prec, **solver_kw)
-    s.reset(atm["T0"])
-    s.autotune()  # the library's sweep-shape autotuner (kept for the process)
-    shape = H.sweep_shapes(s.b, prec)
-    s.reset(atm["T0"])
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         s.step()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    for e0, e1 in ev:  # create the events
+    for e0, e1 in ev:  # torch creates the events on their first record
         e0.record(stream)
         e1.record(stream)
     torch.cuda.synchronize()
@@ -92,12 +101,172 @@ def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict, **solver_kw
         H.set_sweep_events(e0, e1)
         s.step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall = time.perf_counter() - t0
     H.set_sweep_events(None, None)
-    sweep_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps
+    return wall, sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps
+
+
+def require_running(s, what: str):
+    """Every atmosphere of the batch must still be running: a converged or
+    failed one would be skipped by the kernels and its work not done."""
+    import numpy as np
+
+    from paper_1606_05474_amd import helios as H
+
+    st = s.status.cpu().numpy()
+    if np.any(st != H.ATM_RUNNING):
+        codes = {int(c): int((st == c).sum()) for c in np.unique(st)}
+        print(f"{what}: not every atmosphere is running through the timed steps (status counts {codes})",
+              file=sys.stderr, flush=True)
+        sys.exit(3)
+    return int(st.size)
+
+
+def c5_chunk(args):
+    """One production chunk: args.n_atm atmospheres (seed 5) of 200 layers x
+    3000 bins x 20 g, mixed precision, dead band, network warm start.  The
+    convergence test runs at tolerance 0 during the measurement, so no
+    atmosphere (and no layer of the dead band) can freeze and every step does
+    the whole chunk's work; require_running checks that."""
+    import numpy as np
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import warmstart as WS
+    from paper_1606_05474_amd import workloads as W
+
+    n, nb, ng = 200, 3000, 20
+    atms, kt = W.learned_workload(5, args.n_atm, 0, n=n, nb=nb)
+    b = H.Batch(atms)
+    s = H.Solver(b, H.KTable(kt), prec=H.MIXED, opts=H.REOptions(deadband=1, tol=0.0), bin_fluxes=False)
+    x = np.stack([a["params"] for a in atms])
+    s.reset(np.concatenate([a["T0"] for a in atms]))
+    t_tune = time.perf_counter()
+    s.autotune()
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t_tune
+    net = WS.load(args.weights)
+    fb = s.warm_reset(net, x, net.logP, m0=0.3)
+    wall, sweep_ms = timed_steps(s, args.steps, args.warmup)
+    running = require_running(s, "production chunk")
+    units = len(atms) * n * nb * ng
+    alg = UNIT_BYTES["mixed"] * units
+    gbs = alg / (sweep_ms * 1e-3) / 1e9
+    out = {
+        "value": units * args.steps / wall, "ms_per_step": wall / args.steps * 1e3, "units_per_step": units,
+        "sweep_ms": sweep_ms, "running": running, "network_fallbacks": int((fb != 0).sum()),
+        "autotune_s": t_tune, "shapes": {str(k): list(v) for k, v in H.sweep_shapes(s.b, H.MIXED).items()},
+        "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep, one launch per step)",
+                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_entry("c5chunk") if len(atms) == 256 else None,
+                     "bytes_per_unit": UNIT_BYTES["mixed"], "units_per_launch": units,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_ms": sweep_ms,
+                     "kernel_own_bytes_per_launch": len(atms) * sweep_algorithmic_bytes(n, nb, ng, 4)},
+    }
+    cpu_atm = atms[0]
+    del s, b
+    torch.cuda.empty_cache()
+    return out, cpu_atm, kt
+
+
+def c3_batch(steps: int, warmup: int):
+    """RE-iteration throughput of the uneven 512-atmosphere batch (n ~
+    U{50..200}, 400-3000 strided bins), mixed precision, isothermal start,
+    tolerance 0 during the measurement (every atmosphere running)."""
+    import numpy as np
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
+    atms, kt = W.batch_workload(n_atm=512)
+    atms.sort(key=lambda a: int(a["n"]))  # contiguous size classes
+    b = H.Batch(atms)
+    s = H.Solver(b, H.KTable(kt), prec=H.MIXED, opts=H.REOptions(tol=0.0), bin_fluxes=False)
+    T0 = np.concatenate([a["T0"] for a in atms])
+    s.reset(T0)
+    s.autotune()
+    s.reset(T0)
+    wall, sweep_ms = timed_steps(s, steps, warmup)
+    running = require_running(s, "uneven batch")
+    units = int(sum(int(a["n"]) * len(a["lambda_c"]) * int(a["ng"]) for a in atms))
+    alg = UNIT_BYTES["mixed"] * units
+    out = {"value": units * steps / wall, "unit": "layer*bin*g/s", "ms_per_step": wall / steps * 1e3,
+           "units_per_step": units, "steps": steps, "running": running,
+           "sweep_ms_per_step": sweep_ms, "sweep_frac_of_hbm_peak": alg / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "shapes": {str(k): list(v) for k, v in H.sweep_shapes(s.b, H.MIXED).items()}}
+    del s, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_c5(atm: dict, kt: dict, budget_s: float):
+    """The FP64 oracle as it stands on the host: whole RE iterations (profile,
+    opacity, flux with 1 + 4 passes, RE step) of one 200-layer x 3000-bin x
+    20-g atmosphere of the chunk, from its isothermal start: one iteration on
+    one core, then iterations on all the cores it may use (OpenMP over
+    columns; at most 16, the host share of one GPU) until budget_s passed."""
+    import numpy as np
+
+    import oracle as ref
+
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    threads = max(1, min(16, avail))
+    n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
+    P = ref.grid(atm["P_c"])
+    T_c = np.array(atm["T0"], np.float64)
+    m = np.ones(n)
+    hist = np.zeros(n, np.int32)
+    F_up = np.zeros((nb, ng, 2 * n + 1))
+
+    def iteration(th):
+        T = ref.profile(P, T_c)
+        kap = ref.mix_opacity(kt, T, P, atm["vmr"], atm["bin_index"], ng)
+        res = ref.flux(atm, kap, T, P, F_up, n_scat=4, n_threads=th, want_dn=False)
+        ref.radeq(atm, P, res["F_bol"], T_c, m, hist)
+
+    t0 = time.perf_counter()
+    iteration(1)
+    one = time.perf_counter() - t0
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        iteration(threads)
+        iters += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    wall = time.perf_counter() - t0
+    units = n * nb * ng
+    return {"value": units * iters / wall, "unit": "layer*bin*g/s", "cores": threads, "kind": "oracle",
+            "sample": f"{iters} full RE iterations (profile, opacity, 1 + 4 pass flux, RE step) of one "
+                      f"{n}-layer x {nb}-bin x {ng}-g atmosphere of the chunk on {threads} threads "
+                      f"({wall:.1f} s wall), after one iteration on one core ({one:.1f} s)",
+            "single_core": {"value": units / one, "seconds_per_iteration": one},
+            "nproc": nproc, "cpus_available": avail}
+
+
+def run_gpu(prec: int, steps: int, warmup: int, atm: dict, kt: dict, **solver_kw):
+    import torch
+
+    from paper_1606_05474_amd import helios as H
+
+    b = H.Batch([atm])
+    ktd = H.KTable(kt)
+    # tolerance 0: the atmosphere cannot converge (and freeze) while it is timed
+    solver_kw.setdefault("opts", H.REOptions(tol=0.0))
+    s = H.Solver(b, ktd, prec=prec, **solver_kw)
+    s.reset(atm["T0"])
+    s.autotune()  # the library's sweep-shape autotuner (kept for the process)
+    shape = H.sweep_shapes(s.b, prec)
+    s.reset(atm["T0"])
+    wall, sweep_ms = timed_steps(s, steps, warmup)
+    require_running(s, "single atmosphere")
     n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
     units = n * nb * ng
-    wall = t1 - t0
     rbytes = 4 if prec == H.MIXED else 8
     alg = sweep_algorithmic_bytes(n, nb, ng, rbytes)
     return {
@@ -606,17 +775,25 @@ def traffic_entry(prec_name: str):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--extra-steps", type=int, default=50,
+                    help="timed steps of each extra workload of the default line")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="default line: only the production chunk (and the CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0,
+                    help="seconds of all-core oracle iterations in the CPU baseline")
     ap.add_argument("--prec", choices=["both", "fp64", "mixed"], default="both",
                     help="precisions to run (profiling runs pick one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["spectral", "batch", "chunk", "production", "exact", "layers", "modes"],
-                    default="spectral",
-                    help="spectral: one 100-layer x 3000-bin atmosphere (the headline line); "
+    ap.add_argument("--workload", choices=["c5", "spectral", "batch", "chunk", "production", "exact", "layers",
+                                           "modes"],
+                    default="c5",
+                    help="c5: one production chunk (the headline line, with the spectral atmosphere and the "
+                         "uneven batch alongside); "
+                         "spectral: one 100-layer x 3000-bin atmosphere in FP64 and mixed precision; "
                          "batch: the uneven 512-atmosphere batch, throughput and solve to convergence; "
                          "chunk: RE-iteration throughput of one production chunk; "
                          "production: converged atmospheres/s, batched + network + mixed against plain FP64; "
@@ -666,7 +843,7 @@ def main(argv=None):
         return 0
     H.lib()  # fails loudly if the native library is missing
     if args.n_atm is None:
-        args.n_atm = {"production": 4096, "chunk": 128}.get(args.workload, 512)
+        args.n_atm = {"production": 4096, "chunk": 128, "c5": 256}.get(args.workload, 512)
     if args.max_iter is None:
         args.max_iter = {"production": 1500, "layers": 60000}.get(args.workload, 300)
     if args.workload == "batch":
@@ -681,6 +858,74 @@ def main(argv=None):
         return modes_main(args)
     if args.workload == "exact":
         return exact_main(args)
+    if args.workload == "spectral":
+        return spectral_main(args)
+    return c5_main(args)
+
+
+def c5_main(args):
+    """The default line: the production chunk, with the spectral single
+    atmosphere (FP64 and mixed) and the uneven batch as extra keys, and the
+    oracle's rate on one of the chunk's atmospheres."""
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
+    log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
+    if not os.path.exists(args.weights):
+        print(f"no trained warm-start network at {args.weights}", file=sys.stderr)
+        return 2
+    chunk, cpu_atm, kt = c5_chunk(args)
+    log("production chunk", json.dumps(chunk))
+    extra = {}
+    if args.extras:
+        atm2, _ = W.spectral_workload(ktab=kt)
+        for name, prec in (("fp64", H.FP64), ("mixed", H.MIXED)):
+            r = run_gpu(prec, args.extra_steps, args.warmup, atm2, kt)
+            units2 = int(atm2["n"]) * len(atm2["lambda_c"]) * int(atm2["ng"])
+            extra[f"spectral_100x3000x20_{name}"] = {
+                "value": r["value"], "unit": "layer*bin*g/s", "ms_per_step": r["ms_per_step"],
+                "steps": args.extra_steps, "sweep_ms": r["sweep_ms"],
+                "sweep_frac_of_hbm_peak": UNIT_BYTES[name] * units2 / (r["sweep_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "traffic": traffic_entry(name), "shape": r["shape"]}
+            log("spectral", name, json.dumps(extra[f"spectral_100x3000x20_{name}"]))
+        extra["uneven_batch_512_mixed"] = c3_batch(args.extra_steps, args.warmup)
+        log("uneven batch", json.dumps(extra["uneven_batch_512_mixed"]))
+    line = {
+        "metric": "layer*bin*g flux updates/s",
+        "value": chunk["value"],
+        "unit": "layer*bin*g/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": chunk["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"production chunk: {args.n_atm} parameter-described atmospheres (seed 5) x 200 "
+                               "layers x 3000 bins (0.3-30 um) x 20 g, four float32 k-tables 20 T x 20 log P, "
+                               "mixed precision (FP32 sweeps, FP64 sums and update), 1+4 scattering passes, "
+                               "network warm start, dead band; convergence test at tolerance 0 while timed",
+                   "n_atm": args.n_atm, "n_layer": 200, "n_bin": 3000, "n_g": 20, "n_scat": 4,
+                   "step": "mix_opacity + flux + radeq", "units_per_step": chunk["units_per_step"],
+                   "shapes": chunk["shapes"]},
+        "roofline": chunk["roofline"],
+        "running_through_timed_steps": chunk["running"],
+        "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_c5(cpu_atm, kt, args.cpu_budget)
+    print(json.dumps(line))
+    return 0
+
+
+def spectral_main(args):
+    """The single-atmosphere spectral workload (100 layers x 3000 bins x 20 g)
+    in FP64 and mixed precision."""
+    from paper_1606_05474_amd import helios as H
+    from paper_1606_05474_amd import workloads as W
+
     kt = W.table_ktab(2)
     atm, _ = W.spectral_workload(ktab=kt)
     fp64 = run_gpu(H.FP64, args.steps, args.warmup, atm, kt) if args.prec in ("both", "fp64") else None
@@ -689,7 +934,8 @@ def main(argv=None):
         print(json.dumps({"fp64": fp64, "mixed": mixed}))
         return 0
     n, nb, ng = int(atm["n"]), len(atm["lambda_c"]), int(atm["ng"])
-    tr = traffic_entry("fp64")
+    units = n * nb * ng
+    gbs = UNIT_BYTES["fp64"] * units / (fp64["sweep_ms"] * 1e-3) / 1e9
     line = {
         "metric": "layer*bin*g flux updates/s",
         "value": fp64["value"],
@@ -706,20 +952,21 @@ def main(argv=None):
         "config": {"workload": "single atmosphere at full spectral size: 100 layers, 3000 bins 0.3-30 um, "
                                "20 g, four float32 k-tables 20 T x 20 log P, FP64, 1+4 scattering passes",
                    "n_layer": n, "n_bin": nb, "n_g": ng, "n_scat": 4, "step": "mix_opacity + flux + radeq"},
-        "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep)", "achieved": fp64["sweep_gbs"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fp64["sweep_gbs"] / HBM_PEAK_GBS,
-                     "traffic": tr, "algorithmic_bytes_per_launch": fp64["sweep_bytes"],
-                     "avg_launch_ms": fp64["sweep_ms"], "sweep_shape": fp64["shape"]},
+        "roofline": {"bound": "hbm", "kernel": "sweep_kernel (flux sweep)", "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_entry("fp64"), "bytes_per_unit": UNIT_BYTES["fp64"],
+                     "algorithmic_bytes_per_launch": UNIT_BYTES["fp64"] * units,
+                     "avg_launch_ms": fp64["sweep_ms"], "kernel_own_bytes_per_launch": fp64["sweep_bytes"],
+                     "sweep_shape": fp64["shape"]},
         "mixed_precision": {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
-                            "sweep_ms": mixed["sweep_ms"], "sweep_gbs": mixed["sweep_gbs"],
-                            "frac": mixed["sweep_gbs"] / HBM_PEAK_GBS, "traffic": traffic_entry("mixed"),
-                            "sweep_shape": mixed["shape"]},
+                            "sweep_ms": mixed["sweep_ms"],
+                            "frac": UNIT_BYTES["mixed"] * units / (mixed["sweep_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "traffic": traffic_entry("mixed"), "sweep_shape": mixed["shape"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(atm, kt, args.cpu_budget)
     print(json.dumps(line))
     return 0
-
 
 if __name__ == "__main__":
     sys.exit(main())

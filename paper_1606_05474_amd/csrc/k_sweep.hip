@@ -234,88 +234,27 @@ __device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R
     }
 }
 
-// Shifts within a column's group of L lanes.  For L = 16 the group is one
-// DPP row, so row_shl/row_shr moves (out-of-row sources read 0) replace LDS
-// permutes; wider groups use shuffles (out-of-group sources read the own
-// value, which the callers never use).  (Composing the 32-lane shifts from
-// row moves and a permlane16 swap costs four VALU operations per dword where
-// the shuffle costs one LDS permute, and measured 3% slower in this
-// VALU-bound kernel.)
-template <int CTRL>
+// Lane exchanges of the column scans.  A DPP move reads another lane of the
+// wave as an operand modifier of an ordinary VALU instruction (no LDS round
+// trip, no wait): row_shl/row_shr:d read lane +-d within a row of 16 lanes
+// (out-of-row sources read 0), wave_shl/wave_shr:1 read lane +-1 across the
+// whole wave, row_bcast:15 gives every lane of a row the last lane of the
+// row below it, row_newbcast:0 gives every lane of a row the row's first lane.
+template <int CTRL, int ROWS = 0xF>
 __device__ inline float dpp_mov(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ inline double dpp_mov(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// value of lane seg + D of the group (TOA direction)
-template <int L, int D, typename R>
-__device__ inline R grp_down(R v) {
-    if constexpr (L == 16) return dpp_mov<0x100 + D>(v);
-    else return __shfl_down(v, (unsigned)D, L);
-}
-// value of lane seg - D of the group (BOA direction)
-template <int L, int D, typename R>
-__device__ inline R grp_up(R v) {
-    if constexpr (L == 16) return dpp_mov<0x110 + D>(v);
-    else return __shfl_up(v, (unsigned)D, L);
-}
-
-// One scan step of affine maps whose multipliers are pass-invariant:
-// MB <- mult * MB(partner) + MB.
-template <int L, int T, typename R>
-__device__ inline R scan_down_step(R MB, R mult) {
-    return mult * grp_down<L, (1 << T)>(MB) + MB;
-}
-template <int L, int T, typename R>
-__device__ inline R scan_up_step(R MB, R mult) {
-    return mult * grp_up<L, (1 << T)>(MB) + MB;
-}
-
-// Full scan step pairs (multiplier and offset) for when the multipliers are
-// not kept between passes.
-template <int L, int D, typename R>
-__device__ inline void down_pair(R& MA, R& MB, int seg) {
-    const R a2 = grp_down<L, D>(MA), b2 = grp_down<L, D>(MB);
-    const bool ok = seg + D < L;
-    MB = ok ? MA * b2 + MB : MB;
-    MA = ok ? MA * a2 : MA;
-}
-template <int L, int D, typename R>
-__device__ inline void up_pair(R& MA, R& MB, int seg) {
-    const R a2 = grp_up<L, D>(MA), b2 = grp_up<L, D>(MB);
-    const bool ok = seg >= D;
-    MB = ok ? MA * b2 + MB : MB;
-    MA = ok ? MA * a2 : MA;
-}
-template <int L, typename R>
-__device__ inline void scan_down_full(R& MA, R& MB, int seg) {
-    down_pair<L, 1>(MA, MB, seg);
-    down_pair<L, 2>(MA, MB, seg);
-    down_pair<L, 4>(MA, MB, seg);
-    down_pair<L, 8>(MA, MB, seg);
-    if constexpr (L > 16) down_pair<L, 16>(MA, MB, seg);
-    if constexpr (L > 32) down_pair<L, 32>(MA, MB, seg);
-}
-template <int L, typename R>
-__device__ inline void scan_up_full(R& MA, R& MB, int seg) {
-    up_pair<L, 1>(MA, MB, seg);
-    up_pair<L, 2>(MA, MB, seg);
-    up_pair<L, 4>(MA, MB, seg);
-    up_pair<L, 8>(MA, MB, seg);
-    if constexpr (L > 16) up_pair<L, 16>(MA, MB, seg);
-    if constexpr (L > 32) up_pair<L, 32>(MA, MB, seg);
-}
-
-// v(lane) + v(lane ^ S) for S = 16 or 32 with gfx950's permlane swaps (VALU
-// lane exchanges, no LDS round trip): given v as both operands, the swap
-// returns in every lane the lower and the upper member of its lane pair, so
-// both lanes of a pair form the same sum (lower + upper).
+// gfx950's permlane16/permlane32 swaps with one register as both operands
+// return in every lane the lower and the upper member of its lane pair
+// (lanes i and i ^ 16, or i and i ^ 32, of each 32- or 64-lane half).
 template <int S>
 __device__ inline unsigned pair_lo_hi(unsigned u, unsigned& hi) {
     if constexpr (S == 16) {
@@ -328,6 +267,116 @@ __device__ inline unsigned pair_lo_hi(unsigned u, unsigned& hi) {
         return r[0];
     }
 }
+// the upper member (lane i | 16) of every lane's pair
+__device__ inline float upper16(float v) {
+    unsigned hi;
+    (void)pair_lo_hi<16>(__float_as_uint(v), hi);
+    return __uint_as_float(hi);
+}
+__device__ inline double upper16(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    unsigned hi_l, hi_h;
+    (void)pair_lo_hi<16>((unsigned)b, hi_l);
+    (void)pair_lo_hi<16>((unsigned)(b >> 32), hi_h);
+    return __longlong_as_double((long long)(((unsigned long long)hi_h << 32) | hi_l));
+}
+
+// The column scans combine the lanes' affine maps in log2(L) steps.  Step T
+// pairs lane seg with lane seg +- 2^T of its group.  For L = 16 the group is
+// one DPP row.  For L = 32 (two rows) steps 0..3 run within each row and
+// step 4 joins the rows: the lower row takes the first lane of the row above
+// (row_newbcast:0, then the permlane16 swap), the upper row the last lane of
+// the row below (row_bcast:15); every exchange is a VALU operation.  L = 64
+// uses shuffles (out-of-group sources read the own value, which the callers
+// never use).
+template <int L, int T>
+__device__ inline bool has_above(int seg) {  // a partner towards the TOA at step T
+    if constexpr (L == 32 && T < 4) return (seg & 15) + (1 << T) < 16;
+    else if constexpr (L == 32) return seg < 16;
+    else return seg + (1 << T) < L;
+}
+template <int L, int T>
+__device__ inline bool has_below(int seg) {  // a partner towards the BOA at step T
+    if constexpr (L == 32 && T < 4) return (seg & 15) >= (1 << T);
+    else if constexpr (L == 32) return seg >= 16;
+    else return seg >= (1 << T);
+}
+// the partner's value at step T (towards the TOA / towards the BOA)
+template <int L, int T, typename R>
+__device__ inline R from_above(R v) {
+    if constexpr (L == 16 || (L == 32 && T < 4)) return dpp_mov<0x100 + (1 << T)>(v);
+    else if constexpr (L == 32) return upper16(dpp_mov<0x150>(v));
+    else return __shfl_down(v, 1u << T, L);
+}
+template <int L, int T, typename R>
+__device__ inline R from_below(R v) {
+    if constexpr (L == 16 || (L == 32 && T < 4)) return dpp_mov<0x110 + (1 << T)>(v);
+    else if constexpr (L == 32) return dpp_mov<0x142, 0xA>(v);
+    else return __shfl_up(v, 1u << T, L);
+}
+// value of the next lane of the column (towards the TOA) and of the previous
+// one (towards the BOA); the top and bottom lanes' results are not used
+template <int L, typename R>
+__device__ inline R next_lane(R v) {
+    if constexpr (L == 16) return dpp_mov<0x101>(v);
+    else if constexpr (L == 32) return dpp_mov<0x130>(v);
+    else return __shfl_down(v, 1u, L);
+}
+template <int L, typename R>
+__device__ inline R prev_lane(R v) {
+    if constexpr (L == 16) return dpp_mov<0x111>(v);
+    else if constexpr (L == 32) return dpp_mov<0x138>(v);
+    else return __shfl_up(v, 1u, L);
+}
+
+// One scan step of affine maps whose multipliers are pass-invariant:
+// MB <- mult * MB(partner) + MB (mult is 0 where there is no partner).
+template <int L, int T, typename R>
+__device__ inline R scan_down_step(R MB, R mult) {
+    return mult * from_above<L, T>(MB) + MB;
+}
+template <int L, int T, typename R>
+__device__ inline R scan_up_step(R MB, R mult) {
+    return mult * from_below<L, T>(MB) + MB;
+}
+
+// Full scan step pairs (multiplier and offset) for when the multipliers are
+// not kept between passes.
+template <int L, int T, typename R>
+__device__ inline void down_pair(R& MA, R& MB, int seg) {
+    const R a2 = from_above<L, T>(MA), b2 = from_above<L, T>(MB);
+    const bool ok = has_above<L, T>(seg);
+    MB = ok ? MA * b2 + MB : MB;
+    MA = ok ? MA * a2 : MA;
+}
+template <int L, int T, typename R>
+__device__ inline void up_pair(R& MA, R& MB, int seg) {
+    const R a2 = from_below<L, T>(MA), b2 = from_below<L, T>(MB);
+    const bool ok = has_below<L, T>(seg);
+    MB = ok ? MA * b2 + MB : MB;
+    MA = ok ? MA * a2 : MA;
+}
+template <int L, typename R>
+__device__ inline void scan_down_full(R& MA, R& MB, int seg) {
+    down_pair<L, 0>(MA, MB, seg);
+    down_pair<L, 1>(MA, MB, seg);
+    down_pair<L, 2>(MA, MB, seg);
+    down_pair<L, 3>(MA, MB, seg);
+    if constexpr (L > 16) down_pair<L, 4>(MA, MB, seg);
+    if constexpr (L > 32) down_pair<L, 5>(MA, MB, seg);
+}
+template <int L, typename R>
+__device__ inline void scan_up_full(R& MA, R& MB, int seg) {
+    up_pair<L, 0>(MA, MB, seg);
+    up_pair<L, 1>(MA, MB, seg);
+    up_pair<L, 2>(MA, MB, seg);
+    up_pair<L, 3>(MA, MB, seg);
+    if constexpr (L > 16) up_pair<L, 4>(MA, MB, seg);
+    if constexpr (L > 32) up_pair<L, 5>(MA, MB, seg);
+}
+
+// v(lane) + v(lane ^ S) for S = 16 or 32 with the permlane swaps: both
+// lanes of a pair form the same sum (lower + upper).
 template <int S>
 __device__ inline float xor_pair_sum(float v) {
     unsigned hi;
@@ -632,15 +681,14 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             R mb = (seg == 0) ? (R)0 : pseg;
 #pragma unroll
             for (int t = 0; t < LOG2L; ++t) {
-                const int d = 1 << t;
                 R a2, b2;
-                if (t == 0) { a2 = grp_down<L, 1>(ma); b2 = grp_up<L, 1>(mb); }
-                else if (t == 1) { a2 = grp_down<L, 2>(ma); b2 = grp_up<L, 2>(mb); }
-                else if (t == 2) { a2 = grp_down<L, 4>(ma); b2 = grp_up<L, 4>(mb); }
-                else if (t == 3) { a2 = grp_down<L, 8>(ma); b2 = grp_up<L, 8>(mb); }
-                else if (t == 4) { a2 = grp_down<L, 16>(ma); b2 = grp_up<L, 16>(mb); }
-                else { a2 = grp_down<L, 32>(ma); b2 = grp_up<L, 32>(mb); }
-                const bool okd = seg + d < L, oku = seg >= d;
+                bool okd, oku;
+                if (t == 0) { a2 = from_above<L, 0>(ma); b2 = from_below<L, 0>(mb); okd = has_above<L, 0>(seg); oku = has_below<L, 0>(seg); }
+                else if (t == 1) { a2 = from_above<L, 1>(ma); b2 = from_below<L, 1>(mb); okd = has_above<L, 1>(seg); oku = has_below<L, 1>(seg); }
+                else if (t == 2) { a2 = from_above<L, 2>(ma); b2 = from_below<L, 2>(mb); okd = has_above<L, 2>(seg); oku = has_below<L, 2>(seg); }
+                else if (t == 3) { a2 = from_above<L, 3>(ma); b2 = from_below<L, 3>(mb); okd = has_above<L, 3>(seg); oku = has_below<L, 3>(seg); }
+                else if (t == 4) { a2 = from_above<L, 4>(ma); b2 = from_below<L, 4>(mb); okd = has_above<L, 4>(seg); oku = has_below<L, 4>(seg); }
+                else { a2 = from_above<L, 5>(ma); b2 = from_below<L, 5>(mb); okd = has_above<L, 5>(seg); oku = has_below<L, 5>(seg); }
                 mdn[t] = okd ? ma : (R)0;
                 mup[t] = oku ? mb : (R)0;
                 ma = okd ? ma * a2 : ma;
@@ -709,7 +757,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 R MA = (seg == L - 1) ? (R)0 : pseg;
                 scan_down_full<L>(MA, MB, seg);
             }
-            R x = grp_down<L, 1>(MB);  // F_dn at my segment's top point
+            R x = next_lane<L>(MB);  // F_dn at my segment's top point
             if (seg == L - 1) x = Ftop;
             if constexpr (!LAST) {
                 // fu[k] then takes the upward sweep's offset c F_dn + sig
@@ -749,7 +797,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 R MA = (seg == 0) ? (R)0 : pseg;
                 scan_up_full<L>(MA, MB, seg);
             }
-            R y = grp_up<L, 1>(MB);  // F_up at my segment's bottom point
+            R y = prev_lane<L>(MB);  // F_up at my segment's bottom point
             if (seg == 0) y = y0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
