@@ -378,3 +378,44 @@ def test_full_size_spectral_atmosphere_in_the_benchmark_shape(prec, monkeypatch)
         assert col_rel_error(b.split_pb(_np(ub))[0], r["F_up_bin"]).max() < 1e-11
     else:
         assert err.max() < 1e-4, err.max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_full_size_production_atmospheres_in_the_chunk_shape(prec, monkeypatch):
+    """Three production atmospheres (200 layers x 3000 bins x 20 g, seed 5)
+    as one batch, with the sweep in the shape the production chunk runs (14
+    sublayers per lane, 32 lanes per column: the DPP-row scans and their
+    row join): two flux calls from the paper's zero-flux start at a fixed
+    non-isothermal profile, each against the oracle on the same inputs
+    (FP64 1e-10, mixed 1e-4 relative net flux, per atmosphere and point)."""
+    monkeypatch.setenv("HELIOS_SWEEP_K", "14")
+    monkeypatch.setenv("HELIOS_SWEEP_L", "32")
+    kt = W.table_ktab(2)
+    atms, _ = W.learned_workload(5, 3, 0, n=200, nb=3000, ktab=kt)
+    b = H.Batch(atms)
+    H.grid(b)
+    assert H.sweep_shapes(b, prec) == {208: (14, 32)}
+    T_c = [smooth_profile(a, 2200.0 - 200.0 * k, 600.0 + 100.0 * k) for k, a in enumerate(atms)]
+    refs = []
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, kt, T_c[a])
+        up = np.zeros((len(atm["lambda_c"]), atm["ng"], 2 * atm["n"] + 1))
+        r1 = ref.flux(atm, kap_ref, T, P, up, want_dn=False)
+        r2 = ref.flux(atm, kap_ref, T, P, up, want_dn=False)  # warm start: the first call's fluxes
+        refs.append((r1["F_bol"], r2["F_bol"]))
+    rd = H.rdtype(prec)
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_c), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=rd, device="cuda")
+    H.mix_opacity(b, H.KTable(kt), T_pt, kap, prec)
+    F_up = torch.zeros(b.total_cell, dtype=rd, device="cuda")
+    H.state_convert(b, T_pt, F_up, H.CONVERT_ZERO_FLUX, prec=prec)
+    tol = 1e-10 if prec == H.FP64 else 1e-4
+    for call in range(2):
+        _, _, _, bol = _flux(b, kap, T_pt, prec, F_up, want_dn=False)
+        per_atm = b.split_pt(_np(bol).reshape(-1, 3))
+        for a, atm in enumerate(atms):
+            err = net_flux_error(per_atm[a], refs[a][call])
+            assert err.max() < tol, (call, a, err.max())
+            if prec == H.FP64:
+                assert net_flux_error_sigma(per_atm[a], refs[a][call], atm["T_int"]).max() < 1e-10
