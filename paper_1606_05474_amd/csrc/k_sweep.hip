@@ -410,10 +410,10 @@ __device__ inline R col_sum(R v) {
 //   dB, hdm  [K*L + 1]   Planck difference and half column mass per sublayer
 //   tB       [K*L + 1]   (2 pi / D) B per point (flux-state conversion)
 //   lq       [K*L/2][4]  r, kx, sf, gd per layer
-//   pu, pd   [K*L + 2]   Gauss sums per point; the last slot absorbs writes
-//                        of lanes that own no point
+//   pu, pd   [K*L + 2]   Gauss sums per point (slots past the column's
+//                        points take zeros)
 struct SweepLds {
-    int dB, hdm, tB, lq, pu, pd, junk, total;
+    int dB, hdm, tB, lq, pu, pd, total;
     static constexpr int r4(int v) { return (v + 3) & ~3; }
     __host__ __device__ constexpr SweepLds(int KL)
         : dB(0),
@@ -422,7 +422,6 @@ struct SweepLds {
           lq(3 * r4(KL + 1)),
           pu(3 * r4(KL + 1) + 4 * r4(KL / 2)),
           pd(3 * r4(KL + 1) + 4 * r4(KL / 2) + r4(KL + 2)),
-          junk(KL + 1),
           total(3 * r4(KL + 1) + 4 * r4(KL / 2) + 2 * r4(KL + 2)) {}
 };
 
@@ -700,14 +699,19 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // Gauss sums of one stream over the group's columns at my points
         // (v[k] at lo + k, vtop at the TOA for the top segment), added to the
         // wave's LDS accumulators.  Every column of a point computes the same
-        // sum and writes the same value; points past the column go to the
-        // junk slot.
+        // sum and writes the same value.  A lane's K slots lo .. lo + K - 1 are
+        // its own; slots past the column's last sublayer take zeros, and the
+        // TOA point is added last (its slot may be one of them), so all K
+        // reads are issued before the first write.
         auto emit = [&](const R (&v)[K], R vtop, R* acc) {
+            R* a = acc + lo;
+            R prev[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) prev[k] = a[k];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const R sk = col_sum<L>(wg * v[k]);
-                const int idx = (lo + k < nsub) ? lo + k : lay.junk;
-                acc[idx] += sk;
+                a[k] = prev[k] + ((lo + k < nsub) ? sk : (R)0);
             }
             const R st = col_sum<L>(wg * vtop);
             if (top_seg) acc[nsub] += st;
