@@ -229,6 +229,24 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
                 double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
                 helios_prec prec, void* stream);
 
+/* helios_flux for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, arguments and results, without the ws / ws_bytes pair.
+ * The workspace is a static device array of HELIOS_NOALLOC_WS_BYTES inside
+ * the library, one copy per device, kept until the process ends; its device
+ * address is looked up on the first call on each device.  The call itself
+ * allocates nothing.  Errors: HELIOS_EWORKSPACE (nothing enqueued) if the
+ * batch needs more than HELIOS_NOALLOC_WS_BYTES of workspace
+ * (helios_workspace_bytes tells), otherwise as helios_flux.  Every call on
+ * one device uses the same array: calls that can overlap on a device (on
+ * different streams, or from several threads without ordering) race and
+ * must be serialised by the caller; each call rewrites all the workspace it
+ * reads, so no clearing is needed between calls. */
+#define HELIOS_NOALLOC_WS_BYTES ((size_t)64 << 20)
+int helios_flux_noalloc(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                        const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g,
+                        double* F_up_bin, double* F_dn_bin, double* F_bol, helios_prec prec, void* stream);
+
 /* The same two-stream solve on the isothermal-layer grid (Sec. 2.2.1): the
  * atmosphere is n isothermal layers between the n + 1 interfaces at the even
  * points (P_pt[2i]); layer i has the temperature and opacity of its centre

@@ -543,6 +543,35 @@ int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     return HELIOS_OK;
 }
 
+// Workspace of helios_flux_noalloc, for callers that cannot allocate device
+// memory: a fixed array in the library's code object, one copy per device,
+// held until the process ends.  Host code must not use the array's name as
+// an address: each device's copy is looked up once (hipGetSymbolAddress, with
+// that device current) and only that pointer is passed on.
+constexpr size_t kScratchBytes = HELIOS_NOALLOC_WS_BYTES;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+void* g_scratch_ptr[kScratchDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_for_current_device(void** out, const char* name) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, name);
+    if (dev < 0 || dev >= kScratchDevices) return fail(HELIOS_EDEVICE, "%s: device %d beyond %d", name, dev,
+                                                       kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, name);
+        if (!ptr) return fail(HELIOS_EDEVICE, "%s: no device address for the scratch array", name);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HELIOS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -660,6 +689,26 @@ int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, co
                 double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream) {
     return flux_impl(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws, ws_bytes,
                      prec, stream, false, 0.0, "helios_flux");
+}
+
+int helios_flux_noalloc(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
+                        const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g, double* F_up_bin,
+                        double* F_dn_bin, double* F_bol, helios_prec prec, void* stream) {
+    Sizes z;
+    bool mixed = false, fstate = false;
+    int rc = check_atm(atm, z);
+    if (rc) return rc;
+    if (!split_prec((int)prec, mixed, fstate))
+        return fail(HELIOS_EINVAL, "helios_flux_noalloc: unknown precision %d", (int)prec);
+    const size_t need = ws_layout(z, atm->n_g, mixed).total;
+    if (need > kScratchBytes)
+        return fail(HELIOS_EWORKSPACE,
+                    "helios_flux_noalloc: the batch needs %zu bytes of workspace, the static scratch holds %zu",
+                    need, kScratchBytes);
+    void* ws = nullptr;
+    if ((rc = scratch_for_current_device(&ws, "helios_flux_noalloc"))) return rc;
+    return flux_impl(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, F_dn_g, F_up_bin, F_dn_bin, F_bol, ws,
+                     kScratchBytes, prec, stream, false, 0.0, "helios_flux_noalloc");
 }
 
 int helios_flux_iso(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,

@@ -33,6 +33,7 @@ CONVERT_TO_DEVIATION, CONVERT_TO_FLUX, CONVERT_ZERO_FLUX = 0, 1, 2
 LAYERS_SUBLAYERED, LAYERS_ISOTHERMAL = 0, 1
 MAX_SPECIES = 8
 CELL_ALIGN = 32  # column stride of the cell arrays: 2n+1 rounded up to this
+NOALLOC_WS_BYTES = 64 << 20  # static workspace of helios_flux_noalloc (HELIOS_NOALLOC_WS_BYTES)
 
 _P = ctypes.c_void_p
 
@@ -92,6 +93,7 @@ def lib():
         L.helios_workspace_bytes.restype = sz
         L.helios_flux.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
         L.helios_flux_iso.argtypes = L.helios_flux.argtypes
+        L.helios_flux_noalloc.argtypes = [A, _P, _P, _P, _P, i32, dbl, _P, _P, _P, _P, _P, ctypes.c_int, _P]
         L.helios_flux_rayleigh.argtypes = [A, _P, _P, dbl, i32, dbl, _P, _P, _P, _P, _P, _P, sz, ctypes.c_int, _P]
         L.helios_flux_exact.argtypes = [A, _P, _P, _P, _P, _P, _P, _P, _P, sz, i32, _P]
         L.helios_state_convert.argtypes = [A, _P, dbl, _P, i32, i32, ctypes.c_int, _P]
@@ -116,6 +118,7 @@ def lib():
         L.helios_version.restype = i32
         for f in ("helios_grid", "helios_profile", "helios_mix_opacity", "helios_transmission",
                   "helios_flux", "helios_flux_iso", "helios_flux_rayleigh", "helios_flux_exact",
+                  "helios_flux_noalloc",
                   "helios_state_convert", "helios_autotune_reset",
                   "helios_radeq", "helios_autotune", "helios_sweep_shapes", "helios_mlp_sync",
                   "helios_mlp_forward", "helios_mlp_backward", "helios_mlp_adam", "helios_warm_start"):
@@ -375,6 +378,15 @@ def flux(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, n_scat=4,
               int(n_scat), float(D), _ptr(F_up_g), _ptr(F_dn_g), _ptr(F_up_bin),
               _ptr(F_dn_bin), _ptr(F_bol), _ptr(ws), ws.numel() * ws.element_size(),
               prec, _stream(stream)))
+
+
+def flux_noalloc(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, n_scat=4, D=2.0, F_dn_g=None,
+                 prec=FP64, stream=None):
+    """helios_flux_noalloc: helios_flux on the library's static device
+    workspace (batches needing at most NOALLOC_WS_BYTES of it)."""
+    _check(lib().helios_flux_noalloc(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
+                                     int(n_scat), float(D), _ptr(F_up_g), _ptr(F_dn_g), _ptr(F_up_bin),
+                                     _ptr(F_dn_bin), _ptr(F_bol), prec, _stream(stream)))
 
 
 def flux_rayleigh(b: Batch, kappa, T_pt, F_up_g, F_up_bin, F_dn_bin, F_bol, ws, mbar, n_scat=4, D=2.0,
