@@ -60,7 +60,7 @@ extern "C" {
 
 #define HELIOS_MAX_SPECIES 8
 #define HELIOS_MAX_NG 32
-#define HELIOS_MAX_LAYERS 832
+#define HELIOS_MAX_LAYERS 1024
 #define HELIOS_CELL_ALIGN 32
 
 typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;
@@ -82,6 +82,10 @@ typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;
  * helios_state_convert() converts an array between the two. */
 #define HELIOS_STATE_DEVIATION 0x000
 #define HELIOS_STATE_FLUX 0x100
+/* OR'ed into the prec argument of helios_autotune and helios_sweep_shapes:
+ * the shapes of helios_flux_iso's sweep (one slot per layer) instead of
+ * helios_flux's (one per sublayer). */
+#define HELIOS_GRID_ISOTHERMAL 0x200
 typedef enum { HELIOS_KTAB_TABLE = 0, HELIOS_KTAB_POWERLAW = 1 } helios_ktab_mode;
 typedef enum { HELIOS_NORM_SIGMA_T4 = 0, HELIOS_NORM_SIGMA_TINT4 = 1 } helios_norm;
 
@@ -223,7 +227,9 @@ size_t helios_workspace_bytes(const helios_atm* atm, helios_prec prec);
  *             themselves (Sec. 2.2.3).  helios_state_convert() converts.
  *   ws        workspace of at least helios_workspace_bytes(atm, prec) bytes
  * Downward fluxes carry no state between calls: each pass recomputes them
- * from the TOA condition and the previous upward fluxes. */
+ * from the TOA condition and the previous upward fluxes.
+ * Errors: -2 (nothing enqueued) also for an atmosphere of more than 832
+ * layers (the deepest sweep shape holds 1664 sublayers). */
 int helios_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                 const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g,
                 double* F_up_bin, double* F_dn_bin, double* F_bol, void* ws, size_t ws_bytes,
@@ -263,6 +269,8 @@ int helios_flux_noalloc(const helios_atm* atm, const void* kappa, const double* 
  *   F_up_bin, F_dn_bin, F_bol  at the points as for helios_flux; even points
  *                   are the interfaces and point 2i+1 repeats interface i+1,
  *                   so helios_radeq takes F_bol unchanged
+ * A layer is one slot of the sweep, so this grid takes up to
+ * HELIOS_MAX_LAYERS layers (helios_flux up to 832: two slots per layer).
  * Errors: as helios_flux. */
 int helios_flux_iso(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                     const double* g0, int32_t n_scat, double D, void* F_up_g, void* F_dn_g,
@@ -349,7 +357,7 @@ int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double
 
 /* Autotuner of the flux sweep (a batching aid; the paper runs one
  * atmosphere at a time).  helios_flux groups atmospheres into size classes by
- * layer count (n <= 32, 64, 112, 208, 400, 832) and sweeps each class with
+ * layer count (n <= 32, 64, 112, 208, 400, 1024) and sweeps each class with
  * one launch of its own shape (sublayers per lane x lanes per column).  For
  * each class present in the batch, every compiled shape that holds the
  * class's deepest atmosphere (the 64-lane long-column shape only where no
@@ -361,7 +369,8 @@ int helios_radeq(const helios_atm* atm, const double* F_bol, double* T_c, double
  * input values; the workspace must be at least helios_workspace_bytes(atm,
  * prec) bytes.  Atmospheres of a class that are adjacent in the batch share
  * one contiguous launch range; ordering a batch by layer count keeps every
- * class's range free of other classes' bins. */
+ * class's range free of other classes' bins.  With HELIOS_GRID_ISOTHERMAL
+ * OR'ed into prec the shapes are tuned (and kept) for helios_flux_iso. */
 int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                     const double* g0, int32_t n_scat, double D, void* F_up_g, void* ws, size_t ws_bytes,
                     helios_prec prec, void* stream);
@@ -374,8 +383,9 @@ int helios_autotune_reset(void);
 /* The sweep shapes helios_flux would use for this batch: for each of the 6
  * size classes (out holds 3 x max_classes int32, max_classes >= 6) the
  * class's upper layer-count bound, then K (sublayers per lane) and L (lanes
- * per column), both 0 for a class with no member.  Returns the number of
- * classes (> 0) or an error code. */
+ * per column), both 0 for a class with no member (helios_flux_iso's with
+ * HELIOS_GRID_ISOTHERMAL OR'ed into prec).  Returns the number of classes
+ * (> 0) or an error code. */
 int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, int32_t max_classes);
 
 /* ------------------------------------------------------------------

@@ -217,7 +217,7 @@ bool shape_allowed(int K, int L, bool mixed) {
 
 // Shapes chosen by helios_autotune, per (precision, n_g, size class).
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, SweepShape> g_tuned;
+std::map<std::tuple<int, int, int, int>, SweepShape> g_tuned;  // (mixed, n_g, class, isothermal grid)
 
 int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
     // fewest sublayers per lane first (smallest register footprint), then
@@ -238,7 +238,7 @@ int default_shape(int nsub_max, bool mixed, SweepShape& sh) {
 // Shape of class k (deepest member nsub_max sublayers): an environment
 // override (HELIOS_SWEEP_K / HELIOS_SWEEP_L / HELIOS_SWEEP_P, for measurement), else the
 // autotuned one, else the default.
-int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh) {
+int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh, bool iso_grid = false) {
     int fk = env_int("HELIOS_SWEEP_K", 0), fl = env_int("HELIOS_SWEEP_L", 0);
     if (fk || fl) {
         if (!shape_allowed(fk, fl, mixed))
@@ -249,7 +249,7 @@ int pick_shape(int k, int nsub_max, int n_g, bool mixed, SweepShape& sh) {
     }
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tuned.find({mixed ? 1 : 0, n_g, k});
+        auto it = g_tuned.find({mixed ? 1 : 0, n_g, k, iso_grid ? 1 : 0});
         if (it != g_tuned.end() && it->second.K * it->second.L >= nsub_max) {
             sh = it->second;
             return HELIOS_OK;
@@ -279,7 +279,7 @@ bool split_prec(int prec_arg, bool& mixed, bool& flux_state) {
 
 int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0, const double* g0,
               int32_t n_scat, double D, const void* F_up_g, const void* ws, size_t ws_bytes, helios_prec prec,
-              FluxPlan& p, bool need_optics = true) {
+              FluxPlan& p, bool need_optics = true, bool iso_grid = false) {
     int rc = check_atm(atm, p.z);
     if (rc) return rc;
     if (!kappa || !T_pt || (need_optics && (!w0 || !g0)) || !F_up_g || !ws)
@@ -294,7 +294,8 @@ int plan_flux(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     for (int k = 0; k < kNumClasses; ++k) {
         p.sh[k] = {0, 0};
         if (p.z.cls_nmax[k] == 0) continue;
-        rc = pick_shape(k, 2 * p.z.cls_nmax[k], atm->n_g, p.mixed, p.sh[k]);
+        // slots per column: sublayers, or layers on the isothermal-layer grid
+        rc = pick_shape(k, (iso_grid ? 1 : 2) * p.z.cls_nmax[k], atm->n_g, p.mixed, p.sh[k], iso_grid);
         if (rc) return rc;
     }
     return HELIOS_OK;
@@ -491,7 +492,8 @@ int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, cons
               double* F_bol, void* ws, size_t ws_bytes, helios_prec prec, void* stream, bool iso_grid,
               double inv_mbar, const char* name) {
     FluxPlan p;
-    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p, !(inv_mbar > 0.0));
+    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p, !(inv_mbar > 0.0),
+                       iso_grid);
     if (rc) return rc;
     if (!F_bol) return fail(HELIOS_EINVAL, "%s: NULL argument", name);
     hipStream_t s = (hipStream_t)stream;
@@ -782,15 +784,18 @@ int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* 
 int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt, const double* w0,
                     const double* g0, int32_t n_scat, double D, void* F_up_g, void* ws, size_t ws_bytes,
                     helios_prec prec, void* stream) {
+    const bool iso = ((int)prec & HELIOS_GRID_ISOTHERMAL) != 0;
+    const helios_prec pr = (helios_prec)((int)prec & ~HELIOS_GRID_ISOTHERMAL);
     FluxPlan p;
-    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, prec, p);
+    int rc = plan_flux(atm, kappa, T_pt, w0, g0, n_scat, D, F_up_g, ws, ws_bytes, pr, p, true, iso);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     char* wsb = (char*)ws;
     const size_t r = p.mixed ? sizeof(float) : sizeof(double);
-    hipError_t e = launch_sources(atm, p, T_pt, wsb, s);
+    hipError_t e = launch_sources(atm, p, T_pt, wsb, s, iso);
     if (e != hipSuccess) return hip_fail(e, "helios_autotune (sources)");
     SweepArgs A = sweep_args(atm, p, kappa, w0, g0, n_scat, D, F_up_g, nullptr, wsb);
+    A.iso_grid = iso ? 1 : 0;
     A.status = nullptr;  // time the work even where the batch marks a member converged
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<char> saved;
@@ -817,7 +822,7 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
         if ((e = hipMemcpyAsync(saved.data(), fu, cells * r, hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return cleanup(hip_fail(e, "helios_autotune (save)"));
-        const int nsub = 2 * p.z.cls_nmax[k];
+        const int nsub = (iso ? 1 : 2) * p.z.cls_nmax[k];  // slots per column
         SweepShape best = p.sh[k];
         float best_ms = 1e30f;
         for (int L : {16, 32, 64}) {
@@ -852,7 +857,7 @@ int helios_autotune(const helios_atm* atm, const void* kappa, const double* T_pt
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return cleanup(hip_fail(e, "helios_autotune (restore)"));
         std::lock_guard<std::mutex> g(g_tune_mu);
-        g_tuned[{p.mixed ? 1 : 0, atm->n_g, k}] = best;
+        g_tuned[{p.mixed ? 1 : 0, atm->n_g, k, iso ? 1 : 0}] = best;
     }
     g_err[0] = 0;
     return cleanup(HELIOS_OK);
@@ -870,11 +875,13 @@ int helios_sweep_shapes(const helios_atm* atm, helios_prec prec, int32_t* out, i
     if (rc) return rc;
     if (!out || max_classes < kNumClasses) return fail(HELIOS_EINVAL, "out needs %d classes", kNumClasses);
     bool mixed = false, fstate = false;
-    if (!split_prec((int)prec, mixed, fstate)) return fail(HELIOS_EINVAL, "unknown precision 0x%x", (int)prec);
+    const bool iso = ((int)prec & HELIOS_GRID_ISOTHERMAL) != 0;
+    if (!split_prec((int)prec & ~HELIOS_GRID_ISOTHERMAL, mixed, fstate))
+        return fail(HELIOS_EINVAL, "unknown precision 0x%x", (int)prec);
     for (int k = 0; k < kNumClasses; ++k) {
         SweepShape sh = {0, 0};
         if (z.cls_nmax[k]) {
-            rc = pick_shape(k, 2 * z.cls_nmax[k], atm->n_g, mixed, sh);
+            rc = pick_shape(k, (iso ? 1 : 2) * z.cls_nmax[k], atm->n_g, mixed, sh, iso);
             if (rc) return rc;
         }
         out[3 * k] = kClassNHi[k];

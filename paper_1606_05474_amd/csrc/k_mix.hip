@@ -100,12 +100,13 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
         }
     }
     __syncthreads();
-    if (t == 0) {  // runs of equal cells along the chunk: where each starts, and what follows it
-        int next = -1;
-        for (int j = npts - 1; j >= 0; --j) {
-            const bool start = (j == 0) || (s_cell[j] != s_cell[j - 1]);
-            s_next[j] = start ? next : -2;
-            if (start) next = s_cell[j];
+    if (t < 64) {  // runs of equal cells along the chunk: where each starts, and what follows it (one wave)
+        const bool start = (t < npts) && (t == 0 || s_cell[t] != s_cell[t - 1]);
+        const unsigned long long starts = __ballot(start);
+        if (t < npts) {
+            const unsigned long long later = (t + 1 < 64) ? (starts >> (t + 1)) : 0ull;
+            const int nx = later ? t + 1 + __builtin_ctzll(later) : -1;  // the next run's first point
+            s_next[t] = start ? (nx >= 0 ? s_cell[nx] : -1) : -2;
         }
     }
     __syncthreads();

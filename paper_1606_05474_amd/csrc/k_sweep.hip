@@ -56,14 +56,20 @@
 // than to pi B itself, which is what lets FP32 sweeps resolve net fluxes at
 // depth.  Fluxes are recovered as F = G + 2 pi eps B in FP64 by the bin sum.
 //
-// Isothermal-layer grid (Sec. 2.2.1).  The same kernel solves n isothermal
-// layers between n + 1 interfaces on the sublayered point layout: interface i
-// is point 2i, layer i occupies slot 2i (dtau = kappa(centre) times the layer's
-// column mass, reference B(T_i) at both ends, so dB = 0 and eq:isoscat needs
-// no source in the deviation form) and slot 2i+1 has dtau = 0, i.e. a = 1,
-// c = 0: it carries the flux unchanged from point 2i+1 to the next interface
-// while sig = 2 pi eps (B(T_i) - B(T_i+1)) moves the deviation to the next
-// layer's reference.  Point 2i+1 then holds the flux at interface i+1.
+// Isothermal-layer grid (Sec. 2.2.1, template flag ISO).  A slot is a whole
+// isothermal layer j between interfaces j (point 2j) and j+1 (point 2j+2):
+// its optical thickness is the centre opacity (point 2j+1) times its column
+// mass, eq:isoscat (eq:purescat) at any thickness.  Interface j carries the
+// deviation from tpe B_j = (2 pi / D) B(T_j) of the layer above it (the TOA
+// that of the top layer).  The layer maps tpe B_j to itself for any a, c, so
+// substituting F = G + tpe B with the two references leaves as the only
+// source the change of reference dB_j = B_j - B_{j+1}:
+//   up:   G_up(j+1) = a G_up(j) + c G_dn(j+1) + (1 - c) tpe dB_j
+//   down: G_dn(j)   = a G_dn(j+1) + c G_up(j) - a tpe dB_j
+// (the composition of the layer without a source and an identity slot that
+// adds tpe dB_j, both directions).  Each slot writes two points: 2j holds
+// interface j, 2j+1 interface j+1 in the layer's own reference, i.e.
+// G(j+1) - tpe dB_j, so the output layout is that of the sublayered grid.
 //
 // Rayleigh scattering (Sec. 2.1.4, template flag RAY).  The bin's H2
 // scattering opacity sigma/mbar is added to every sublayer and the albedo
@@ -412,17 +418,20 @@ __device__ inline R col_sum(R v) {
 //   lq       [K*L/2][4]  r, kx, sf, gd per layer
 //   pu, pd   [K*L + 2]   Gauss sums per point (slots past the column's
 //                        points take zeros)
+// On the isothermal-layer grid a slot is a whole layer with two points (its
+// lower interface and the point above it), so dB, hdm and lq are per layer
+// and tB, pu, pd span 2 K*L + 2 points.
 struct SweepLds {
     int dB, hdm, tB, lq, pu, pd, total;
     static constexpr int r4(int v) { return (v + 3) & ~3; }
-    __host__ __device__ constexpr SweepLds(int KL)
+    __host__ __device__ constexpr SweepLds(int KL, bool iso = false)
         : dB(0),
           hdm(r4(KL + 1)),
           tB(2 * r4(KL + 1)),
-          lq(3 * r4(KL + 1)),
-          pu(3 * r4(KL + 1) + 4 * r4(KL / 2)),
-          pd(3 * r4(KL + 1) + 4 * r4(KL / 2) + r4(KL + 2)),
-          total(3 * r4(KL + 1) + 4 * r4(KL / 2) + 2 * r4(KL + 2)) {}
+          lq(tB + r4(iso ? 2 * KL + 2 : KL + 1)),
+          pu(lq + 4 * r4(iso ? KL : KL / 2)),
+          pd(pu + r4(iso ? 2 * KL + 2 : KL + 2)),
+          total(pd + r4(iso ? 2 * KL + 2 : KL + 2)) {}
 };
 
 // One workgroup = one wave, which owns one (bin, part) at a time.  It stages
@@ -437,14 +446,15 @@ struct SweepLds {
 // give a bin one part; launches with few bins split a bin's groups over
 // several waves.  The bin-sum kernel adds a bin's partials in order, adds the
 // Planck term and sums over bins.  No barrier spans more than the wave.
-template <int K, int L, typename R, int OCC, bool RAY>
+template <int K, int L, typename R, int OCC, bool RAY, bool ISO>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using R2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
     constexpr int C = 64 / L;
     constexpr int KH = K / 2;
     constexpr int KL = K * L;
-    constexpr SweepLds lay(KL);
+    constexpr SweepLds lay(KL, ISO);
     static_assert(K % 2 == 0, "segments hold whole layers");
+    static_assert(!(RAY && ISO), "Rayleigh scattering is solved on the sublayered grid");
     extern __shared__ unsigned char smem_raw[];
     R* sm = reinterpret_cast<R*>(smem_raw);
     R* s_dB = sm + lay.dB;
@@ -477,10 +487,11 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const int l = (int)(gb - A.bin_off[at]);
         const int n = A.n_layer[at];
         if (n < A.n_lo || n > A.n_hi || frozen(A.status, at)) continue;  // uniform per wave
-        const int nsub = 2 * n, npt = nsub + 1;
-        const int nact = (nsub + K - 1) / K;
-        const int scnt = (seg < nact) ? min(K, nsub - lo) : 0;  // sublayers owned (any column); even
-        const bool top_seg = (seg == nact - 1);                 // also owns the TOA point
+        const int nsub = 2 * n, npt = nsub + 1;  // the TOA point is nsub on both grids
+        const int nsl = ISO ? n : nsub;         // slots: layers (isothermal grid) or sublayers
+        const int nact = (nsl + K - 1) / K;
+        const int scnt = (seg < nact) ? min(K, nsl - lo) : 0;  // slots owned (any column)
+        const bool top_seg = (seg == nact - 1);                // also owns the TOA point
         const int cs = col_stride(n);
         const int64_t pb = A.pb_off[at] + (int64_t)l * npt;
         const int64_t lb = A.lb_off[at] + (int64_t)l * n;
@@ -510,7 +521,41 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // all g, padded with the identity up to the shape's capacity.  All
         // loads are issued before the first is consumed (compile-time bounds,
         // indices clamped into the bin's own rows).
-        {
+        if constexpr (ISO) {
+            // per layer j: dB = B(2j+1) - B(2j+2) (its own Planck value minus the
+            // reference of its upper interface), half its column mass, and its
+            // r, kx, sf, gd; per point: the flux-state reference; the Gauss-sum
+            // slots of every point of the capacity cleared
+            constexpr int SCH = (KL + 63) / 64;
+            constexpr int QCH = (2 * KL + 2 + 63) / 64;
+            for (int q = 0; q < SCH; ++q) {  // one chunk of 64 layers at a time
+                const int j = lane + 64 * q;
+                const int jc = min(j, n - 1);
+                const double b1 = B_all[pb + 2 * jc + 1], b2 = B_all[pb + 2 * jc + 2];
+                const double p0 = P[2 * jc], p2 = P[2 * jc + 2];
+                const double wv = A.w0[lb + jc], gv = A.g0[lb + jc];
+                if (j < KL) {
+                    const bool real = j < n;
+                    s_dB[j] = real ? (R)(b1 - b2) : (R)0;
+                    s_hdm[j] = real ? (R)((p0 - p2) * higrav) : (R)0;
+                    R r = (R)1, kx = (R)0, sf = (R)0, gd = (R)-1;
+                    if (real) layer_g<R>((R)wv, (R)gv, D, inv_D, tpe, r, kx, sf, gd);
+                    s_lq[4 * j + 0] = r;
+                    s_lq[4 * j + 1] = kx;
+                    s_lq[4 * j + 2] = sf;
+                    s_lq[4 * j + 3] = gd;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < QCH; ++q) {
+                const int i = lane + 64 * q;
+                if (i <= 2 * KL + 1) {
+                    s_tB[i] = (i < npt) ? (R)(tpe_d * B_all[pb + i]) : (R)0;
+                    s_pu[i] = (R)0;
+                    s_pd[i] = (R)0;
+                }
+            }
+        } else {
             constexpr int PCH = (KL + 2 + 63) / 64;
             constexpr int LCH = (KL / 2 + 63) / 64;
             double bv[PCH], pv[PCH], wv[LCH], gv[LCH];
@@ -587,7 +632,20 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         // pairs starting at even indices, clamped to nsub; a pair at nsub also
         // reads index nsub + 1 < col_stride (npt is odd), which is not used
         R kv[K + 2], fu[K];
-        {
+        if constexpr (ISO) {
+            // slot k is layer lo + k: the warm start at its lower interface
+            // 2(lo + k) and the opacity at its centre 2(lo + k) + 1
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t pt = (uint32_t)min(2 * (lo + k), nsub - 1);  // interface; its layer's centre is pt + 1
+                kv[k] = kap_g[col + pt + 1];
+                fu[k] = fu_g[col + pt];
+            }
+            if (fstate) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) fu[k] -= s_tB[2 * (lo + k)];
+            }
+        } else {
             R2 kp2[KH + 1], fp2[KH];
 #pragma unroll
             for (int p = 0; p <= KH; ++p)
@@ -619,6 +677,28 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const bool act = k < cnt;
+                if constexpr (ISO) {
+                    // the whole layer at its centre's opacity, eq:isoscat at any
+                    // optical depth (eq:purescat where 1 - w0 < 1e-6); its source
+                    // in the deviation form only moves the reference from the
+                    // layer's own Planck value to that of its upper interface
+                    const R* lq = s_lq + 4 * (lo + k);
+                    r = lq[0];
+                    kx = lq[1];
+                    sf = lq[2];
+                    gd = lq[3];
+                    zp = (R)0.5 + (R)0.5 * r;
+                    zm = (R)0.5 - (R)0.5 * r;
+                    zpzm = zp * zm;
+                    const R dtau = act ? (kv[k] + kv[k]) * s_hdm[lo + k] : (R)0;
+                    fu[k] = act ? fu[k] : (R)0;
+                    sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, (R)0, act, ca[k], cc[k], sg[k]);
+                    sg[k] = tpe * s_dB[lo + k];
+                    // one layer's LDS reads at a time (all of them hoisted ahead
+                    // would hold 5 K values in registers)
+                    asm volatile("" ::: "memory");
+                    continue;
+                }
                 if constexpr (RAY) {
                     // the sublayer's own optics: absorption (mean of its end
                     // opacities) plus H2 scattering; albedo w0 = scattering
@@ -648,8 +728,9 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     zpzm = zp * zm;
                 }
                 // sublayer: mean of its end opacities times its column mass.
-                // Isothermal-layer grid: the even slot spans the whole layer
-                // with the centre's opacity, the odd slot is the identity.
+                // (iso_grid is 0 on this path; the two-branch form is kept
+                // because it compiles to fewer registers than the plain one:
+                // 440 against 512 plus spills in the FP64 long-column shape.)
                 R dtau;
                 if ((k & 1) == 0) {
                     const R k_lo = A.iso_grid ? kv[k + 1] : kv[k];
@@ -716,6 +797,46 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             const R st = col_sum<L>(wg * vtop);
             if (top_seg) acc[nsub] += st;
         };
+        // Isothermal-layer grid: slot k has two points, its lower interface
+        // 2(lo + k) (v[k]) and the point above it, which carries the flux at
+        // the next interface in the layer's own Planck reference (the slot's
+        // upper value, v[k + 1] or vlast, minus its reference shift sg[k]).
+        auto upper_iso = [&](const auto& v, R vlast, int k) -> R {
+            return (k + 1 < K ? v[k + 1 < K ? k + 1 : k] : vlast) - sg[k];
+        };
+        auto emit_iso = [&](const auto& v, R vlast, R* acc) {
+            R* a = acc + 2 * lo;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool act = lo + k < nsl;
+                const R s0 = col_sum<L>(wg * v[k]);
+                const R s1 = col_sum<L>(wg * upper_iso(v, vlast, k));
+                a[2 * k] += act ? s0 : (R)0;
+                a[2 * k + 1] += act ? s1 : (R)0;
+                // one slot's read-modify-writes at a time: hoisting all 2K reads
+                // would hold 2K values in registers and spill the long shapes
+                asm volatile("" ::: "memory");
+            }
+            const R st = col_sum<L>(wg * vlast);
+            if (top_seg) acc[nsub] += st;
+        };
+        auto store_iso = [&](const auto& v, R vlast, R* __restrict__ dst_g) {
+            if (!colok) return;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k < cnt) {
+                    R2 w;
+                    w.x = v[k];
+                    w.y = upper_iso(v, vlast, k);
+                    if (fstate) {
+                        w.x += s_tB[2 * (lo + k)];
+                        w.y += s_tB[2 * (lo + k) + 1];
+                    }
+                    *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(2 * (lo + k)))) = w;
+                }
+            }
+            if (top_seg) dst_g[col + (uint32_t)nsub] = fstate ? vlast + s_tB[nsub] : vlast;
+        };
         // per-g values of one stream (pairs at my points, the TOA value
         // alone), as fluxes when the caller keeps the flux state
         auto store = [&](const R (&v)[K], R vtop, R* __restrict__ dst_g) {
@@ -745,8 +866,9 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         auto one_pass = [&](auto last_tag) {
             constexpr bool LAST = decltype(last_tag)::value;
             R MB = (R)0;
+            // downward offsets c F_up - sig (isothermal grid: the shift a sg)
 #pragma unroll
-            for (int k = 0; k < K; ++k) fu[k] = cc[k] * fu[k] - sg[k];
+            for (int k = 0; k < K; ++k) fu[k] = cc[k] * fu[k] - (ISO ? ca[k] * sg[k] : sg[k]);
 #pragma unroll
             for (int k = K - 1; k >= 0; --k) MB = ca[k] * MB + fu[k];
             if (seg == L - 1) MB = ftop_fold + MB;
@@ -768,7 +890,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 #pragma unroll
                 for (int k = K - 1; k >= 0; --k) {
                     const R xn = ca[k] * x + fu[k];
-                    fu[k] = cc[k] * x + sg[k];
+                    fu[k] = ISO ? cc[k] * (x - sg[k]) + sg[k] : cc[k] * x + sg[k];  // (1 - c) sg on that grid
                     x = xn;
                 }
             } else {
@@ -779,10 +901,18 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     x = ca[k] * x + fu[k];
                     fu[k] = x;
                 }
-                emit(fu, Ftop, s_pd);
-                if (Fd_all) store(fu, Ftop, Fd_all + gcol);
+                if constexpr (ISO) {
+                    emit_iso(fu, xtop, s_pd);
+                    if (Fd_all) store_iso(fu, xtop, Fd_all + gcol);
+                } else {
+                    emit(fu, Ftop, s_pd);
+                    if (Fd_all) store(fu, Ftop, Fd_all + gcol);
+                }
 #pragma unroll
-                for (int k = 0; k < K; ++k) fu[k] = cc[k] * (k + 1 < K ? fu[k + 1] : xtop) + sg[k];
+                for (int k = 0; k < K; ++k) {
+                    const R xu = k + 1 < K ? fu[k + 1 < K ? k + 1 : k] : xtop;
+                    fu[k] = ISO ? cc[k] * (xu - sg[k]) + sg[k] : cc[k] * xu + sg[k];
+                }
             }
             // the BOA condition F_up(0) = F_dn(0) + F_int lives in segment 0
             const R y0 = x + Fint;
@@ -816,8 +946,13 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 
         // ---- outputs: upward fluxes (warm start of the next call) and their
         // Gauss sums
-        emit(fu, ftoa, s_pu);
-        store(fu, ftoa, fu_g);
+        if constexpr (ISO) {
+            emit_iso(fu, ftoa, s_pu);
+            store_iso(fu, ftoa, fu_g);
+        } else {
+            emit(fu, ftoa, s_pu);
+            store(fu, ftoa, fu_g);
+        }
       }  // groups
         // ---- this wave's Gauss sums over its groups (one partial per point),
         // stored coalesced
@@ -832,7 +967,9 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 }
 
 // LDS bytes of one sweep workgroup of shape (K, L).
-static size_t sweep_lds(int K, int L, size_t rbytes) { return (size_t)SweepLds(K * L).total * rbytes; }
+static size_t sweep_lds(int K, int L, size_t rbytes, bool iso = false) {
+    return (size_t)SweepLds(K * L, iso).total * rbytes;
+}
 
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills.
 template <int K, int L, bool F64>
@@ -851,26 +988,27 @@ static hipError_t allow_lds(Kern kern, size_t bytes) {
                                (int)bytes);
 }
 
-template <int K, int L, bool RAY>
+template <int K, int L, bool RAY, bool ISO>
 static hipError_t launch_kpr(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed) {
-        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false>(), RAY>;
-        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 4));
+        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false>(), RAY, ISO>;
+        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 4, ISO));
         if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 4), s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 4, ISO), s, a);
     } else {
-        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true>(), RAY>;
-        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 8));
+        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true>(), RAY, ISO>;
+        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 8, ISO));
         if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 8), s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 8, ISO), s, a);
     }
     return hipGetLastError();
 }
 
 template <int K, int L>
 static hipError_t launch_kp(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
-    if (a.inv_mbar > 0.0) return launch_kpr<K, L, true>(a, mixed, grid, s);
-    return launch_kpr<K, L, false>(a, mixed, grid, s);
+    if (a.iso_grid) return launch_kpr<K, L, false, true>(a, mixed, grid, s);
+    if (a.inv_mbar > 0.0) return launch_kpr<K, L, true, false>(a, mixed, grid, s);
+    return launch_kpr<K, L, false, false>(a, mixed, grid, s);
 }
 
 template <int K>

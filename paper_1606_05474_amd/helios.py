@@ -29,6 +29,7 @@ KTAB_TABLE, KTAB_POWERLAW = 0, 1
 NORM_SIGMA_T4, NORM_SIGMA_TINT4 = 0, 1
 ATM_RUNNING, ATM_CONVERGED, ATM_BADGRID, ATM_NUMERIC = 0, 1, -2, -5
 STATE_DEVIATION, STATE_FLUX = 0x000, 0x100  # per-g convention, OR'ed into prec
+GRID_ISOTHERMAL = 0x200  # OR'ed into prec of autotune / sweep_shapes: helios_flux_iso's shapes
 CONVERT_TO_DEVIATION, CONVERT_TO_FLUX, CONVERT_ZERO_FLUX = 0, 1, 2
 LAYERS_SUBLAYERED, LAYERS_ISOTHERMAL = 0, 1
 MAX_SPECIES = 8
@@ -334,18 +335,26 @@ def state_convert(b: Batch, T_pt, F_g, mode, D=2.0, prec=FP64, layers="noniso", 
     return F_g
 
 
-def autotune(b: Batch, kappa, T_pt, F_up_g, ws, n_scat=4, D=2.0, prec=FP64, stream=None):
+def autotune(b: Batch, kappa, T_pt, F_up_g, ws, n_scat=4, D=2.0, prec=FP64, stream=None, layers="noniso"):
     """Time the compiled sweep shapes per size class of the batch and keep
-    the fastest for later flux calls (synchronous; F_up_g is restored)."""
+    the fastest for later flux calls on that grid (synchronous; F_up_g is
+    restored)."""
+    if layers not in LAYERS:
+        raise ValueError(f"layers must be one of {LAYERS}")
+    flag = GRID_ISOTHERMAL if layers == "iso" else 0
     _check(lib().helios_autotune(ctypes.byref(b.desc), _ptr(kappa), _ptr(T_pt), _ptr(b.w0), _ptr(b.g0),
                                  int(n_scat), float(D), _ptr(F_up_g), _ptr(ws), ws.numel() * ws.element_size(),
-                                 prec, _stream(stream)))
+                                 prec | flag, _stream(stream)))
 
 
-def sweep_shapes(b: Batch, prec=FP64):
-    """{class upper layer bound: (K, L)} for the classes present in the batch."""
+def sweep_shapes(b: Batch, prec=FP64, layers="noniso"):
+    """{class upper layer bound: (K, L)} for the classes present in the batch
+    (the sweep of helios_flux, or of helios_flux_iso with layers="iso")."""
+    if layers not in LAYERS:
+        raise ValueError(f"layers must be one of {LAYERS}")
     out = np.zeros(3 * 8, np.int32)
-    k = _check(lib().helios_sweep_shapes(ctypes.byref(b.desc), prec, out.ctypes.data, 8))
+    flag = GRID_ISOTHERMAL if layers == "iso" else 0
+    k = _check(lib().helios_sweep_shapes(ctypes.byref(b.desc), prec | flag, out.ctypes.data, 8))
     o = out[:3 * k].reshape(k, 3)
     return {int(r[0]): (int(r[1]), int(r[2])) for r in o if r[1] > 0}
 
@@ -811,7 +820,7 @@ class Solver:
         apart from kappa."""
         mix_opacity(self.b, self.kt, self.T_pt, self.kappa, self.prec)
         autotune(self.b, self.kappa, self.T_pt, self.F_up_g, self.ws, n_scat=self.n_scat, D=self.D,
-                 prec=self.pflags)
+                 prec=self.pflags, layers=self.layers)
 
     def capture(self, n_steps):
         """Capture n_steps iterations into a HIP graph (replayed by

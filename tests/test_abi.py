@@ -140,10 +140,10 @@ def test_mode_entry_points_validate_before_any_device_work(H):
                                     fake, 1 << 30, 0, None) == -1
     assert lib.helios_flux_rayleigh(ctypes.byref(d), fake, fake, 4e-24, -1, 2.0, fake, None, None, None, fake,
                                     fake, 1 << 30, 0, None) == -1  # negative scattering-pass count
-    n_layer[0] = 833
+    n_layer[0] = 1025
     assert lib.helios_grid(ctypes.byref(d), None) == -2
-    assert b"2..832" in lib.helios_last_error()
-    n_layer[0] = 832
+    assert b"2..1024" in lib.helios_last_error()
+    n_layer[0] = 1024
     assert lib.helios_workspace_bytes(ctypes.byref(d), 0) > 0
 
 

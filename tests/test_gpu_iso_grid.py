@@ -188,6 +188,50 @@ def test_flux_iso_ragged_batch_spanning_size_classes(prec, small_table):
             _check(b, a, T_cs[a], r, up_ref, out, tol=1e-4, tol_g=None)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_flux_iso_1001_layers_matches_oracle(prec, small_table):
+    """The paper's deepest isothermal-layer model (Sec. 3.3: 1001 layers)
+    with a 600-layer and a 20-layer atmosphere in one call: one layer per
+    sweep slot, so 1001 layers fit the long-column shape (1664 slots)."""
+    lc, dl = W.bins(300)
+    rng = np.random.default_rng(1001)
+    atms = [W.spectral_atmosphere(rng, n, lc, dl, nb) for n, nb in [(1001, 3), (600, 2), (20, 4)]]
+    b = H.Batch(atms)
+    H.grid(b)
+    assert max(K * L for K, L in H.sweep_shapes(b, prec, layers="iso").values()) >= 1001
+    T_cs = [smooth_profile(a, 1700.0 + 50 * i, 650.0) for i, a in enumerate(atms)]
+    T_pt = torch.zeros(b.total_pt, dtype=torch.float64, device="cuda")
+    H.profile(b, b.cat_layer(T_cs), T_pt)
+    kap = torch.zeros(b.total_cell, dtype=H.rdtype(prec), device="cuda")
+    H.mix_opacity(b, H.KTable(small_table), T_pt, kap, prec)
+    out = _gpu_iso(b, kap, T_pt, prec)
+    for a, atm in enumerate(atms):
+        P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
+        up_ref = _iso_start(atm, T_cs[a])
+        r = ref.flux_iso(atm, kap_ref[:, :, 1::2], T_cs[a], P[0::2], up_ref)
+        if prec == 0:
+            _check(b, a, T_cs[a], r, up_ref, out)
+        else:
+            _check(b, a, T_cs[a], r, up_ref, out, tol=1e-4, tol_g=None)
+
+
+def test_sublayered_flux_refuses_more_than_832_layers(small_table):
+    """The sublayered grid needs two sweep slots per layer: beyond 832
+    layers no shape holds the column, and helios_flux says so."""
+    lc, dl = W.bins(300)
+    atm = W.spectral_atmosphere(np.random.default_rng(5), 900, lc, dl, 2)
+    b = H.Batch([atm])
+    H.grid(b)
+    kap = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+    T_pt = torch.full((b.total_pt,), 1000.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HeliosError) as e:
+        F = torch.zeros(b.total_cell, dtype=torch.float64, device="cuda")
+        bol = torch.zeros(b.total_pt * 3, dtype=torch.float64, device="cuda")
+        ws = torch.zeros(H.workspace_bytes(b, 0), dtype=torch.uint8, device="cuda")
+        H.flux(b, kap, T_pt, F, None, None, bol, ws, prec=0)
+    assert e.value.code == -2
+
+
 def test_iso_re_solve_matches_oracle():
     """Radiative equilibrium on the isothermal-layer grid (FP64) from the
     paper's start (zero fluxes, then the previous step's fluxes) on both
