@@ -694,9 +694,9 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     fu[k] = act ? fu[k] : (R)0;
                     sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, (R)0, act, ca[k], cc[k], sg[k]);
                     sg[k] = tpe * s_dB[lo + k];
-                    // one layer's LDS reads at a time (all of them hoisted ahead
-                    // would hold 5 K values in registers)
-                    asm volatile("" ::: "memory");
+                    // the long shapes read one layer's LDS values at a time (all
+                    // of them hoisted ahead would hold 5 K values in registers)
+                    if constexpr (K >= kLongK) asm volatile("" ::: "memory");
                     continue;
                 }
                 if constexpr (RAY) {
@@ -813,9 +813,9 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 const R s1 = col_sum<L>(wg * upper_iso(v, vlast, k));
                 a[2 * k] += act ? s0 : (R)0;
                 a[2 * k + 1] += act ? s1 : (R)0;
-                // one slot's read-modify-writes at a time: hoisting all 2K reads
-                // would hold 2K values in registers and spill the long shapes
-                asm volatile("" ::: "memory");
+                // the long shapes take one slot's read-modify-writes at a time:
+                // hoisting all 2K reads would hold 2K values in registers
+                if constexpr (K >= kLongK) asm volatile("" ::: "memory");
             }
             const R st = col_sum<L>(wg * vlast);
             if (top_seg) acc[nsub] += st;
@@ -971,12 +971,13 @@ static size_t sweep_lds(int K, int L, size_t rbytes, bool iso = false) {
     return (size_t)SweepLds(K * L, iso).total * rbytes;
 }
 
-// Occupancy hint (waves per SIMD) so the register arrays fit without spills.
-template <int K, int L, bool F64>
+// Occupancy hint (waves per SIMD) so the register arrays fit without spills
+// (the isothermal grid's two output points per slot take one step less).
+template <int K, int L, bool F64, bool ISO = false>
 constexpr int sweep_occ() {
     if (L == 64) return 1;  // the long-column shape: whole register file, large LDS staging
-    if (F64) return (K <= 4) ? 4 : ((K <= 8) ? 3 : (K <= 14 ? 2 : 1));
-    return K <= 8 ? 4 : (K <= 14 ? 3 : 2);
+    const int occ = F64 ? ((K <= 4) ? 4 : ((K <= 8) ? 3 : (K <= 14 ? 2 : 1))) : (K <= 8 ? 4 : (K <= 14 ? 3 : 2));
+    return (ISO && occ > 1) ? occ - 1 : occ;
 }
 
 // Dynamic LDS beyond 64 KB (the FP64 long-column shape) is declared to the
@@ -991,12 +992,12 @@ static hipError_t allow_lds(Kern kern, size_t bytes) {
 template <int K, int L, bool RAY, bool ISO>
 static hipError_t launch_kpr(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed) {
-        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false>(), RAY, ISO>;
+        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false, ISO>(), RAY, ISO>;
         static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 4, ISO));
         if (ok != hipSuccess) return ok;
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 4, ISO), s, a);
     } else {
-        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true>(), RAY, ISO>;
+        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true, ISO>(), RAY, ISO>;
         static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 8, ISO));
         if (ok != hipSuccess) return ok;
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 8, ISO), s, a);
