@@ -216,6 +216,34 @@ class Batch:
             None)
         self.device = dev
 
+    def replace(self, slots, atms):
+        """Put new atmospheres into the given slots of the batch, in place:
+        each must have the slot's layer and bin counts, n_g and table bins,
+        so every offset and buffer stays where it is (a captured graph that
+        reads them stays valid).  The point pressures are recomputed
+        (helios_grid) for the whole batch."""
+        for a, atm in zip(slots, atms):
+            a = int(a)
+            n, nb = int(atm["n"]), len(atm["lambda_c"])
+            if n != int(self.n[a]) or nb != int(self.nb[a]) or int(atm["ng"]) != self.ng:
+                raise ValueError(f"slot {a}: the new atmosphere's sizes differ from the slot's")
+            if not np.array_equal(np.asarray(atm["bin_index"], np.int32),
+                                  self.h_bin_index[self.bin_off[a]:self.bin_off[a + 1]]):
+                raise ValueError(f"slot {a}: the new atmosphere uses other table bins")
+            dev = self.device
+            f64 = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)  # noqa: E731
+            d = self.d
+            d["P_c"][self.lay_off[a]:self.lay_off[a + 1]] = f64(atm["P_c"])
+            d["lambda_c"][self.bin_off[a]:self.bin_off[a + 1]] = f64(atm["lambda_c"])
+            d["dlambda"][self.bin_off[a]:self.bin_off[a + 1]] = f64(atm["dlambda"])
+            for key in ("grav", "T_star", "T_irr", "T_int"):
+                d[key][a] = float(atm[key])
+            self.w0[self.lb_off[a]:self.lb_off[a + 1]] = f64(np.ravel(atm["w0"]))
+            self.g0[self.lb_off[a]:self.lb_off[a + 1]] = f64(np.ravel(atm["g0"]))
+            self.vmr[:, self.pt_off[a]:self.pt_off[a + 1]] = f64(atm["vmr"])
+            self.atms[a] = atm
+        grid(self)
+
     def with_status(self, status):
         """A view of this batch whose descriptor carries a device status
         array: atmospheres that are not ATM_RUNNING are skipped by
@@ -675,6 +703,7 @@ class Solver:
         self.b = b.with_status(self.status)
         self._graph = None
         self._warm = None
+        self._x = None  # network inputs per atmosphere (network starts only)
         self._T_iso = 1000.0
         grid(b)
 
@@ -718,6 +747,7 @@ class Solver:
         per-atmosphere fallback flags (numpy)."""
         fb = torch.zeros(self.b.n_atm, dtype=torch.int32, device=self.b.device)
         warm_start(self.b, net, x, logP_net, self.T_c, fb, T_iso=T_iso, T_lo=T_lo, T_hi=T_hi)
+        self._x = np.asarray(x, np.float32).copy()
         self._reset_state()
         fb = fb.cpu().numpy()
         if m0 != 1.0:
@@ -726,6 +756,48 @@ class Solver:
                 self.m[int(self.b.lay_off[a]):int(self.b.lay_off[a + 1])] = 1.0
         self._warm = fb == 0
         self._T_iso = float(T_iso)
+        return fb
+
+    def refill(self, slots, atms, net: MLP | None = None, x=None, m0=1.0):
+        """Replace the atmospheres in the given slots by new ones of the same
+        sizes (Batch.replace) and start them, in place: from the network's
+        profiles (isothermal where unusable; step multipliers m0) when a
+        network and the new rows of parameters x are given, else
+        isothermally at the solver's isothermal temperature.  The other
+        atmospheres continue untouched, and every buffer keeps its place, so
+        a captured graph stays valid.  Returns the fallback flags of the new
+        atmospheres."""
+        slots = np.asarray(slots, np.int64)
+        b = self.b
+        b.replace(slots, atms)
+        fb = np.zeros(slots.size, np.int32)
+        if net is not None:
+            if self._x is None:
+                self._x = np.zeros((b.n_atm, net.dims[0]), np.float32)
+            self._x[slots] = np.asarray(x, np.float32)
+            T_tmp = torch.empty_like(self.T_c)
+            fb_all = torch.zeros(b.n_atm, dtype=torch.int32, device=b.device)
+            warm_start(b, net, self._x, net.logP, T_tmp, fb_all, T_iso=self._T_iso)
+            fb = fb_all.cpu().numpy()[slots]
+        for k, a in enumerate(slots):
+            a = int(a)
+            lo, hi = int(b.lay_off[a]), int(b.lay_off[a + 1])
+            if net is not None:
+                self.T_c[lo:hi] = T_tmp[lo:hi]
+            else:
+                self.T_c[lo:hi] = self._T_iso
+            self.m[lo:hi] = m0 if (net is not None and fb[k] == 0) else 1.0
+            self.hist[lo:hi] = 0
+            self.F_up_g[int(b.cell_off[a]):int(b.cell_off[a + 1])] = 0
+        idx = torch.as_tensor(slots, device=b.device)
+        self.iters[idx] = 0
+        self.resid[idx] = 0.0
+        self.status[idx] = ATM_RUNNING
+        if self._warm is None:
+            self._warm = np.zeros(b.n_atm, bool)
+        self._warm[slots] = (fb == 0) if net is not None else False
+        profile(self.b, self.T_c, self.T_pt)
+        self._start_fluxes(self._only(slots))
         return fb
 
     def restart(self, which, T_iso=1000.0):

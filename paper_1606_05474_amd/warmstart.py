@@ -32,6 +32,7 @@ from . import helios as H
 from . import workloads as W
 
 DIMS = (6, 256, 256, 256, 100)
+ATM_STOPPED = 2  # a status the production form gives atmospheres it stops (any but RUNNING is skipped)
 
 
 def generate(seed: int, count: int, start: int = 0, chunk: int = 1024, prec: int = H.MIXED, max_iter: int = 400,
@@ -160,7 +161,8 @@ def evaluate(net: H.MLP, seed: int = 40, count: int = 256, start: int = 0, prec:
 def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int = 0, pool: int = 256,
                n: int = 200, nb: int = 3000, max_iter: int = 1500, restart_after: int = 1000,
                check_every: int = 10, deadband: int = 1, polish_iter: int = 0, m0: float = 0.3, keep_T: int = 0,
-               tol: float = 7e-4, refill: float = 0.75, log=print):
+               tol: float = 1e-3, refill_min: int = 32, verify: bool = True, verify_tol: float = 1e-3,
+               verify_iter: int = 300, log=print):
     """The production form: atmospheres start..start+count-1 of a parameter
     set solved by one device batch of up to `pool` atmospheres that is
     refilled as atmospheres finish (size-class sweeps, graph replay of blocks
@@ -174,15 +176,20 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
        running after `max_iter` updates leaves the batch unconverged (or, with
        polish_iter > 0, continues in FP64 from its full state for up to that
        many updates, all such atmospheres as one batch at the end);
-    3. whenever at most a fraction `refill` of the batch is still running
-       (or no new atmospheres are left and at most half are), the running
-       ones move into a new batch (Solver.concat carries their state) together
-       with enough new atmospheres to fill the pool, so the device keeps
-       working on a full batch until the last atmospheres.
+    3. whenever `refill_min` atmospheres of the batch have finished, new
+       atmospheres take their slots in place (Solver.refill: same sizes, so
+       the batch's buffers and the captured graph stay valid), and the device
+       keeps working on a full batch; once no new atmospheres are left and at
+       most half of the batch runs, the running ones move into a smaller
+       batch (Solver.subset carries their state);
+    4. with `verify`, an atmosphere that passed the test in mixed precision
+       continues in FP64 (temperatures, step control and warm start carried
+       over) until it passes the plain form's FP64 test at `verify_tol` (at
+       most `verify_iter` more updates, usually none): only then does it
+       count as converged, so both forms meet the same test in FP64.
 
-    The convergence test is the plain form's, with tolerance `tol` (7e-4 by
-    default, so that the profiles also pass the FP64 test at the plain
-    form's 1e-3).  The timed region starts after the one-time shape tuning
+    The mixed stage's test is the plain form's with tolerance `tol`.  The
+    timed region starts after the one-time shape tuning
     and excludes the host-side generation of the inputs; it includes the
     device batches' construction, the network inference and every update.
     Returns totals and the converged profiles of the first `keep_T`
@@ -211,15 +218,40 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         fallbacks[0] += int(fb.sum())
         return sv
 
-    def harvest(sv, ids, which):
+    vstats = {"checked": 0, "passed_at_once": 0, "updates": 0, "failed": 0}
+
+    def fp64_verify(sv, ids, idx):
+        """The FP64 stage: atmospheres idx of sv continue in FP64 until the
+        plain form's test passes there."""
+        idx = np.asarray(idx, np.int64)
+        if idx.size == 0:
+            return
+        s64 = sv.subset(idx, prec=H.FP64)
+        s64.opts = H.REOptions(deadband=deadband, tol=verify_tol)
+        it0 = s64.iters.cpu().numpy().copy()
+        c, it, _, T, _, _ = _run_compacting(s64, verify_iter, 2, None)
+        for k, a in enumerate(ids[idx]):
+            a = int(a)
+            conv[a], its[a], T_out[a] = bool(c[k]), int(it[k]), T[k]
+        extra = it - it0
+        vstats["checked"] += int(idx.size)
+        vstats["passed_at_once"] += int(np.sum(c & (extra == 0)))
+        vstats["updates"] += int(extra.sum())
+        vstats["failed"] += int(np.sum(~c))
+        del s64
+
+    def harvest(sv, ids, which, over):
         st = sv.status.cpu().numpy()
         it = sv.iters.cpu().numpy()
         Tc = sv.T_c.cpu().numpy()
+        ok = [k for k in which if st[k] == H.ATM_CONVERGED and not over[k]]
         for k in which:
             a = int(ids[k])
-            conv[a] = st[k] == H.ATM_CONVERGED
+            conv[a] = k in ok and not verify
             its[a] = it[k]
             T_out[a] = Tc[int(sv.b.lay_off[k]):int(sv.b.lay_off[k + 1])].copy()
+        if verify:
+            fp64_verify(sv, ids, ok)
 
     first = min(pool, count)
     s = make(0, first)
@@ -231,7 +263,7 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = make(0, first)
-    ids = np.arange(first)
+    ids = np.arange(first)  # atmosphere held by each slot, -1 once a slot is empty for good
     nxt = first
     rs_cur = np.zeros(first, bool)
     over_parts = []  # (solver, indices, original ids) of atmospheres that reached max_iter
@@ -241,41 +273,64 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
         st = s.status.cpu().numpy()
         it = s.iters.cpu().numpy()
         if restart_after is not None and s._warm is not None:
-            late = np.where(s._warm & ~rs_cur & (st == H.ATM_RUNNING) & (it >= restart_after))[0]
+            late = np.where(s._warm & ~rs_cur & (st == H.ATM_RUNNING) & (it >= restart_after) & (ids >= 0))[0]
             if late.size:
                 s.restart(late, s._T_iso)
                 rs_cur[late] = True
                 restarted[ids[late]] = True
                 st = s.status.cpu().numpy()
-        over = (st == H.ATM_RUNNING) & (it >= max_iter)
-        running = (st == H.ATM_RUNNING) & ~over
-        nrun = int(running.sum())
-        if nrun == 0 and nxt >= count:
-            harvest(s, ids, range(len(ids)))
+        over = (st == H.ATM_RUNNING) & (it >= max_iter) & (ids >= 0)
+        if over.any():  # stop them now (any status but RUNNING is skipped); harvested as unconverged
+            s.status[torch.as_tensor(np.where(over)[0], device=s.b.device)] = ATM_STOPPED
+        running = (st == H.ATM_RUNNING) & ~over & (ids >= 0)
+        done = (ids >= 0) & ~running
+        nrun, ndone = int(running.sum()), int(done.sum())
+        left = count - nxt
+        if nrun == 0 and left == 0:
+            fs = np.where(done)[0]
+            harvest(s, ids, fs, over)
             if over.any() and polish_iter > 0:
                 over_parts.append((s, np.where(over)[0], ids[over]))
             break
-        left = count - nxt
-        if (left > 0 and nrun <= refill * len(ids)) or (left == 0 and nrun <= len(ids) // 2 and len(ids) > 8):
-            harvest(s, ids, np.where(~running)[0])
+        if left > 0 and ndone >= min(refill_min, left):
+            # finished atmospheres leave their slots; new ones take them in place,
+            # so the batch, its buffers and the captured graph stay as they are
+            fs = np.where(done)[0]
+            harvest(s, ids, fs, over)
+            if over.any() and polish_iter > 0:
+                over_parts.append((s.subset(np.where(over)[0], prec=H.FP64), None, ids[over]))
+            k_new = min(fs.size, left)
+            slots = fs[:k_new]
+            tg = time.perf_counter()
+            atms, _ = W.learned_workload(seed, k_new, start + nxt, n=n, nb=nb, ktab=kt)
+            gen[0] += time.perf_counter() - tg
+            if net is not None:
+                fb = s.refill(slots, atms, net=net, x=np.stack([a["params"] for a in atms]), m0=m0)
+                fallbacks[0] += int(fb.sum())
+            else:
+                s.refill(slots, atms)
+            ids[slots] = np.arange(nxt, nxt + k_new)
+            rs_cur[slots] = False
+            empty = fs[k_new:]
+            if empty.size:
+                s.status[torch.as_tensor(empty, device=s.b.device)] = ATM_STOPPED
+                ids[empty] = -1
+            nxt += k_new
+            refills[0] += 1
+            if refills[0] % 16 == 0:  # progress: finished so far, elapsed
+                log(f"production: {nxt - nrun - k_new} of {count} finished or stopped, "
+                    f"{time.perf_counter() - t0 - gen[0]:.0f} s")
+        elif left == 0 and nrun <= int((ids >= 0).sum()) // 2 and s.b.n_atm > 8:
+            # the last atmospheres: harvest the finished ones and move the running
+            # ones into a smaller batch, so later launches cover live atmospheres only
+            fs = np.where(done)[0]
+            harvest(s, ids, fs, over)
             if over.any() and polish_iter > 0:
                 over_parts.append((s.subset(np.where(over)[0], prec=H.FP64), None, ids[over]))
             keep = np.where(running)[0]
-            k_new = min(pool - keep.size, left)
-            parts = [(s, keep)] if keep.size else []
-            new_ids = np.arange(nxt, nxt + k_new)
-            if k_new > 0:
-                sn = make(nxt, k_new)
-                parts.append((sn, np.arange(k_new)))
-            s2 = H.Solver.concat(parts)
-            refills[0] += 1
-            if refills[0] % 8 == 0:  # progress: finished so far, elapsed
-                log(f"production: {nxt - keep.size} of {count} finished or stopped, "
-                    f"{time.perf_counter() - t0 - gen[0]:.0f} s")
-            rs_cur = np.concatenate([rs_cur[keep], np.zeros(k_new, bool)])
-            ids = np.concatenate([ids[keep], new_ids])
-            nxt += k_new
-            del parts, s
+            s2 = s.subset(keep)
+            ids, rs_cur = ids[keep], rs_cur[keep]
+            del s
             s = s2
             s.capture(check_every)
     polished = 0
@@ -295,11 +350,12 @@ def production(net: H.MLP | None, seed: int = 5, count: int = 4096, start: int =
     torch.cuda.empty_cache()
     out = {"count": count, "converged": int(conv.sum()), "seconds": seconds, "updates": its,
            "fallbacks": fallbacks[0], "restarts": int(restarted.sum()), "polished": polished,
+           "fp64_stage": dict(vstats) if verify else None,
            "T": T_out[:keep_T], "conv_flags": conv, "converged_per_s": float(conv.sum()) / seconds,
            "input_generation_s": gen[0], "refills": refills[0]}
     log(f"production: {out['converged']}/{count} converged in {seconds:.1f} s (inputs generated in "
         f"{gen[0]:.1f} s, not timed), median updates {np.median(its):.0f}, fallbacks {fallbacks[0]}, "
-        f"restarts {out['restarts']}, FP64 polish {polished}, batch refills {refills[0]}")
+        f"restarts {out['restarts']}, FP64 polish {polished}, batch refills {refills[0]}, FP64 stage {vstats}")
     return out
 
 
