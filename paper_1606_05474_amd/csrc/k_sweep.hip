@@ -414,21 +414,19 @@ __device__ inline R col_sum(R v) {
 // capacity of K*L sublayers so that every lane can address its K sublayers
 // without bounds tests: sublayers past the column hold the identity.
 //   dB, hdm  [K*L + 1]   Planck difference and half column mass per sublayer
-//   tB       [K*L + 1]   (2 pi / D) B per point (flux-state conversion)
 //   lq       [K*L/2][4]  r, kx, sf, gd per layer
 //   pu, pd   [K*L + 2]   Gauss sums per point (slots past the column's
 //                        points take zeros)
 // On the isothermal-layer grid a slot is a whole layer with two points (its
 // lower interface and the point above it), so dB, hdm and lq are per layer
-// and tB, pu, pd span 2 K*L + 2 points.
+// and pu, pd span 2 K*L + 2 points.
 struct SweepLds {
-    int dB, hdm, tB, lq, pu, pd, total;
+    int dB, hdm, lq, pu, pd, total;
     static constexpr int r4(int v) { return (v + 3) & ~3; }
     __host__ __device__ constexpr SweepLds(int KL, bool iso = false)
         : dB(0),
           hdm(r4(KL + 1)),
-          tB(2 * r4(KL + 1)),
-          lq(tB + r4(iso ? 2 * KL + 2 : KL + 1)),
+          lq(2 * r4(KL + 1)),
           pu(lq + 4 * r4(iso ? KL : KL / 2)),
           pd(pu + r4(iso ? 2 * KL + 2 : KL + 2)),
           total(pd + r4(iso ? 2 * KL + 2 : KL + 2)) {}
@@ -459,7 +457,6 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     R* sm = reinterpret_cast<R*>(smem_raw);
     R* s_dB = sm + lay.dB;
     R* s_hdm = sm + lay.hdm;
-    R* s_tB = sm + lay.tB;
     R* s_lq = sm + lay.lq;
     R* s_pu = sm + lay.pu;
     R* s_pd = sm + lay.pd;
@@ -477,8 +474,6 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     const R D = (R)A.D;
     const R inv_D = (R)(1.0 / A.D);
     const R tpe = (R)(2.0 * kPi / A.D);
-    const double tpe_d = 2.0 * kPi / A.D;
-    const bool fstate = A.flux_state != 0;  // per-g arrays hold F, not F - (2 pi / D) B
 
     for (int64_t item = A.w_begin + blockIdx.x; item < A.w_end; item += gridDim.x) {
         const int64_t gb = (A.parts == 1) ? item : item / A.parts;
@@ -524,8 +519,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         if constexpr (ISO) {
             // per layer j: dB = B(2j+1) - B(2j+2) (its own Planck value minus the
             // reference of its upper interface), half its column mass, and its
-            // r, kx, sf, gd; per point: the flux-state reference; the Gauss-sum
-            // slots of every point of the capacity cleared
+            // r, kx, sf, gd; the Gauss-sum slots of every point of the
+            // capacity cleared
             constexpr int SCH = (KL + 63) / 64;
             constexpr int QCH = (2 * KL + 2 + 63) / 64;
             for (int q = 0; q < SCH; ++q) {  // one chunk of 64 layers at a time
@@ -550,7 +545,6 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             for (int q = 0; q < QCH; ++q) {
                 const int i = lane + 64 * q;
                 if (i <= 2 * KL + 1) {
-                    s_tB[i] = (i < npt) ? (R)(tpe_d * B_all[pb + i]) : (R)0;
                     s_pu[i] = (R)0;
                     s_pd[i] = (R)0;
                 }
@@ -589,7 +583,6 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 if (i <= KL) {
                     s_dB[i] = real ? (R)(bv[q] - bn) : (R)0;
                     s_hdm[i] = real ? (R)((pv[q] - pn) * higrav) : (R)0;
-                    s_tB[i] = (i < npt) ? (R)(tpe_d * bv[q]) : (R)0;
                 }
                 if (i <= KL + 1) {
                     s_pu[i] = (R)0;
@@ -641,10 +634,6 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 kv[k] = kap_g[col + pt + 1];
                 fu[k] = fu_g[col + pt];
             }
-            if (fstate) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) fu[k] -= s_tB[2 * (lo + k)];
-            }
         } else {
             R2 kp2[KH + 1], fp2[KH];
 #pragma unroll
@@ -662,10 +651,6 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             for (int p = 0; p < KH; ++p) {
                 fu[2 * p] = fp2[p].x;
                 fu[2 * p + 1] = fp2[p].y;
-            }
-            if (fstate) {  // the sweep carries deviations from the isothermal flux
-#pragma unroll
-                for (int k = 0; k < K; ++k) fu[k] -= s_tB[lo + k];
             }
         }
 
@@ -828,17 +813,13 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     R2 w;
                     w.x = v[k];
                     w.y = upper_iso(v, vlast, k);
-                    if (fstate) {
-                        w.x += s_tB[2 * (lo + k)];
-                        w.y += s_tB[2 * (lo + k) + 1];
-                    }
                     *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(2 * (lo + k)))) = w;
                 }
             }
-            if (top_seg) dst_g[col + (uint32_t)nsub] = fstate ? vlast + s_tB[nsub] : vlast;
+            if (top_seg) dst_g[col + (uint32_t)nsub] = vlast;
         };
         // per-g values of one stream (pairs at my points, the TOA value
-        // alone), as fluxes when the caller keeps the flux state
+        // alone)
         auto store = [&](const R (&v)[K], R vtop, R* __restrict__ dst_g) {
             if (!colok) return;
 #pragma unroll
@@ -847,14 +828,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     R2 w;
                     w.x = v[2 * p];
                     w.y = v[2 * p + 1];
-                    if (fstate) {
-                        w.x += s_tB[lo + 2 * p];
-                        w.y += s_tB[lo + 2 * p + 1];
-                    }
                     *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(lo + 2 * p))) = w;
                 }
             }
-            if (top_seg) dst_g[col + (uint32_t)nsub] = fstate ? vtop + s_tB[nsub] : vtop;
+            if (top_seg) dst_g[col + (uint32_t)nsub] = vtop;
         };
 
         // One scattering pass: downward sweep (top -> bottom), then upward

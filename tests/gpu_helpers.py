@@ -32,11 +32,29 @@ def net_flux_error(F_bol_gpu, F_bol_ref):
 def net_flux_error_sigma(F_bol_gpu, F_bol_ref, T_int):
     """Per-point |net_gpu - net_ref| / max(|net_ref|, sigma T_int^4): the
     error against the net flux itself, or against the flux the atmosphere
-    carries at equilibrium where the net flux is smaller than that."""
+    carries at equilibrium where the net flux is smaller than that.  With
+    T_int = 0 that flux is zero and the net flux can vanish exactly (at the
+    BOA), so such atmospheres are measured against the gross flux
+    (net_flux_error) instead."""
+    if float(T_int) <= 0.0:
+        return net_flux_error(F_bol_gpu, F_bol_ref)
     F_bol_gpu = np.asarray(F_bol_gpu).reshape(-1, 3)
     F_bol_ref = np.asarray(F_bol_ref).reshape(-1, 3)
     floor = 5.670374419e-5 * float(T_int) ** 4
     return np.abs(F_bol_gpu[:, 2] - F_bol_ref[:, 2]) / np.maximum(np.abs(F_bol_ref[:, 2]), floor)
+
+
+# Bound of net_flux_error_sigma for the mixed path (float32 sweeps; the FP64
+# path is held to 1e-10 in both measures).  The float32 per-g deviations are
+# rounded at every one of the 2n sublayer steps of each of the 1 + n_scat
+# passes, and at a low T_int the fluxes they carry exceed sigma T_int^4 by
+# orders of magnitude, so this measure exceeds 1e-4 (measured: 1.2e-4 and
+# 1.4e-4 on the ragged and full-size two-stream tests, 5.7e-4 on the ragged
+# Rayleigh batch, up to 3.5e-4 on production atmospheres with T_int near
+# 100 K).  The mixed path's flux error is held below the convergence
+# tolerance of 1e-3 sigma T_int^4 it feeds (Sec. 2.2.4); a profile's final
+# acceptance is the FP64 path's.
+MIXED_SIGMA_TOL = 1e-3
 
 
 def col_rel_error(x, y, axis=-1):

@@ -15,7 +15,8 @@ import pytest
 import torch
 
 import oracle as ref
-from gpu_helpers import col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux
+from gpu_helpers import (MIXED_SIGMA_TOL, col_rel_error, net_flux_error, net_flux_error_sigma, oracle_state,
+                         smooth_profile, to_flux)
 from paper_1606_05474_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -87,6 +88,8 @@ def _check(b, a, T_c, r, up_ref, out, tol=1e-10, tol_g=1e-11):
     bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
     err = net_flux_error(bol_a, r["F_bol"][j])
     assert err.max() < tol, err.max()
+    err_sig = net_flux_error_sigma(bol_a, r["F_bol"][j], atm["T_int"])
+    assert err_sig.max() < (tol if tol_g is not None else MIXED_SIGMA_TOL), err_sig.max()
     iso = ref.isothermal_flux(atm, _ref_T(T_c, npt))
     if tol_g is None:
         return

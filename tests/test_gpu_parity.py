@@ -15,8 +15,8 @@ import pytest
 import torch
 
 import oracle as ref
-from gpu_helpers import (col_rel_error, net_flux_error, oracle_state, smooth_profile, to_flux,
-                         well_conditioned_layers)
+from gpu_helpers import (MIXED_SIGMA_TOL, col_rel_error, net_flux_error, net_flux_error_sigma, oracle_state,
+                         smooth_profile, to_flux, well_conditioned_layers)
 from paper_1606_05474_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -161,8 +161,11 @@ def _check_flux_fp64(b, a, T, res_ref, F_up_ref, F_up, F_dn, ub, db, bol, tol=1e
     """FP64 flux call of atmosphere a (point temperatures T) against the
     oracle's result; the per-g GPU arrays hold deviations from the
     isothermal flux, which the oracle's own Planck values turn into fluxes."""
-    err_net = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], res_ref["F_bol"])
+    bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
+    err_net = net_flux_error(bol_a, res_ref["F_bol"])
     assert err_net.max() < tol, err_net.max()
+    err_sig = net_flux_error_sigma(bol_a, res_ref["F_bol"], b.atms[a]["T_int"])
+    assert err_sig.max() < tol, err_sig.max()
     iso = ref.isothermal_flux(b.atms[a], T)
     gu = to_flux(b.split_cell(_np(F_up))[a], iso)
     assert col_rel_error(gu, F_up_ref).max() < 1e-11
@@ -252,6 +255,8 @@ def test_flux_mixed_precision_within_tolerance(small_table):
     F_up, F_dn, ub, db, bol = _gpu_flux(b, kap_m, _t(T), 1)
     err = net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"])
     assert err.max() < 1e-4, err.max()
+    err_sig = net_flux_error_sigma(_np(bol).reshape(-1, 3), r["F_bol"], atm["T_int"])
+    assert err_sig.max() < MIXED_SIGMA_TOL, err_sig.max()
     assert col_rel_error(b.split_pb(_np(ub))[0], r["F_up_bin"]).max() < 1e-4
 
 
@@ -456,6 +461,8 @@ def test_flux_every_sweep_shape(K, L, prec, small_table, monkeypatch):
         _check_flux_fp64(b, 0, T, r, up_ref, F_up, F_dn, ub, db, bol)
     else:
         assert net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"]).max() < 1e-4
+        err_sig = net_flux_error_sigma(_np(bol).reshape(-1, 3), r["F_bol"], atm["T_int"])
+        assert err_sig.max() < MIXED_SIGMA_TOL, err_sig.max()
         assert col_rel_error(to_flux(b.split_cell(_np(F_up))[0], ref.isothermal_flux(atm, T)), up_ref).max() < 1e-4
 
 
@@ -487,8 +494,11 @@ def test_ragged_batch_spanning_every_size_class(prec, small_table):
         if prec == 0:
             _check_flux_fp64(b, a, T, r, up_ref, F_up, F_dn, ub, db, bol)
         else:
-            err = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], r["F_bol"])
+            bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
+            err = net_flux_error(bol_a, r["F_bol"])
             assert err.max() < 1e-4, (a, err.max())
+            err_sig = net_flux_error_sigma(bol_a, r["F_bol"], atm["T_int"])
+            assert err_sig.max() < MIXED_SIGMA_TOL, (a, err_sig.max())
 
 
 def test_status_skips_atmospheres_that_are_not_running(small_table):
@@ -557,8 +567,11 @@ def test_autotune_restores_warm_start_and_keeps_parity(prec, small_table):
         P, T, kap_ref = oracle_state(atm, small_table, T_cs[a])
         up_ref = ref.isothermal_start(atm, T)
         r = ref.flux(atm, kap_ref, T, P, up_ref)
-        err = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[a], r["F_bol"])
+        bol_a = b.split_pt(_np(bol).reshape(-1, 3))[a]
+        err = net_flux_error(bol_a, r["F_bol"])
         assert err.max() < (1e-10 if prec == 0 else 1e-4), (a, err.max())
+        err_sig = net_flux_error_sigma(bol_a, r["F_bol"], atm["T_int"])
+        assert err_sig.max() < (1e-10 if prec == 0 else MIXED_SIGMA_TOL), (a, err_sig.max())
 
 
 def test_graph_replayed_solve_equals_eager_solve():
@@ -604,6 +617,8 @@ def test_full_size_production_atmosphere_against_oracle(prec):
     F_up, F_dn, ub, db, bol = _gpu_flux(b, kap, T_pt, prec, want_dn=False)
     err = net_flux_error(_np(bol).reshape(-1, 3), r["F_bol"])
     assert err.max() < (1e-10 if prec == 0 else 1e-4), err.max()
+    err_sig = net_flux_error_sigma(_np(bol).reshape(-1, 3), r["F_bol"], atm["T_int"])
+    assert err_sig.max() < (1e-10 if prec == 0 else MIXED_SIGMA_TOL), err_sig.max()
 
 
 def test_compacted_batch_continues_the_same_iteration():
@@ -686,6 +701,8 @@ def test_flux_exact_matches_oracle(case, small_table):
     F_up, F_dn, ub, db, bol = _exact_gpu(b, b.pack_cell([kap]), _t(T))
     err_net = net_flux_error(b.split_pt(_np(bol).reshape(-1, 3))[0], r["F_bol"])
     assert err_net.max() < 1e-10, err_net.max()
+    err_sig = net_flux_error_sigma(b.split_pt(_np(bol).reshape(-1, 3))[0], r["F_bol"], atm["T_int"])
+    assert err_sig.max() < 1e-10, err_sig.max()
     iso = ref.isothermal_flux(atm, T)  # pi B for D = 2
     assert col_rel_error(to_flux(b.split_cell(_np(F_up))[0], iso), r["F_up"]).max() < 1e-11
     assert col_rel_error(to_flux(b.split_cell(_np(F_dn))[0], iso), r["F_dn"]).max() < 1e-11
@@ -711,3 +728,4 @@ def test_flux_exact_ragged_batch_equals_single_atmospheres(small_table):
         P = ref.grid(atm["P_c"])
         r = ref.flux_exact(atm, kaps[a], Ts[a], P)
         assert net_flux_error(bol[a], r["F_bol"]).max() < 1e-10
+        assert net_flux_error_sigma(bol[a], r["F_bol"], atm["T_int"]).max() < 1e-10
