@@ -452,7 +452,14 @@ def layers_main(args):
     model's spectrum, the updates to converge and the time per update.  The
     step control counts any sign change within the 6-step window as an
     oscillation: with the strict-alternation reading a 400-layer model
-    oscillates with period 4 and its step multipliers never shrink."""
+    oscillates with period 4 and its step multipliers never shrink.
+
+    The 1001-layer isothermal model needs a few hundred thousand updates, more
+    than one run of a few minutes holds: --layers-budget bounds its wall time
+    in this run, --layers-save writes its state when the budget ends first
+    (layer temperatures, step multipliers, sign histories, updates), and
+    --layers-resume continues from such a file (its scattering iteration
+    restarts from zero fluxes; the temperature iteration continues)."""
     import time
 
     import numpy as np
@@ -464,26 +471,49 @@ def layers_main(args):
     kt = W.table_ktab(2)
     KT = H.KTable(kt)
     lc, dl = W.bins(3000)
-    grids = {"noniso": (21, 51, 101, 501), "iso": (51, 101, 201, 1001)}
+    groups = {"noniso": ("noniso", (21, 51, 101, 501)), "iso": ("iso", (51, 101, 201)),
+              "iso_deep": ("iso", (1001,))}
+    if args.layers_models:
+        groups = {k: v for k, v in groups.items() if k in args.layers_models.split(",")}
     res = {}
     log = lambda *v: print("#", *v, file=sys.stderr, flush=True)  # noqa: E731
-    for layers, ns in grids.items():
+    for name, (layers, ns) in groups.items():
         atms = [W.resolution_atmosphere(6, n, lc, dl) for n in ns]
         b = H.Batch(atms)
         s = H.Solver(b, KT, prec=H.FP64, layers=layers, bin_fluxes=False, opts=H.REOptions(osc_any=1))
         s.reset(b.cat_layer([a["T0"] for a in atms]))
+        resumed = 0
+        if name == "iso_deep" and args.layers_resume and os.path.exists(args.layers_resume):
+            with np.load(args.layers_resume) as d:
+                s.T_c.copy_(torch.as_tensor(d["T_c"], device=s.T_c.device))
+                s._reset_state()  # interface temperatures and the zero-flux start from the saved profile
+                s.m.copy_(torch.as_tensor(d["m"], device=s.m.device))
+                s.hist.copy_(torch.as_tensor(d["hist"], device=s.hist.device))
+                s.iters.copy_(torch.as_tensor(d["iters"], device=s.iters.device))
+                resumed = int(d["iters"].max())
+            log(f"{name}: resumed at {resumed} updates")
+        budget = args.layers_budget if name == "iso_deep" else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        done, block = 0, 2000
+        done, block = resumed, 2000
+        stopped = False
+        conv, iters = np.zeros(len(ns), bool), s.iters.cpu().numpy()
         while done < args.max_iter:
             conv, iters, _ = s.run(block - 1, check_every=100, graph=True)
             done += block
-            log(f"{layers}: {done} updates, converged {conv.tolist()}, updates {iters.tolist()}, "
+            log(f"{name}: {done} updates, converged {conv.tolist()}, updates {iters.tolist()}, "
                 f"{time.perf_counter() - t0:.1f} s")
             if conv.all():
                 break
+            if budget is not None and time.perf_counter() - t0 > budget:
+                stopped = True
+                break
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
+        if stopped and args.layers_save:
+            np.savez(args.layers_save, T_c=s.T_c.cpu().numpy(), m=s.m.cpu().numpy(), hist=s.hist.cpu().numpy(),
+                     iters=s.iters.cpu().numpy())
+            log(f"{name}: state after {int(iters.max())} updates saved to {args.layers_save}")
         T = [t.cpu().numpy() for t in b.split_layer(s.T_c)]
         toa, _ = H.emission_spectrum(b, KT, s.T_c, n_scat=80, layers=layers)
         # one RE update's time on this batch with every member running
@@ -502,7 +532,13 @@ def layers_main(args):
         for k, n in enumerate(ns):
             res[f"{layers}{n}"] = {"P_c": atms[k]["P_c"], "T": T[k], "spec": toa[k].cpu().numpy(),
                                    "converged": bool(conv[k]), "updates": int(iters[k])}
-        res[layers] = {"seconds": sec, "ms_per_update_all_running": e0.elapsed_time(e1) / 10}
+        res[name] = {"seconds": sec, "resumed_at": resumed, "ms_per_update_all_running": e0.elapsed_time(e1) / 10}
+    if "noniso501" not in res:
+        print(json.dumps({"metric": "layer resolution study", "partial": True,
+                          "models": {k: {"converged": v["converged"], "updates": v["updates"]}
+                                     for k, v in res.items() if "T" in v},
+                          "time": {k: v for k, v in res.items() if "T" not in v}}))
+        return 0
     ref_m = res["noniso501"]
     lp_ref = np.log(ref_m["P_c"])[::-1]
     out = {}
@@ -532,7 +568,7 @@ def layers_main(args):
                                    "6-step window shrinks the step), spectra with 80 "
                                    "scattering passes on each model's own grid; reference: 501 sublayered layers"},
             "models": out,
-            "time": {k: res[k] for k in grids}}
+            "time": {k: res[k] for k in groups}}
     print(json.dumps(line))
     return 0
 
@@ -829,8 +865,16 @@ def main(argv=None):
                     help="default line: atmospheres of the production-form subset (0: skip it)")
     ap.add_argument("--subset-plain", type=int, default=16,
                     help="default line: atmospheres of the plain-form subset")
+    ap.add_argument("--layers-models", default=None,
+                    help="layers: comma-separated groups to run (noniso, iso, iso_deep; default all)")
+    ap.add_argument("--layers-budget", type=float, default=None,
+                    help="layers: seconds of updates for the 1001-layer isothermal model in this run")
+    ap.add_argument("--layers-save", default=None,
+                    help="layers: where to write the 1001-layer model's state when its budget ends first")
+    ap.add_argument("--layers-resume", default=None,
+                    help="layers: continue the 1001-layer model from a state written by --layers-save")
     ap.add_argument("--max-iter", type=int, default=None,
-                    help="update cap (batch: 300; production: 1500 for both forms; layers: 250000)")
+                    help="update cap (batch: 300; production: 1500 for both forms; layers: 1000000)")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -862,7 +906,7 @@ def main(argv=None):
     if args.n_atm is None:
         args.n_atm = {"production": 4096, "chunk": 128, "c5": 256}.get(args.workload, 512)
     if args.max_iter is None:
-        args.max_iter = {"production": 1500, "layers": 250000}.get(args.workload, 300)
+        args.max_iter = {"production": 1500, "layers": 1000000}.get(args.workload, 300)
     if args.workload == "batch":
         return batch_main(args)
     if args.workload == "production":
