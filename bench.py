@@ -454,10 +454,12 @@ def layers_main(args):
     oscillation: with the strict-alternation reading a 400-layer model
     oscillates with period 4 and its step multipliers never shrink.
 
-    The 1001-layer isothermal model needs a few hundred thousand updates, more
-    than one run of a few minutes holds: --layers-budget bounds its wall time
-    in this run, --layers-save writes its state when the budget ends first
-    (layer temperatures, step multipliers, sign histories, updates), and
+    The 1001-layer isothermal model does not converge: under the step control
+    its deep layers run away from the isothermal start (the oracle does the
+    same on a 30-bin stand-in, with either oscillation reading), as the paper
+    reports no convergence with 1001 isothermal layers.  --layers-budget
+    bounds its wall time, --layers-save writes its state when the budget ends
+    first (layer temperatures, step multipliers, sign histories, updates), and
     --layers-resume continues from such a file (its scattering iteration
     restarts from zero fluxes; the temperature iteration continues)."""
     import time
@@ -501,7 +503,8 @@ def layers_main(args):
         while done < args.max_iter:
             conv, iters, _ = s.run(block - 1, check_every=100, graph=True)
             done += block
-            log(f"{name}: {done} updates, converged {conv.tolist()}, updates {iters.tolist()}, "
+            tmax = [round(float(t.max()), 1) for t in b.split_layer(s.T_c)]
+            log(f"{name}: {done} updates, converged {conv.tolist()}, updates {iters.tolist()}, max T {tmax}, "
                 f"{time.perf_counter() - t0:.1f} s")
             if conv.all():
                 break
@@ -550,7 +553,8 @@ def layers_main(args):
         dev = np.abs(m["spec"] / ref_m["spec"] - 1.0)
         bright = ref_m["spec"] >= 1e-3 * ref_m["spec"].max()  # bins that carry the emitted flux
         k_max = int(np.argmax(dT))
-        out[key] = {"converged": m["converged"], "updates": m["updates"],
+        out[key] = {"converged": m["converged"], "updates": m["updates"], "T_range_K": [float(m["T"].min()),
+                                                                                     float(m["T"].max())],
                     "max_abs_dT_vs_noniso501_K": float(dT.max()),
                     "max_abs_dT_at_bar": float(m["P_c"][k_max] / 1e6),
                     "median_abs_dT_vs_noniso501_K": float(np.median(dT)),

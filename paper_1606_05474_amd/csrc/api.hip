@@ -139,7 +139,7 @@ WsLayout ws_layout(const Sizes& z, int n_g, bool /*mixed*/) {
     w.part_dn = align256(w.part_up + (size_t)z.total_pb * wpb * 8);
     w.chunk = align256(w.part_dn + (size_t)z.total_pb * wpb * 8);
     w.bnd_maxch = (z.nb_max + kBndChunk - 1) / kBndChunk;
-    w.bnd_part = align256(w.chunk + (size_t)z.total_pt * n_chunk * 6 * sizeof(double));
+    w.bnd_part = align256(w.chunk + (size_t)z.total_pt * n_chunk * kBolQ * sizeof(double));
     w.total = align256(w.bnd_part + (size_t)z.n_atm * w.bnd_maxch * sizeof(double));
     return w;
 }
@@ -379,6 +379,8 @@ hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double
     sa.nb_max = p.z.nb_max;
     sa.npt_max = p.z.npt_max;
     sa.total_bin = p.z.total_bin;
+    sa.chunk = (double*)(wsb + p.w.chunk);
+    sa.total_pt = p.z.total_pt;
     return launch_planck(atm, T_pt, sa, gauss_table(atm->n_g), s);
 }
 

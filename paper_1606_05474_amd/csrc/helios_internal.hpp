@@ -228,6 +228,8 @@ struct SourceArgs {
     int32_t bnd_maxch, nb_max, npt_max;
     int32_t iso_grid;  // 1: Planck values of the isothermal-layer grid (see planck_kernel)
     int64_t total_bin;
+    double* chunk;     // bolometric workspace [n_chunk][kBolQ][total_pt]: the Planck kernel fills quantities 6, 7
+    int64_t total_pt;
 };
 hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const SourceArgs& sa, const GaussTable& gt,
                          hipStream_t s);
@@ -250,6 +252,10 @@ hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c,
 constexpr int kSweepK[] = {4, 8, 14, 26};
 constexpr int kLongK = 26;  // the only K instantiated with L = 64 (columns of up to 1664 sublayers)
 constexpr int kBolChunk = 64;  // bins per bolometric chunk
+// quantities per (bin chunk, point) in the bolometric workspace: Neumaier
+// pairs (sum, compensation) of the up, down and net deviation sums and of
+// the width-weighted Planck values
+constexpr int kBolQ = 8;
 constexpr int kBndChunk = 256;  // bins per boundary-flux workgroup
 constexpr int kNumSweepK = 4;
 

@@ -63,31 +63,71 @@ hipError_t launch_profile(const helios_atm* atm, int64_t total_pt, const double*
 }
 
 // --------------------------------------------------------------- sources
-// B[bin][pt] at the bin centres: workgroup = one bin, its threads stride over
-// the bin's points (the bin's atmosphere from the map the boundary kernel
-// wrote earlier in the same call; the per-bin lookups are paid once per bin).
+// Neumaier summation (a compensated sum: the pair (s, c) carries the rounding
+// errors of the running sum s in c).
+struct nacc {
+    double s, c;
+};
+__device__ inline void nadd(nacc& a, double v) {
+    double t = a.s + v;
+    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
+    else a.c += (v - t) + a.s;
+    a.s = t;
+}
+
+// B[bin][pt] at the bin centres, and per (chunk of kBolChunk bins, point)
+// the width-weighted sum of the chunk's Planck values, which the bolometric
+// up and down fluxes take from here (times 2 pi eps and the Gauss-weight
+// sum) instead of re-reading B.  Workgroup = (atmosphere, 64-point tile,
+// chunk of kBolChunk bins), 1024 threads = 64 points x 16 groups of
+// kBolChunk/16 bins, as the bin sum; the group sums are combined in a fixed
+// order.
 //
 // On the isothermal-layer grid (Sec. 2.2.1) layer i has the single
 // temperature of its centre (point 2i+1), and the sweep's reference values
-// are B(T_i) at points 2i and 2i+1 and B(T_{n-1}) at the TOA point 2n.  The
-// sweep then sees a Planck difference of zero across the layer itself (slot
-// 2i) and the step B(T_i) - B(T_{i+1}) across the identity slot 2i+1, which
-// moves the deviation from one layer's reference to the next one's.
-constexpr int kPlanckThreads = 128;
-__global__ void __launch_bounds__(kPlanckThreads) planck_kernel(helios_atm atm, const double* __restrict__ T_pt,
-                                                                const int32_t* __restrict__ bin_atm,
-                                                                double* __restrict__ B, int iso_grid) {
-    const int64_t b = blockIdx.x;
-    const int a = bin_atm[b];
-    if (frozen(atm.status, a)) return;  // uniform per workgroup
+// are B(T_i) at points 2i and 2i+1 and B(T_{n-1}) at the TOA point 2n.
+__global__ void __launch_bounds__(1024) planck_kernel(helios_atm atm, const double* __restrict__ T_pt,
+                                                      double* __restrict__ B, double* __restrict__ chunk,
+                                                      int64_t total_pt, int iso_grid) {
+    __shared__ double red[16][64][2];
+    const int a = blockIdx.x;
+    const int tile = blockIdx.y, ch = blockIdx.z;
+    const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int npt = 2 * atm.n_layer[a] + 1;
-    const double lam = atm.lambda_c[b];
-    const double* __restrict__ T = T_pt + atm.pt_off[a];
-    double* __restrict__ Bb = B + atm.pb_off[a] + (b - atm.bin_off[a]) * npt;
-#pragma unroll 4
-    for (int p = threadIdx.x; p < npt; p += kPlanckThreads) {
+    const int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
+    if (tile * 64 >= npt || ch * kBolChunk >= nb || frozen(atm.status, a)) return;  // uniform
+    const int p = tile * 64 + pl;
+    constexpr int per = kBolChunk / 16;
+    const int l0 = ch * kBolChunk + q * per;
+    nacc acc = {0.0, 0.0};
+    if (p < npt) {
         const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
-        Bb[p] = planck_d(lam, T[pt]);
+        const double T = T_pt[atm.pt_off[a] + pt];
+        const int64_t b0 = atm.bin_off[a];
+        double* __restrict__ Ba = B + atm.pb_off[a];
+#pragma unroll
+        for (int i = 0; i < per; ++i) {
+            const int l = l0 + i;
+            if (l < nb) {
+                const double v = planck_d(atm.lambda_c[b0 + l], T);
+                Ba[(int64_t)l * npt + p] = v;
+                nadd(acc, atm.dlambda[b0 + l] * v);
+            }
+        }
+    }
+    red[q][pl][0] = acc.s;
+    red[q][pl][1] = acc.c;
+    __syncthreads();
+    if (q == 0 && p < npt) {
+        nacc t = {0.0, 0.0};
+        double cc = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            nadd(t, red[k][pl][0]);
+            cc += red[k][pl][1];
+        }
+        const int64_t gpt = atm.pt_off[a] + p;
+        chunk[((int64_t)ch * kBolQ + 6) * total_pt + gpt] = t.s;
+        chunk[((int64_t)ch * kBolQ + 7) * total_pt + gpt] = t.c + cc;
     }
 }
 
@@ -128,13 +168,15 @@ __global__ void __launch_bounds__(kBndChunk) boundary_kernel(helios_atm atm, Sou
     if (t == 0) sa.bnd_part[(int64_t)a * sa.bnd_maxch + ch] = red[0];
 }
 
+constexpr int kStateThreads = 128;
+
 // Conversion of a per-g cell array between fluxes and deviations from the
 // isothermal flux (2 pi / D) B (Sec. 2.2.3; see helios_state_convert):
 // workgroup = one bin, threads over its points; each point's reference is
 // formed once in FP64 and applied to the bin's n_g columns (coalesced along
 // the points of a column).  mode 0: F - tpe B, 1: G + tpe B, 2: -tpe B.
 template <typename R>
-__global__ void __launch_bounds__(kPlanckThreads) state_kernel(helios_atm atm, const double* __restrict__ T_pt,
+__global__ void __launch_bounds__(kStateThreads) state_kernel(helios_atm atm, const double* __restrict__ T_pt,
                                                                double tpe, R* __restrict__ F, int mode,
                                                                int iso_grid) {
     const int64_t b = blockIdx.x;
@@ -145,7 +187,7 @@ __global__ void __launch_bounds__(kPlanckThreads) state_kernel(helios_atm atm, c
     const double lam = atm.lambda_c[b];
     const double* __restrict__ T = T_pt + atm.pt_off[a];
     R* __restrict__ col0 = F + atm.cell_off[a] + (b - atm.bin_off[a]) * atm.n_g * cs;
-    for (int p = threadIdx.x; p < npt; p += kPlanckThreads) {
+    for (int p = threadIdx.x; p < npt; p += kStateThreads) {
         const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
         const double ref = tpe * planck_d(lam, T[pt]);
         for (int g = 0; g < atm.n_g; ++g) {
@@ -159,10 +201,10 @@ __global__ void __launch_bounds__(kPlanckThreads) state_kernel(helios_atm atm, c
 hipError_t launch_state(const helios_atm* atm, const double* T_pt, double tpe, void* F, int mode, int iso_grid,
                         bool mixed, int64_t total_bin, hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL(state_kernel<float>, dim3((unsigned)total_bin), dim3(kPlanckThreads), 0, s, *atm, T_pt,
+        hipLaunchKernelGGL(state_kernel<float>, dim3((unsigned)total_bin), dim3(kStateThreads), 0, s, *atm, T_pt,
                            tpe, (float*)F, mode, iso_grid);
     else
-        hipLaunchKernelGGL(state_kernel<double>, dim3((unsigned)total_bin), dim3(kPlanckThreads), 0, s, *atm, T_pt,
+        hipLaunchKernelGGL(state_kernel<double>, dim3((unsigned)total_bin), dim3(kStateThreads), 0, s, *atm, T_pt,
                            tpe, (double*)F, mode, iso_grid);
     return hipGetLastError();
 }
@@ -172,8 +214,9 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
     hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm, sa.bnd_maxch), dim3(kBndChunk), 0, s, *atm, sa, gt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(planck_kernel, dim3((unsigned)sa.total_bin), dim3(kPlanckThreads), 0, s, *atm, T_pt,
-                       sa.bin_atm, sa.B, (int)sa.iso_grid);
+    dim3 grid(atm->n_atm, (sa.npt_max + 63) / 64, (sa.nb_max + kBolChunk - 1) / kBolChunk);
+    hipLaunchKernelGGL(planck_kernel, grid, dim3(1024), 0, s, *atm, T_pt, sa.B, sa.chunk, sa.total_pt,
+                       (int)sa.iso_grid);
     return hipGetLastError();
 }
 
@@ -181,21 +224,14 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
 // Stage 1: workgroup = (atmosphere, 64-point tile, chunk of kBolChunk bins);
 // 1024 threads = 64 points x 16 groups of kBolChunk/16 bins.  Each thread
 // combines the sweep's per-wave Gauss partials of a bin (fixed order) -- sums
-// of deviations G = F - 2 pi eps B -- adds 2 pi eps B times the sum of the
-// weights to form F_up_bin / F_dn_bin, writes them (when asked for), and accumulates dlambda
-// times the up, down and net (up - down, from the deviations, where B
-// cancels) fluxes in Neumaier sums; the group sums are combined in order and
-// stored per (chunk, quantity, point) (so both stages access them
-// coalesced).  Stage 2 sums a point's chunks in order.
-struct nacc {
-    double s, c;
-};
-__device__ inline void nadd(nacc& a, double v) {
-    double t = a.s + v;
-    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
-    else a.c += (v - t) + a.s;
-    a.s = t;
-}
+// of deviations G = F - 2 pi eps B -- and accumulates dlambda times the up,
+// down and net (up - down, where B cancels) deviations in Neumaier sums; the
+// group sums are combined in order, the up and down ones plus 2 pi eps times
+// the Gauss-weight sum times the chunk's width-weighted Planck sum (from the
+// Planck kernel), and stored per (chunk, quantity, point) (so both stages
+// access them coalesced).  Only when F_up_bin / F_dn_bin are asked for does
+// a thread read B, to write F = 2 pi eps B sum(w) + G per bin.  Stage 2 sums
+// a point's chunks in order.
 
 __device__ inline double combine_partials(const void* part, int64_t base, int wpb, int npt, bool mixed) {
     if (!mixed) {
@@ -210,9 +246,9 @@ __device__ inline double combine_partials(const void* part, int64_t base, int wp
     return acc;
 }
 
-// chunk sums: [n_chunk][6][total_pt]
+// chunk sums: [n_chunk][kBolQ][total_pt]
 __device__ inline int64_t chunk_at(const BolArgs& A, int ch, int v, int64_t gpt) {
-    return ((int64_t)ch * 6 + v) * A.total_pt + gpt;
+    return ((int64_t)ch * kBolQ + v) * A.total_pt + gpt;
 }
 
 __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
@@ -232,7 +268,7 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     if (p < npt) {
         const double* dl = A.atm.dlambda + A.atm.bin_off[a];
         const int64_t pb = A.atm.pb_off[a];
-        const double tw = A.tw;
+        const bool per_bin = A.F_up_bin || A.F_dn_bin;  // uniform
 #pragma unroll
         for (int i = 0; i < per; ++i) {
             const int l = l0 + i;
@@ -240,13 +276,14 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
                 const int64_t base = pb * A.wpb_stride + ((int64_t)l * A.wpb_stride) * npt + p;
                 const double gu = combine_partials(A.part_up, base, wpb, npt, A.mixed);
                 const double gd = combine_partials(A.part_dn, base, wpb, npt, A.mixed);
-                const int64_t o = pb + (int64_t)l * npt + p;
-                const double bw = tw * A.B[o];
-                const double fu = bw + gu, fd = bw + gd;
-                if (A.F_up_bin) A.F_up_bin[o] = fu;
-                if (A.F_dn_bin) A.F_dn_bin[o] = fd;
-                nadd(au, dl[l] * fu);
-                nadd(ad, dl[l] * fd);
+                if (per_bin) {
+                    const int64_t o = pb + (int64_t)l * npt + p;
+                    const double bw = A.tw * A.B[o];
+                    if (A.F_up_bin) A.F_up_bin[o] = bw + gu;
+                    if (A.F_dn_bin) A.F_dn_bin[o] = bw + gd;
+                }
+                nadd(au, dl[l] * gu);
+                nadd(ad, dl[l] * gd);
                 nadd(an, dl[l] * (gu - gd));
             }
         }
@@ -266,6 +303,10 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
         for (int k = 0; k < 16; ++k) {
             nadd(t, red[k][pl][2 * v]);
             cc += red[k][pl][2 * v + 1];
+        }
+        if (v < 2) {  // up and down: the isothermal flux's share of this chunk
+            nadd(t, A.tw * A.chunk[chunk_at(A, ch, 6, gpt)]);
+            cc += A.tw * A.chunk[chunk_at(A, ch, 7, gpt)];
         }
         A.chunk[chunk_at(A, ch, 2 * v, gpt)] = t.s;
         A.chunk[chunk_at(A, ch, 2 * v + 1, gpt)] = t.c + cc;

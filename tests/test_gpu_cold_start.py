@@ -7,7 +7,8 @@ parity in the sweep shape the benchmarks run -- GPU against the FP64 oracle.
 Tolerances as in test_gpu_parity: FP64 net flux within 1e-10 of the gross
 flux per point (and of max(|net|, sigma T_int^4)), per-g and per-bin fluxes
 within 1e-11 of their column's largest value; mixed precision 1e-4 of the
-gross flux; converged profiles within 0.1 K and +-10 updates.
+gross flux and MIXED_SIGMA_TOL of max(|net|, sigma T_int^4); converged
+profiles within 0.1 K and +-10 updates.
 """
 import numpy as np
 import pytest
@@ -252,10 +253,11 @@ def test_deviation_warm_start_reaches_the_paper_profile():
 
 def test_mixed_precision_reaches_the_paper_profile():
     """Mixed precision (deviation convention, zero-flux start) against the
-    oracle's paper reading: within 0.1 K over the well-conditioned layers.
-    The optically thin top layers, whose divergence hardly depends on their
-    own temperature, are weakly determined by the convergence test and are
-    not held to it (measured: 12 K at the top layer of this workload)."""
+    oracle's paper reading: within 0.1 K over the well-conditioned layers
+    (27 of the 50 here).  The optically thick bottom layers and the thin
+    upper ones, whose divergence hardly depends on their own temperature,
+    are weakly determined by the convergence test and are not held to it
+    (measured: up to 12 K at the top layer of this workload)."""
     atm, kt = W.plain_workload()
     sol = ref.solve(atm, kt, max_iter=300)
     assert sol["converged"]
@@ -265,6 +267,8 @@ def test_mixed_precision_reaches_the_paper_profile():
     assert conv[0]
     dT = np.abs(_np(s.T_c) - sol["T_c"])
     ok = well_conditioned_layers(atm, kt, sol)
+    # the excluded layers and their differences (shown with pytest -s)
+    print("excluded layers, |dT| K:", {int(i): round(float(dT[i]), 4) for i in np.where(~ok)[0]})
     assert ok.sum() >= atm["n"] // 2, ok.sum()
     assert dT[ok].max() < 0.1, (dT[ok].max(), dT.max(), np.argmax(dT))
 
