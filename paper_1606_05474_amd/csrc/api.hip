@@ -129,7 +129,8 @@ int parts_stride(const Sizes& z, int n_g) {
 WsLayout ws_layout(const Sizes& z, int n_g, bool /*mixed*/) {
     WsLayout w;
     const size_t wpb = (size_t)parts_stride(z, n_g);
-    const size_t n_chunk = (size_t)((z.nb_max + kBolChunk - 1) / kBolChunk);
+    const int cb = bol_chunk_bins(z.total_bin);
+    const size_t n_chunk = (size_t)((z.nb_max + cb - 1) / cb);
     w.B = 0;  // Planck values in FP64 for both precisions
     w.F_top = align256(w.B + (size_t)z.total_pb * sizeof(double));
     w.F_int = align256(w.F_top + (size_t)z.total_bin * sizeof(double));
@@ -381,6 +382,7 @@ hipError_t launch_sources(const helios_atm* atm, const FluxPlan& p, const double
     sa.total_bin = p.z.total_bin;
     sa.chunk = (double*)(wsb + p.w.chunk);
     sa.total_pt = p.z.total_pt;
+    sa.chunk_bins = bol_chunk_bins(p.z.total_bin);
     return launch_planck(atm, T_pt, sa, gauss_table(atm->n_g), s);
 }
 
@@ -551,7 +553,8 @@ int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     Bo.tpe = 2.0 * kPi / D;
     Bo.tw = Bo.tpe * gauss_weight_sum(atm->n_g);
     Bo.wpb_stride = A.wpb_stride;
-    Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
+    Bo.chunk_bins = bol_chunk_bins(p.z.total_bin);
+    Bo.n_chunk = (p.z.nb_max + Bo.chunk_bins - 1) / Bo.chunk_bins;
     Bo.mixed = p.mixed ? 1 : 0;
     Bo.n_cls = kNumClasses;
     for (int k = 0; k < kNumClasses; ++k) {
@@ -787,7 +790,8 @@ int helios_flux_exact(const helios_atm* atm, const double* kappa, const double* 
     Bo.tpe = kPi;  // the deviations are taken from pi B
     Bo.tw = Bo.tpe * gauss_weight_sum(atm->n_g);
     Bo.wpb_stride = A.wpb_stride;
-    Bo.n_chunk = (p.z.nb_max + kBolChunk - 1) / kBolChunk;
+    Bo.chunk_bins = bol_chunk_bins(p.z.total_bin);
+    Bo.n_chunk = (p.z.nb_max + Bo.chunk_bins - 1) / Bo.chunk_bins;
     Bo.mixed = 0;
     Bo.n_cls = kNumClasses;
     for (int k = 0; k < kNumClasses; ++k) {

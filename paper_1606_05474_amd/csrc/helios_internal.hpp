@@ -138,7 +138,8 @@ struct SweepArgs {
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
     int32_t bnd_maxch;    // boundary chunks per atmosphere in bnd_part
     int32_t iso_grid;     // 1: isothermal-layer grid (layer i = sublayer slot 2i, slot 2i+1 the identity)
-    int32_t flux_state;   // 1: F_up_g / F_dn_g hold fluxes; 0: deviations from (2 pi / D) B
+    int32_t flux_state;   // exact mode: 1 if F_up_g / F_dn_g hold fluxes, 0 for deviations from pi B (the
+                          // two-stream sweep always carries deviations; flux-state callers are converted around it)
     double D;
     const double* lambda_c;  // [sum nb] bin centres (Rayleigh scattering)
     double inv_mbar;         // > 0: add H2 Rayleigh scattering with this 1/mbar (g^-1); w0, g0 unused
@@ -164,6 +165,7 @@ struct BolArgs {
     double tpe;           // 2 pi eps = 2 pi / D: the sweep's partials are deviations from tpe B
     double tw;            // tpe times the sum of the Gauss weights (in g order), formed on the host
     int32_t wpb_stride, n_chunk, mixed;
+    int32_t chunk_bins;              // bins per chunk (bol_chunk_bins of the batch)
     int32_t n_cls;                   // size classes: atmosphere with n <= cls_nhi[k] (first k)
     int32_t cls_nhi[kMaxClasses];    // uses cls_wpb[k] waves per bin
     int32_t cls_wpb[kMaxClasses];
@@ -230,6 +232,7 @@ struct SourceArgs {
     int64_t total_bin;
     double* chunk;     // bolometric workspace [n_chunk][kBolQ][total_pt]: the Planck kernel fills quantities 6, 7
     int64_t total_pt;
+    int32_t chunk_bins;  // bins per chunk (bol_chunk_bins of the batch)
 };
 hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const SourceArgs& sa, const GaussTable& gt,
                          hipStream_t s);
@@ -251,7 +254,12 @@ hipError_t launch_radeq(const helios_atm* atm, const double* F_bol, double* T_c,
 // Sweep instantiations available (sublayers per lane).
 constexpr int kSweepK[] = {4, 8, 14, 26};
 constexpr int kLongK = 26;  // the only K instantiated with L = 64 (columns of up to 1664 sublayers)
-constexpr int kBolChunk = 64;  // bins per bolometric chunk
+// bins per bolometric chunk: 64 keeps enough workgroups in flight for a few
+// atmospheres; batches of at least kBolLargeBins bins take 256 (more loads in
+// flight per thread, a quarter of the chunk sums)
+constexpr int kBolChunkSmall = 64, kBolChunkLarge = 256;
+constexpr int64_t kBolLargeBins = 65536;
+inline int bol_chunk_bins(int64_t total_bin) { return total_bin >= kBolLargeBins ? kBolChunkLarge : kBolChunkSmall; }
 // quantities per (bin chunk, point) in the bolometric workspace: Neumaier
 // pairs (sum, compensation) of the up, down and net deviation sums and of
 // the width-weighted Planck values

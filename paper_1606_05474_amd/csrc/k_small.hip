@@ -75,12 +75,12 @@ __device__ inline void nadd(nacc& a, double v) {
     a.s = t;
 }
 
-// B[bin][pt] at the bin centres, and per (chunk of kBolChunk bins, point)
+// B[bin][pt] at the bin centres, and per (chunk of cb bins, point)
 // the width-weighted sum of the chunk's Planck values, which the bolometric
 // up and down fluxes take from here (times 2 pi eps and the Gauss-weight
 // sum) instead of re-reading B.  Workgroup = (atmosphere, 64-point tile,
-// chunk of kBolChunk bins), 1024 threads = 64 points x 16 groups of
-// kBolChunk/16 bins, as the bin sum; the group sums are combined in a fixed
+// chunk of cb bins), 1024 threads = 64 points x 16 groups of cb/16 bins
+// (cb = 64 or 256, by batch size), as the bin sum; the group sums are combined in a fixed
 // order.
 //
 // On the isothermal-layer grid (Sec. 2.2.1) layer i has the single
@@ -88,24 +88,24 @@ __device__ inline void nadd(nacc& a, double v) {
 // are B(T_i) at points 2i and 2i+1 and B(T_{n-1}) at the TOA point 2n.
 __global__ void __launch_bounds__(1024) planck_kernel(helios_atm atm, const double* __restrict__ T_pt,
                                                       double* __restrict__ B, double* __restrict__ chunk,
-                                                      int64_t total_pt, int iso_grid) {
+                                                      int64_t total_pt, int iso_grid, int cb) {
     __shared__ double red[16][64][2];
     const int a = blockIdx.x;
     const int tile = blockIdx.y, ch = blockIdx.z;
     const int pl = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int npt = 2 * atm.n_layer[a] + 1;
     const int nb = (int)(atm.bin_off[a + 1] - atm.bin_off[a]);
-    if (tile * 64 >= npt || ch * kBolChunk >= nb || frozen(atm.status, a)) return;  // uniform
+    if (tile * 64 >= npt || ch * cb >= nb || frozen(atm.status, a)) return;  // uniform
     const int p = tile * 64 + pl;
-    constexpr int per = kBolChunk / 16;
-    const int l0 = ch * kBolChunk + q * per;
+    const int per = cb / 16;
+    const int l0 = ch * cb + q * per;
     nacc acc = {0.0, 0.0};
     if (p < npt) {
         const int pt = (!iso_grid || (p & 1)) ? p : (p + 1 < npt ? p + 1 : p - 1);
         const double T = T_pt[atm.pt_off[a] + pt];
         const int64_t b0 = atm.bin_off[a];
         double* __restrict__ Ba = B + atm.pb_off[a];
-#pragma unroll
+#pragma unroll 4
         for (int i = 0; i < per; ++i) {
             const int l = l0 + i;
             if (l < nb) {
@@ -214,15 +214,15 @@ hipError_t launch_planck(const helios_atm* atm, const double* T_pt, const Source
     hipLaunchKernelGGL(boundary_kernel, dim3(atm->n_atm, sa.bnd_maxch), dim3(kBndChunk), 0, s, *atm, sa, gt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 grid(atm->n_atm, (sa.npt_max + 63) / 64, (sa.nb_max + kBolChunk - 1) / kBolChunk);
+    dim3 grid(atm->n_atm, (sa.npt_max + 63) / 64, (sa.nb_max + sa.chunk_bins - 1) / sa.chunk_bins);
     hipLaunchKernelGGL(planck_kernel, grid, dim3(1024), 0, s, *atm, T_pt, sa.B, sa.chunk, sa.total_pt,
-                       (int)sa.iso_grid);
+                       (int)sa.iso_grid, (int)sa.chunk_bins);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------ bolometric sums
-// Stage 1: workgroup = (atmosphere, 64-point tile, chunk of kBolChunk bins);
-// 1024 threads = 64 points x 16 groups of kBolChunk/16 bins.  Each thread
+// Stage 1: workgroup = (atmosphere, 64-point tile, chunk of chunk_bins bins);
+// 1024 threads = 64 points x 16 groups of chunk_bins/16 bins.  Each thread
 // combines the sweep's per-wave Gauss partials of a bin (fixed order) -- sums
 // of deviations G = F - 2 pi eps B -- and accumulates dlambda times the up,
 // down and net (up - down, where B cancels) deviations in Neumaier sums; the
@@ -259,17 +259,18 @@ __global__ void __launch_bounds__(1024) bin_sum_kernel(const BolArgs A) {
     const int n = A.atm.n_layer[a];
     const int npt = 2 * n + 1;
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
-    if (tile * 64 >= npt || ch * kBolChunk >= nb || frozen(A.atm.status, a)) return;  // uniform
+    const int cb = A.chunk_bins;
+    if (tile * 64 >= npt || ch * cb >= nb || frozen(A.atm.status, a)) return;  // uniform
     const int wpb = class_wpb(A, n);
     const int p = tile * 64 + pl;
-    constexpr int per = kBolChunk / 16;
-    const int l0 = ch * kBolChunk + q * per;
+    const int per = cb / 16;
+    const int l0 = ch * cb + q * per;
     nacc au = {0.0, 0.0}, ad = {0.0, 0.0}, an = {0.0, 0.0};
     if (p < npt) {
         const double* dl = A.atm.dlambda + A.atm.bin_off[a];
         const int64_t pb = A.atm.pb_off[a];
         const bool per_bin = A.F_up_bin || A.F_dn_bin;  // uniform
-#pragma unroll
+#pragma unroll 4
         for (int i = 0; i < per; ++i) {
             const int l = l0 + i;
             if (l < nb) {
@@ -323,7 +324,7 @@ __global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
     if (tile * 64 >= npt || frozen(A.atm.status, a)) return;
     const int p = tile * 64 + pl;
     const int nb = (int)(A.atm.bin_off[a + 1] - A.atm.bin_off[a]);
-    const int nch = (nb + kBolChunk - 1) / kBolChunk;
+    const int nch = (nb + A.chunk_bins - 1) / A.chunk_bins;
     nacc t[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     double e[3] = {0.0, 0.0, 0.0};
     const int64_t gpt = A.atm.pt_off[a] + p;
@@ -368,7 +369,7 @@ __global__ void __launch_bounds__(1024) bol_final_kernel(const BolArgs A) {
 }
 
 hipError_t launch_bolometric(const BolArgs& a, int npt_max, int nb_max, int64_t /*total_pt*/, hipStream_t s) {
-    dim3 grid(a.atm.n_atm, (npt_max + 63) / 64, (nb_max + kBolChunk - 1) / kBolChunk);
+    dim3 grid(a.atm.n_atm, (npt_max + 63) / 64, (nb_max + a.chunk_bins - 1) / a.chunk_bins);
     hipLaunchKernelGGL(bin_sum_kernel, grid, dim3(1024), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
