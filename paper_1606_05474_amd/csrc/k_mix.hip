@@ -203,7 +203,12 @@ __global__ void __launch_bounds__(kMixCols) mix_kernel(const MixArgs A) {
                 w = V{s_out[cc][4 * v], s_out[cc][4 * v + 1], s_out[cc][4 * v + 2], s_out[cc][4 * v + 3]};
             else
                 w = V{s_out[cc][2 * v], s_out[cc][2 * v + 1]};
-            *reinterpret_cast<V*>(kap + (int64_t)cc * cs + per * v) = w;
+            using NV = R __attribute__((ext_vector_type(per)));
+            NV nv;
+            if constexpr (per == 4) nv = NV{w.x, w.y, w.z, w.w};
+            else nv = NV{w.x, w.y};
+            // streamed past the caches: the array is far larger than they are
+            __builtin_nontemporal_store(nv, reinterpret_cast<NV*>(kap + (int64_t)cc * cs + per * v));
         }
     }
 }
