@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(1024) planck_kernel(helios_atm atm, const doub
             const int l = l0 + i;
             if (l < nb) {
                 const double v = planck_d(atm.lambda_c[b0 + l], T);
-                Ba[(int64_t)l * npt + p] = v;
+                __builtin_nontemporal_store(v, Ba + (int64_t)l * npt + p);
                 nadd(acc, atm.dlambda[b0 + l] * v);
             }
         }
