@@ -711,6 +711,7 @@ def production_main(args):
                          restart_after=args.restart_after or None, keep_T=args.plain_count, tol=args.prod_tol,
                          verify=not args.no_fp64_stage, log=log)
     base = WS.plain(seed=5, count=args.plain_count, max_iter=args.max_iter, keep_T=args.plain_count, log=log)
+    base_g = WS.plain(seed=5, count=args.plain_count, max_iter=args.max_iter, graph=True, log=log)
     if args.save_profiles:  # the production form's converged profiles, for checks outside this run
         keep = [k for k in range(len(prod["T"])) if prod["conv_flags"][k]]
         np.savez(args.save_profiles, index=np.array(keep), T=np.stack([prod["T"][k] for k in keep]),
@@ -759,6 +760,13 @@ def production_main(args):
                                      "median_updates": float(np.median(base["updates"]))},
         "speedup_converged_per_s": prod["converged_per_s"] / base["converged_per_s"]
         if base["converged_per_s"] > 0 else None,
+        "plain_fp64_graph_replayed": {"converged": base_g["converged"], "count": base_g["count"],
+                                      "seconds": base_g["seconds"], "converged_per_s": base_g["converged_per_s"],
+                                      "median_updates": float(np.median(base_g["updates"])),
+                                      "note": "the plain form with captured blocks of 10 updates replayed (host-"
+                                              "launch cost removed; graph replay belongs to the batching extension)"},
+        "speedup_vs_graph_replayed_plain": prod["converged_per_s"] / base_g["converged_per_s"]
+        if base_g["converged_per_s"] > 0 else None,
         "fp64_convergence_test_of_production_profiles": {
             "atmospheres": len(ok), "max_resid": float(max(resid[ok])) if ok else None, "tol": 1e-3,
             "pass": int(sum(resid[k] < 1e-3 for k in ok))},

@@ -414,10 +414,12 @@ def _run_compacting(s: H.Solver, max_iter: int, check_every: int, restart_after:
 
 
 def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int = 3000, max_iter: int = 400,
-          keep_T: int = 0, log=print):
+          keep_T: int = 0, graph: bool = False, log=print):
     """The plain form: the same atmospheres one at a time, FP64, isothermal
     start, an eager iteration loop (timed per atmosphere with its inputs
-    resident on the device)."""
+    resident on the device).  graph=True replays captured blocks of 10
+    updates instead (no host launch cost per kernel; a sensitivity check,
+    since graph replay belongs to the batching extension)."""
     kt = W.table_ktab(2, nbt=3000)
     ktd = H.KTable(kt)
     atms, _ = W.learned_workload(seed, count, start, n=n, nb=nb, ktab=kt)
@@ -431,7 +433,7 @@ def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int 
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.reset(atm["T0"])
-        conv, it, _ = s.run(max_iter, 10, graph=False)
+        conv, it, _ = s.run(max_iter, 10, graph=graph)
         torch.cuda.synchronize()
         out["seconds"] += time.perf_counter() - t0
         out["converged"] += int(conv[0])
@@ -443,8 +445,8 @@ def plain(seed: int = 5, count: int = 64, start: int = 0, n: int = 200, nb: int 
     out["updates"] = np.array(out["updates"])
     out["conv_flags"] = np.array(out["conv_flags"])
     out["converged_per_s"] = out["converged"] / out["seconds"]
-    log(f"plain: {out['converged']}/{count} converged in {out['seconds']:.1f} s, median updates "
-        f"{np.median(out['updates']):.0f}")
+    log(f"plain{' (graph replay)' if graph else ''}: {out['converged']}/{count} converged in {out['seconds']:.1f} s, "
+        f"median updates {np.median(out['updates']):.0f}")
     return out
 
 
