@@ -77,11 +77,10 @@ typedef enum { HELIOS_FP64 = 0, HELIOS_MIXED = 1 } helios_prec;
  *   HELIOS_STATE_FLUX: each value is the flux F itself (Sec. 2.2.3: the
  *     scattering iteration starts from zero fluxes, and later temperature
  *     steps start from the previous step's fluxes).  A zero array is the
- *     paper's cold start.  The flux calls convert the warm start to
- *     deviations in place before the sweep and the per-g outputs back after
- *     it (one FP64 conversion pass each way, as helios_state_convert does);
- *     meant for HELIOS_FP64.  If a call fails after its first launch the
- *     per-g arrays' contents are unspecified.
+ *     paper's cold start.  The sweep still carries deviations: it takes
+ *     (2 pi / D) B off the warm start as it reads it and adds it back to the
+ *     per-g values it stores, in the precision of the per-g arrays (meant
+ *     for HELIOS_FP64).
  * helios_state_convert() converts an array between the two. */
 #define HELIOS_STATE_DEVIATION 0x000
 #define HELIOS_STATE_FLUX 0x100

@@ -508,16 +508,7 @@ int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     SweepArgs A = sweep_args(atm, p, kappa, w0, g0, n_scat, D, F_up_g, F_dn_g, wsb);
     A.iso_grid = iso_grid ? 1 : 0;
     A.inv_mbar = inv_mbar;
-    A.flux_state = 0;  // the sweep reads and writes deviations only
-    // A caller that keeps fluxes has its warm start turned into deviations
-    // in place before the sweep and the per-g outputs turned back after it,
-    // so that the sweep carries no conversion of its own.
-    const double tpe = 2.0 * kPi / D;
-    if (p.flux_state) {
-        e = launch_state(atm, T_pt, tpe, F_up_g, HELIOS_CONVERT_TO_DEVIATION, iso_grid ? 1 : 0, p.mixed,
-                         p.z.total_bin, s);
-        if (e != hipSuccess) return hip_fail(e, name);
-    }
+    A.flux_state = p.flux_state ? 1 : 0;  // the sweep's flux-state variant converts as it reads and stores
     if (g_ev_before && g_ev_after) {
         e = hipEventRecord(g_ev_before, s);
         if (e != hipSuccess) return hip_fail(e, name);
@@ -531,13 +522,6 @@ int flux_impl(const helios_atm* atm, const void* kappa, const double* T_pt, cons
     if (g_ev_before && g_ev_after) {
         e = hipEventRecord(g_ev_after, s);
         if (e != hipSuccess) return hip_fail(e, name);
-    }
-    if (p.flux_state) {
-        for (void* F : {F_up_g, F_dn_g}) {
-            if (!F) continue;
-            e = launch_state(atm, T_pt, tpe, F, HELIOS_CONVERT_TO_FLUX, iso_grid ? 1 : 0, p.mixed, p.z.total_bin, s);
-            if (e != hipSuccess) return hip_fail(e, name);
-        }
     }
     BolArgs Bo;
     Bo.atm = *atm;

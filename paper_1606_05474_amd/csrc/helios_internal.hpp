@@ -138,8 +138,8 @@ struct SweepArgs {
     int32_t npt_max;      // largest 2n+1 of the batch (LDS staging size)
     int32_t bnd_maxch;    // boundary chunks per atmosphere in bnd_part
     int32_t iso_grid;     // 1: isothermal-layer grid (layer i = sublayer slot 2i, slot 2i+1 the identity)
-    int32_t flux_state;   // exact mode: 1 if F_up_g / F_dn_g hold fluxes, 0 for deviations from pi B (the
-                          // two-stream sweep always carries deviations; flux-state callers are converted around it)
+    int32_t flux_state;   // 1 if F_up_g / F_dn_g hold fluxes, 0 for deviations (from (2 pi / D) B in the
+                          // two-stream sweep, which carries deviations either way; from pi B in exact mode)
     double D;
     const double* lambda_c;  // [sum nb] bin centres (Rayleigh scattering)
     double inv_mbar;         // > 0: add H2 Rayleigh scattering with this 1/mbar (g^-1); w0, g0 unused

@@ -414,19 +414,21 @@ __device__ inline R col_sum(R v) {
 // capacity of K*L sublayers so that every lane can address its K sublayers
 // without bounds tests: sublayers past the column hold the identity.
 //   dB, hdm  [K*L + 1]   Planck difference and half column mass per sublayer
+//   tB       [K*L + 1]   (2 pi / D) B per point (flux-state variant only)
 //   lq       [K*L/2][4]  r, kx, sf, gd per layer
 //   pu, pd   [K*L + 2]   Gauss sums per point (slots past the column's
 //                        points take zeros)
 // On the isothermal-layer grid a slot is a whole layer with two points (its
 // lower interface and the point above it), so dB, hdm and lq are per layer
-// and pu, pd span 2 K*L + 2 points.
+// and tB, pu, pd span 2 K*L + 2 points.
 struct SweepLds {
-    int dB, hdm, lq, pu, pd, total;
+    int dB, hdm, tB, lq, pu, pd, total;
     static constexpr int r4(int v) { return (v + 3) & ~3; }
-    __host__ __device__ constexpr SweepLds(int KL, bool iso = false)
+    __host__ __device__ constexpr SweepLds(int KL, bool iso = false, bool fs = false)
         : dB(0),
           hdm(r4(KL + 1)),
-          lq(2 * r4(KL + 1)),
+          tB(2 * r4(KL + 1)),
+          lq(tB + (fs ? r4(iso ? 2 * KL + 2 : KL + 1) : 0)),
           pu(lq + 4 * r4(iso ? KL : KL / 2)),
           pd(pu + r4(iso ? 2 * KL + 2 : KL + 2)),
           total(pd + r4(iso ? 2 * KL + 2 : KL + 2)) {}
@@ -444,19 +446,23 @@ struct SweepLds {
 // give a bin one part; launches with few bins split a bin's groups over
 // several waves.  The bin-sum kernel adds a bin's partials in order, adds the
 // Planck term and sums over bins.  No barrier spans more than the wave.
-template <int K, int L, typename R, int OCC, bool RAY, bool ISO>
+// FS: the caller's per-g arrays hold fluxes (HELIOS_STATE_FLUX); the sweep
+// still carries deviations, taking (2 pi / D) B off the warm start as it is
+// read and adding it back to the per-g values as they are stored.
+template <int K, int L, typename R, int OCC, bool RAY, bool ISO, bool FS>
 __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     using R2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
     constexpr int C = 64 / L;
     constexpr int KH = K / 2;
     constexpr int KL = K * L;
-    constexpr SweepLds lay(KL, ISO);
+    constexpr SweepLds lay(KL, ISO, FS);
     static_assert(K % 2 == 0, "segments hold whole layers");
     static_assert(!(RAY && ISO), "Rayleigh scattering is solved on the sublayered grid");
     extern __shared__ unsigned char smem_raw[];
     R* sm = reinterpret_cast<R*>(smem_raw);
     R* s_dB = sm + lay.dB;
     R* s_hdm = sm + lay.hdm;
+    R* s_tB = sm + lay.tB;
     R* s_lq = sm + lay.lq;
     R* s_pu = sm + lay.pu;
     R* s_pd = sm + lay.pd;
@@ -474,6 +480,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     const R D = (R)A.D;
     const R inv_D = (R)(1.0 / A.D);
     const R tpe = (R)(2.0 * kPi / A.D);
+    const double tpe_d = 2.0 * kPi / A.D;
 
     for (int64_t item = A.w_begin + blockIdx.x; item < A.w_end; item += gridDim.x) {
         const int64_t gb = (A.parts == 1) ? item : item / A.parts;
@@ -519,8 +526,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         if constexpr (ISO) {
             // per layer j: dB = B(2j+1) - B(2j+2) (its own Planck value minus the
             // reference of its upper interface), half its column mass, and its
-            // r, kx, sf, gd; the Gauss-sum slots of every point of the
-            // capacity cleared
+            // r, kx, sf, gd; per point: the flux-state reference (FS) and the
+            // Gauss-sum slots of every point of the capacity cleared
             constexpr int SCH = (KL + 63) / 64;
             constexpr int QCH = (2 * KL + 2 + 63) / 64;
             for (int q = 0; q < SCH; ++q) {  // one chunk of 64 layers at a time
@@ -545,6 +552,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             for (int q = 0; q < QCH; ++q) {
                 const int i = lane + 64 * q;
                 if (i <= 2 * KL + 1) {
+                    if constexpr (FS) s_tB[i] = (i < npt) ? (R)(tpe_d * B_all[pb + i]) : (R)0;
                     s_pu[i] = (R)0;
                     s_pd[i] = (R)0;
                 }
@@ -583,6 +591,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 if (i <= KL) {
                     s_dB[i] = real ? (R)(bv[q] - bn) : (R)0;
                     s_hdm[i] = real ? (R)((pv[q] - pn) * higrav) : (R)0;
+                    if constexpr (FS) s_tB[i] = (i < npt) ? (R)(tpe_d * bv[q]) : (R)0;
                 }
                 if (i <= KL + 1) {
                     s_pu[i] = (R)0;
@@ -634,6 +643,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                 kv[k] = kap_g[col + pt + 1];
                 fu[k] = fu_g[col + pt];
             }
+            if constexpr (FS) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) fu[k] -= s_tB[2 * (lo + k)];
+            }
         } else {
             R2 kp2[KH + 1], fp2[KH];
 #pragma unroll
@@ -651,6 +664,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
             for (int p = 0; p < KH; ++p) {
                 fu[2 * p] = fp2[p].x;
                 fu[2 * p + 1] = fp2[p].y;
+            }
+            if constexpr (FS) {  // the sweep carries deviations from the isothermal flux
+#pragma unroll
+                for (int k = 0; k < K; ++k) fu[k] -= s_tB[lo + k];
             }
         }
 
@@ -813,13 +830,17 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     R2 w;
                     w.x = v[k];
                     w.y = upper_iso(v, vlast, k);
+                    if constexpr (FS) {
+                        w.x += s_tB[2 * (lo + k)];
+                        w.y += s_tB[2 * (lo + k) + 1];
+                    }
                     *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(2 * (lo + k)))) = w;
                 }
             }
-            if (top_seg) dst_g[col + (uint32_t)nsub] = vlast;
+            if (top_seg) dst_g[col + (uint32_t)nsub] = FS ? vlast + s_tB[nsub] : vlast;
         };
         // per-g values of one stream (pairs at my points, the TOA value
-        // alone)
+        // alone), as fluxes in the flux-state variant
         auto store = [&](const R (&v)[K], R vtop, R* __restrict__ dst_g) {
             if (!colok) return;
 #pragma unroll
@@ -828,10 +849,14 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     R2 w;
                     w.x = v[2 * p];
                     w.y = v[2 * p + 1];
+                    if constexpr (FS) {
+                        w.x += s_tB[lo + 2 * p];
+                        w.y += s_tB[lo + 2 * p + 1];
+                    }
                     *reinterpret_cast<R2*>(dst_g + (col + (uint32_t)(lo + 2 * p))) = w;
                 }
             }
-            if (top_seg) dst_g[col + (uint32_t)nsub] = vtop;
+            if (top_seg) dst_g[col + (uint32_t)nsub] = FS ? vtop + s_tB[nsub] : vtop;
         };
 
         // One scattering pass: downward sweep (top -> bottom), then upward
@@ -944,8 +969,8 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
 }
 
 // LDS bytes of one sweep workgroup of shape (K, L).
-static size_t sweep_lds(int K, int L, size_t rbytes, bool iso = false) {
-    return (size_t)SweepLds(K * L, iso).total * rbytes;
+static size_t sweep_lds(int K, int L, size_t rbytes, bool iso = false, bool fs = false) {
+    return (size_t)SweepLds(K * L, iso, fs).total * rbytes;
 }
 
 // Occupancy hint (waves per SIMD) so the register arrays fit without spills
@@ -966,20 +991,26 @@ static hipError_t allow_lds(Kern kern, size_t bytes) {
                                (int)bytes);
 }
 
-template <int K, int L, bool RAY, bool ISO>
-static hipError_t launch_kpr(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
+template <int K, int L, bool RAY, bool ISO, bool FS>
+static hipError_t launch_kprf(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
     if (mixed) {
-        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false, ISO>(), RAY, ISO>;
-        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 4, ISO));
+        auto kern = sweep_kernel<K, L, float, sweep_occ<K, L, false, ISO>(), RAY, ISO, FS>;
+        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 4, ISO, FS));
         if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 4, ISO), s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 4, ISO, FS), s, a);
     } else {
-        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true, ISO>(), RAY, ISO>;
-        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 8, ISO));
+        auto kern = sweep_kernel<K, L, double, sweep_occ<K, L, true, ISO>(), RAY, ISO, FS>;
+        static const hipError_t ok = allow_lds(kern, sweep_lds(K, L, 8, ISO, FS));
         if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 8, ISO), s, a);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sweep_lds(K, L, 8, ISO, FS), s, a);
     }
     return hipGetLastError();
+}
+
+template <int K, int L, bool RAY, bool ISO>
+static hipError_t launch_kpr(const SweepArgs& a, bool mixed, int grid, hipStream_t s) {
+    if (a.flux_state) return launch_kprf<K, L, RAY, ISO, true>(a, mixed, grid, s);
+    return launch_kprf<K, L, RAY, ISO, false>(a, mixed, grid, s);
 }
 
 template <int K, int L>
