@@ -290,7 +290,9 @@ def run_batch(prec: int, steps: int, warmup: int, atms: list, kt: dict, max_iter
     from paper_1606_05474_amd import helios as H
 
     b = H.Batch(atms)
-    s = H.Solver(b, H.KTable(kt), prec=prec)
+    # mixed precision takes the dead band (thin layers within the tolerance keep
+    # their temperature; without it their FP32 drift can run away)
+    s = H.Solver(b, H.KTable(kt), prec=prec, opts=H.REOptions(deadband=1 if prec == H.MIXED else 0))
     T0 = np.concatenate([a["T0"] for a in atms])
     s.reset(T0)
     t_tune = time.perf_counter()
