@@ -1068,6 +1068,12 @@ def spectral_main(args):
                             "frac": UNIT_BYTES["mixed"] * units / (mixed["sweep_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                             "traffic": traffic_entry("mixed"), "sweep_shape": mixed["shape"]},
     }
+    # the FP64 solver keeps the paper's fluxes between iterations (its sweep
+    # converts them as it reads and stores); the same steps with the per-g
+    # state kept as deviations show what that conversion costs
+    dev = run_gpu(H.FP64, args.steps, args.warmup, atm, kt, state="deviation")
+    line["fp64_deviation_state"] = {"value": dev["value"], "ms_per_step": dev["ms_per_step"],
+                                    "sweep_ms": dev["sweep_ms"], "sweep_shape": dev["shape"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(atm, kt, args.cpu_budget)
     print(json.dumps(line))
