@@ -89,6 +89,9 @@ template <>
 struct Prec<double> {
     // T = exp(-x) and om = 1 - T (om accurate for thin layers)
     __device__ static inline void t_om(double x, double& T, double& om) { exp_neg_om(x, T, om); }
+    // the sweep's staged kx carries no unit factor in FP64
+    static constexpr double kx_unit = 1.0;
+    __device__ static inline void t_om_u(double x, double& T, double& om) { exp_neg_om(x, T, om); }
     // reciprocal: hardware estimate refined by two Newton steps (the
     // arguments here are well scaled: no denormals, no overflow)
     __device__ static inline double rcp(double v) {
@@ -112,6 +115,20 @@ struct Prec<float> {
         p = x * p - 0.5f;
         p = x * p + 1.0f;
         om = (x < 0.25f) ? x * p : 1.0f - T;
+    }
+    // The sweep's FP32 kx is staged in base-2 units (times log2 e), so that
+    // y = kx dtau feeds the hardware exp2 directly: T = 2^-y, and
+    // om = 1 - 2^-y from its Taylor series in y (coefficients (-1)^k
+    // ln2^(k+1)/(k+1)!, the same truncation as above) below y = 0.25/ln2.
+    static constexpr float kx_unit = 1.4426950408889634f;
+    __device__ static inline void t_om_u(float y, float& T, float& om) {
+        T = __builtin_amdgcn_exp2f(-y);
+        float p = y * -1.5403530393381606e-4f + 1.3333558146428441e-3f;
+        p = y * p - 9.618129107628477e-3f;
+        p = y * p + 5.5504108664821576e-2f;
+        p = y * p - 0.2402265069591007f;
+        p = y * p + 0.6931471805599453f;
+        om = (y < 0.36067376f) ? y * p : 1.0f - T;
     }
     __device__ static inline float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
     // hardware square root (about 1 ulp), enough for the mixed path
@@ -200,7 +217,7 @@ __device__ inline void layer_g(R w0, R g0, R D, R inv_D, R tpe, R& r, R& kx, R& 
     const R omg = one - w0 * g0;
     const R iomg = Prec<R>::rcp(omg);
     r = Prec<R>::sqrt_((one - w0) * iomg);
-    kx = D * r * omg;
+    kx = D * r * omg * Prec<R>::kx_unit;
     sf = tpe * iomg * inv_D;
     gd = ((one - w0) < (R)1e-6) ? D * (one - g0) * (R)0.5 : (R)-1;
 }
@@ -218,7 +235,7 @@ __device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R
                                     bool act, R& a, R& c, R& sig) {
     const R one = (R)1;
     R T, om;
-    Prec<R>::t_om(kx * dtau, T, om);
+    Prec<R>::t_om_u(kx * dtau, T, om);
     const R u = zp - zm * T, v = zp + zm * T;
     const R den = u * v;
     const R dd = fmax(dtau, sizeof(R) == 8 ? (R)0x1p-960 : (R)0x1p-100);
@@ -709,7 +726,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     const R dtau = act ? dabs + kR2 * s_hdm[lo + k] : (R)0;
                     const R omw = (dtau > (R)0) ? dabs * Prec<R>::rcp(dtau) : (R)1;
                     r = Prec<R>::sqrt_(omw);
-                    kx = D * r;
+                    kx = D * Prec<R>::kx_unit * r;
                     sf = tpe * inv_D;
                     gd = (omw < (R)1e-6) ? D * (R)0.5 : (R)-1;
                     zp = (R)0.5 + (R)0.5 * r;
@@ -730,18 +747,26 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     zpzm = zp * zm;
                 }
                 // sublayer: mean of its end opacities times its column mass.
-                // (iso_grid is 0 on this path; the two-branch form is kept
-                // because it compiles to fewer registers than the plain one:
-                // 440 against 512 plus spills in the FP64 long-column shape.)
+                // (iso_grid is 0 on this path; the long shapes keep a
+                // two-branch form that compiles to fewer registers there: 440
+                // against 512 plus spills in the FP64 long-column shape.)
                 R dtau;
-                if ((k & 1) == 0) {
-                    const R k_lo = A.iso_grid ? kv[k + 1] : kv[k];
-                    const R hm = A.iso_grid ? s_hdm[lo + k] + s_hdm[lo + k + 1] : s_hdm[lo + k];
-                    dtau = act ? (k_lo + kv[k + 1]) * hm : (R)0;
+                if constexpr (K >= kLongK) {
+                    if ((k & 1) == 0) {
+                        const R k_lo = A.iso_grid ? kv[k + 1] : kv[k];
+                        const R hm = A.iso_grid ? s_hdm[lo + k] + s_hdm[lo + k + 1] : s_hdm[lo + k];
+                        dtau = act ? (k_lo + kv[k + 1]) * hm : (R)0;
+                    } else {
+                        dtau = (act && !A.iso_grid) ? (kv[k] + kv[k + 1]) * s_hdm[lo + k] : (R)0;
+                    }
                 } else {
-                    dtau = (act && !A.iso_grid) ? (kv[k] + kv[k + 1]) * s_hdm[lo + k] : (R)0;
+                    // past the column's last sublayer the LDS padding gives
+                    // dtau = 0 (a surplus column's lanes compute values that
+                    // carry zero Gauss weight and are not stored), and the
+                    // identity map's c = 0 cancels the clamped warm start
+                    dtau = (kv[k] + kv[k + 1]) * s_hdm[lo + k];
                 }
-                fu[k] = act ? fu[k] : (R)0;
+                if constexpr (K >= kLongK) fu[k] = act ? fu[k] : (R)0;
                 sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], act, ca[k], cc[k], sg[k]);
             }
         }
