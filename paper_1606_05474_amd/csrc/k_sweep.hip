@@ -238,7 +238,11 @@ __device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R
     Prec<R>::t_om_u(kx * dtau, T, om);
     const R u = zp - zm * T, v = zp + zm * T;
     const R den = u * v;
-    const R dd = fmax(dtau, sizeof(R) == 8 ? (R)0x1p-960 : (R)0x1p-100);
+    R dd;
+    if constexpr (sizeof(R) == 4)  // dtau >= 0: the integer maximum of the bit patterns is the float one
+        dd = __int_as_float(max(__float_as_int(dtau), __float_as_int(0x1p-100f)));
+    else
+        dd = fmax(dtau, (R)0x1p-960);
     const R rec = Prec<R>::rcp(den * dd);
     const R iden = rec * dd;  // 1/den
     const R omi = om * iden;
@@ -498,6 +502,10 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
     const R inv_D = (R)(1.0 / A.D);
     const R tpe = (R)(2.0 * kPi / A.D);
     const double tpe_d = 2.0 * kPi / A.D;
+    // FP32: the Gauss weights held one per lane (n_g <= HELIOS_MAX_NG = 32 <
+    // 64), so that a group takes its columns' weights with a lane exchange
+    // instead of reloading the weight array's address
+    const float gw_lane = (lane < A.n_g) ? (float)A.gw[lane] : 0.0f;
 
     for (int64_t item = A.w_begin + blockIdx.x; item < A.w_end; item += gridDim.x) {
         const int64_t gb = (A.parts == 1) ? item : item / A.parts;
@@ -645,7 +653,13 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
         const R* __restrict__ kap_g = kap_all + gcol;
         R* __restrict__ fu_g = Fu_all + gcol;
         const uint32_t col = (uint32_t)(min(cw, ncols - 1) * cs);
-        const R wg = colok ? (R)A.gw[j * C + cw] : (R)0;  // Gauss weight of my column
+        R wg;  // Gauss weight of my column
+        if constexpr (sizeof(R) == 4) {
+            const float wsrc = __shfl(gw_lane, min(j * C + cw, 63), 64);  // every lane takes part
+            wg = colok ? wsrc : 0.0f;
+        } else {
+            wg = colok ? (R)A.gw[j * C + cw] : (R)0;
+        }
 
         // ---- my points' opacities (lo .. lo + K) and warm start (lo .. lo + K - 1):
         // pairs starting at even indices, clamped to nsub; a pair at nsub also
