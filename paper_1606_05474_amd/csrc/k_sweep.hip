@@ -228,11 +228,12 @@ __device__ inline void layer_g(R w0, R g0, R D, R inv_D, R tpe, R& r, R& kx, R& 
 // rec = 1/((zp - zm T)(zp + zm T) dtau), serves a, c and the gradient term.
 // dtau is floored at a power of two, so that a transparent sublayer stays
 // finite and a padding sublayer (dtau = 0, dB = 0, r = 1, kx = sf = 0) is
-// exactly the identity map (a = 1, c = sig = 0).  Only real sublayers (act)
-// take the eq:isoscat form.
+// exactly the identity map (a = 1, c = sig = 0).  Thin sublayers with a
+// Planck difference take the eq:isoscat form (with dB = 0 both forms give
+// sig = 0).
 template <typename R>
 __device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R dtau, R two_pi_eps, R dB,
-                                    bool act, R& a, R& c, R& sig) {
+                                    R& a, R& c, R& sig) {
     const R one = (R)1;
     R T, om;
     Prec<R>::t_om_u(kx * dtau, T, om);
@@ -249,9 +250,10 @@ __device__ inline void sub_coeffs_g(R r, R kx, R sf, R gd, R zp, R zm, R zpzm, R
     a = r * T * iden;
     c = zpzm * (one + T) * omi;
     sig = sf * dB * v * om * rec;  // 2 pi eps f dB om / ((zp - zm T) dtau)
-    const bool iso = act && dtau < (R)1e-4;
-    if (__any(iso)) sig = iso ? (R)0.5 * two_pi_eps * (one + a - c) * dB : sig;
-    if (__any(gd >= (R)0)) {  // eq:purescat
+    // eq:isoscat; the wave-wide tests are ballots of the compare masks
+    const bool iso = dtau < (R)1e-4 && dB != (R)0;
+    if (__builtin_amdgcn_ballot_w64(iso) != 0) sig = iso ? (R)0.5 * two_pi_eps * (one + a - c) * dB : sig;
+    if (__builtin_amdgcn_ballot_w64(gd >= (R)0) != 0) {  // eq:purescat
         const bool ps = gd >= (R)0;
         const R g = gd * dtau;
         const R qq = g * Prec<R>::rcp(one + g);
@@ -725,7 +727,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     zpzm = zp * zm;
                     const R dtau = act ? (kv[k] + kv[k]) * s_hdm[lo + k] : (R)0;
                     fu[k] = act ? fu[k] : (R)0;
-                    sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, (R)0, act, ca[k], cc[k], sg[k]);
+                    sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, (R)0, ca[k], cc[k], sg[k]);
                     sg[k] = tpe * s_dB[lo + k];
                     // the long shapes read one layer's LDS values at a time (all
                     // of them hoisted ahead would hold 5 K values in registers)
@@ -747,7 +749,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     zm = (R)0.5 - (R)0.5 * r;
                     zpzm = zp * zm;
                     fu[k] = act ? fu[k] : (R)0;
-                    sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], act, ca[k], cc[k], sg[k]);
+                    sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], ca[k], cc[k], sg[k]);
                     continue;
                 }
                 if ((k & 1) == 0) {
@@ -781,7 +783,7 @@ __global__ void __launch_bounds__(64, OCC) sweep_kernel(const SweepArgs A) {
                     dtau = (kv[k] + kv[k + 1]) * s_hdm[lo + k];
                 }
                 if constexpr (K >= kLongK) fu[k] = act ? fu[k] : (R)0;
-                sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], act, ca[k], cc[k], sg[k]);
+                sub_coeffs_g<R>(r, kx, sf, gd, zp, zm, zpzm, dtau, tpe, s_dB[lo + k], ca[k], cc[k], sg[k]);
             }
         }
 
