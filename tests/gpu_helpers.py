@@ -51,10 +51,26 @@ def net_flux_error_sigma(F_bol_gpu, F_bol_ref, T_int):
 # orders of magnitude, so this measure exceeds 1e-4 (measured: 1.2e-4 and
 # 1.4e-4 on the ragged and full-size two-stream tests, 5.7e-4 on the ragged
 # Rayleigh batch, up to 3.5e-4 on production atmospheres with T_int near
-# 100 K).  The mixed path's flux error is held below the convergence
-# tolerance of 1e-3 sigma T_int^4 it feeds (Sec. 2.2.4); a profile's final
-# acceptance is the FP64 path's.
+# 100 K).  The bound is the convergence tolerance of 1e-3 sigma T_int^4
+# (Sec. 2.2.4) wherever float32 can reach it; a profile's final acceptance
+# is the FP64 path's.
 MIXED_SIGMA_TOL = 1e-3
+
+
+def mixed_sigma_bound(F_bol_ref, T_int, ulps=4.0):
+    """Bound of net_flux_error_sigma for the mixed path on one atmosphere:
+    MIXED_SIGMA_TOL, or `ulps` float32 roundings (2^-24 each) of the gross
+    flux measured the same way where that is larger.  A float32 deviation
+    carries the gross flux's rounding into the net flux, so where the gross
+    flux exceeds max(|net|, sigma T_int^4) by more than about 2e4 (deep
+    layers of atmospheres with T_int near 100-150 K) no float32 sweep can
+    resolve the net flux to 1e-3 of it."""
+    F = np.asarray(F_bol_ref).reshape(-1, 3)
+    gross = F[:, 0] + F[:, 1]
+    if float(T_int) <= 0.0:
+        return MIXED_SIGMA_TOL
+    floor = 5.670374419e-5 * float(T_int) ** 4
+    return max(MIXED_SIGMA_TOL, ulps * 2.0 ** -24 * float(np.max(gross / np.maximum(np.abs(F[:, 2]), floor))))
 
 
 def col_rel_error(x, y, axis=-1):

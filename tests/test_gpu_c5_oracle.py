@@ -11,7 +11,9 @@ isothermal flux, each warm-started from the previous one); it is written by
 same atmospheres, as one batch in the production sweep shape, take the same 20
 solves from the same start: FP64 to 1e-10 of the gross flux and of
 max(|net|, sigma T_int^4) per point, mixed precision to 1e-4 of the gross flux
-and MIXED_SIGMA_TOL of max(|net|, sigma T_int^4).
+and, against max(|net|, sigma T_int^4), to MIXED_SIGMA_TOL or a few float32
+roundings of the gross flux where that is larger (the atmospheres with T_int
+near 100-150 K: mixed_sigma_bound).
 """
 import os
 
@@ -19,7 +21,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import MIXED_SIGMA_TOL, net_flux_error, net_flux_error_sigma
+from gpu_helpers import mixed_sigma_bound, net_flux_error, net_flux_error_sigma
 from paper_1606_05474_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -75,4 +77,4 @@ def test_settled_flux_at_the_oracle_equilibrium(prec, golden, monkeypatch):
         if prec == 0:
             assert err < 1e-10 and sig < 1e-10, (a, err, sig)
         else:
-            assert err < 1e-4 and sig < MIXED_SIGMA_TOL, (a, err, sig)
+            assert err < 1e-4 and sig < mixed_sigma_bound(g["F_bol"][a], atm["T_int"]), (a, err, sig)
